@@ -1,0 +1,289 @@
+"""Seeded synthetic inputs shaped like the paper's biofilm workloads.
+
+This module only draws inputs: node positions, spring lists, stiffnesses,
+initial and boundary velocities, and the parameter set of each workload.  It
+holds none of the method's arithmetic (no delta kernels, stencils or solves)
+and is the one module that both the HIP path and the CPU oracle read.
+
+Nondimensional constants follow the paper's scaling table (L = 50 um,
+u0 = 1e-3 m/s, T = 1 s, rho0 = 998 kg/m^3, mu = 1e-3 kg/(m s),
+pressure drop 0.8144 Pa): sigma = L / (T u0) = 0.05,
+eps = dp / (rho0 u0^2) = 816.03, Re = rho0 L u0 / mu = 0.0499.
+The paper's microscopy cell coordinates are not available, so node clouds are
+drawn from the shapes and spacings it describes (mounds and films on the
+bottom wall, about 1 um between cells, springs to neighbours within a few um).
+"""
+import math
+
+import numpy as np
+
+AX_PERIODIC, AX_WALLS, AX_INOUT = 0, 1, 2
+
+L_CHAR = 50e-6
+SIGMA = L_CHAR / (1.0 * 1e-3)
+EPS = 0.8144 / (998.0 * 1e-6)
+RE = 998.0 * L_CHAR * 1e-3 / 1e-3
+
+
+def base_params(dim, n, axis_bc, h):
+    return dict(
+        dim=dim, n=list(n) + [1] * (3 - len(n)), axis_bc=list(axis_bc) + [0] * (3 - len(axis_bc)), h=h,
+        sigma=SIGMA, eps=EPS, inv_re=1.0 / RE, force_coef=1.0, dt=1e-4,
+        body_force=[0.0, 0.0, 0.0], rho0=1.0, rho_b=0.0, d0_pow_d=0.0,
+        mu_out=1.0, mu_max=1.0, omega=0.02, kernel=0, break_ratio=2.0,
+        nu1=2, nu2=2, max_levels=0, max_cycles=200, rtol=1e-10, gamma=[1.0] * 16,
+    )
+
+
+# --------------------------------------------------------------------------
+# node clouds
+# --------------------------------------------------------------------------
+def half_disc_uniform(rng, n, cx, r):
+    """n points uniform in the half-disc of radius r centred at (cx, 0), y >= 0."""
+    pts = []
+    while len(pts) < n:
+        x = rng.uniform(-r, r, size=4 * n)
+        y = rng.uniform(0.0, r, size=4 * n)
+        ok = x * x + y * y < r * r
+        for a, b in zip(x[ok], y[ok]):
+            pts.append((cx + a, b))
+            if len(pts) == n:
+                break
+    return np.array(pts).T.copy()
+
+
+def poisson_disc(rng, inside, lo, hi, rmin, limit, seed_point, k=30):
+    """Bridson's dart throwing grown from seed_point: points at least rmin
+    apart inside the region given by the vectorised predicate inside(P),
+    within the box [lo, hi]; growth stops at `limit` points."""
+    lo, hi = np.asarray(lo, float), np.asarray(hi, float)
+    D = lo.size
+    cs = rmin / math.sqrt(D)
+    shape = np.maximum(1, np.ceil((hi - lo) / cs).astype(int))
+    grid = -np.ones(tuple(shape), dtype=np.int64)
+    pts = [np.asarray(seed_point, float)]
+    grid[tuple(np.minimum(((pts[0] - lo) / cs).astype(int), shape - 1))] = 0
+    active = [0]
+    reach = int(math.ceil(math.sqrt(D))) + 1
+    while active and len(pts) < limit:
+        ai = rng.integers(len(active))
+        base = pts[active[ai]]
+        # k candidates in the shell [rmin, 2 rmin)
+        dirs = rng.normal(size=(k, D))
+        dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+        rad = rmin * (1.0 + rng.random(k))
+        cand = base + dirs * rad[:, None]
+        ok_box = np.all((cand >= lo) & (cand <= hi), axis=1)
+        ok_in = np.zeros(k, bool)
+        if ok_box.any():
+            ok_in[ok_box] = inside(cand[ok_box])
+        placed = False
+        for c in cand[ok_in]:
+            gi = np.minimum(((c - lo) / cs).astype(int), shape - 1)
+            sl = tuple(slice(max(0, g - reach), min(s, g + reach + 1)) for g, s in zip(gi, shape))
+            near = grid[sl]
+            near = near[near >= 0]
+            if near.size:
+                dd = np.linalg.norm(np.asarray([pts[j] for j in near]) - c, axis=1)
+                if np.any(dd < rmin):
+                    continue
+            grid[tuple(gi)] = len(pts)
+            pts.append(c)
+            active.append(len(pts) - 1)
+            placed = True
+            break
+        if not placed:
+            active.pop(ai)
+    return np.asarray(pts).T.copy()
+
+
+def spring_pairs(X, cutoff):
+    """All node pairs closer than cutoff (strictly), as int32 [2][m], i < j."""
+    from scipy.spatial import cKDTree
+    pairs = cKDTree(X.T).query_pairs(cutoff, output_type="ndarray")
+    if pairs.size == 0:
+        return np.zeros((2, 0), np.int32)
+    d = np.linalg.norm(X[:, pairs[:, 0]] - X[:, pairs[:, 1]], axis=0)
+    pairs = pairs[d < cutoff]
+    order = np.lexsort((pairs[:, 1], pairs[:, 0]))
+    return np.ascontiguousarray(pairs[order].T.astype(np.int32))
+
+
+def rest_lengths(X, ij):
+    return np.linalg.norm(X[:, ij[1]] - X[:, ij[0]], axis=0)
+
+
+# --------------------------------------------------------------------------
+# boundary and initial velocity data
+# --------------------------------------------------------------------------
+def face_dims(p, a):
+    """Closed-domain extent of the a-face lattice along x, y, z."""
+    dims = []
+    for d in range(3):
+        if d >= p["dim"]:
+            dims.append(1)
+        elif d == a:
+            dims.append(p["n"][d] if p["axis_bc"][d] == AX_PERIODIC else p["n"][d] + 1)
+        else:
+            dims.append(p["n"][d])
+    return dims
+
+
+def duct_profile(nx, ny, h, terms=199):
+    """Laminar axial velocity in a square duct (Spiga-Morini double series),
+    at cell centres of an nx x ny cross-section, scaled to 1 at the centre."""
+    ax, ay = nx * h, ny * h
+    x = (np.arange(nx) + 0.5) * h
+    y = (np.arange(ny) + 0.5) * h
+    s = np.zeros((ny, nx))
+    s0 = 0.0
+    for nn in range(1, terms + 1, 2):
+        sx = np.sin(nn * math.pi * x / ax)
+        for mm in range(1, terms + 1, 2):
+            c = 1.0 / (nn * mm * (nn * nn + mm * mm))
+            s += c * np.outer(np.sin(mm * math.pi * y / ay), sx)
+            s0 += c * math.sin(nn * math.pi / 2) * math.sin(mm * math.pi / 2)
+    return s / s0
+
+
+def initial_velocity(p, umax=1.0):
+    """Laminar flow in the channel (2D: parabola across y; 3D: duct profile
+    along z), written on every face of the flow component including the
+    inflow face; other components zero."""
+    comps = []
+    for a in range(p["dim"]):
+        comps.append(np.zeros(face_dims(p, a)[::-1]))
+    h = p["h"]
+    if p["dim"] == 2:
+        ly = p["n"][1] * h
+        y = (np.arange(p["n"][1]) + 0.5) * h
+        prof = umax * 4.0 * y * (ly - y) / (ly * ly)
+        comps[0][:] = prof[None, :, None]
+    else:
+        prof = umax * duct_profile(p["n"][0], p["n"][1], h)
+        comps[2][:, :, :] = prof[None, :, :]
+    return np.concatenate([c.ravel() for c in comps])
+
+
+# --------------------------------------------------------------------------
+# workloads
+# --------------------------------------------------------------------------
+def _finish(p, X, ij, K, region_measure, rng):
+    eta = X.shape[1]
+    p["d0_pow_d"] = region_measure / max(eta, 1)
+    rest = rest_lengths(X, ij) if ij.shape[1] else np.zeros(0)
+    n_cells = int(np.prod(p["n"][:p["dim"]]))
+    return dict(params=p, u0=initial_velocity(p), p0=np.zeros(n_cells), X=X, ij=ij, rest=rest,
+                K=np.asarray(K, float), seed=None)
+
+
+def channel_2d(seed=1, nx=64, ny=32, eta=200, radius=0.25, cutoff=0.08):
+    """2D channel, periodic in x with walls in y, driven by a body force that
+    makes the unit-peak parabola the biofilm-free steady state; uniform nodes
+    in a half-disc on the bottom wall."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / ny
+    p = base_params(2, [nx, ny], [AX_PERIODIC, AX_WALLS], h)
+    ly = ny * h
+    p["body_force"] = [8.0 * 1.0 * p["mu_out"] * p["inv_re"] / (ly * ly), 0.0, 0.0]
+    p.update(rho_b=0.1, mu_max=10.0, omega=0.02, break_ratio=1.5)
+    X = half_disc_uniform(rng, eta, 0.5 * nx * h, radius)
+    ij = spring_pairs(X, cutoff)
+    K = np.full(ij.shape[1], 1e2)
+    out = _finish(p, X, ij, K, 0.5 * math.pi * radius * radius, rng)
+    out["seed"] = seed
+    return out
+
+
+def _mound_inside(H, s, cx, cz):
+    def inside(P):
+        x, y, z = P[:, 0], P[:, 1], P[:, 2]
+        return (y >= 0.0) & (y <= H * np.exp(-((x - cx) ** 2 + (z - cz) ** 2) / (2 * s * s)))
+    return inside
+
+
+def _mound_volume(H, s):
+    return H * 2.0 * math.pi * s * s
+
+
+def tube_3d(seed=2, n=(64, 64, 128), eta=5000, spacing=0.02, cutoff=0.05, rho_b=0.05, mu_max=100.0,
+            omega=0.01, mounds=1, K_range=None, H=0.3, s=0.18, nu=(2, 2)):
+    """3D square tube: walls in x and y, laminar inflow at z = 0 and a free
+    outflow at z = Lz; Poisson-disc nodes filling Gaussian mounds on the
+    bottom wall y = 0."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n[0]
+    p = base_params(3, list(n), [AX_WALLS, AX_WALLS, AX_INOUT], h)
+    p.update(rho_b=rho_b, mu_max=mu_max, omega=omega, break_ratio=2.0, nu1=nu[0], nu2=nu[1])
+    Lz = n[2] * h
+    per = int(math.ceil(eta / mounds))
+    clouds = []
+    for m in range(mounds):
+        cz = Lz * (m + 1) / (mounds + 1)
+        inside = _mound_inside(H, s, 0.5, cz)
+        lo = [max(0.0, 0.5 - 3 * s), 0.0, max(0.0, cz - 3 * s)]
+        hi = [min(1.0, 0.5 + 3 * s), H, min(Lz, cz + 3 * s)]
+        pts = poisson_disc(rng, inside, lo, hi, spacing, per, [0.5, 0.25 * spacing, cz])
+        clouds.append(pts)
+    X = np.concatenate(clouds, axis=1)[:, :eta]
+    ij = spring_pairs(X, cutoff)
+    if K_range is None:
+        K = np.full(ij.shape[1], 1e2)
+    else:
+        K = 10.0 ** rng.uniform(math.log10(K_range[0]), math.log10(K_range[1]), size=ij.shape[1])
+    vol = _mound_volume(H, s) * mounds * min(1.0, X.shape[1] / max(1, per * mounds))
+    out = _finish(p, X, ij, K, vol, rng)
+    out["seed"] = seed
+    return out
+
+
+def tiny_2d(seed=11, nx=16, ny=8, eta=12, inout=False):
+    """Small 2D case for the oracle tests (a few tiles, a handful of nodes)."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / ny
+    bc = [AX_INOUT, AX_WALLS] if inout else [AX_PERIODIC, AX_WALLS]
+    p = base_params(2, [nx, ny], bc, h)
+    if not inout:
+        p["body_force"] = [8.0 * p["mu_out"] * p["inv_re"], 0.0, 0.0]
+    p.update(rho_b=0.1, mu_max=10.0, omega=0.12, break_ratio=1.5)
+    X = half_disc_uniform(rng, eta, 0.5 * nx * h, 0.3)
+    ij = spring_pairs(X, 0.2)
+    K = np.full(ij.shape[1], 1e2)
+    out = _finish(p, X, ij, K, 0.5 * math.pi * 0.09, rng)
+    if inout:
+        ly = ny * h
+        y = (np.arange(ny) + 0.5) * h
+        prof = 4.0 * y * (ly - y) / (ly * ly)
+        u = np.zeros((ny, nx + 1))
+        u[:, :] = prof[:, None]
+        out["u0"] = np.concatenate([u.ravel(), np.zeros(nx * (ny + 1))])
+    out["seed"] = seed
+    return out
+
+
+def tiny_3d(seed=12, n=(8, 8, 16), eta=20, periodic_z=False):
+    """Small 3D tube for the oracle tests."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n[0]
+    bc = [AX_WALLS, AX_WALLS, AX_PERIODIC if periodic_z else AX_INOUT]
+    p = base_params(3, list(n), bc, h)
+    if periodic_z:
+        p["body_force"] = [0.0, 0.0, 1.0]
+    p.update(rho_b=0.05, mu_max=20.0, omega=0.15, break_ratio=2.0)
+    Lz = n[2] * h
+    inside = _mound_inside(0.4, 0.2, 0.5, 0.5 * Lz)
+    X = poisson_disc(rng, inside, [0.1, 0.0, 0.5 * Lz - 0.6], [0.9, 0.4, 0.5 * Lz + 0.6], 0.09, eta,
+                     [0.5, 0.02, 0.5 * Lz])
+    ij = spring_pairs(X, 0.2)
+    K = np.full(ij.shape[1], 50.0)
+    out = _finish(p, X, ij, K, _mound_volume(0.4, 0.2), rng)
+    out["seed"] = seed
+    return out
+
+
+WORKLOADS = {
+    "channel2d_64x32": lambda: channel_2d(seed=1),
+    "tube3d_64x64x128": lambda: tube_3d(seed=2),
+    "tube3d_128x128x256": lambda: tube_3d(seed=3, n=(128, 128, 256), eta=50000, mounds=3, rho_b=0.2,
+                                          mu_max=1e3, K_range=(1e1, 1e3), H=0.3, s=0.2, nu=(3, 3)),
+}
