@@ -1,0 +1,235 @@
+/*
+ * ibmg.h -- C interface of the MI355X (gfx950) immersed-boundary biofilm
+ * library: multigrid projection step on a staggered MAC grid, delta-function
+ * spread and interpolation with the delta width set to the bacterial radius,
+ * Hookean springs with breakage.
+ *
+ * The method is that of Hammond, Stewart, Younger, Solomon and Bortz,
+ * "Spatially heterogeneous biofilm simulations using an immersed boundary
+ * method with Lagrangian nodes defined by bacterial locations".  Each entry
+ * point below names the passage that defines what it computes.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.  Every array argument is a DEVICE pointer unless stated otherwise.
+ *   The caller owns all memory, including the workspace handed to
+ *   ibb_create; the library never allocates device memory.  The workspace
+ *   must stay valid until ibb_destroy.  Input arrays are read in stream order
+ *   during the call and are not retained.
+ * Streams.  All work is enqueued on the stream given to ibb_create
+ *   (a hipStream_t passed as void*; NULL is the default stream).  Calls that
+ *   return statistics or convergence results synchronise that stream.  A
+ *   context is not thread-safe.
+ * Errors.  Every call returns an ibb_status; nothing is thrown across the
+ *   interface.  Arguments are validated before any work is enqueued.
+ *   IBB_ENOCONV is not fatal: the iterate is kept and statistics are filled.
+ *   ibb_last_error() gives a message for the last failure on a context.
+ * Units.  Nondimensional, as in the paper's scaling (sigma = Strouhal number,
+ *   eps = Euler number, Re = Reynolds number).
+ *
+ * Grid and layouts
+ * ----------------
+ * The domain is n[0] x n[1] (x n[2]) cells of width h.  Pressure and the cell
+ * viscosity live at cell centres; velocity component a, density and the
+ * force component a live on the faces normal to axis a; the cross viscosity
+ * lives on cell edges (in 2D on cell corners).  Each axis is PERIODIC,
+ * WALLS (no-slip walls on both sides) or INOUT (prescribed inflow on the low
+ * side, zero normal derivative on the high side, where the pressure is 0).
+ *
+ * Arrays are exchanged in the "compact" layout: one lattice lists its
+ * closed-domain positions with x fastest, then y, then z.  Along an axis a
+ * lattice is cell-centred (n positions) or vertex-centred (n + 1 positions,
+ * n on a periodic axis).  Velocity, force and density arrays concatenate the
+ * D face lattices (faces normal to x, then y, then z).  Edge arrays
+ * concatenate the edge lattices parallel to x, y, z (2D: the corner lattice).
+ * ibb_lattice_count gives each size.  Node arrays are structure-of-arrays
+ * [dim][n] in FP64.  Spring endpoints are int32 [2][m].
+ */
+#ifndef IBMG_H
+#define IBMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    IBB_OK = 0,
+    IBB_EINVAL = 1,   /* bad descriptor, shape, size or pointer */
+    IBB_ENOMEM = 2,   /* workspace smaller than ibb_footprint_bytes */
+    IBB_ENOCONV = 3,  /* a solve hit max_cycles before reaching rtol */
+    IBB_ENUMERIC = 4, /* NaN or Inf in a residual norm */
+    IBB_EDEVICE = 5,  /* a HIP runtime call failed */
+    IBB_ESTATE = 6    /* call out of order (e.g. a step before coefficients) */
+} ibb_status;
+
+typedef enum { IBB_AXIS_PERIODIC = 0, IBB_AXIS_WALLS = 1, IBB_AXIS_INOUT = 2 } ibb_axis_bc;
+
+/* regularised delta: cosine phi_2 (eq:PhiCosAlternative, the paper's choice)
+ * or Peskin's four-point phi_1 (eq:PhiPeskin) */
+typedef enum { IBB_PHI_COS = 0, IBB_PHI_PESKIN4 = 1 } ibb_kernel;
+
+/* IBB_FP64: V-cycles in FP64.  IBB_FP32_REFINED: V-cycles in FP32 inside an
+ * FP64 defect-correction loop (FP64 residual of the full operator, FP64
+ * update, FP64 coarsest-level inverse). */
+typedef enum { IBB_FP64 = 0, IBB_FP32_REFINED = 1 } ibb_precision;
+
+typedef struct {
+    int dim;            /* 2 or 3 */
+    int n[3];           /* cells per axis, each even; n[2] ignored in 2D */
+    int axis_bc[3];     /* ibb_axis_bc per axis */
+    double h;           /* mesh width (isotropic) */
+    double sigma;       /* Strouhal number */
+    double eps;         /* Euler number */
+    double inv_re;      /* 1 / Reynolds number */
+    double force_coef;  /* L f0 / (rho0 u0^2), eq:N-SnondimFull */
+    double dt;          /* time step */
+    double body_force[3]; /* constant body force added to the momentum equation */
+    double rho0;        /* fluid density, eq:discrDensCouple */
+    double rho_b;       /* extra biofilm density */
+    double d0_pow_d;    /* average node volume (area in 2D) */
+    double mu_out;      /* fluid viscosity, eq:ViscExp */
+    double mu_max;      /* viscosity at a node */
+    double omega;       /* spread width (bacterial radius) */
+    int kernel;         /* ibb_kernel */
+    double break_ratio; /* springs break beyond break_ratio x rest length */
+    int nu1, nu2;       /* pre- and post-smoothing sweeps per V-cycle */
+    int max_levels;     /* 0: coarsen while every axis stays even and >= 2 */
+    int max_cycles;     /* cap on V-cycles (FP64) or outer iterations (refined) */
+    double rtol;        /* relative residual target ||b - A x|| / ||b|| */
+    double gamma[16];   /* coarse viscosity scaling per level, eq:ViscCoarseGrid (<= 0 means 1) */
+    int precision;      /* ibb_precision */
+    int inner_cycles;   /* FP32 V-cycles per outer FP64 iteration (refined) */
+} ibb_desc;
+
+typedef struct {
+    int status_u, status_p;    /* ibb_status of each solve */
+    int cycles_u, cycles_p;    /* V-cycles (FP64) or outer iterations (refined) */
+    int vcycles_u, vcycles_p;  /* V-cycles actually run (refined: outer x inner) */
+    double relres_u, relres_p; /* final FP64 relative residuals */
+    double t_u_ms, t_p_ms;     /* device time of each solve, RHS ready to converged */
+    long long dof_u, dof_p;    /* unknowns of each system */
+} ibb_solve_stats;
+
+typedef struct {
+    int n_broken;  /* springs broken in this update */
+    int n_alive;   /* springs alive afterwards */
+    double t_ms;   /* device time of the update */
+} ibb_lag_stats;
+
+typedef struct ibb_ctx ibb_ctx;
+
+/* --- sizes ------------------------------------------------------------ */
+
+/* Number of closed-domain positions of a lattice in the compact layout.
+ * kind: 0 cell centres, 1 faces normal to `axis`, 2 edges parallel to `axis`
+ * (2D: axis 2 is the corner lattice).  dims (host, may be NULL) receives the
+ * extent along x, y, z. */
+ibb_status ibb_lattice_count(const ibb_desc *desc, int kind, int axis, int64_t *count, int dims[3]);
+
+/* Workspace bytes needed for a context with up to max_nodes nodes and
+ * max_springs springs. */
+ibb_status ibb_footprint_bytes(const ibb_desc *desc, int64_t max_nodes, int64_t max_springs, size_t *bytes);
+
+/* --- lifetime ------------------------------------------------------------ */
+
+/* Validate desc, carve the workspace and set every field to zero.  The
+ * multigrid hierarchy has one level per halving of the grid (Sec.
+ * "Multigrid"). */
+ibb_status ibb_create(const ibb_desc *desc, int64_t max_nodes, int64_t max_springs, void *workspace,
+                      size_t workspace_bytes, void *stream, ibb_ctx **out);
+ibb_status ibb_destroy(ibb_ctx *ctx);
+
+/* --- state ------------------------------------------------------------- */
+
+/* Velocity (compact, all face lattices, boundary faces included: the values
+ * on fixed faces are the boundary data, e.g. the inflow profile) and
+ * pressure (compact cells).  p may be NULL to leave the pressure as is. */
+ibb_status ibb_set_state(ibb_ctx *ctx, const double *u, const double *p);
+ibb_status ibb_get_state(ibb_ctx *ctx, double *u, double *p);
+
+/* Node positions X [dim][n], n <= max_nodes. */
+ibb_status ibb_set_nodes(ibb_ctx *ctx, int64_t n, const double *X);
+
+/* Node positions, total spring force [dim][n] and spring alive flags [m]
+ * (each may be NULL). */
+ibb_status ibb_get_nodes(ibb_ctx *ctx, double *X, double *F, uint8_t *alive);
+
+/* Spring network (eq:springF): endpoints ij [2][m] (int32, distinct node
+ * indices), rest lengths r [m], stiffnesses K [m], alive flags [m] (NULL:
+ * all alive).  Builds the per-node incidence lists used by the force pass. */
+ibb_status ibb_set_springs(ibb_ctx *ctx, int64_t m, const int32_t *ij, const double *rest, const double *K,
+                           const uint8_t *alive);
+
+/* --- the step ------------------------------------------------------------ */
+
+/* At the current node positions: spring forces (no breakage), the spread
+ * force f and density rho on the faces (eq:discrForceCouple,
+ * eq:discrDensCouple), the viscosity at cells and edges (eq:ViscExp), and
+ * every coarse level's coefficients (full-weighting restriction, viscosity
+ * scaled by gamma, eq:ViscCoarseGrid).  Call once after setting nodes and
+ * springs; ibb_lagrangian_update repeats it after moving the nodes. */
+ibb_status ibb_update_coefficients(ibb_ctx *ctx);
+
+/* One projection step (eq:NSdis1-1, eq:NSdis4, eq:NSdis2): the momentum
+ * right-hand side, the viscous multigrid solve for u~ (warm start u^n), the
+ * pressure right-hand side, the pressure multigrid solve (warm start p^n),
+ * and the projection to u^{n+1}.  stats (host, may be NULL) is filled. */
+ibb_status ibb_projection_step(ibb_ctx *ctx, ibb_solve_stats *stats);
+
+/* Lagrangian update: interpolate u^{n+1} to the nodes with width h
+ * (eq:discrVelCouple), move them by dt / sigma times that velocity
+ * (periodic axes wrap), break springs stretched beyond break_ratio times
+ * their rest length, recompute forces, and rebuild the Eulerian
+ * coefficients as in ibb_update_coefficients.  stats (host) may be NULL. */
+ibb_status ibb_lagrangian_update(ibb_ctx *ctx, ibb_lag_stats *stats);
+
+/* --- individual steps (for checking each against a reference) ----------- */
+
+/* Level-l coefficient fields in compact layout (each may be NULL): force f
+ * (level 0 only), density rho, cell viscosity mu_c, edge viscosity mu_e. */
+ibb_status ibb_get_fields(ibb_ctx *ctx, int level, double *f, double *rho, double *mu_c, double *mu_e);
+
+/* Momentum right-hand side of eq:NSdis1-1 at the current state, with the
+ * fixed boundary values moved to the right (compact faces; only unknown
+ * positions are written). */
+ibb_status ibb_momentum_rhs(ibb_ctx *ctx, double *b);
+
+/* Pressure right-hand side -(sigma / (eps dt)) D u~ of eq:NSdis4 (mean
+ * removed when no outflow face exists) from a compact face field ut. */
+ibb_status ibb_pressure_rhs(ibb_ctx *ctx, const double *ut, double *bp);
+
+/* Multigrid solve of the viscous (which = 1) or pressure (which = 0) system
+ * A x = b on the current coefficients (Sec. "Multigrid"), V-cycles until
+ * ||b - A x|| <= rtol ||b||.  b and x are compact (faces or cells); x holds
+ * the initial guess and receives the result at unknown positions.
+ * cycles, relres (host) may be NULL.  max_cycles_override > 0 replaces
+ * desc.max_cycles for this call; ncycles_exact > 0 runs exactly that many
+ * cycles without a stopping test. */
+ibb_status ibb_mg_solve(ibb_ctx *ctx, int which, const double *b, double *x, int max_cycles_override,
+                        int ncycles_exact, int *cycles, double *relres);
+
+/* Projection of eq:NSdis2 from u~ (compact faces) and p (compact cells). */
+ibb_status ibb_project(ibb_ctx *ctx, const double *ut, const double *p, double *u);
+
+/* Interpolation of a compact face field u to nodes X [dim][n] with delta
+ * width `width` (eq:discrVelCouple uses width h); U [dim][n]. */
+ibb_status ibb_interp(ibb_ctx *ctx, double width, int64_t n, const double *X, const double *u, double *U);
+
+/* Spread of node vectors F [dim][n] at X to the face lattices with width
+ * `width` (eq:discrForceCouple); out is compact faces. */
+ibb_status ibb_spread(ibb_ctx *ctx, double width, int64_t n, const double *X, const double *F, double *out);
+
+/* --- diagnostics ----------------------------------------------------------- */
+const char *ibb_status_string(ibb_status s);
+const char *ibb_last_error(const ibb_ctx *ctx);
+/* number of multigrid levels and the cell counts of level l (host) */
+ibb_status ibb_level_info(const ibb_ctx *ctx, int level, int *nlevels, int n[3]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IBMG_H */

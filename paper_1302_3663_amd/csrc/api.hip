@@ -1,0 +1,1081 @@
+// Host side of the library: context and workspace, the multigrid drivers
+// (FP64 V-cycles, and FP32 V-cycles inside FP64 defect correction), the
+// projection step and the Lagrangian update, and the C interface declared
+// in include/ibmg.h.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ibmg.h"
+#include "common.h"
+#include "kernels.h"
+
+using namespace ibmg;
+
+namespace {
+
+constexpr int DENSE_MAX = 64;   // coarsest systems up to this size are inverted
+constexpr int MAXLEV = 16;
+
+struct Level {
+    Grid g;
+    long long np = 0, nu = 0;
+    // FP64 solver arrays (level 0: x is u~ / the pressure iterate)
+    double *xp = nullptr, *bp = nullptr, *rp = nullptr;
+    double *xu[3] = {}, *bu[3] = {}, *ru[3] = {};
+    double *rho[3] = {}, *beta[3] = {}, *muc = nullptr, *mue[3] = {};
+    // FP32 copies for the inner cycles of the refined solver
+    float *xp32 = nullptr, *bp32 = nullptr, *rp32 = nullptr;
+    float *xu32[3] = {}, *bu32[3] = {}, *ru32[3] = {};
+    float *rho32[3] = {}, *beta32[3] = {}, *muc32 = nullptr, *mue32[3] = {};
+};
+
+struct Carver {
+    char *base;
+    size_t off = 0;
+    bool dry;
+    template <typename T>
+    T *take(size_t n)
+    {
+        off = (off + 255) & ~(size_t)255;
+        T *p = dry ? nullptr : reinterpret_cast<T *>(base + off);
+        off += n * sizeof(T);
+        return p;
+    }
+};
+
+}  // namespace
+
+struct ibb_ctx {
+    ibb_desc d;
+    hipStream_t s = nullptr;
+    int L = 0;
+    int E = 0;              // edge lattices (3 in 3D, 1 in 2D)
+    int edge_axis[3] = {};  // their parallel axes
+    Level lv[MAXLEV];
+    bool singular_p = false;
+    Phys ph;
+    // state
+    double *u[3] = {}, *p = nullptr, *f[3] = {};
+    // coarsest dense inverses
+    long long *uidx_p = nullptr, *uidx_u = nullptr;
+    int *ucomp_p = nullptr, *ucomp_u = nullptr;
+    double *Mp = nullptr, *Mu = nullptr, *Aw = nullptr;
+    // reductions
+    double *partial = nullptr, *scalar = nullptr;
+    // nodes and springs
+    long long eta_max = 0, m_max = 0;
+    int eta = 0, m = 0;
+    double *X = nullptr, *F = nullptr, *U = nullptr;
+    Bins bins;
+    int nbins_cap = 0;
+    int *ij = nullptr;
+    double *rest = nullptr, *K = nullptr;
+    unsigned char *alive = nullptr;
+    int *inc_keys = nullptr, *inc_count = nullptr, *inc_start = nullptr, *inc_list = nullptr;
+    int *counters = nullptr;
+    bool have_nodes = false, have_springs = false, have_coefs = false;
+    hipEvent_t ev[4] = {};
+    std::string err;
+};
+
+namespace {
+
+ibb_status fail(ibb_ctx *c, ibb_status st, const char *msg)
+{
+    if (c) c->err = msg;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            if (c) c->err = std::string(#expr) + ": " + hipGetErrorString(e_);               \
+            return IBB_EDEVICE;                                                              \
+        }                                                                                    \
+    } while (0)
+
+ibb_status check_desc(const ibb_desc *d)
+{
+    if (!d) return IBB_EINVAL;
+    if (d->dim != 2 && d->dim != 3) return IBB_EINVAL;
+    for (int a = 0; a < d->dim; ++a) {
+        if (d->n[a] < 2 || d->n[a] % 2) return IBB_EINVAL;
+        if (d->axis_bc[a] < 0 || d->axis_bc[a] > 2) return IBB_EINVAL;
+    }
+    if (!(d->h > 0) || !(d->dt > 0) || !(d->sigma > 0) || !(d->eps > 0)) return IBB_EINVAL;
+    if (!(d->omega > 0) || !(d->rho0 > 0) || !(d->mu_out > 0)) return IBB_EINVAL;
+    if (d->kernel != 0 && d->kernel != 1) return IBB_EINVAL;
+    if (d->nu1 < 0 || d->nu2 < 0 || d->nu1 + d->nu2 < 1 || d->max_cycles < 1) return IBB_EINVAL;
+    if (d->precision != IBB_FP64 && d->precision != IBB_FP32_REFINED) return IBB_EINVAL;
+    if (d->precision == IBB_FP32_REFINED && d->inner_cycles < 1) return IBB_EINVAL;
+    for (int a = 0; a < d->dim; ++a)
+        if (d->axis_bc[a] == IBB_AXIS_PERIODIC && 4.0 * d->omega > d->n[a] * d->h) return IBB_EINVAL;
+    return IBB_OK;
+}
+
+int count_levels(const ibb_desc *d)
+{
+    int n[3] = {d->n[0], d->n[1], d->dim == 3 ? d->n[2] : 2};
+    int L = 1;
+    while (L < MAXLEV) {
+        bool ok = true;
+        for (int a = 0; a < d->dim; ++a)
+            if (n[a] % 2 || n[a] / 2 < 2) ok = false;
+        if (!ok) break;
+        for (int a = 0; a < d->dim; ++a) n[a] /= 2;
+        ++L;
+    }
+    if (d->max_levels > 0 && d->max_levels < L) L = d->max_levels;
+    return L;
+}
+
+Grid make_grid(const ibb_desc *d, int l)
+{
+    Grid g;
+    g.D = d->dim;
+    for (int a = 0; a < 3; ++a) {
+        g.n[a] = a < d->dim ? d->n[a] >> l : 1;
+        g.bc[a] = a < d->dim ? d->axis_bc[a] : 0;
+    }
+    g.NX = g.n[0] + 1;
+    g.NY = g.n[1] + 1;
+    g.NXY = (long long)g.NX * g.NY;
+    g.nel = g.NXY * (d->dim == 3 ? g.n[2] + 1 : 1);
+    g.h = d->h * (double)(1 << l);
+    return g;
+}
+
+long long unknowns_of(const Grid &g, int vmask)
+{
+    long long n = 1;
+    for (int d = 0; d < 3; ++d) {
+        int lo, hi;
+        unk_range(g, d, (vmask >> d) & 1, lo, hi);
+        n *= (hi - lo + 1);
+    }
+    return n;
+}
+
+long long lattice_count(const Grid &g, int vmask)
+{
+    long long n = 1;
+    for (int d = 0; d < 3; ++d) n *= stored_extent(g, d, (vmask >> d) & 1);
+    return n;
+}
+
+void bins_for_width(const ibb_desc *d, double w, int nb[3], double bs[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        if (a >= d->dim) { nb[a] = 1; bs[a] = 1.0; continue; }
+        const double L = d->n[a] * d->h;
+        int k = (int)floor(L / (2.0 * w));
+        if (k < 1) k = 1;
+        nb[a] = k;
+        bs[a] = L / k;
+    }
+}
+
+// carve every array out of the workspace (dry run: only count bytes)
+size_t carve(ibb_ctx *c, char *base, bool dry)
+{
+    Carver cv{base, 0, dry};
+    const ibb_desc *d = &c->d;
+    const int D = d->dim;
+    const bool refined = d->precision == IBB_FP32_REFINED;
+    for (int l = 0; l < c->L; ++l) {
+        Level &L = c->lv[l];
+        const size_t n = (size_t)L.g.nel;
+        L.xp = cv.take<double>(n);
+        L.bp = cv.take<double>(n);
+        L.rp = cv.take<double>(n);
+        for (int a = 0; a < D; ++a) {
+            L.xu[a] = cv.take<double>(n);
+            L.bu[a] = cv.take<double>(n);
+            L.ru[a] = cv.take<double>(n);
+            L.rho[a] = cv.take<double>(n);
+            L.beta[a] = cv.take<double>(n);
+        }
+        L.muc = cv.take<double>(n);
+        for (int e = 0; e < c->E; ++e) L.mue[c->edge_axis[e]] = cv.take<double>(n);
+        if (refined) {
+            L.xp32 = cv.take<float>(n);
+            L.bp32 = cv.take<float>(n);
+            L.rp32 = cv.take<float>(n);
+            for (int a = 0; a < D; ++a) {
+                L.xu32[a] = cv.take<float>(n);
+                L.bu32[a] = cv.take<float>(n);
+                L.ru32[a] = cv.take<float>(n);
+                L.rho32[a] = cv.take<float>(n);
+                L.beta32[a] = cv.take<float>(n);
+            }
+            L.muc32 = cv.take<float>(n);
+            for (int e = 0; e < c->E; ++e) L.mue32[c->edge_axis[e]] = cv.take<float>(n);
+        }
+    }
+    const size_t n0 = (size_t)c->lv[0].g.nel;
+    for (int a = 0; a < D; ++a) {
+        c->u[a] = cv.take<double>(n0);
+        c->f[a] = cv.take<double>(n0);
+    }
+    c->p = cv.take<double>(n0);
+    c->uidx_p = cv.take<long long>(DENSE_MAX);
+    c->uidx_u = cv.take<long long>(DENSE_MAX);
+    c->ucomp_p = cv.take<int>(DENSE_MAX);
+    c->ucomp_u = cv.take<int>(DENSE_MAX);
+    c->Mp = cv.take<double>(DENSE_MAX * DENSE_MAX);
+    c->Mu = cv.take<double>(DENSE_MAX * DENSE_MAX);
+    c->Aw = cv.take<double>(DENSE_MAX * DENSE_MAX);
+    c->partial = cv.take<double>(3 * NORM_BLOCKS);
+    c->scalar = cv.take<double>(8);
+    const size_t em = (size_t)(c->eta_max > 0 ? c->eta_max : 1);
+    const size_t mm = (size_t)(c->m_max > 0 ? c->m_max : 1);
+    c->X = cv.take<double>(3 * em);
+    c->F = cv.take<double>(3 * em);
+    c->U = cv.take<double>(3 * em);
+    c->bins.bin_of = cv.take<int>(em);
+    c->bins.sorted = cv.take<int>(em);
+    c->bins.count = cv.take<int>((size_t)c->nbins_cap);
+    c->bins.start = cv.take<int>((size_t)c->nbins_cap + 1);
+    c->ij = cv.take<int>(2 * mm);
+    c->rest = cv.take<double>(mm);
+    c->K = cv.take<double>(mm);
+    c->alive = cv.take<unsigned char>(mm);
+    c->inc_keys = cv.take<int>(2 * mm);
+    c->inc_list = cv.take<int>(2 * mm);
+    c->inc_count = cv.take<int>(em);
+    c->inc_start = cv.take<int>(em + 1);
+    c->counters = cv.take<int>(8);
+    return cv.off + 256;
+}
+
+void setup_shapes(ibb_ctx *c, const ibb_desc *d, int64_t max_nodes, int64_t max_springs)
+{
+    c->d = *d;
+    c->L = count_levels(d);
+    c->E = d->dim == 3 ? 3 : 1;
+    if (d->dim == 3) { c->edge_axis[0] = 0; c->edge_axis[1] = 1; c->edge_axis[2] = 2; }
+    else c->edge_axis[0] = 2;
+    for (int l = 0; l < c->L; ++l) {
+        Level &L = c->lv[l];
+        L.g = make_grid(d, l);
+        L.np = unknowns_of(L.g, 0);
+        L.nu = 0;
+        for (int a = 0; a < d->dim; ++a) L.nu += unknowns_of(L.g, face_mask(a));
+    }
+    c->singular_p = true;
+    for (int a = 0; a < d->dim; ++a)
+        if (d->axis_bc[a] == IBB_AXIS_INOUT) c->singular_p = false;
+    c->eta_max = max_nodes;
+    c->m_max = max_springs;
+    int nb[3];
+    double bs[3];
+    bins_for_width(d, d->omega < d->h ? d->omega : d->h, nb, bs);
+    c->nbins_cap = nb[0] * nb[1] * nb[2];
+    Phys &ph = c->ph;
+    ph.sigma = d->sigma;
+    ph.eps = d->eps;
+    ph.inv_re = d->inv_re;
+    ph.force_coef = d->force_coef;
+    ph.dt = d->dt;
+    for (int a = 0; a < 3; ++a) ph.body_force[a] = a < d->dim ? d->body_force[a] : 0.0;
+    ph.rho0 = d->rho0;
+    ph.rho_b = d->rho_b;
+    ph.d0_pow_d = d->d0_pow_d;
+    ph.mu_out = d->mu_out;
+    ph.mu_max = d->mu_max;
+    ph.omega = d->omega;
+    ph.kernel = d->kernel;
+}
+
+// views of a level in one precision
+template <typename T>
+struct View {
+    T *xp, *bp, *rp;
+    VelArr<T> xu, bu, ru;
+    CoefP<T> cp;
+    CoefU<T> cu;
+};
+
+View<double> view64(Level &L)
+{
+    View<double> v;
+    v.xp = L.xp;
+    v.bp = L.bp;
+    v.rp = L.rp;
+    for (int a = 0; a < 3; ++a) {
+        v.xu.c[a] = L.xu[a];
+        v.bu.c[a] = L.bu[a];
+        v.ru.c[a] = L.ru[a];
+        v.cp.beta[a] = L.beta[a];
+        v.cu.rho[a] = L.rho[a];
+        v.cu.mue[a] = L.mue[a];
+    }
+    v.cu.muc = L.muc;
+    return v;
+}
+
+View<float> view32(Level &L)
+{
+    View<float> v;
+    v.xp = L.xp32;
+    v.bp = L.bp32;
+    v.rp = L.rp32;
+    for (int a = 0; a < 3; ++a) {
+        v.xu.c[a] = L.xu32[a];
+        v.bu.c[a] = L.bu32[a];
+        v.ru.c[a] = L.ru32[a];
+        v.cp.beta[a] = L.beta32[a];
+        v.cu.rho[a] = L.rho32[a];
+        v.cu.mue[a] = L.mue32[a];
+    }
+    v.cu.muc = L.muc32;
+    return v;
+}
+
+template <typename T>
+View<T> view(Level &L);
+template <>
+View<double> view<double>(Level &L) { return view64(L); }
+template <>
+View<float> view<float>(Level &L) { return view32(L); }
+
+void vel_masks(int D, int *m)
+{
+    for (int a = 0; a < 3; ++a) m[a] = a < D ? face_mask(a) : 0;
+}
+
+template <typename T>
+void sweep(ibb_ctx *c, bool vel, int l)
+{
+    Level &L = c->lv[l];
+    View<T> v = view<T>(L);
+    const T cvp = (T)(1.0 / (L.g.h * L.g.h));
+    const T cvu = (T)(c->d.inv_re / (L.g.h * L.g.h));
+    const T mass = (T)(c->d.sigma / c->d.dt);
+    if (vel) {
+        for (int a = 0; a < c->d.dim; ++a)
+            for (int colour = 0; colour < 2; ++colour)
+                launch_smooth_u<T>(L.g, a, v.bu.c[a], v.xu, v.cu, mass, cvu, colour, c->s);
+    } else {
+        for (int colour = 0; colour < 2; ++colour) launch_smooth_p<T>(L.g, v.bp, v.xp, v.cp, cvp, colour, c->s);
+    }
+}
+
+// residual of level l (written to r), optional squared-norm partial sums
+template <typename T>
+int residual(ibb_ctx *c, bool vel, int l, double *partial)
+{
+    Level &L = c->lv[l];
+    View<T> v = view<T>(L);
+    const T cvp = (T)(1.0 / (L.g.h * L.g.h));
+    const T cvu = (T)(c->d.inv_re / (L.g.h * L.g.h));
+    const T mass = (T)(c->d.sigma / c->d.dt);
+    if (vel) return launch_resid_u<T>(L.g, cview(v.bu), v.xu, v.cu, mass, cvu, v.ru, partial, c->s);
+    return launch_resid_p<T>(L.g, v.bp, v.xp, v.cp, cvp, v.rp, partial, c->s);
+}
+
+template <typename T>
+void vcycle(ibb_ctx *c, bool vel, int l)
+{
+    Level &L = c->lv[l];
+    const int D = c->d.dim;
+    int vm[3];
+    vel_masks(D, vm);
+    const int pm[3] = {0, 0, 0};
+    View<T> v = view<T>(L);
+    if (l == c->L - 1) {
+        const long long n = vel ? L.nu : L.np;
+        if (n <= DENSE_MAX) {
+            if (vel) launch_dense_apply<T>((int)n, c->uidx_u, c->ucomp_u, c->Mu, cview(v.bu), v.xu, c->s);
+            else {
+                VelArr<T> x{{v.xp, nullptr, nullptr}};
+                VelArrC<T> b{{v.bp, nullptr, nullptr}};
+                launch_dense_apply<T>((int)n, c->uidx_p, c->ucomp_p, c->Mp, b, x, c->s);
+            }
+        } else {
+            for (int s = 0; s < c->d.nu1 + c->d.nu2; ++s) sweep<T>(c, vel, l);
+        }
+        return;
+    }
+    for (int s = 0; s < c->d.nu1; ++s) sweep<T>(c, vel, l);
+    residual<T>(c, vel, l, nullptr);
+    Level &C = c->lv[l + 1];
+    View<T> w = view<T>(C);
+    if (vel) {
+        launch_restrict<T>(L.g, C.g, D, vm, ROLE_V, false, cview(v.ru), w.bu, (T)1, c->s);
+        for (int a = 0; a < D; ++a) launch_fill<T>(w.xu.c[a], C.g.nel, (T)0, c->s);
+    } else {
+        VelArrC<T> rf{{v.rp, nullptr, nullptr}};
+        VelArr<T> bc{{w.bp, nullptr, nullptr}};
+        launch_restrict<T>(L.g, C.g, 1, pm, ROLE_P, false, rf, bc, (T)1, c->s);
+        launch_fill<T>(w.xp, C.g.nel, (T)0, c->s);
+    }
+    vcycle<T>(c, vel, l + 1);
+    if (vel) {
+        launch_prolong_add<T>(C.g, L.g, D, vm, ROLE_V, cview(w.xu), v.xu, c->s);
+    } else {
+        VelArrC<T> xc{{w.xp, nullptr, nullptr}};
+        VelArr<T> xf{{v.xp, nullptr, nullptr}};
+        launch_prolong_add<T>(C.g, L.g, 1, pm, ROLE_P, xc, xf, c->s);
+    }
+    for (int s = 0; s < c->d.nu2; ++s) sweep<T>(c, vel, l);
+}
+
+ibb_status read_scalar(ibb_ctx *c, int nparts, double *out)
+{
+    launch_reduce_final(c->partial, nparts, c->scalar, c->s);
+    HIPCHK(hipMemcpyAsync(out, c->scalar, sizeof(double), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    return IBB_OK;
+}
+
+// ||b|| over the unknowns of level 0 (FP64)
+ibb_status norm_b(ibb_ctx *c, bool vel, double *out)
+{
+    Level &L = c->lv[0];
+    int vm[3];
+    vel_masks(c->d.dim, vm);
+    const int pm[3] = {0, 0, 0};
+    int np;
+    if (vel) np = launch_norm2<double>(L.g, c->d.dim, vm, VelArrC<double>{{L.bu[0], L.bu[1], L.bu[2]}}, c->partial, c->s);
+    else np = launch_norm2<double>(L.g, 1, pm, VelArrC<double>{{L.bp, nullptr, nullptr}}, c->partial, c->s);
+    double s2;
+    ibb_status st = read_scalar(c, np, &s2);
+    *out = sqrt(s2);
+    return st;
+}
+
+ibb_status resid_norm(ibb_ctx *c, bool vel, double *out)
+{
+    const int np = residual<double>(c, vel, 0, c->partial);
+    double s2;
+    ibb_status st = read_scalar(c, np, &s2);
+    *out = sqrt(s2);
+    return st;
+}
+
+void zero_unknowns(ibb_ctx *c, bool vel)
+{
+    // x(unknowns) = 0 through a cast from the zeroed FP64 residual scratch is
+    // avoided: write zeros with a cast of an all-zero array of the same level
+    Level &L = c->lv[0];
+    const int D = c->d.dim;
+    int vm[3];
+    vel_masks(D, vm);
+    const int pm[3] = {0, 0, 0};
+    if (vel) {
+        for (int a = 0; a < D; ++a) launch_fill<double>(L.ru[a], L.g.nel, 0.0, c->s);
+        // x = x * 0 at unknowns: copy zeros from r into x at the unknown positions
+        launch_cast_unknowns<double, double>(L.g, D, vm, VelArrC<double>{{L.ru[0], L.ru[1], L.ru[2]}},
+                                             VelArr<double>{{L.xu[0], L.xu[1], L.xu[2]}}, c->s);
+    } else {
+        launch_fill<double>(L.rp, L.g.nel, 0.0, c->s);
+        launch_cast_unknowns<double, double>(L.g, 1, pm, VelArrC<double>{{L.rp, nullptr, nullptr}},
+                                             VelArr<double>{{L.xp, nullptr, nullptr}}, c->s);
+    }
+}
+
+struct SolveOut {
+    int status = IBB_OK;
+    int cycles = 0;
+    int vcycles = 0;
+    double relres = 0.0;
+};
+
+// V-cycles on level 0 arrays (b and x already in place)
+ibb_status solve(ibb_ctx *c, bool vel, int max_cycles, int exact, SolveOut *o)
+{
+    const bool refined = c->d.precision == IBB_FP32_REFINED;
+    const int D = c->d.dim;
+    int vm[3];
+    vel_masks(D, vm);
+    const int pm[3] = {0, 0, 0};
+    Level &L0 = c->lv[0];
+    double nb;
+    ibb_status st = norm_b(c, vel, &nb);
+    if (st) return st;
+    o->cycles = o->vcycles = 0;
+    o->relres = 0.0;
+    o->status = IBB_OK;
+    if (nb == 0.0) {
+        zero_unknowns(c, vel);
+        return IBB_OK;
+    }
+    double rn;
+    auto one_iteration = [&]() {
+        if (!refined) {
+            vcycle<double>(c, vel, 0);
+            o->vcycles++;
+            return;
+        }
+        // r64 already holds b - A x (from the last residual evaluation)
+        if (vel) {
+            launch_cast_unknowns<double, float>(L0.g, D, vm, VelArrC<double>{{L0.ru[0], L0.ru[1], L0.ru[2]}},
+                                                VelArr<float>{{L0.bu32[0], L0.bu32[1], L0.bu32[2]}}, c->s);
+            for (int a = 0; a < D; ++a) launch_fill<float>(L0.xu32[a], L0.g.nel, 0.0f, c->s);
+        } else {
+            launch_cast_unknowns<double, float>(L0.g, 1, pm, VelArrC<double>{{L0.rp, nullptr, nullptr}},
+                                                VelArr<float>{{L0.bp32, nullptr, nullptr}}, c->s);
+            launch_fill<float>(L0.xp32, L0.g.nel, 0.0f, c->s);
+        }
+        for (int it = 0; it < c->d.inner_cycles; ++it) {
+            vcycle<float>(c, vel, 0);
+            o->vcycles++;
+        }
+        if (vel)
+            launch_add_correction(L0.g, D, vm, VelArrC<float>{{L0.xu32[0], L0.xu32[1], L0.xu32[2]}},
+                                  VelArr<double>{{L0.xu[0], L0.xu[1], L0.xu[2]}}, c->s);
+        else
+            launch_add_correction(L0.g, 1, pm, VelArrC<float>{{L0.xp32, nullptr, nullptr}},
+                                  VelArr<double>{{L0.xp, nullptr, nullptr}}, c->s);
+    };
+    if ((st = resid_norm(c, vel, &rn))) return st;
+    double rel = rn / nb;
+    if (exact > 0) {
+        for (int k = 0; k < exact; ++k) {
+            one_iteration();
+            o->cycles++;
+            if ((st = resid_norm(c, vel, &rn))) return st;
+        }
+        o->relres = rn / nb;
+        return IBB_OK;
+    }
+    while (!(rel <= c->d.rtol)) {
+        if (!(rel == rel) || isinf(rel)) { o->status = IBB_ENUMERIC; break; }
+        if (o->cycles >= max_cycles) { o->status = IBB_ENOCONV; break; }
+        one_iteration();
+        o->cycles++;
+        if ((st = resid_norm(c, vel, &rn))) return st;
+        rel = rn / nb;
+    }
+    o->relres = rel;
+    return IBB_OK;
+}
+
+// host-side table of coarsest unknowns in the order comp, z, y, x
+void coarsest_tables(ibb_ctx *c, std::vector<long long> &ip, std::vector<int> &cp, std::vector<long long> &iu,
+                     std::vector<int> &cu)
+{
+    Level &L = c->lv[c->L - 1];
+    auto add = [&](int vmask, int comp, std::vector<long long> &idx, std::vector<int> &cmp) {
+        int lo[3], hi[3];
+        for (int d = 0; d < 3; ++d) unk_range(L.g, d, (vmask >> d) & 1, lo[d], hi[d]);
+        for (int k = lo[2]; k <= hi[2]; ++k)
+            for (int j = lo[1]; j <= hi[1]; ++j)
+                for (int i = lo[0]; i <= hi[0]; ++i) {
+                    idx.push_back(at(L.g, i, j, k));
+                    cmp.push_back(comp);
+                }
+    };
+    add(0, 0, ip, cp);
+    for (int a = 0; a < c->d.dim; ++a) add(face_mask(a), a, iu, cu);
+}
+
+// spread, coarse coefficients, FP32 copies, coarsest inverses
+ibb_status rebuild_coefficients(ibb_ctx *c)
+{
+    const ibb_desc *d = &c->d;
+    const int D = d->dim;
+    Level &L0 = c->lv[0];
+    const long long em = c->eta_max > 0 ? c->eta_max : 1;
+    // spring forces at the current positions
+    for (int a = 0; a < D; ++a) launch_fill<double>(c->F + a * em, em, 0.0, c->s);
+    if (c->have_springs && c->m > 0)
+        launch_spring_force(L0.g, c->X, em, c->eta, c->ij, c->m, c->rest, c->K, c->alive, c->inc_start, c->inc_list,
+                            c->F, c->s);
+    // bins at width omega, then the gathers
+    Bins b = c->bins;
+    bins_for_width(d, d->omega, b.nb, b.bs);
+    b.nbins = b.nb[0] * b.nb[1] * b.nb[2];
+    launch_bin_nodes(L0.g, b, c->X, em, c->eta, c->s);
+    for (int a = 0; a < D; ++a)
+        launch_spread_face(L0.g, c->ph, b, c->X, c->F, em, a, d->omega, c->f[a], L0.rho[a], c->s);
+    launch_spread_visc(L0.g, c->ph, b, c->X, em, 0, L0.muc, c->s);
+    for (int e = 0; e < c->E; ++e)
+        launch_spread_visc(L0.g, c->ph, b, c->X, em, edge_mask(D, c->edge_axis[e]), L0.mue[c->edge_axis[e]], c->s);
+    // coarse levels: full weighting of rho, mu (times gamma)
+    int fm[3], em3[3];
+    vel_masks(D, fm);
+    for (int e = 0; e < 3; ++e) em3[e] = e < c->E ? edge_mask(D, c->edge_axis[e]) : 0;
+    const int cm[3] = {0, 0, 0};
+    for (int l = 0; l < c->L; ++l) {
+        Level &L = c->lv[l];
+        if (l > 0) {
+            Level &F = c->lv[l - 1];
+            const double gm = d->gamma[l] > 0 ? d->gamma[l] : 1.0;
+            launch_restrict<double>(F.g, L.g, D, fm, ROLE_C, true, VelArrC<double>{{F.rho[0], F.rho[1], F.rho[2]}},
+                                    VelArr<double>{{L.rho[0], L.rho[1], L.rho[2]}}, 1.0, c->s);
+            launch_restrict<double>(F.g, L.g, 1, cm, ROLE_C, true, VelArrC<double>{{F.muc, nullptr, nullptr}},
+                                    VelArr<double>{{L.muc, nullptr, nullptr}}, gm, c->s);
+            VelArrC<double> fe{{nullptr, nullptr, nullptr}};
+            VelArr<double> ce{{nullptr, nullptr, nullptr}};
+            for (int e = 0; e < c->E; ++e) {
+                fe.c[e] = F.mue[c->edge_axis[e]];
+                ce.c[e] = L.mue[c->edge_axis[e]];
+            }
+            launch_restrict<double>(F.g, L.g, c->E, em3, ROLE_C, true, fe, ce, gm, c->s);
+        }
+        for (int a = 0; a < D; ++a) launch_beta_face(L.g, a, L.rho[a], L.beta[a], c->s);
+        if (d->precision == IBB_FP32_REFINED) {
+            for (int a = 0; a < D; ++a) {
+                launch_to_f32(L.rho[a], L.rho32[a], L.g.nel, c->s);
+                launch_to_f32(L.beta[a], L.beta32[a], L.g.nel, c->s);
+            }
+            launch_to_f32(L.muc, L.muc32, L.g.nel, c->s);
+            for (int e = 0; e < c->E; ++e)
+                launch_to_f32(L.mue[c->edge_axis[e]], L.mue32[c->edge_axis[e]], L.g.nel, c->s);
+        }
+    }
+    // coarsest inverses
+    Level &LC = c->lv[c->L - 1];
+    const double hc2 = LC.g.h * LC.g.h;
+    View<double> v = view64(LC);
+    if (LC.np <= DENSE_MAX)
+        launch_dense_inverse(LC.g, 0, (int)LC.np, c->uidx_p, c->ucomp_p, v.cp, v.cu, d->sigma / d->dt, 1.0 / hc2,
+                             VelArr<double>{{LC.rp, nullptr, nullptr}}, c->singular_p ? 1 : 0, c->Aw, c->Mp, c->s);
+    if (LC.nu <= DENSE_MAX)
+        launch_dense_inverse(LC.g, 1, (int)LC.nu, c->uidx_u, c->ucomp_u, v.cp, v.cu, d->sigma / d->dt,
+                             d->inv_re / hc2, VelArr<double>{{LC.ru[0], LC.ru[1], LC.ru[2]}}, 0, c->Aw, c->Mu, c->s);
+    c->have_coefs = true;
+    return IBB_OK;
+}
+
+ibb_status remove_cell_mean(ibb_ctx *c, double *v)
+{
+    Level &L0 = c->lv[0];
+    const int np = launch_sum_cells(L0.g, v, c->partial, c->s);
+    launch_reduce_final(c->partial, np, c->scalar, c->s);
+    launch_add_scalar_cells(L0.g, v, c->scalar, -1.0 / (double)L0.np, c->s);
+    return IBB_OK;
+}
+
+ibb_status faces_in(ibb_ctx *c, const double *src, double *const *dst)
+{
+    Level &L0 = c->lv[0];
+    long long off = 0;
+    for (int a = 0; a < c->d.dim; ++a) {
+        launch_layout(L0.g, face_mask(a), src + off, dst[a], true, c->s);
+        off += lattice_count(L0.g, face_mask(a));
+    }
+    return IBB_OK;
+}
+
+ibb_status faces_out(ibb_ctx *c, int level, double *const *src, double *dst)
+{
+    Level &L = c->lv[level];
+    long long off = 0;
+    for (int a = 0; a < c->d.dim; ++a) {
+        launch_layout(L.g, face_mask(a), src[a], dst + off, false, c->s);
+        off += lattice_count(L.g, face_mask(a));
+    }
+    return IBB_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C interface
+// ===========================================================================
+extern "C" {
+
+const char *ibb_status_string(ibb_status s)
+{
+    switch (s) {
+    case IBB_OK: return "ok";
+    case IBB_EINVAL: return "invalid argument";
+    case IBB_ENOMEM: return "workspace too small";
+    case IBB_ENOCONV: return "multigrid did not reach the tolerance";
+    case IBB_ENUMERIC: return "non-finite residual";
+    case IBB_EDEVICE: return "HIP runtime error";
+    case IBB_ESTATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+const char *ibb_last_error(const ibb_ctx *c) { return c ? c->err.c_str() : ""; }
+
+ibb_status ibb_lattice_count(const ibb_desc *desc, int kind, int axis, int64_t *count, int dims[3])
+{
+    if (check_desc(desc) || !count || kind < 0 || kind > 2 || axis < 0 || axis > 2) return IBB_EINVAL;
+    if (kind == 1 && axis >= desc->dim) return IBB_EINVAL;
+    if (kind == 2 && desc->dim == 2 && axis != 2) return IBB_EINVAL;
+    Grid g = make_grid(desc, 0);
+    const int vmask = kind == 0 ? 0 : (kind == 1 ? face_mask(axis) : edge_mask(desc->dim, axis));
+    *count = lattice_count(g, vmask);
+    if (dims)
+        for (int d = 0; d < 3; ++d) dims[d] = stored_extent(g, d, (vmask >> d) & 1);
+    return IBB_OK;
+}
+
+ibb_status ibb_footprint_bytes(const ibb_desc *desc, int64_t max_nodes, int64_t max_springs, size_t *bytes)
+{
+    if (check_desc(desc) || !bytes || max_nodes < 0 || max_springs < 0 || max_nodes > INT32_MAX / 2 ||
+        max_springs > INT32_MAX / 2)
+        return IBB_EINVAL;
+    ibb_ctx tmp;
+    setup_shapes(&tmp, desc, max_nodes, max_springs);
+    *bytes = carve(&tmp, nullptr, true);
+    return IBB_OK;
+}
+
+ibb_status ibb_create(const ibb_desc *desc, int64_t max_nodes, int64_t max_springs, void *workspace,
+                      size_t workspace_bytes, void *stream, ibb_ctx **out)
+{
+    if (!out) return IBB_EINVAL;
+    *out = nullptr;
+    if (check_desc(desc) || !workspace || max_nodes < 0 || max_springs < 0 || max_nodes > INT32_MAX / 2 ||
+        max_springs > INT32_MAX / 2)
+        return IBB_EINVAL;
+    ibb_ctx *c = new ibb_ctx();
+    setup_shapes(c, desc, max_nodes, max_springs);
+    const size_t need = carve(c, nullptr, true);
+    if (workspace_bytes < need) {
+        delete c;
+        return IBB_ENOMEM;
+    }
+    char *base = reinterpret_cast<char *>(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+    carve(c, base, false);
+    c->s = reinterpret_cast<hipStream_t>(stream);
+    // zero the whole workspace
+    const size_t used = need - 256;
+    launch_fill<unsigned char>(reinterpret_cast<unsigned char *>(base), (long long)used, 0, c->s);
+    // initial coefficients: uniform fluid
+    for (int l = 0; l < c->L; ++l) {
+        Level &L = c->lv[l];
+        for (int a = 0; a < desc->dim; ++a) launch_fill<double>(L.rho[a], L.g.nel, desc->rho0, c->s);
+        launch_fill<double>(L.muc, L.g.nel, desc->mu_out, c->s);
+        for (int e = 0; e < c->E; ++e) launch_fill<double>(L.mue[c->edge_axis[e]], L.g.nel, desc->mu_out, c->s);
+    }
+    // coarsest unknown tables
+    std::vector<long long> ip, iu;
+    std::vector<int> cp, cu;
+    coarsest_tables(c, ip, cp, iu, cu);
+    hipError_t e = hipSuccess;
+    if (ip.size() <= (size_t)DENSE_MAX && !ip.empty()) {
+        e = hipMemcpyAsync(c->uidx_p, ip.data(), ip.size() * sizeof(long long), hipMemcpyHostToDevice, c->s);
+        if (e == hipSuccess) e = hipMemcpyAsync(c->ucomp_p, cp.data(), cp.size() * sizeof(int), hipMemcpyHostToDevice, c->s);
+    }
+    if (e == hipSuccess && iu.size() <= (size_t)DENSE_MAX && !iu.empty()) {
+        e = hipMemcpyAsync(c->uidx_u, iu.data(), iu.size() * sizeof(long long), hipMemcpyHostToDevice, c->s);
+        if (e == hipSuccess) e = hipMemcpyAsync(c->ucomp_u, cu.data(), cu.size() * sizeof(int), hipMemcpyHostToDevice, c->s);
+    }
+    for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&c->ev[i]);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->s);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) {
+        delete c;
+        return IBB_EDEVICE;
+    }
+    *out = c;
+    return IBB_OK;
+}
+
+ibb_status ibb_destroy(ibb_ctx *c)
+{
+    if (!c) return IBB_EINVAL;
+    (void)hipStreamSynchronize(c->s);
+    for (int i = 0; i < 4; ++i)
+        if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    delete c;
+    return IBB_OK;
+}
+
+ibb_status ibb_set_state(ibb_ctx *c, const double *u, const double *p)
+{
+    if (!c || !u) return fail(c, IBB_EINVAL, "ibb_set_state: null pointer");
+    faces_in(c, u, c->u);
+    if (p) launch_layout(c->lv[0].g, 0, p, c->p, true, c->s);
+    HIPCHK(hipGetLastError());
+    return IBB_OK;
+}
+
+ibb_status ibb_get_state(ibb_ctx *c, double *u, double *p)
+{
+    if (!c) return IBB_EINVAL;
+    if (u) faces_out(c, 0, c->u, u);
+    if (p) launch_layout(c->lv[0].g, 0, c->p, p, false, c->s);
+    HIPCHK(hipGetLastError());
+    return IBB_OK;
+}
+
+ibb_status ibb_set_nodes(ibb_ctx *c, int64_t n, const double *X)
+{
+    if (!c || n < 0 || n > c->eta_max || (n > 0 && !X)) return fail(c, IBB_EINVAL, "ibb_set_nodes: bad size or pointer");
+    const long long em = c->eta_max > 0 ? c->eta_max : 1;
+    for (int a = 0; a < c->d.dim; ++a)
+        if (n > 0) HIPCHK(hipMemcpyAsync(c->X + a * em, X + a * n, n * sizeof(double), hipMemcpyDeviceToDevice, c->s));
+    c->eta = (int)n;
+    c->have_nodes = true;
+    return IBB_OK;
+}
+
+ibb_status ibb_get_nodes(ibb_ctx *c, double *X, double *F, uint8_t *alive)
+{
+    if (!c) return IBB_EINVAL;
+    const long long em = c->eta_max > 0 ? c->eta_max : 1;
+    const long long n = c->eta;
+    for (int a = 0; a < c->d.dim && n > 0; ++a) {
+        if (X) HIPCHK(hipMemcpyAsync(X + a * n, c->X + a * em, n * sizeof(double), hipMemcpyDeviceToDevice, c->s));
+        if (F) HIPCHK(hipMemcpyAsync(F + a * n, c->F + a * em, n * sizeof(double), hipMemcpyDeviceToDevice, c->s));
+    }
+    if (alive && c->m > 0) HIPCHK(hipMemcpyAsync(alive, c->alive, c->m, hipMemcpyDeviceToDevice, c->s));
+    return IBB_OK;
+}
+
+ibb_status ibb_set_springs(ibb_ctx *c, int64_t m, const int32_t *ij, const double *rest, const double *K,
+                           const uint8_t *alive)
+{
+    if (!c || m < 0 || m > c->m_max || (m > 0 && (!ij || !rest || !K)))
+        return fail(c, IBB_EINVAL, "ibb_set_springs: bad size or pointer");
+    if (!c->have_nodes) return fail(c, IBB_ESTATE, "ibb_set_springs: set the nodes first");
+    c->m = (int)m;
+    if (m > 0) {
+        HIPCHK(hipMemcpyAsync(c->ij, ij, m * sizeof(int), hipMemcpyDeviceToDevice, c->s));
+        HIPCHK(hipMemcpyAsync(c->ij + m, ij + m, m * sizeof(int), hipMemcpyDeviceToDevice, c->s));
+        HIPCHK(hipMemcpyAsync(c->rest, rest, m * sizeof(double), hipMemcpyDeviceToDevice, c->s));
+        HIPCHK(hipMemcpyAsync(c->K, K, m * sizeof(double), hipMemcpyDeviceToDevice, c->s));
+        if (alive) HIPCHK(hipMemcpyAsync(c->alive, alive, m, hipMemcpyDeviceToDevice, c->s));
+        else launch_fill<unsigned char>(c->alive, m, 1, c->s);
+        launch_incidence_keys(c->ij, (int)m, c->inc_keys, c->s);
+    }
+    launch_bucket_sort(c->inc_keys, (int)(2 * m), c->eta > 0 ? c->eta : 1, c->inc_count, c->inc_start, c->inc_list,
+                       (int)(m > 0 ? m : 1), c->s);
+    HIPCHK(hipGetLastError());
+    c->have_springs = true;
+    return IBB_OK;
+}
+
+ibb_status ibb_update_coefficients(ibb_ctx *c)
+{
+    if (!c) return IBB_EINVAL;
+    if (!c->have_nodes) return fail(c, IBB_ESTATE, "ibb_update_coefficients: no nodes set");
+    ibb_status st = rebuild_coefficients(c);
+    if (st) return st;
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->s));
+    return IBB_OK;
+}
+
+ibb_status ibb_projection_step(ibb_ctx *c, ibb_solve_stats *stats)
+{
+    if (!c) return IBB_EINVAL;
+    if (!c->have_coefs) return fail(c, IBB_ESTATE, "ibb_projection_step: coefficients not built");
+    Level &L0 = c->lv[0];
+    const int D = c->d.dim;
+    const long long n0 = L0.g.nel;
+    View<double> v = view64(L0);
+    // momentum right-hand side and the viscous solve, warm start u^n
+    for (int a = 0; a < D; ++a) launch_copy(c->u[a], L0.xu[a], n0, c->s);
+    launch_momentum_rhs(L0.g, c->ph, VelArrC<double>{{c->u[0], c->u[1], c->u[2]}}, v.cu,
+                        VelArrC<double>{{c->f[0], c->f[1], c->f[2]}}, v.bu, c->s);
+    HIPCHK(hipEventRecord(c->ev[0], c->s));
+    SolveOut su, sp;
+    ibb_status st = solve(c, true, c->d.max_cycles, 0, &su);
+    if (st) return st;
+    HIPCHK(hipEventRecord(c->ev[1], c->s));
+    // pressure right-hand side and solve, warm start p^n
+    launch_pressure_div(L0.g, c->ph, cview(v.xu), L0.bp, c->s);
+    if (c->singular_p) remove_cell_mean(c, L0.bp);
+    launch_copy(c->p, L0.xp, n0, c->s);
+    HIPCHK(hipEventRecord(c->ev[2], c->s));
+    st = solve(c, false, c->d.max_cycles, 0, &sp);
+    if (st) return st;
+    HIPCHK(hipEventRecord(c->ev[3], c->s));
+    if (c->singular_p) remove_cell_mean(c, L0.xp);
+    launch_copy(L0.xp, c->p, n0, c->s);
+    // projection
+    for (int a = 0; a < D; ++a) launch_copy(L0.xu[a], c->u[a], n0, c->s);
+    launch_project(L0.g, c->ph, cview(v.xu), L0.xp, v.cp, VelArr<double>{{c->u[0], c->u[1], c->u[2]}}, c->s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->s));
+    if (stats) {
+        float tu = 0, tp = 0;
+        (void)hipEventElapsedTime(&tu, c->ev[0], c->ev[1]);
+        (void)hipEventElapsedTime(&tp, c->ev[2], c->ev[3]);
+        stats->status_u = su.status;
+        stats->status_p = sp.status;
+        stats->cycles_u = su.cycles;
+        stats->cycles_p = sp.cycles;
+        stats->vcycles_u = su.vcycles;
+        stats->vcycles_p = sp.vcycles;
+        stats->relres_u = su.relres;
+        stats->relres_p = sp.relres;
+        stats->t_u_ms = tu;
+        stats->t_p_ms = tp;
+        stats->dof_u = L0.nu;
+        stats->dof_p = L0.np;
+    }
+    if (su.status) return fail(c, (ibb_status)su.status, "viscous solve did not converge");
+    if (sp.status) return fail(c, (ibb_status)sp.status, "pressure solve did not converge");
+    return IBB_OK;
+}
+
+ibb_status ibb_lagrangian_update(ibb_ctx *c, ibb_lag_stats *stats)
+{
+    if (!c) return IBB_EINVAL;
+    if (!c->have_coefs) return fail(c, IBB_ESTATE, "ibb_lagrangian_update: coefficients not built");
+    Level &L0 = c->lv[0];
+    const long long em = c->eta_max > 0 ? c->eta_max : 1;
+    HIPCHK(hipEventRecord(c->ev[0], c->s));
+    launch_interp(L0.g, c->d.kernel, c->d.h, VelArrC<double>{{c->u[0], c->u[1], c->u[2]}}, c->X, em, c->eta, c->U,
+                  em, c->s);
+    launch_euler(L0.g, c->d.dt / c->d.sigma, c->U, c->X, em, c->eta, c->s);
+    launch_fill<int>(c->counters, 2, 0, c->s);
+    if (c->have_springs && c->m > 0)
+        launch_spring_break(L0.g, c->d.break_ratio, c->X, em, c->ij, c->m, c->rest, c->alive, c->counters, c->s);
+    ibb_status st = rebuild_coefficients(c);
+    if (st) return st;
+    if (c->have_springs) launch_count_alive(c->alive, c->m, c->counters + 1, c->s);
+    HIPCHK(hipEventRecord(c->ev[1], c->s));
+    int cnt[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(cnt, c->counters, 2 * sizeof(int), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->s));
+    if (stats) {
+        float t = 0;
+        (void)hipEventElapsedTime(&t, c->ev[0], c->ev[1]);
+        stats->n_broken = cnt[0];
+        stats->n_alive = cnt[1];
+        stats->t_ms = t;
+    }
+    return IBB_OK;
+}
+
+ibb_status ibb_get_fields(ibb_ctx *c, int level, double *f, double *rho, double *mu_c, double *mu_e)
+{
+    if (!c || level < 0 || level >= c->L || (f && level != 0)) return fail(c, IBB_EINVAL, "ibb_get_fields: bad level");
+    Level &L = c->lv[level];
+    if (f) faces_out(c, 0, c->f, f);
+    if (rho) faces_out(c, level, L.rho, rho);
+    if (mu_c) launch_layout(L.g, 0, L.muc, mu_c, false, c->s);
+    if (mu_e) {
+        long long off = 0;
+        for (int e = 0; e < c->E; ++e) {
+            const int vm = edge_mask(c->d.dim, c->edge_axis[e]);
+            launch_layout(L.g, vm, L.mue[c->edge_axis[e]], mu_e + off, false, c->s);
+            off += lattice_count(L.g, vm);
+        }
+    }
+    HIPCHK(hipGetLastError());
+    return IBB_OK;
+}
+
+ibb_status ibb_momentum_rhs(ibb_ctx *c, double *b)
+{
+    if (!c || !b) return IBB_EINVAL;
+    if (!c->have_coefs) return fail(c, IBB_ESTATE, "ibb_momentum_rhs: coefficients not built");
+    Level &L0 = c->lv[0];
+    View<double> v = view64(L0);
+    for (int a = 0; a < c->d.dim; ++a) launch_fill<double>(L0.ru[a], L0.g.nel, 0.0, c->s);
+    launch_momentum_rhs(L0.g, c->ph, VelArrC<double>{{c->u[0], c->u[1], c->u[2]}}, v.cu,
+                        VelArrC<double>{{c->f[0], c->f[1], c->f[2]}}, v.ru, c->s);
+    faces_out(c, 0, L0.ru, b);
+    HIPCHK(hipGetLastError());
+    return IBB_OK;
+}
+
+ibb_status ibb_pressure_rhs(ibb_ctx *c, const double *ut, double *bp)
+{
+    if (!c || !ut || !bp) return IBB_EINVAL;
+    Level &L0 = c->lv[0];
+    faces_in(c, ut, L0.ru);
+    launch_pressure_div(L0.g, c->ph, VelArrC<double>{{L0.ru[0], L0.ru[1], L0.ru[2]}}, L0.rp, c->s);
+    if (c->singular_p) remove_cell_mean(c, L0.rp);
+    launch_layout(L0.g, 0, L0.rp, bp, false, c->s);
+    HIPCHK(hipGetLastError());
+    return IBB_OK;
+}
+
+ibb_status ibb_mg_solve(ibb_ctx *c, int which, const double *b, double *x, int max_cycles_override, int ncycles_exact,
+                        int *cycles, double *relres)
+{
+    if (!c || !b || !x || (which != 0 && which != 1)) return IBB_EINVAL;
+    if (!c->have_coefs) return fail(c, IBB_ESTATE, "ibb_mg_solve: coefficients not built");
+    Level &L0 = c->lv[0];
+    const bool vel = which == 1;
+    if (vel) {
+        for (int a = 0; a < c->d.dim; ++a) launch_fill<double>(L0.bu[a], L0.g.nel, 0.0, c->s);
+        faces_in(c, b, L0.bu);
+        faces_in(c, x, L0.xu);
+    } else {
+        launch_layout(L0.g, 0, b, L0.bp, true, c->s);
+        launch_layout(L0.g, 0, x, L0.xp, true, c->s);
+    }
+    SolveOut o;
+    ibb_status st = solve(c, vel, max_cycles_override > 0 ? max_cycles_override : c->d.max_cycles, ncycles_exact, &o);
+    if (st) return st;
+    if (vel) faces_out(c, 0, L0.xu, x);
+    else launch_layout(L0.g, 0, L0.xp, x, false, c->s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->s));
+    if (cycles) *cycles = o.cycles;
+    if (relres) *relres = o.relres;
+    if (o.status) return fail(c, (ibb_status)o.status, "ibb_mg_solve: no convergence");
+    return IBB_OK;
+}
+
+ibb_status ibb_project(ibb_ctx *c, const double *ut, const double *p, double *u)
+{
+    if (!c || !ut || !p || !u) return IBB_EINVAL;
+    if (!c->have_coefs) return fail(c, IBB_ESTATE, "ibb_project: coefficients not built");
+    Level &L0 = c->lv[0];
+    View<double> v = view64(L0);
+    faces_in(c, ut, L0.xu);
+    launch_layout(L0.g, 0, p, L0.xp, true, c->s);
+    for (int a = 0; a < c->d.dim; ++a) launch_copy(L0.xu[a], L0.ru[a], L0.g.nel, c->s);
+    launch_project(L0.g, c->ph, cview(v.xu), L0.xp, v.cp, v.ru, c->s);
+    faces_out(c, 0, L0.ru, u);
+    HIPCHK(hipGetLastError());
+    return IBB_OK;
+}
+
+ibb_status ibb_interp(ibb_ctx *c, double width, int64_t n, const double *X, const double *u, double *U)
+{
+    if (!c || n < 0 || (n > 0 && (!X || !u || !U)) || !(width > 0)) return IBB_EINVAL;
+    for (int a = 0; a < c->d.dim; ++a)
+        if (c->d.axis_bc[a] == IBB_AXIS_PERIODIC && 4.0 * width > c->d.n[a] * c->d.h)
+            return fail(c, IBB_EINVAL, "ibb_interp: width too large for a periodic axis");
+    Level &L0 = c->lv[0];
+    faces_in(c, u, L0.ru);
+    launch_interp(L0.g, c->d.kernel, width, VelArrC<double>{{L0.ru[0], L0.ru[1], L0.ru[2]}}, X, n, (int)n, U, n, c->s);
+    HIPCHK(hipGetLastError());
+    return IBB_OK;
+}
+
+ibb_status ibb_spread(ibb_ctx *c, double width, int64_t n, const double *X, const double *F, double *out)
+{
+    if (!c || n < 0 || n > c->eta_max || (n > 0 && (!X || !F)) || !out || !(width > 0)) return IBB_EINVAL;
+    const double wmin = c->d.omega < c->d.h ? c->d.omega : c->d.h;
+    if (width < wmin) return fail(c, IBB_EINVAL, "ibb_spread: width below min(omega, h)");
+    for (int a = 0; a < c->d.dim; ++a)
+        if (c->d.axis_bc[a] == IBB_AXIS_PERIODIC && 4.0 * width > c->d.n[a] * c->d.h)
+            return fail(c, IBB_EINVAL, "ibb_spread: width too large for a periodic axis");
+    Level &L0 = c->lv[0];
+    Bins b = c->bins;
+    bins_for_width(&c->d, width, b.nb, b.bs);
+    b.nbins = b.nb[0] * b.nb[1] * b.nb[2];
+    launch_bin_nodes(L0.g, b, X, n > 0 ? n : 1, (int)n, c->s);
+    for (int a = 0; a < c->d.dim; ++a)
+        launch_spread_face(L0.g, c->ph, b, X, F, n > 0 ? n : 1, a, width, L0.ru[a], nullptr, c->s);
+    faces_out(c, 0, L0.ru, out);
+    HIPCHK(hipGetLastError());
+    return IBB_OK;
+}
+
+ibb_status ibb_level_info(const ibb_ctx *c, int level, int *nlevels, int n[3])
+{
+    if (!c) return IBB_EINVAL;
+    if (nlevels) *nlevels = c->L;
+    if (n) {
+        if (level < 0 || level >= c->L) return IBB_EINVAL;
+        for (int d = 0; d < 3; ++d) n[d] = c->lv[level].g.n[d];
+    }
+    return IBB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,145 @@
+// Internal definitions shared by the HIP translation units of the library:
+// the per-level grid descriptor passed to kernels, the boundary rules that
+// map an out-of-range lattice index to the value it stands for, and the
+// regularised delta.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ibmg {
+
+// axis kinds (same numbering as ibb_axis_bc)
+enum { AX_PERIODIC = 0, AX_WALLS = 1, AX_INOUT = 2 };
+
+// How a field behaves beyond the domain:
+//  ROLE_P  pressure / pressure corrections: zero normal derivative at walls
+//          and inflow, zero value on the outflow face;
+//  ROLE_V  velocity with homogeneous boundary data (unknowns, corrections,
+//          residuals): the fixed normal faces read as zero, the tangential
+//          component is odd across walls and the inflow plane and even
+//          across the outflow plane, the outflow face mirrors evenly;
+//  ROLE_C  coefficient fields: even reflection.
+// Periodic axes wrap for every role.
+enum { ROLE_P = 0, ROLE_V = 1, ROLE_C = 3 };
+
+// One multigrid level.  Every field of the level (cell, face or edge
+// lattice) uses the same uniform array of (n[0]+1) x (n[1]+1) (x (n[2]+1))
+// entries, so that neighbouring positions of different lattices sit at fixed
+// offsets.  Lattice position (i, j, k) is entry at(i, j, k).
+struct Grid {
+    int D;
+    int n[3];
+    int bc[3];
+    int NX, NY;        // row length and rows per plane of the uniform array
+    long long NXY;     // entries per plane
+    long long nel;     // entries per array
+    double h;
+};
+
+__host__ __device__ inline long long at(const Grid &g, int i, int j, int k)
+{
+    return ((long long)k * g.NY + j) * g.NX + i;
+}
+
+__host__ __device__ inline long long stride_of(const Grid &g, int d)
+{
+    return d == 0 ? 1 : (d == 1 ? (long long)g.NX : g.NXY);
+}
+
+// Range of unknowns along axis d for a lattice that is vertex-centred
+// (vert) or cell-centred along d.  Fixed faces (walls, inflow) are not
+// unknowns; the outflow face is.
+__host__ __device__ inline void unk_range(const Grid &g, int d, int vert, int &lo, int &hi)
+{
+    if (d >= g.D) { lo = hi = 0; return; }
+    if (!vert) { lo = 0; hi = g.n[d] - 1; return; }
+    if (g.bc[d] == AX_PERIODIC) { lo = 0; hi = g.n[d] - 1; }
+    else if (g.bc[d] == AX_WALLS) { lo = 1; hi = g.n[d] - 1; }
+    else { lo = 1; hi = g.n[d]; }
+}
+
+// Closed-domain positions stored along axis d (the compact layout).
+__host__ __device__ inline int stored_extent(const Grid &g, int d, int vert)
+{
+    if (d >= g.D) return 1;
+    if (!vert) return g.n[d];
+    return g.bc[d] == AX_PERIODIC ? g.n[d] : g.n[d] + 1;
+}
+
+// Map coordinate q along axis d into the stored range under a role.
+// Returns false when the value there is the zero of a fixed face;
+// otherwise updates q and multiplies s by the reflection sign.
+__host__ __device__ inline bool resolve(const Grid &g, int d, int vert, int role, int &q, int &s)
+{
+    const int n = g.n[d], bc = g.bc[d];
+    if (!vert) {
+        if (q >= 0 && q < n) return true;
+        if (bc == AX_PERIODIC) { q = q < 0 ? q + n : q - n; return true; }
+        if (q < 0) {                 // wall or inflow side
+            q = 0;
+            if (role == ROLE_V) s = -s;
+            return true;
+        }
+        q = n - 1;                   // wall or outflow side
+        if (role == ROLE_P && bc == AX_INOUT) s = -s;
+        if (role == ROLE_V && bc == AX_WALLS) s = -s;
+        return true;
+    }
+    if (bc == AX_PERIODIC) {
+        if (q < 0) q += n;
+        else if (q >= n) q -= n;
+        return true;
+    }
+    if (role == ROLE_C) {
+        if (q < 0) q = -q;
+        else if (q > n) q = 2 * n - q;
+        return true;
+    }
+    if (q <= 0) return false;        // fixed low face
+    if (q < n) return true;
+    if (q == n) return bc == AX_INOUT;
+    q = 2 * n - q;                   // one past the outflow face mirrors evenly
+    return true;
+}
+
+// Resolved reference: entry index and sign (s == 0 means the value is 0).
+struct Ref {
+    long long idx;
+    int s;
+};
+
+// vmask bit d set: the lattice is vertex-centred along axis d
+__host__ __device__ inline Ref ref_at(const Grid &g, int vmask, int role, int i, int j, int k)
+{
+    int q[3] = {i, j, k};
+    int s = 1;
+    for (int d = 0; d < g.D; ++d)
+        if (!resolve(g, d, (vmask >> d) & 1, role, q[d], s)) return Ref{0, 0};
+    return Ref{at(g, q[0], q[1], q[2]), s};
+}
+
+template <typename T>
+__device__ inline T load_ref(const T *__restrict__ v, Ref r)
+{
+    return r.s == 0 ? T(0) : (r.s > 0 ? v[r.idx] : -v[r.idx]);
+}
+
+// lattice masks
+__host__ __device__ inline int face_mask(int a) { return 1 << a; }
+__host__ __device__ inline int edge_mask(int D, int c) { return ((1 << D) - 1) & ~(1 << c); }
+
+// The two regularised deltas of the paper's "Dirac Delta Approximation"
+// section: kernel 0 the cosine phi_2, kernel 1 Peskin's four-point phi_1.
+__device__ inline double phi_eval(int kernel, double r)
+{
+    double a = fabs(r);
+    if (!(a < 2.0)) return 0.0;
+    if (kernel == 1) {
+        if (a <= 1.0) return (3.0 - 2.0 * a + sqrt(1.0 + 4.0 * a - 4.0 * a * a)) * 0.125;
+        return (5.0 - 2.0 * a - sqrt(-7.0 + 12.0 * a - 4.0 * a * a)) * 0.125;
+    }
+    return 0.25 * (1.0 + cos(1.5707963267948966 * a));
+}
+
+}  // namespace ibmg

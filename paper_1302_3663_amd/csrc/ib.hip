@@ -1,0 +1,476 @@
+// Immersed-boundary kernels: node binning, the spread of force and density
+// to the faces (eq:discrForceCouple, eq:discrDensCouple) and of the
+// viscosity maximum to cells and edges (eq:ViscExp), the interpolation of
+// face velocities to nodes (eq:discrVelCouple), the Euler move of the
+// nodes, and the spring breakage and force passes (eq:springF and the
+// breakage rule of the "Elastic Forces" section).
+//
+// The spread runs as a gather: each lattice point visits the nodes of the
+// bins around it, in ascending node order within a bin, so the result does
+// not depend on thread timing and no atomics touch the fields.
+#include "common.h"
+#include "kernels.h"
+
+namespace ibmg {
+
+static inline unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
+
+__device__ inline double domain_len(const Grid &g, int d) { return g.n[d] * g.h; }
+
+// nearest periodic image of a separation along axis d
+__device__ inline double min_image(const Grid &g, int d, double v)
+{
+    if (g.bc[d] != AX_PERIODIC) return v;
+    const double L = domain_len(g, d);
+    return v - L * floor(v / L + 0.5);
+}
+
+// ---------------------------------------------------------------------------
+// counting sort with a deterministic order inside each bucket
+// ---------------------------------------------------------------------------
+__global__ void k_count_keys(const int *__restrict__ keys, int n, int *count)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) atomicAdd(&count[keys[t]], 1);
+}
+
+// single workgroup exclusive scan of count[0..nb) into start[0..nb]
+__global__ void __launch_bounds__(1024) k_scan(const int *__restrict__ count, int nb, int *start)
+{
+    __shared__ int part[1024];
+    const int t = threadIdx.x;
+    const int chunk = (nb + blockDim.x - 1) / blockDim.x;
+    const int lo = t * chunk, hi = min(nb, lo + chunk);
+    int s = 0;
+    for (int i = lo; i < hi; ++i) s += count[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+        const int v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = t ? part[t - 1] : 0;
+    for (int i = lo; i < hi; ++i) {
+        start[i] = run;
+        run += count[i];
+    }
+    if (t == blockDim.x - 1) start[nb] = part[t];
+}
+
+__global__ void k_scatter_keys(const int *__restrict__ keys, int n, const int *__restrict__ start, int *cursor, int *ids)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int k = keys[t];
+    const int pos = start[k] + atomicAdd(&cursor[k], 1);
+    ids[pos] = t;
+}
+
+// insertion sort of each bucket by id modulo `mod` (mod = 0: by id);
+// buckets are short
+__global__ void k_sort_buckets(const int *__restrict__ start, int nb, int *ids, int mod)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const int lo = start[b], hi = start[b + 1];
+    for (int i = lo + 1; i < hi; ++i) {
+        const int v = ids[i];
+        const int kv = mod ? v % mod : v;
+        int j = i - 1;
+        while (j >= lo && (mod ? ids[j] % mod : ids[j]) > kv) {
+            ids[j + 1] = ids[j];
+            --j;
+        }
+        ids[j + 1] = v;
+    }
+}
+
+void launch_bucket_sort(const int *keys, int n, int nbuckets, int *count, int *start, int *ids, int mod, hipStream_t s)
+{
+    launch_fill<int>(count, nbuckets, 0, s);
+    if (n > 0) hipLaunchKernelGGL(k_count_keys, dim3(nblk(n)), dim3(256), 0, s, keys, n, count);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, count, nbuckets, start);
+    launch_fill<int>(count, nbuckets, 0, s);
+    if (n > 0) hipLaunchKernelGGL(k_scatter_keys, dim3(nblk(n)), dim3(256), 0, s, keys, n, start, count, ids);
+    hipLaunchKernelGGL(k_sort_buckets, dim3(nblk(nbuckets)), dim3(256), 0, s, start, nbuckets, ids, mod);
+}
+
+// ---------------------------------------------------------------------------
+// bins: cell size at least twice the delta width along each axis, so every
+// node within the support of a point lies in the point's bin or a neighbour
+// ---------------------------------------------------------------------------
+__device__ inline int bin_coord(const Bins &bins, int d, double x)
+{
+    int b = (int)floor(x / bins.bs[d]);
+    return b < 0 ? 0 : (b >= bins.nb[d] ? bins.nb[d] - 1 : b);
+}
+
+__global__ void k_bin_of(Grid g, Bins bins, const double *__restrict__ X, long long stride, int eta)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= eta) return;
+    int b[3] = {0, 0, 0};
+    for (int d = 0; d < g.D; ++d) {
+        double x = X[d * stride + s];
+        if (g.bc[d] == AX_PERIODIC) {
+            const double L = domain_len(g, d);
+            x -= L * floor(x / L);
+        }
+        b[d] = bin_coord(bins, d, x);
+    }
+    bins.bin_of[s] = (b[2] * bins.nb[1] + b[1]) * bins.nb[0] + b[0];
+}
+
+void launch_bin_nodes(const Grid &g, const Bins &bins, const double *X, long long stride, int eta, hipStream_t s)
+{
+    if (eta > 0) hipLaunchKernelGGL(k_bin_of, dim3(nblk(eta)), dim3(256), 0, s, g, bins, X, stride, eta);
+    launch_bucket_sort(bins.bin_of, eta, bins.nbins, bins.count, bins.start, bins.sorted, 0, s);
+}
+
+// distinct neighbouring bins of a point along each axis
+struct BinNbr {
+    int cnt[3];
+    int lst[3][3];
+};
+
+__device__ inline BinNbr bin_neighbours(const Grid &g, const Bins &bins, const double x[3])
+{
+    BinNbr r;
+    for (int d = 0; d < 3; ++d) {
+        if (d >= g.D) { r.cnt[d] = 1; r.lst[d][0] = 0; continue; }
+        const int nb = bins.nb[d];
+        if (g.bc[d] == AX_PERIODIC && nb <= 2) {
+            r.cnt[d] = nb;
+            for (int t = 0; t < nb; ++t) r.lst[d][t] = t;
+            continue;
+        }
+        double xx = x[d];
+        if (g.bc[d] == AX_PERIODIC) {
+            const double L = domain_len(g, d);
+            xx -= L * floor(xx / L);
+        }
+        const int b = bin_coord(bins, d, xx);
+        int c = 0;
+        for (int o = -1; o <= 1; ++o) {
+            int t = b + o;
+            if (g.bc[d] == AX_PERIODIC) t = (t + nb) % nb;
+            else if (t < 0 || t >= nb) continue;
+            r.lst[d][c++] = t;
+        }
+        r.cnt[d] = c;
+    }
+    return r;
+}
+
+// delta~(x - X_s, w) = w^-D prod_d phi((x_d - X_d) / w), zero outside the support
+__device__ inline double delta_w(const Grid &g, int kernel, double inv_w, double scale, const double x[3],
+                                 const double *__restrict__ X, long long stride, int s)
+{
+    double w = scale;
+    for (int d = 0; d < g.D; ++d) {
+        const double r = min_image(g, d, x[d] - X[d * stride + s]) * inv_w;
+        if (!(fabs(r) < 2.0)) return 0.0;
+        w *= phi_eval(kernel, r);
+    }
+    return w;
+}
+
+__device__ inline void lattice_coord(const Grid &g, int vmask, int i, int j, int k, double x[3])
+{
+    const int q[3] = {i, j, k};
+    for (int d = 0; d < 3; ++d) x[d] = ((vmask >> d) & 1) ? q[d] * g.h : (q[d] + 0.5) * g.h;
+}
+
+// f_a(x) = sum_s F_a(s) delta~ and rho_a(x) = rho0 + rho_b d0^D sum_s delta~
+// at every closed-domain a-face
+__global__ void __launch_bounds__(256) k_spread_face(Grid g, Phys ph, Bins bins, const double *__restrict__ X,
+                                                     const double *__restrict__ F, long long stride, int a,
+                                                     double width, double *f_out, double *rho_out)
+{
+    const int vmask = face_mask(a);
+    int ext[3];
+    for (int d = 0; d < 3; ++d) ext[d] = stored_extent(g, d, (vmask >> d) & 1);
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)ext[0] * ext[1] * ext[2]) return;
+    const int i = (int)(t % ext[0]);
+    t /= ext[0];
+    const int j = (int)(t % ext[1]);
+    const int k = (int)(t / ext[1]);
+    double x[3];
+    lattice_coord(g, vmask, i, j, k, x);
+    const double inv_w = 1.0 / width;
+    double scale = 1.0;
+    for (int d = 0; d < g.D; ++d) scale /= width;
+    const BinNbr nbr = bin_neighbours(g, bins, x);
+    double accf = 0.0, accw = 0.0;
+    for (int c = 0; c < nbr.cnt[2]; ++c)
+        for (int b = 0; b < nbr.cnt[1]; ++b)
+            for (int e = 0; e < nbr.cnt[0]; ++e) {
+                const int bin = (nbr.lst[2][c] * bins.nb[1] + nbr.lst[1][b]) * bins.nb[0] + nbr.lst[0][e];
+                for (int p = bins.start[bin]; p < bins.start[bin + 1]; ++p) {
+                    const int s = bins.sorted[p];
+                    const double w = delta_w(g, ph.kernel, inv_w, scale, x, X, stride, s);
+                    if (w == 0.0) continue;
+                    if (F) accf += F[a * stride + s] * w;
+                    accw += w;
+                }
+            }
+    const long long u = at(g, i, j, k);
+    if (f_out) f_out[u] = accf;
+    if (rho_out) rho_out[u] = ph.rho0 + ph.rho_b * ph.d0_pow_d * accw;
+}
+
+void launch_spread_face(const Grid &g, const Phys &ph, const Bins &bins, const double *X, const double *F,
+                        long long stride, int a, double width, double *f_out, double *rho_out, hipStream_t s)
+{
+    long long n = 1;
+    for (int d = 0; d < 3; ++d) n *= stored_extent(g, d, d == a);
+    hipLaunchKernelGGL(k_spread_face, dim3(nblk(n)), dim3(256), 0, s, g, ph, bins, X, F, stride, a, width, f_out,
+                       rho_out);
+}
+
+// mu(x) = max over nodes of (2 omega)^D (mu_max - mu_out) delta~ + mu_out,
+// mu_out where no node reaches
+__global__ void __launch_bounds__(256) k_spread_visc(Grid g, Phys ph, Bins bins, const double *__restrict__ X,
+                                                     long long stride, int vmask, double *mu_out)
+{
+    int ext[3];
+    for (int d = 0; d < 3; ++d) ext[d] = stored_extent(g, d, (vmask >> d) & 1);
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)ext[0] * ext[1] * ext[2]) return;
+    const int i = (int)(t % ext[0]);
+    t /= ext[0];
+    const int j = (int)(t % ext[1]);
+    const int k = (int)(t / ext[1]);
+    double x[3];
+    lattice_coord(g, vmask, i, j, k, x);
+    const double width = ph.omega;
+    const double inv_w = 1.0 / width;
+    double scale = 1.0, vol = 1.0;
+    for (int d = 0; d < g.D; ++d) {
+        scale /= width;
+        vol *= 2.0 * width;
+    }
+    const double dmu = ph.mu_max - ph.mu_out;
+    double best = ph.mu_out;
+    if (dmu > 0.0) {
+        const BinNbr nbr = bin_neighbours(g, bins, x);
+        double wmax = 0.0;
+        for (int c = 0; c < nbr.cnt[2]; ++c)
+            for (int b = 0; b < nbr.cnt[1]; ++b)
+                for (int e = 0; e < nbr.cnt[0]; ++e) {
+                    const int bin = (nbr.lst[2][c] * bins.nb[1] + nbr.lst[1][b]) * bins.nb[0] + nbr.lst[0][e];
+                    for (int p = bins.start[bin]; p < bins.start[bin + 1]; ++p) {
+                        const double w = delta_w(g, ph.kernel, inv_w, scale, x, X, stride, bins.sorted[p]);
+                        wmax = w > wmax ? w : wmax;
+                    }
+                }
+        if (wmax > 0.0) {
+            const double cand = vol * dmu * wmax + ph.mu_out;
+            best = cand > best ? cand : best;
+        }
+    }
+    mu_out[at(g, i, j, k)] = best;
+}
+
+void launch_spread_visc(const Grid &g, const Phys &ph, const Bins &bins, const double *X, long long stride, int vmask,
+                        double *mu_out, hipStream_t s)
+{
+    long long n = 1;
+    for (int d = 0; d < 3; ++d) n *= stored_extent(g, d, (vmask >> d) & 1);
+    hipLaunchKernelGGL(k_spread_visc, dim3(nblk(n)), dim3(256), 0, s, g, ph, bins, X, stride, vmask, mu_out);
+}
+
+// ---------------------------------------------------------------------------
+// interpolation U_a(s) = sum_x u_a(x) delta~(x - X_s, w) h^D over the
+// closed-domain a-faces (fixed faces contribute the values they hold)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_interp(Grid g, int kernel, double width, VelArrC<double> u,
+                                                const double *__restrict__ X, long long xstride, int eta, double *U,
+                                                long long ustride)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= eta) return;
+    const double inv_w = 1.0 / width;
+    double scale = 1.0, hD = 1.0;
+    for (int d = 0; d < g.D; ++d) {
+        scale /= width;
+        hD *= g.h;
+    }
+    double Xs[3] = {0.0, 0.0, 0.0};
+    for (int d = 0; d < g.D; ++d) Xs[d] = X[d * xstride + s];
+    for (int a = 0; a < g.D; ++a) {
+        const int vmask = face_mask(a);
+        int qlo[3], qhi[3];
+        for (int d = 0; d < 3; ++d) {
+            if (d >= g.D) { qlo[d] = qhi[d] = 0; continue; }
+            const double off = ((vmask >> d) & 1) ? 0.0 : 0.5;
+            qlo[d] = (int)floor((Xs[d] - 2.0 * width) / g.h - off);
+            qhi[d] = (int)ceil((Xs[d] + 2.0 * width) / g.h - off);
+        }
+        double acc = 0.0;
+        for (int k = qlo[2]; k <= qhi[2]; ++k)
+            for (int j = qlo[1]; j <= qhi[1]; ++j)
+                for (int i = qlo[0]; i <= qhi[0]; ++i) {
+                    const int q[3] = {i, j, k};
+                    int qs[3] = {0, 0, 0};
+                    double w = scale;
+                    bool keep = true;
+                    for (int d = 0; d < g.D; ++d) {
+                        const int vert = (vmask >> d) & 1;
+                        const double xc = vert ? q[d] * g.h : (q[d] + 0.5) * g.h;
+                        const double r = (xc - Xs[d]) * inv_w;
+                        if (!(fabs(r) < 2.0)) { keep = false; break; }
+                        int tq = q[d];
+                        const int ext = stored_extent(g, d, vert);
+                        if (g.bc[d] == AX_PERIODIC) tq = ((tq % g.n[d]) + g.n[d]) % g.n[d];
+                        else if (tq < 0 || tq >= ext) { keep = false; break; }
+                        qs[d] = tq;
+                        w *= phi_eval(kernel, r);
+                    }
+                    if (!keep) continue;
+                    acc += u.c[a][at(g, qs[0], qs[1], qs[2])] * w;
+                }
+        U[a * ustride + s] = acc * hD;
+    }
+}
+
+void launch_interp(const Grid &g, int kernel, double width, const VelArrC<double> &u, const double *X,
+                   long long xstride, int eta, double *U, long long ustride, hipStream_t s)
+{
+    if (eta <= 0) return;
+    hipLaunchKernelGGL(k_interp, dim3(nblk(eta)), dim3(256), 0, s, g, kernel, width, u, X, xstride, eta, U, ustride);
+}
+
+// X += c U, periodic axes wrapped back into [0, L)
+__global__ void k_euler(Grid g, double c, const double *__restrict__ U, double *X, long long stride, int eta)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= eta) return;
+    for (int d = 0; d < g.D; ++d) {
+        double x = X[d * stride + s] + c * U[d * stride + s];
+        if (g.bc[d] == AX_PERIODIC) {
+            const double L = domain_len(g, d);
+            x -= L * floor(x / L);
+        }
+        X[d * stride + s] = x;
+    }
+}
+
+void launch_euler(const Grid &g, double c, const double *U, double *X, long long stride, int eta, hipStream_t s)
+{
+    if (eta > 0) hipLaunchKernelGGL(k_euler, dim3(nblk(eta)), dim3(256), 0, s, g, c, U, X, stride, eta);
+}
+
+// ---------------------------------------------------------------------------
+// springs
+// ---------------------------------------------------------------------------
+// separation X_j - X_i (nearest periodic image), each operation rounded on
+// its own so that the breakage decision is reproducible
+__device__ inline void separation_rn(const Grid &g, const double *__restrict__ X, long long stride, int i, int j,
+                                     double v[3])
+{
+    for (int d = 0; d < 3; ++d) {
+        v[d] = 0.0;
+        if (d >= g.D) continue;
+        double x = __dsub_rn(X[d * stride + j], X[d * stride + i]);
+        if (g.bc[d] == AX_PERIODIC) {
+            const double L = domain_len(g, d);
+            x = __dsub_rn(x, __dmul_rn(L, floor(__dadd_rn(__ddiv_rn(x, L), 0.5))));
+        }
+        v[d] = x;
+    }
+}
+
+__device__ inline double len2_rn(const double v[3])
+{
+    return __dadd_rn(__dadd_rn(__dmul_rn(v[0], v[0]), __dmul_rn(v[1], v[1])), __dmul_rn(v[2], v[2]));
+}
+
+__global__ void k_spring_break(Grid g, double ratio, const double *__restrict__ X, long long stride,
+                               const int *__restrict__ ij, int m, const double *__restrict__ rest,
+                               unsigned char *alive, int *n_broken)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m || !alive[e]) return;
+    double v[3];
+    separation_rn(g, X, stride, ij[e], ij[m + e], v);
+    const double lim = __dmul_rn(ratio, rest[e]);
+    if (len2_rn(v) > __dmul_rn(lim, lim)) {
+        alive[e] = 0;
+        atomicAdd(n_broken, 1);
+    }
+}
+
+void launch_spring_break(const Grid &g, double ratio, const double *X, long long stride, const int *ij, int m,
+                         const double *rest, unsigned char *alive, int *n_broken, hipStream_t s)
+{
+    if (m > 0)
+        hipLaunchKernelGGL(k_spring_break, dim3(nblk(m)), dim3(256), 0, s, g, ratio, X, stride, ij, m, rest, alive,
+                           n_broken);
+}
+
+// F_s = sum over surviving springs at s, in ascending spring order, of
+// K (l - r) d / l with d = X_j - X_i (added at i, subtracted at j)
+__global__ void __launch_bounds__(256) k_spring_force(Grid g, const double *__restrict__ X, long long stride, int eta,
+                                                      const int *__restrict__ ij, int m,
+                                                      const double *__restrict__ rest, const double *__restrict__ K,
+                                                      const unsigned char *__restrict__ alive,
+                                                      const int *__restrict__ inc_start,
+                                                      const int *__restrict__ inc_list, double *F)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= eta) return;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int p = inc_start[s]; p < inc_start[s + 1]; ++p) {
+        const int entry = inc_list[p];
+        const int e = entry >= m ? entry - m : entry;
+        if (!alive[e]) continue;
+        const int i = ij[e], j = ij[m + e];
+        double v[3];
+        separation_rn(g, X, stride, i, j, v);
+        const double l = sqrt(len2_rn(v));
+        if (l == 0.0) continue;
+        const double T = K[e] * (l - rest[e]);
+        const double sg = (s == i) ? 1.0 : -1.0;
+        for (int d = 0; d < g.D; ++d) acc[d] += sg * (T * v[d] / l);
+    }
+    for (int d = 0; d < g.D; ++d) F[d * stride + s] = acc[d];
+}
+
+void launch_spring_force(const Grid &g, const double *X, long long stride, int eta, const int *ij, int m,
+                         const double *rest, const double *K, const unsigned char *alive, const int *inc_start,
+                         const int *inc_list, double *F, hipStream_t s)
+{
+    if (eta > 0)
+        hipLaunchKernelGGL(k_spring_force, dim3(nblk(eta)), dim3(256), 0, s, g, X, stride, eta, ij, m, rest, K, alive,
+                           inc_start, inc_list, F);
+}
+
+// incidence keys: entry e -> node i of spring e, entry m + e -> node j
+__global__ void k_incidence_keys(const int *__restrict__ ij, int m, int *keys)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < 2 * m) keys[t] = ij[t];
+}
+
+void launch_incidence_keys(const int *ij, int m, int *keys, hipStream_t s)
+{
+    if (m > 0) hipLaunchKernelGGL(k_incidence_keys, dim3(nblk(2LL * m)), dim3(256), 0, s, ij, m, keys);
+}
+
+__global__ void k_count_alive(const unsigned char *__restrict__ alive, int m, int *out)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < m && alive[e]) atomicAdd(out, 1);
+}
+
+void launch_count_alive(const unsigned char *alive, int m, int *out, hipStream_t s)
+{
+    launch_fill<int>(out, 1, 0, s);
+    if (m > 0) hipLaunchKernelGGL(k_count_alive, dim3(nblk(m)), dim3(256), 0, s, alive, m, out);
+}
+
+}  // namespace ibmg

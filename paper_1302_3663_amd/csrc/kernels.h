@@ -1,0 +1,136 @@
+// Argument bundles and host launchers of the library's kernels.
+#pragma once
+
+#include "common.h"
+
+namespace ibmg {
+
+// grid-stride reductions use at most this many blocks per component
+constexpr unsigned NORM_BLOCKS = 1024;
+
+// a box of lattice positions: lo[d] .. lo[d] + ext[d] - 1
+struct Box {
+    int lo[3];
+    int ext[3];
+};
+struct VelBox {
+    Box b[3];
+};
+
+template <typename T>
+struct VelArr {
+    T *c[3];
+};
+template <typename T>
+struct VelArrC {
+    const T *c[3];
+};
+
+// pressure operator coefficients: beta = 1 / rho on the D face lattices
+template <typename T>
+struct CoefP {
+    const T *beta[3];
+};
+// viscous operator coefficients: rho on the faces, mu at cells, mu on the
+// edge lattices indexed by their parallel axis (2D: corners in mue[2])
+template <typename T>
+struct CoefU {
+    const T *rho[3];
+    const T *muc;
+    const T *mue[3];
+};
+
+template <typename T>
+inline VelArrC<T> cview(const VelArr<T> &v)
+{
+    return VelArrC<T>{{v.c[0], v.c[1], v.c[2]}};
+}
+
+// ---- multigrid (mg.hip) ----
+template <typename T>
+void launch_smooth_p(const Grid &g, const T *b, T *x, const CoefP<T> &cf, T cvisc, int colour, hipStream_t s);
+template <typename T>
+void launch_smooth_u(const Grid &g, int a, const T *b, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc,
+                     int colour, hipStream_t s);
+template <typename T>
+int launch_resid_p(const Grid &g, const T *b, const T *x, const CoefP<T> &cf, T cvisc, T *r, double *partial,
+                   hipStream_t s);
+template <typename T>
+int launch_resid_u(const Grid &g, const VelArrC<T> &b, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc,
+                   const VelArr<T> &r, double *partial, hipStream_t s);
+template <typename T>
+int launch_norm2(const Grid &g, int ncomp, const int *vmasks, const VelArrC<T> &v, double *partial, hipStream_t s);
+void launch_reduce_final(const double *partial, long long n, double *out, hipStream_t s);
+template <typename T>
+void launch_restrict(const Grid &gf, const Grid &gc, int ncomp, const int *vmasks, int role, bool all_stored,
+                     const VelArrC<T> &fine, const VelArr<T> &coarse, T scale, hipStream_t s);
+template <typename T>
+void launch_prolong_add(const Grid &gc, const Grid &gf, int ncomp, const int *vmasks, int role,
+                        const VelArrC<T> &coarse, const VelArr<T> &fine, hipStream_t s);
+void launch_dense_inverse(const Grid &g, int velocity, int n, const long long *uidx, const int *ucomp,
+                          const CoefP<double> &cp, const CoefU<double> &cu, double mass, double cvisc,
+                          const VelArr<double> &tmp, int singular, double *Aw, double *M, hipStream_t s);
+template <typename T>
+void launch_dense_apply(int n, const long long *uidx, const int *ucomp, const double *M, const VelArrC<T> &b,
+                        const VelArr<T> &x, hipStream_t s);
+template <typename T>
+void launch_fill(T *p, long long n, T v, hipStream_t s);
+template <typename Ts, typename Td>
+void launch_cast_unknowns(const Grid &g, int ncomp, const int *vmasks, const VelArrC<Ts> &src, const VelArr<Td> &dst,
+                          hipStream_t s);
+void launch_add_correction(const Grid &g, int ncomp, const int *vmasks, const VelArrC<float> &e,
+                           const VelArr<double> &x, hipStream_t s);
+
+// ---- fields (fields.hip) ----
+struct Phys {
+    double sigma, eps, inv_re, force_coef, dt;
+    double body_force[3];
+    double rho0, rho_b, d0_pow_d, mu_out, mu_max, omega;
+    int kernel;
+};
+// compact <-> uniform layout of one lattice (vmask), to_uniform selects direction
+void launch_layout(const Grid &g, int vmask, const double *src, double *dst, bool to_uniform, hipStream_t s);
+void launch_momentum_rhs(const Grid &g, const Phys &ph, const VelArrC<double> &u, const CoefU<double> &cf,
+                         const VelArrC<double> &f, const VelArr<double> &b, hipStream_t s);
+void launch_pressure_div(const Grid &g, const Phys &ph, const VelArrC<double> &ut, double *bp, hipStream_t s);
+void launch_add_scalar_cells(const Grid &g, double *v, const double *sum, double scale, hipStream_t s);
+void launch_project(const Grid &g, const Phys &ph, const VelArrC<double> &ut, const double *p,
+                    const CoefP<double> &beta, const VelArr<double> &u, hipStream_t s);
+void launch_copy(const double *src, double *dst, long long n, hipStream_t s);
+void launch_beta_face(const Grid &g, int a, const double *rho, double *beta, hipStream_t s);
+int launch_sum_cells(const Grid &g, const double *v, double *partial, hipStream_t s);
+void launch_to_f32(const double *src, float *dst, long long n, hipStream_t s);
+
+// ---- immersed boundary (ib.hip) ----
+struct Bins {
+    int nb[3];          // bins per axis
+    double bs[3];       // bin width per axis
+    int nbins;
+    int *bin_of;        // [eta] bin of each node
+    int *count;         // [nbins] nodes per bin, then a cursor
+    int *start;         // [nbins + 1] exclusive prefix
+    int *sorted;        // [eta] node ids grouped by bin, ascending within a bin
+};
+void launch_bin_nodes(const Grid &g, const Bins &bins, const double *X, long long stride, int eta, hipStream_t s);
+// spread of the face force (F may be null) and density, or of the viscosity
+// max at cells and edges; kind: 0 faces (axis a), 1 cells, 2 edges (axis c)
+void launch_spread_face(const Grid &g, const Phys &ph, const Bins &bins, const double *X, const double *F,
+                        long long stride, int a, double width, double *f_out, double *rho_out, hipStream_t s);
+void launch_spread_visc(const Grid &g, const Phys &ph, const Bins &bins, const double *X, long long stride, int vmask,
+                        double *mu_out, hipStream_t s);
+void launch_interp(const Grid &g, int kernel, double width, const VelArrC<double> &u, const double *X,
+                   long long xstride, int eta, double *U, long long ustride, hipStream_t s);
+void launch_euler(const Grid &g, double c, const double *U, double *X, long long stride, int eta, hipStream_t s);
+void launch_spring_break(const Grid &g, double ratio, const double *X, long long stride, const int *ij, int m,
+                         const double *rest, unsigned char *alive, int *n_broken, hipStream_t s);
+void launch_spring_force(const Grid &g, const double *X, long long stride, int eta, const int *ij, int m,
+                         const double *rest, const double *K, const unsigned char *alive, const int *inc_start,
+                         const int *inc_list, double *F, hipStream_t s);
+// counting sort of keys[0..n) into buckets [0, nbuckets): start (exclusive
+// prefix, nbuckets + 1 entries) and ids grouped by bucket, ascending in
+// id % mod within a bucket (mod = 0: ascending id)
+void launch_bucket_sort(const int *keys, int n, int nbuckets, int *count, int *start, int *ids, int mod, hipStream_t s);
+void launch_incidence_keys(const int *ij, int m, int *keys, hipStream_t s);
+void launch_count_alive(const unsigned char *alive, int m, int *out, hipStream_t s);
+
+}  // namespace ibmg

@@ -1,0 +1,85 @@
+"""The C interface without a GPU: the library loads, exports every function
+that include/ibmg.h declares, agrees with the oracle on lattice sizes, sizes
+its workspace, and rejects invalid descriptors before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle as O
+from paper_1302_3663_amd import _lib as L
+from paper_1302_3663_amd import ibmg, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "ibmg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ibb_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    lib = L.load()
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in L.ABI_FUNCTIONS, n
+
+
+CASES = [synth.tiny_2d(), synth.tiny_2d(inout=True), synth.tiny_3d(), synth.tiny_3d(periodic_z=True)]
+
+
+@pytest.mark.parametrize("ci", range(len(CASES)))
+def test_lattice_sizes_match_oracle(ci):
+    p = CASES[ci]["params"]
+    assert ibmg.face_counts(p) == O.face_counts(p)
+    assert ibmg.cell_count(p) == O.cell_count(p)
+    assert ibmg.edge_counts(p) == O.edge_counts(p)
+    assert len(CASES[ci]["u0"]) == sum(ibmg.face_counts(p))
+
+
+def test_footprint_grows_with_precision_and_nodes():
+    p = synth.tiny_3d()["params"]
+    a = ibmg.footprint_bytes(p, 10, 10)
+    b = ibmg.footprint_bytes(p, 1000, 10)
+    c = ibmg.footprint_bytes(p, 10, 10, precision=L.IBB_FP32_REFINED, inner_cycles=1)
+    assert 0 < a < b and a < c
+
+
+@pytest.mark.parametrize("field,value", [("dim", 4), ("h", 0.0), ("omega", -1.0), ("nu1", -1), ("kernel", 7),
+                                         ("precision", 5)])
+def test_invalid_descriptor_rejected(field, value):
+    lib = L.load()
+    p = synth.tiny_2d()["params"]
+    d = L.make_desc(p)
+    setattr(d, field, value)
+    n = ctypes.c_size_t()
+    assert lib.ibb_footprint_bytes(ctypes.byref(d), 10, 10, ctypes.byref(n)) == L.IBB_EINVAL
+    ctx = ctypes.c_void_p()
+    buf = ctypes.create_string_buffer(16)
+    assert lib.ibb_create(ctypes.byref(d), 10, 10, ctypes.cast(buf, ctypes.c_void_p), 16, None,
+                          ctypes.byref(ctx)) == L.IBB_EINVAL
+    assert not ctx.value
+
+
+def test_odd_grid_and_small_workspace_rejected():
+    lib = L.load()
+    p = dict(synth.tiny_2d()["params"])
+    p["n"] = [15, 8, 1]
+    d = L.make_desc(p)
+    n = ctypes.c_size_t()
+    assert lib.ibb_footprint_bytes(ctypes.byref(d), 1, 1, ctypes.byref(n)) == L.IBB_EINVAL
+    d = L.make_desc(synth.tiny_2d()["params"])
+    ctx = ctypes.c_void_p()
+    buf = ctypes.create_string_buffer(64)
+    assert lib.ibb_create(ctypes.byref(d), 10, 10, ctypes.cast(buf, ctypes.c_void_p), 64, None,
+                          ctypes.byref(ctx)) == L.IBB_ENOMEM
+
+
+def test_status_strings():
+    lib = L.load()
+    for s in range(7):
+        assert lib.ibb_status_string(s)
