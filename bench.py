@@ -1,0 +1,248 @@
+#!/usr/bin/env python3
+"""Throughput of the biofilm time step on one MI355X.
+
+Workload: the 3D square tube of 64 x 64 x 128 cells (walls on the sides,
+laminar inflow, free outflow) with 5 000 seeded Poisson-disc nodes in a
+Gaussian mound on the bottom wall, springs to neighbours within 2.5 um,
+density ratio 1.05, viscosity ratio 100, V(2,2) cycles to 1e-10 relative
+residual.  One step is the whole path: momentum right-hand side, viscous and
+pressure multigrid solves, projection, interpolation, node move, spring
+breakage and forces, spread, coefficient hierarchy.
+
+The metric is multigrid-solve throughput, unknowns solved per second of
+solve time (device time from right-hand side ready to converged), summed
+over both solves of every timed step; the FP32-refined solver gives `value`,
+the plain FP64 solver is reported beside it.  Step latency percentiles are
+wall-clock per step.  The dominant finest-level kernel is timed live with HIP
+events on the context's stream and set against the HBM roofline using its
+algorithmic bytes per unknown.  The CPU baseline times the FP64 oracle on a
+bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MG solve DOF/s at 1e-10 rel residual, FP32-refined vs FP64; p50/p99 latency"
+
+# kernel classes of ibb_profile_read and their algorithmic bytes per unknown
+# (minimum traffic of one full update or evaluation, in units of the word size)
+CLASS_NAMES = {0: "smooth_u_f64", 1: "smooth_p_f64", 2: "smooth_u_f32", 3: "smooth_p_f32", 4: "resid_u_f64",
+               5: "resid_p_f64"}
+KERNEL_SYMBOLS = {0: "k_smooth_u<double>", 1: "k_smooth_p<double>", 2: "k_smooth_u<float>", 3: "k_smooth_p<float>",
+                  4: "k_resid_u<double>", 5: "k_resid_p<double>"}
+
+
+def words_per_unknown(cls, D):
+    if cls in (0, 2, 4):   # u_a read+write (residual: read + r write), b, rho, mu_c, D-1 mu_e, D-1 u_b
+        return 5 + 2 * (D - 1)
+    return 2 + 1 + D       # p read+write (residual: read + r write), b, D beta
+
+
+def word_size(cls):
+    return 4 if cls in (2, 3) else 8
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(os.path.join(ROOT, "paper_1302_3663_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_1302_3663_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(cls, workload):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{CLASS_NAMES[cls]}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_sha = re.search(r"source_digest:\s*([0-9a-f]+)", text)
+    m_val = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_sha or not m_val or m_sha.group(1) != source_digest():
+        return None
+    return float(m_val.group(1))
+
+
+def percentile(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v), q)) if v else None
+
+
+def run_mode(case, precision, inner, steps, warmup, log):
+    import torch
+
+    from paper_1302_3663_amd import ibmg
+    ctx = ibmg.from_case(case, precision=precision, inner_cycles=inner)
+    for _ in range(warmup):
+        ctx.projection_step()
+        ctx.lagrangian_update()
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step_ms, dof, solve_ms, cyc_u, cyc_p, vcyc, relres = [], 0, 0.0, [], [], [], []
+    for k in range(steps):
+        ts = time.perf_counter()
+        s = ctx.projection_step()
+        ctx.lagrangian_update()
+        step_ms.append((time.perf_counter() - ts) * 1e3)
+        dof += s["dof_u"] + s["dof_p"]
+        solve_ms += s["t_u_ms"] + s["t_p_ms"]
+        cyc_u.append(s["cycles_u"])
+        cyc_p.append(s["cycles_p"])
+        vcyc.append(s["vcycles_u"] + s["vcycles_p"])
+        relres.append(max(s["relres_u"], s["relres_p"]))
+        log(f"  step {k}: {step_ms[-1]:.2f} ms, cycles u {s['cycles_u']} p {s['cycles_p']}, "
+            f"solve {s['t_u_ms'] + s['t_p_ms']:.2f} ms")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = {cls: ctx.profile_read(cls) for cls in CLASS_NAMES}
+    ctx.profile_enable(False)
+    ctx.close()
+    return dict(dof_per_s=dof / (solve_ms / 1e3), wall_s=wall, ms_per_step=wall * 1e3 / steps, solve_ms=solve_ms,
+                dof_total=dof, step_ms=step_ms, cycles_u=cyc_u, cycles_p=cyc_p, vcycles=vcyc,
+                max_relres=max(relres), prof=prof)
+
+
+def cpu_baseline(case, log):
+    """The FP64 oracle on one viscous and one pressure solve of the first step."""
+    import numpy as np
+
+    import oracle as O
+    p = case["params"]
+    X = case["X"]
+    F, _, _ = O.springs(p, X, case["ij"], case["rest"], case["K"], np.ones(case["ij"].shape[1], np.uint8),
+                        do_break=False)
+    f = O.spread_vec(p, p["omega"], X, F)
+    rho, mc, me = O.density(p, X), O.viscosity_cells(p, X), O.viscosity_edges(p, X)
+    H = O.Hierarchy(p, rho, mc, me)
+    b = O.momentum_rhs(p, case["u0"], rho, mc, me, f)
+    t0 = time.perf_counter()
+    ut, su = H.solve(True, b, case["u0"])
+    t1 = time.perf_counter()
+    bp = O.pressure_rhs(p, ut)
+    t2 = time.perf_counter()
+    _, sp = H.solve(False, bp, case["p0"])
+    t3 = time.perf_counter()
+    dof = H.nunk[0][0] + H.nunk[0][1]
+    secs = (t1 - t0) + (t3 - t2)
+    log(f"  oracle: viscous {t1 - t0:.1f} s ({su['cycles']} cycles), pressure {t3 - t2:.1f} s ({sp['cycles']} cycles)")
+    return dict(value=dof / secs, unit="DOF/s", cores=1, kind="oracle",
+                sample="one viscous and one pressure solve (FP64, V(2,2) to 1e-10) of the first step of the "
+                       f"same workload, {secs:.1f} s single-threaded")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--inner", type=int, default=2, help="FP32 V-cycles per FP64 outer iteration")
+    ap.add_argument("--modes", default="both", choices=["both", "fp64", "refined"])
+    ap.add_argument("--workload", default="tube3d_64x64x128")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
+                    help="also run a plain device copy of this size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
+        sys.exit(2)
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    import numpy as np
+    import torch
+
+    import paper_1302_3663_amd as pkg
+    from paper_1302_3663_amd import synth
+    pkg.load()   # raises when the HIP library is missing: there is no fallback
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    log(f"workload {args.workload}: generating inputs")
+    case = synth.WORKLOADS[args.workload]()
+    p = case["params"]
+    modes = {"both": ["fp64", "refined"], "fp64": ["fp64"], "refined": ["refined"]}[args.modes]
+    res = {}
+    for m in modes:
+        log(f"mode {m}: {args.warmup} warmup + {args.steps} timed steps")
+        res[m] = run_mode(case, pkg.IBB_FP32_REFINED if m == "refined" else pkg.IBB_FP64, args.inner, args.steps,
+                          args.warmup, log)
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy * (1 << 20) // 4
+        a = torch.empty(n, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 5 copies of {args.calibrate_copy} MiB")
+    head = res["refined"] if "refined" in res else res["fp64"]
+    head_mode = "refined" if "refined" in res else "fp64"
+    # roofline of the dominant finest-level kernel of the headline mode
+    D = p["dim"]
+    dom = max(head["prof"], key=lambda c: head["prof"][c]["total_ms"])
+    pr = head["prof"][dom]
+    bpu = words_per_unknown(dom, D) * word_size(dom)
+    per_launch_bytes = bpu * pr["units"] / max(pr["launches"], 1)
+    avg_ms = pr["total_ms"] / max(pr["launches"], 1)
+    achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
+    traffic = committed_traffic(dom, args.workload)
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=KERNEL_SYMBOLS[dom],
+                avg_launch_us=round(avg_ms * 1e3, 2), launches=pr["launches"],
+                algorithmic_bytes_per_launch=int(per_launch_bytes), bytes_per_unknown=bpu)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle")
+        cpu = cpu_baseline(case, log)
+    all_steps = head["step_ms"]
+    out = {
+        "metric": METRIC,
+        "value": round(head["dof_per_s"], 1),
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-inner/f64-outer" if head_mode == "refined" else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "grid": p["n"][:p["dim"]], "nodes": int(case["X"].shape[1]),
+                   "springs": int(case["ij"].shape[1]), "viscosity_ratio": p["mu_max"] / p["mu_out"],
+                   "density_ratio": (p["rho0"] + p["rho_b"]) / p["rho0"], "rtol": p["rtol"],
+                   "nu": [p["nu1"], p["nu2"]], "precision": head_mode,
+                   "inner_cycles": args.inner if head_mode == "refined" else None},
+        "p50_step_ms": round(percentile(all_steps, 50), 3),
+        "p99_step_ms": round(percentile(all_steps, 99), 3),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    for m in res:
+        r = res[m]
+        out[m] = dict(dof_per_s=round(r["dof_per_s"], 1), ms_per_step=round(r["ms_per_step"], 3),
+                      solve_ms_per_step=round(r["solve_ms"] / args.steps, 3),
+                      mean_cycles_u=float(np.mean(r["cycles_u"])), mean_cycles_p=float(np.mean(r["cycles_p"])),
+                      mean_vcycles=float(np.mean(r["vcycles"])), max_relres=r["max_relres"],
+                      p50_step_ms=round(percentile(r["step_ms"], 50), 3),
+                      p99_step_ms=round(percentile(r["step_ms"], 99), 3),
+                      kernels={CLASS_NAMES[c]: dict(launches=v["launches"], avg_us=round(
+                          1e3 * v["total_ms"] / max(v["launches"], 1), 2), total_ms=round(v["total_ms"], 3))
+                          for c, v in r["prof"].items() if v["launches"]})
+    if "fp64" in res and "refined" in res:
+        out["refined_over_fp64"] = round(res["refined"]["dof_per_s"] / res["fp64"]["dof_per_s"], 3)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -115,6 +115,9 @@ ABI_FUNCTIONS = {
     "ibb_spread": (ctypes.c_int, [CTX, ctypes.c_double, I64, VP, VP, VP]),
     "ibb_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ibb_last_error": (ctypes.c_char_p, [CTX]),
+    "ibb_profile_enable": (ctypes.c_int, [CTX, ctypes.c_int]),
+    "ibb_profile_read": (ctypes.c_int, [CTX, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong),
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
     "ibb_level_info": (ctypes.c_int, [CTX, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
 }
 

@@ -79,6 +79,15 @@ struct ibb_ctx {
     int *counters = nullptr;
     bool have_nodes = false, have_springs = false, have_coefs = false;
     hipEvent_t ev[4] = {};
+    // finest-level kernel timing (ibb_profile_*)
+    bool prof = false;
+    std::vector<hipEvent_t> pev;           // pairs: start, stop
+    std::vector<int> pcls;                 // class of each recorded pair
+    std::vector<long long> punits;         // unknowns of each recorded pair
+    int pused = 0;
+    long long plaunch[8] = {};
+    double pms[8] = {};
+    long long punit_tot[8] = {};
     std::string err;
 };
 
@@ -98,6 +107,40 @@ ibb_status fail(ibb_ctx *c, ibb_status st, const char *msg)
             return IBB_EDEVICE;                                                              \
         }                                                                                    \
     } while (0)
+
+constexpr int PROF_PAIRS = 2048;
+
+// start a timed launch of class cls: returns the pair slot or -1
+int prof_begin(ibb_ctx *c, int cls, long long units)
+{
+    if (!c->prof || c->pused >= PROF_PAIRS) return -1;
+    const int k = c->pused++;
+    c->pcls[k] = cls;
+    c->punits[k] = units;
+    (void)hipEventRecord(c->pev[2 * k], c->s);
+    return k;
+}
+
+void prof_end(ibb_ctx *c, int k)
+{
+    if (k >= 0) (void)hipEventRecord(c->pev[2 * k + 1], c->s);
+}
+
+// fold the recorded pairs into the totals (synchronises on the last event)
+void prof_flush(ibb_ctx *c)
+{
+    if (!c->prof || c->pused == 0) return;
+    (void)hipEventSynchronize(c->pev[2 * (c->pused - 1) + 1]);
+    for (int k = 0; k < c->pused; ++k) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, c->pev[2 * k], c->pev[2 * k + 1]) == hipSuccess) {
+            c->plaunch[c->pcls[k]] += 1;
+            c->pms[c->pcls[k]] += ms;
+            c->punit_tot[c->pcls[k]] += c->punits[k];
+        }
+    }
+    c->pused = 0;
+}
 
 ibb_status check_desc(const ibb_desc *d)
 {
@@ -357,12 +400,20 @@ void sweep(ibb_ctx *c, bool vel, int l)
     const T cvp = (T)(1.0 / (L.g.h * L.g.h));
     const T cvu = (T)(c->d.inv_re / (L.g.h * L.g.h));
     const T mass = (T)(c->d.sigma / c->d.dt);
+    const int cls = (vel ? 0 : 1) + (sizeof(T) == 4 ? 2 : 0);
     if (vel) {
         for (int a = 0; a < c->d.dim; ++a)
-            for (int colour = 0; colour < 2; ++colour)
+            for (int colour = 0; colour < 2; ++colour) {
+                const int k = l == 0 ? prof_begin(c, cls, unknowns_of(L.g, face_mask(a)) / 2) : -1;
                 launch_smooth_u<T>(L.g, a, v.bu.c[a], v.xu, v.cu, mass, cvu, colour, c->s);
+                prof_end(c, k);
+            }
     } else {
-        for (int colour = 0; colour < 2; ++colour) launch_smooth_p<T>(L.g, v.bp, v.xp, v.cp, cvp, colour, c->s);
+        for (int colour = 0; colour < 2; ++colour) {
+            const int k = l == 0 ? prof_begin(c, cls, L.np / 2) : -1;
+            launch_smooth_p<T>(L.g, v.bp, v.xp, v.cp, cvp, colour, c->s);
+            prof_end(c, k);
+        }
     }
 }
 
@@ -407,13 +458,12 @@ void vcycle(ibb_ctx *c, bool vel, int l)
     Level &C = c->lv[l + 1];
     View<T> w = view<T>(C);
     if (vel) {
-        launch_restrict<T>(L.g, C.g, D, vm, ROLE_V, false, cview(v.ru), w.bu, (T)1, c->s);
-        for (int a = 0; a < D; ++a) launch_fill<T>(w.xu.c[a], C.g.nel, (T)0, c->s);
+        launch_restrict<T>(L.g, C.g, D, vm, ROLE_V, false, cview(v.ru), w.bu, (T)1, c->s, &w.xu);
     } else {
         VelArrC<T> rf{{v.rp, nullptr, nullptr}};
         VelArr<T> bc{{w.bp, nullptr, nullptr}};
-        launch_restrict<T>(L.g, C.g, 1, pm, ROLE_P, false, rf, bc, (T)1, c->s);
-        launch_fill<T>(w.xp, C.g.nel, (T)0, c->s);
+        VelArr<T> xc{{w.xp, nullptr, nullptr}};
+        launch_restrict<T>(L.g, C.g, 1, pm, ROLE_P, false, rf, bc, (T)1, c->s, &xc);
     }
     vcycle<T>(c, vel, l + 1);
     if (vel) {
@@ -452,7 +502,9 @@ ibb_status norm_b(ibb_ctx *c, bool vel, double *out)
 
 ibb_status resid_norm(ibb_ctx *c, bool vel, double *out)
 {
+    const int k = prof_begin(c, vel ? 4 : 5, vel ? c->lv[0].nu : c->lv[0].np);
     const int np = residual<double>(c, vel, 0, c->partial);
+    prof_end(c, k);
     double s2;
     ibb_status st = read_scalar(c, np, &s2);
     *out = sqrt(s2);
@@ -551,9 +603,11 @@ ibb_status solve(ibb_ctx *c, bool vel, int max_cycles, int exact, SolveOut *o)
         one_iteration();
         o->cycles++;
         if ((st = resid_norm(c, vel, &rn))) return st;
+        prof_flush(c);
         rel = rn / nb;
     }
     o->relres = rel;
+    prof_flush(c);
     return IBB_OK;
 }
 
@@ -781,6 +835,8 @@ ibb_status ibb_destroy(ibb_ctx *c)
     (void)hipStreamSynchronize(c->s);
     for (int i = 0; i < 4; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    for (auto &e : c->pev)
+        if (e) (void)hipEventDestroy(e);
     delete c;
     return IBB_OK;
 }
@@ -1064,6 +1120,36 @@ ibb_status ibb_spread(ibb_ctx *c, double width, int64_t n, const double *X, cons
         launch_spread_face(L0.g, c->ph, b, X, F, n > 0 ? n : 1, a, width, L0.ru[a], nullptr, c->s);
     faces_out(c, 0, L0.ru, out);
     HIPCHK(hipGetLastError());
+    return IBB_OK;
+}
+
+ibb_status ibb_profile_enable(ibb_ctx *c, int enable)
+{
+    if (!c) return IBB_EINVAL;
+    prof_flush(c);
+    if (enable && c->pev.empty()) {
+        c->pev.resize(2 * PROF_PAIRS);
+        c->pcls.resize(PROF_PAIRS);
+        c->punits.resize(PROF_PAIRS);
+        for (auto &e : c->pev) HIPCHK(hipEventCreate(&e));
+    }
+    c->prof = enable != 0;
+    c->pused = 0;
+    for (int i = 0; i < 8; ++i) {
+        c->plaunch[i] = 0;
+        c->pms[i] = 0.0;
+        c->punit_tot[i] = 0;
+    }
+    return IBB_OK;
+}
+
+ibb_status ibb_profile_read(ibb_ctx *c, int kernel_class, long long *launches, double *total_ms, long long *units)
+{
+    if (!c || kernel_class < 0 || kernel_class >= 8) return IBB_EINVAL;
+    prof_flush(c);
+    if (launches) *launches = c->plaunch[kernel_class];
+    if (total_ms) *total_ms = c->pms[kernel_class];
+    if (units) *units = c->punit_tot[kernel_class];
     return IBB_OK;
 }
 

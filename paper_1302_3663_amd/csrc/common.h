@@ -125,6 +125,16 @@ __device__ inline T load_ref(const T *__restrict__ v, Ref r)
     return r.s == 0 ? T(0) : (r.s > 0 ? v[r.idx] : -v[r.idx]);
 }
 
+// The same value through an unconditional load: a reference to a fixed
+// zero still points at a valid entry (index 0), so every load of a row can
+// be issued together and the sign is applied afterwards.
+template <typename T>
+__device__ inline T ld(const T *__restrict__ v, Ref r)
+{
+    const T x = v[r.idx];
+    return r.s == 0 ? T(0) : (r.s > 0 ? x : -x);
+}
+
 // lattice masks
 __host__ __device__ inline int face_mask(int a) { return 1 << a; }
 __host__ __device__ inline int edge_mask(int D, int c) { return ((1 << D) - 1) & ~(1 << c); }

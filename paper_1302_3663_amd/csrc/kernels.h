@@ -17,6 +17,17 @@ struct VelBox {
     Box b[3];
 };
 
+// A box split into an inner box (part 0: every neighbour of every point is
+// reached at a fixed offset) and up to six boundary slabs.  off[p] counts the
+// threads of parts before p; a launch covers off[n] threads, so the
+// wavefronts of the inner part never take the boundary path.
+struct PBox {
+    Box b[7];
+    int off[8];   // off[n] is the total thread count
+    int n;        // parts in use
+    int inner;    // part 0 is the inner box
+};
+
 template <typename T>
 struct VelArr {
     T *c[3];
@@ -61,9 +72,11 @@ int launch_resid_u(const Grid &g, const VelArrC<T> &b, const VelArr<T> &x, const
 template <typename T>
 int launch_norm2(const Grid &g, int ncomp, const int *vmasks, const VelArrC<T> &v, double *partial, hipStream_t s);
 void launch_reduce_final(const double *partial, long long n, double *out, hipStream_t s);
+// zero_x (may be null): coarse arrays cleared at the restricted positions
 template <typename T>
 void launch_restrict(const Grid &gf, const Grid &gc, int ncomp, const int *vmasks, int role, bool all_stored,
-                     const VelArrC<T> &fine, const VelArr<T> &coarse, T scale, hipStream_t s);
+                     const VelArrC<T> &fine, const VelArr<T> &coarse, T scale, hipStream_t s,
+                     const VelArr<T> *zero_x = nullptr);
 template <typename T>
 void launch_prolong_add(const Grid &gc, const Grid &gf, int ncomp, const int *vmasks, int role,
                         const VelArrC<T> &coarse, const VelArr<T> &fine, hipStream_t s);

@@ -16,159 +16,207 @@
 namespace ibmg {
 
 // ---------------------------------------------------------------------------
-// rows of the two operators: (A x) at one unknown and the diagonal entry
+// rows of the two operators: (A x) at one unknown and the diagonal entry.
+// Templated on the dimension D and (viscous) the component A so that every
+// loop unrolls and all loads of a row issue together.
 // ---------------------------------------------------------------------------
 __device__ inline int self_sign(Ref r, long long c) { return (r.s != 0 && r.idx == c) ? r.s : 0; }
 
-template <typename T>
-__device__ inline void p_row_fast(const Grid &g, const T *__restrict__ x, const CoefP<T> &cf, T cvisc, long long c,
-                                  T &Ax, T &dg)
+// the bi-th axis other than A
+template <int A>
+__device__ constexpr int other_axis(int bi) { return bi < A ? bi : bi + 1; }
+
+template <typename T, int D>
+__device__ inline void p_row_fast(const Grid &g, const T *__restrict__ x, const CoefP<T> &cf, T cvisc, int c, T &Ax,
+                                  T &dg)
 {
+    const int st[3] = {1, g.NX, (int)g.NXY};
+    T xn[2 * D], bt[2 * D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        xn[2 * a] = x[c + st[a]];
+        xn[2 * a + 1] = x[c - st[a]];
+        bt[2 * a] = cf.beta[a][c + st[a]];
+        bt[2 * a + 1] = cf.beta[a][c];
+    }
     const T xc = x[c];
     T acc = 0, d = 0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        if (a >= g.D) break;
-        const long long s = stride_of(g, a);
-        const T bp = cf.beta[a][c + s], bm = cf.beta[a][c];
-        acc += bp * (xc - x[c + s]) + bm * (xc - x[c - s]);
-        d += bp + bm;
+    for (int a = 0; a < D; ++a) {
+        acc += bt[2 * a] * (xc - xn[2 * a]) + bt[2 * a + 1] * (xc - xn[2 * a + 1]);
+        d += bt[2 * a] + bt[2 * a + 1];
     }
     Ax = acc * cvisc;
     dg = d * cvisc;
 }
 
-template <typename T>
+template <typename T, int D>
 __device__ inline void p_row_slow(const Grid &g, const T *__restrict__ x, const CoefP<T> &cf, T cvisc, int i, int j,
                                   int k, T &Ax, T &dg)
 {
     const long long c = at(g, i, j, k);
-    const T xc = x[c];
-    T acc = 0, d = 0;
-    for (int a = 0; a < g.D; ++a) {
+    Ref rb[2 * D], rx[2 * D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
         int qp[3] = {i, j, k}, qm[3] = {i, j, k};
         qp[a] += 1;
         qm[a] -= 1;
-        const T bp = load_ref(cf.beta[a], ref_at(g, face_mask(a), ROLE_C, qp[0], qp[1], qp[2]));
-        const T bm = load_ref(cf.beta[a], ref_at(g, face_mask(a), ROLE_C, i, j, k));
-        const Ref rp = ref_at(g, 0, ROLE_P, qp[0], qp[1], qp[2]);
-        const Ref rm = ref_at(g, 0, ROLE_P, qm[0], qm[1], qm[2]);
-        acc += bp * (xc - load_ref(x, rp)) + bm * (xc - load_ref(x, rm));
-        d += bp * T(1 - self_sign(rp, c)) + bm * T(1 - self_sign(rm, c));
+        rb[2 * a] = ref_at(g, face_mask(a), ROLE_C, qp[0], qp[1], qp[2]);
+        rb[2 * a + 1] = ref_at(g, face_mask(a), ROLE_C, i, j, k);
+        rx[2 * a] = ref_at(g, 0, ROLE_P, qp[0], qp[1], qp[2]);
+        rx[2 * a + 1] = ref_at(g, 0, ROLE_P, qm[0], qm[1], qm[2]);
+    }
+    T bt[2 * D], xn[2 * D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        bt[2 * a] = ld(cf.beta[a], rb[2 * a]);
+        bt[2 * a + 1] = ld(cf.beta[a], rb[2 * a + 1]);
+        xn[2 * a] = ld(x, rx[2 * a]);
+        xn[2 * a + 1] = ld(x, rx[2 * a + 1]);
+    }
+    const T xc = x[c];
+    T acc = 0, d = 0;
+#pragma unroll
+    for (int t = 0; t < 2 * D; ++t) {
+        acc += bt[t] * (xc - xn[t]);
+        d += bt[t] * T(1 - self_sign(rx[t], c));
     }
     Ax = acc * cvisc;
     dg = d * cvisc;
 }
 
-template <typename T>
-__device__ inline bool p_interior(const Grid &g, int i, int j, int k)
+template <typename T, int D, int A>
+__device__ inline void u_row_fast(const Grid &g, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc, int f, T &Ax,
+                                  T &dg)
 {
-    const int q[3] = {i, j, k};
-    for (int a = 0; a < g.D; ++a)
-        if (q[a] < 1 || q[a] > g.n[a] - 2) return false;
-    return true;
-}
-
-template <typename T>
-__device__ inline void p_row(const Grid &g, const T *__restrict__ x, const CoefP<T> &cf, T cvisc, int i, int j, int k,
-                             T &Ax, T &dg)
-{
-    if (p_interior<T>(g, i, j, k)) p_row_fast<T>(g, x, cf, cvisc, at(g, i, j, k), Ax, dg);
-    else p_row_slow<T>(g, x, cf, cvisc, i, j, k, Ax, dg);
-}
-
-template <typename T>
-__device__ inline void u_row_fast(const Grid &g, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc, int a,
-                                  long long f, T &Ax, T &dg)
-{
-    const T *__restrict__ ua = x.c[a];
-    const long long sa = stride_of(g, a);
+    const int st[3] = {1, g.NX, (int)g.NXY};
+    const int sa = st[A];
+    const T *__restrict__ ua = x.c[A];
     const T xf = ua[f];
     const T cp = T(2) * cf.muc[f], cm = T(2) * cf.muc[f - sa];
-    T acc = cp * (ua[f + sa] - xf) - cm * (xf - ua[f - sa]);
+    const T vp = ua[f + sa], vm = ua[f - sa];
+    const T rho = cf.rho[A][f];
+    T mp[D - 1], mm[D - 1], ap[D - 1], am[D - 1], b0[D - 1], b1[D - 1], b2[D - 1], b3[D - 1];
+#pragma unroll
+    for (int bi = 0; bi < D - 1; ++bi) {
+        const int B = other_axis<A>(bi);
+        const int sb = st[B];
+        const T *__restrict__ ub = x.c[B];
+        const T *__restrict__ me = cf.mue[3 - A - B];
+        mp[bi] = me[f + sb];
+        mm[bi] = me[f];
+        ap[bi] = ua[f + sb];
+        am[bi] = ua[f - sb];
+        b0[bi] = ub[f + sb];
+        b1[bi] = ub[f + sb - sa];
+        b2[bi] = ub[f];
+        b3[bi] = ub[f - sa];
+    }
+    T acc = cp * (vp - xf) - cm * (xf - vm);
     T d = cp + cm;
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
-        if (b >= g.D) break;
-        if (b == a) continue;
-        const long long sb = stride_of(g, b);
-        const T *__restrict__ ub = x.c[b];
-        const T *__restrict__ me = cf.mue[3 - a - b];
-        const T mp = me[f + sb], mm = me[f];
-        acc += mp * ((ua[f + sb] - xf) + (ub[f + sb] - ub[f + sb - sa])) -
-               mm * ((xf - ua[f - sb]) + (ub[f] - ub[f - sa]));
-        d += mp + mm;
+    for (int bi = 0; bi < D - 1; ++bi) {
+        acc += mp[bi] * ((ap[bi] - xf) + (b0[bi] - b1[bi])) - mm[bi] * ((xf - am[bi]) + (b2[bi] - b3[bi]));
+        d += mp[bi] + mm[bi];
     }
-    const T m = mass * cf.rho[a][f];
+    const T m = mass * rho;
     Ax = m * xf - cvisc * acc;
     dg = m + cvisc * d;
 }
 
-template <typename T>
-__device__ inline void u_row_slow(const Grid &g, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc, int a, int i,
-                                  int j, int k, T &Ax, T &dg)
+template <typename T, int D, int A>
+__device__ inline void u_row_slow(const Grid &g, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc, int i, int j,
+                                  int k, T &Ax, T &dg)
 {
     const int q[3] = {i, j, k};
     const long long f = at(g, i, j, k);
-    const T *__restrict__ ua = x.c[a];
-    const int ma = face_mask(a);
-    const T xf = ua[f];
-    int qa_p[3] = {i, j, k}, qa_m[3] = {i, j, k};
-    qa_p[a] += 1;
-    qa_m[a] -= 1;
-    // viscosity at the cells right (index q) and left (q - e_a) of the face
-    const T cp = T(2) * load_ref(cf.muc, ref_at(g, 0, ROLE_C, i, j, k));
-    const T cm = T(2) * load_ref(cf.muc, ref_at(g, 0, ROLE_C, qa_m[0], qa_m[1], qa_m[2]));
+    const int ma = face_mask(A);
+    int qa_m[3] = {i, j, k}, qa_p[3] = {i, j, k};
+    qa_m[A] -= 1;
+    qa_p[A] += 1;
+    // resolve every reference first (arithmetic only)
+    const Ref rcp = ref_at(g, 0, ROLE_C, i, j, k);
+    const Ref rcm = ref_at(g, 0, ROLE_C, qa_m[0], qa_m[1], qa_m[2]);
     const Ref rvp = ref_at(g, ma, ROLE_V, qa_p[0], qa_p[1], qa_p[2]);
     const Ref rvm = ref_at(g, ma, ROLE_V, qa_m[0], qa_m[1], qa_m[2]);
-    T acc = cp * (load_ref(ua, rvp) - xf) - cm * (xf - load_ref(ua, rvm));
-    T d = cp * T(1 - self_sign(rvp, f)) + cm * T(1 - self_sign(rvm, f));
-    for (int b = 0; b < g.D; ++b) {
-        if (b == a) continue;
-        const int c = 3 - a - b;
-        const int mb = face_mask(b), me_mask = edge_mask(g.D, c);
-        const T *__restrict__ ub = x.c[b];
-        const T *__restrict__ me = cf.mue[c];
+    Ref rmp[D - 1], rmm[D - 1], rap[D - 1], ram[D - 1], r0[D - 1], r1[D - 1], r2[D - 1], r3[D - 1];
+#pragma unroll
+    for (int bi = 0; bi < D - 1; ++bi) {
+        const int B = other_axis<A>(bi);
+        const int c = 3 - A - B;
+        const int mb = face_mask(B), mem = edge_mask(D, c);
         int qb_p[3] = {q[0], q[1], q[2]}, qb_m[3] = {q[0], q[1], q[2]};
-        qb_p[b] += 1;
-        qb_m[b] -= 1;
+        qb_p[B] += 1;
+        qb_m[B] -= 1;
         int qbp_am[3] = {qb_p[0], qb_p[1], qb_p[2]};
-        qbp_am[a] -= 1;
-        // edges above (q + e_b) and below (q) along b
-        const T mp = load_ref(me, ref_at(g, me_mask, ROLE_C, qb_p[0], qb_p[1], qb_p[2]));
-        const T mm = load_ref(me, ref_at(g, me_mask, ROLE_C, i, j, k));
-        const Ref rap = ref_at(g, ma, ROLE_V, qb_p[0], qb_p[1], qb_p[2]);
-        const Ref ram = ref_at(g, ma, ROLE_V, qb_m[0], qb_m[1], qb_m[2]);
-        const T ubpp = load_ref(ub, ref_at(g, mb, ROLE_V, qb_p[0], qb_p[1], qb_p[2]));
-        const T ubpm = load_ref(ub, ref_at(g, mb, ROLE_V, qbp_am[0], qbp_am[1], qbp_am[2]));
-        const T ub0p = load_ref(ub, ref_at(g, mb, ROLE_V, i, j, k));
-        const T ub0m = load_ref(ub, ref_at(g, mb, ROLE_V, qa_m[0], qa_m[1], qa_m[2]));
-        acc += mp * ((load_ref(ua, rap) - xf) + (ubpp - ubpm)) - mm * ((xf - load_ref(ua, ram)) + (ub0p - ub0m));
-        d += mp * T(1 - self_sign(rap, f)) + mm * T(1 - self_sign(ram, f));
+        qbp_am[A] -= 1;
+        rmp[bi] = ref_at(g, mem, ROLE_C, qb_p[0], qb_p[1], qb_p[2]);
+        rmm[bi] = ref_at(g, mem, ROLE_C, i, j, k);
+        rap[bi] = ref_at(g, ma, ROLE_V, qb_p[0], qb_p[1], qb_p[2]);
+        ram[bi] = ref_at(g, ma, ROLE_V, qb_m[0], qb_m[1], qb_m[2]);
+        r0[bi] = ref_at(g, mb, ROLE_V, qb_p[0], qb_p[1], qb_p[2]);
+        r1[bi] = ref_at(g, mb, ROLE_V, qbp_am[0], qbp_am[1], qbp_am[2]);
+        r2[bi] = ref_at(g, mb, ROLE_V, i, j, k);
+        r3[bi] = ref_at(g, mb, ROLE_V, qa_m[0], qa_m[1], qa_m[2]);
     }
-    const T m = mass * cf.rho[a][f];
+    // then every load
+    const T *__restrict__ ua = x.c[A];
+    const T xf = ua[f];
+    const T rho = cf.rho[A][f];
+    const T cp = T(2) * ld(cf.muc, rcp), cm = T(2) * ld(cf.muc, rcm);
+    const T vp = ld(ua, rvp), vm = ld(ua, rvm);
+    T mp[D - 1], mm[D - 1], ap[D - 1], am[D - 1], b0[D - 1], b1[D - 1], b2[D - 1], b3[D - 1];
+#pragma unroll
+    for (int bi = 0; bi < D - 1; ++bi) {
+        const int B = other_axis<A>(bi);
+        const T *__restrict__ ub = x.c[B];
+        const T *__restrict__ me = cf.mue[3 - A - B];
+        mp[bi] = ld(me, rmp[bi]);
+        mm[bi] = ld(me, rmm[bi]);
+        ap[bi] = ld(ua, rap[bi]);
+        am[bi] = ld(ua, ram[bi]);
+        b0[bi] = ld(ub, r0[bi]);
+        b1[bi] = ld(ub, r1[bi]);
+        b2[bi] = ld(ub, r2[bi]);
+        b3[bi] = ld(ub, r3[bi]);
+    }
+    T acc = cp * (vp - xf) - cm * (xf - vm);
+    T d = cp * T(1 - self_sign(rvp, f)) + cm * T(1 - self_sign(rvm, f));
+#pragma unroll
+    for (int bi = 0; bi < D - 1; ++bi) {
+        acc += mp[bi] * ((ap[bi] - xf) + (b0[bi] - b1[bi])) - mm[bi] * ((xf - am[bi]) + (b2[bi] - b3[bi]));
+        d += mp[bi] * T(1 - self_sign(rap[bi], f)) + mm[bi] * T(1 - self_sign(ram[bi], f));
+    }
+    const T m = mass * rho;
     Ax = m * xf - cvisc * acc;
     dg = m + cvisc * d;
 }
 
-__device__ inline bool u_interior(const Grid &g, int i, int j, int k)
+// runtime-dimension entry points (coarsest dense assembly)
+template <typename T>
+__device__ inline void p_row_slow_any(const Grid &g, const T *x, const CoefP<T> &cf, T cvisc, int i, int j, int k, T &Ax,
+                                      T &dg)
 {
-    const int q[3] = {i, j, k};
-    for (int a = 0; a < g.D; ++a)
-        if (q[a] < 2 || q[a] > g.n[a] - 2) return false;
-    return true;
+    if (g.D == 3) p_row_slow<T, 3>(g, x, cf, cvisc, i, j, k, Ax, dg);
+    else p_row_slow<T, 2>(g, x, cf, cvisc, i, j, k, Ax, dg);
 }
 
 template <typename T>
-__device__ inline void u_row(const Grid &g, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc, int a, int i,
-                             int j, int k, T &Ax, T &dg)
+__device__ inline void u_row_slow_any(const Grid &g, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc, int a,
+                                      int i, int j, int k, T &Ax, T &dg)
 {
-    if (u_interior(g, i, j, k)) u_row_fast<T>(g, x, cf, mass, cvisc, a, at(g, i, j, k), Ax, dg);
-    else u_row_slow<T>(g, x, cf, mass, cvisc, a, i, j, k, Ax, dg);
+    if (g.D == 3) {
+        if (a == 0) u_row_slow<T, 3, 0>(g, x, cf, mass, cvisc, i, j, k, Ax, dg);
+        else if (a == 1) u_row_slow<T, 3, 1>(g, x, cf, mass, cvisc, i, j, k, Ax, dg);
+        else u_row_slow<T, 3, 2>(g, x, cf, mass, cvisc, i, j, k, Ax, dg);
+    } else {
+        if (a == 0) u_row_slow<T, 2, 0>(g, x, cf, mass, cvisc, i, j, k, Ax, dg);
+        else u_row_slow<T, 2, 1>(g, x, cf, mass, cvisc, i, j, k, Ax, dg);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// index helpers: unknown boxes and their colour classes
+// index helpers: unknown boxes, their colour classes and partitions
 // ---------------------------------------------------------------------------
 __host__ __device__ inline Box unk_box(const Grid &g, int vmask)
 {
@@ -182,58 +230,145 @@ __host__ __device__ inline Box unk_box(const Grid &g, int vmask)
     return b;
 }
 
-__device__ inline bool box_pos(const Box &b, long long t, int &i, int &j, int &k)
+__host__ __device__ inline bool box_pos(const Box &b, int t, int &i, int &j, int &k)
 {
-    const long long n = (long long)b.ext[0] * b.ext[1] * b.ext[2];
+    const int n = b.ext[0] * b.ext[1] * b.ext[2];
     if (t >= n) return false;
-    i = b.lo[0] + (int)(t % b.ext[0]);
+    i = b.lo[0] + t % b.ext[0];
     t /= b.ext[0];
-    j = b.lo[1] + (int)(t % b.ext[1]);
-    k = b.lo[2] + (int)(t / b.ext[1]);
+    j = b.lo[1] + t % b.ext[1];
+    k = b.lo[2] + t / b.ext[1];
     return true;
 }
 
 // t-th point of colour `colour` ((i + j + k) mod 2) in the box
-__device__ inline bool box_colour_pos(const Box &b, int colour, long long t, int &i, int &j, int &k)
+__host__ __device__ inline bool box_colour_pos(const Box &b, int colour, int t, int &i, int &j, int &k)
 {
     const int half = (b.ext[0] + 1) >> 1;
-    const long long n = (long long)half * b.ext[1] * b.ext[2];
-    if (t >= n) return false;
-    const int ih = (int)(t % half);
+    if (t >= half * b.ext[1] * b.ext[2]) return false;
+    const int ih = t % half;
     t /= half;
-    j = b.lo[1] + (int)(t % b.ext[1]);
-    k = b.lo[2] + (int)(t / b.ext[1]);
+    j = b.lo[1] + t % b.ext[1];
+    k = b.lo[2] + t / b.ext[1];
     i = b.lo[0] + 2 * ih + ((b.lo[0] + j + k + colour) & 1);
     return i < b.lo[0] + b.ext[0];
+}
+
+// position of thread t in a partitioned box; inner is true for part 0 when
+// the partition has an inner box.  colour < 0: every point.
+__host__ __device__ inline bool pbox_pos(const PBox &P, int colour, int t, int &i, int &j, int &k, bool &inner)
+{
+    if (t >= P.off[P.n]) return false;
+    int p = 0;
+    while (p + 1 < P.n && t >= P.off[p + 1]) ++p;
+    inner = p == 0 && P.inner;
+    const int tl = t - P.off[p];
+    return colour < 0 ? box_pos(P.b[p], tl, i, j, k) : box_colour_pos(P.b[p], colour, tl, i, j, k);
+}
+
+// Split `full` into the inner box [ilo, ihi] (clipped) and boundary slabs.
+static PBox make_pbox(const Grid &g, const Box &full, const int ilo[3], const int ihi[3], bool colour)
+{
+    PBox P;
+    for (int p = 0; p < 7; ++p) P.b[p] = Box{{0, 0, 0}, {0, 0, 0}};
+    P.n = 0;
+    P.inner = 0;
+    for (int p = 0; p < 8; ++p) P.off[p] = 0;
+    int flo[3], fhi[3], lo[3], hi[3];
+    bool empty = false;
+    for (int d = 0; d < 3; ++d) {
+        flo[d] = full.lo[d];
+        fhi[d] = full.lo[d] + full.ext[d] - 1;
+        if (d >= g.D) { lo[d] = flo[d]; hi[d] = fhi[d]; continue; }
+        lo[d] = ilo[d] > flo[d] ? ilo[d] : flo[d];
+        hi[d] = ihi[d] < fhi[d] ? ihi[d] : fhi[d];
+        if (hi[d] < lo[d]) empty = true;
+    }
+    if (full.ext[0] <= 0 || full.ext[1] <= 0 || full.ext[2] <= 0) return P;
+    auto add = [&](int x0, int x1, int y0, int y1, int z0, int z1) {
+        if (x1 < x0 || y1 < y0 || z1 < z0) return;
+        P.b[P.n++] = Box{{x0, y0, z0}, {x1 - x0 + 1, y1 - y0 + 1, z1 - z0 + 1}};
+    };
+    bool inner = !empty;
+    if (inner) {
+        add(lo[0], hi[0], lo[1], hi[1], lo[2], hi[2]);
+        add(flo[0], fhi[0], flo[1], fhi[1], flo[2], lo[2] - 1);
+        add(flo[0], fhi[0], flo[1], fhi[1], hi[2] + 1, fhi[2]);
+        add(flo[0], fhi[0], flo[1], lo[1] - 1, lo[2], hi[2]);
+        add(flo[0], fhi[0], hi[1] + 1, fhi[1], lo[2], hi[2]);
+        add(flo[0], lo[0] - 1, lo[1], hi[1], lo[2], hi[2]);
+        add(hi[0] + 1, fhi[0], lo[1], hi[1], lo[2], hi[2]);
+    } else {
+        add(flo[0], fhi[0], flo[1], fhi[1], flo[2], fhi[2]);
+    }
+    int acc = 0;
+    for (int p = 0; p < P.n; ++p) {
+        P.off[p] = acc;
+        const Box &b = P.b[p];
+        acc += (colour ? (b.ext[0] + 1) / 2 : b.ext[0]) * b.ext[1] * b.ext[2];
+    }
+    for (int p = P.n; p < 8; ++p) P.off[p] = acc;
+    P.inner = inner ? 1 : 0;
+    return P;
+}
+
+static inline int pbox_total(const PBox &P) { return P.off[P.n]; }
+
+// inner ranges: velocity rows read two layers (2 .. n-2), pressure rows one (1 .. n-2)
+static PBox smoother_pbox(const Grid &g, int vmask, bool velocity, bool colour)
+{
+    const Box full = unk_box(g, vmask);
+    int ilo[3], ihi[3];
+    for (int d = 0; d < 3; ++d) {
+        ilo[d] = velocity ? 2 : 1;
+        ihi[d] = d < g.D ? g.n[d] - 2 : 0;
+    }
+    return make_pbox(g, full, ilo, ihi, colour);
+}
+
+template <typename T, int D>
+__device__ inline void p_row_pos(const Grid &g, const T *__restrict__ x, const CoefP<T> &cf, T cvisc, int i, int j,
+                                 int k, bool inner, T &Ax, T &dg)
+{
+    if (inner) p_row_fast<T, D>(g, x, cf, cvisc, (int)at(g, i, j, k), Ax, dg);
+    else p_row_slow<T, D>(g, x, cf, cvisc, i, j, k, Ax, dg);
+}
+
+template <typename T, int D, int A>
+__device__ inline void u_row_pos(const Grid &g, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc, int i, int j,
+                                 int k, bool inner, T &Ax, T &dg)
+{
+    if (inner) u_row_fast<T, D, A>(g, x, cf, mass, cvisc, (int)at(g, i, j, k), Ax, dg);
+    else u_row_slow<T, D, A>(g, x, cf, mass, cvisc, i, j, k, Ax, dg);
 }
 
 // ---------------------------------------------------------------------------
 // smoothers
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(256) k_smooth_p(Grid g, Box box, const T *__restrict__ b, T *x, CoefP<T> cf, T cvisc,
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_smooth_p(Grid g, PBox P, const T *__restrict__ b, T *x, CoefP<T> cf, T cvisc,
                                                   int colour)
 {
     int i, j, k;
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (!box_colour_pos(box, colour, t, i, j, k)) return;
+    bool inner;
+    if (!pbox_pos(P, colour, blockIdx.x * blockDim.x + threadIdx.x, i, j, k, inner)) return;
     T Ax, dg;
-    p_row<T>(g, x, cf, cvisc, i, j, k, Ax, dg);
+    p_row_pos<T, D>(g, x, cf, cvisc, i, j, k, inner, Ax, dg);
     const long long c = at(g, i, j, k);
     x[c] += (b[c] - Ax) / dg;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_smooth_u(Grid g, Box box, int a, const T *__restrict__ b, VelArr<T> x,
-                                                  CoefU<T> cf, T mass, T cvisc, int colour)
+template <typename T, int D, int A>
+__global__ void __launch_bounds__(256) k_smooth_u(Grid g, PBox P, const T *__restrict__ b, VelArr<T> x, CoefU<T> cf,
+                                                  T mass, T cvisc, int colour)
 {
     int i, j, k;
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (!box_colour_pos(box, colour, t, i, j, k)) return;
+    bool inner;
+    if (!pbox_pos(P, colour, blockIdx.x * blockDim.x + threadIdx.x, i, j, k, inner)) return;
     T Ax, dg;
-    u_row<T>(g, x, cf, mass, cvisc, a, i, j, k, Ax, dg);
+    u_row_pos<T, D, A>(g, x, cf, mass, cvisc, i, j, k, inner, Ax, dg);
     const long long f = at(g, i, j, k);
-    x.c[a][f] += (b[f] - Ax) / dg;
+    x.c[A][f] += (b[f] - Ax) / dg;
 }
 
 // ---------------------------------------------------------------------------
@@ -251,19 +386,24 @@ __device__ inline void block_sum_store(double v, double *partial, long long slot
     if (threadIdx.x == 0) partial[slot] = red[0];
 }
 
+struct VelPBox {
+    PBox p[3];
+};
+
 // residual r = b - A x at every unknown (r may be null) and per-block
-// partial sums of r^2 (partial may be null); grid-stride over the box
-template <typename T>
-__global__ void __launch_bounds__(256) k_resid_p(Grid g, Box box, const T *__restrict__ b, const T *__restrict__ x,
+// partial sums of r^2 (partial may be null); grid-stride over the partition
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_resid_p(Grid g, PBox P, const T *__restrict__ b, const T *__restrict__ x,
                                                  CoefP<T> cf, T cvisc, T *r, double *partial)
 {
-    const long long n = (long long)box.ext[0] * box.ext[1] * box.ext[2];
+    const int n = P.off[P.n];
     double acc = 0.0;
-    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
         int i, j, k;
-        box_pos(box, t, i, j, k);
+        bool inner;
+        pbox_pos(P, -1, t, i, j, k, inner);
         T Ax, dg;
-        p_row<T>(g, x, cf, cvisc, i, j, k, Ax, dg);
+        p_row_pos<T, D>(g, x, cf, cvisc, i, j, k, inner, Ax, dg);
         const long long c = at(g, i, j, k);
         const T rv = b[c] - Ax;
         if (r) r[c] = rv;
@@ -272,19 +412,29 @@ __global__ void __launch_bounds__(256) k_resid_p(Grid g, Box box, const T *__res
     if (partial) block_sum_store(acc, partial, blockIdx.x);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_resid_u(Grid g, VelBox boxes, VelArrC<T> b, VelArr<T> x, CoefU<T> cf, T mass,
+template <typename T, int D, int A>
+__device__ inline void u_row_dispatch(const Grid &g, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc, int i,
+                                      int j, int k, bool inner, T &Ax, T &dg)
+{
+    u_row_pos<T, D, A>(g, x, cf, mass, cvisc, i, j, k, inner, Ax, dg);
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_resid_u(Grid g, VelPBox parts, VelArrC<T> b, VelArr<T> x, CoefU<T> cf, T mass,
                                                  T cvisc, VelArr<T> r, double *partial)
 {
     const int a = blockIdx.y;
-    const Box box = boxes.b[a];
-    const long long n = (long long)box.ext[0] * box.ext[1] * box.ext[2];
+    const PBox &P = parts.p[a];
+    const int n = P.off[P.n];
     double acc = 0.0;
-    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
         int i, j, k;
-        box_pos(box, t, i, j, k);
+        bool inner;
+        pbox_pos(P, -1, t, i, j, k, inner);
         T Ax, dg;
-        u_row<T>(g, x, cf, mass, cvisc, a, i, j, k, Ax, dg);
+        if (a == 0) u_row_dispatch<T, D, 0>(g, x, cf, mass, cvisc, i, j, k, inner, Ax, dg);
+        else if (a == 1) u_row_dispatch<T, D, 1>(g, x, cf, mass, cvisc, i, j, k, inner, Ax, dg);
+        else u_row_dispatch<T, D, (D == 3 ? 2 : 1)>(g, x, cf, mass, cvisc, i, j, k, inner, Ax, dg);
         const long long f = at(g, i, j, k);
         const T rv = b.c[a][f] - Ax;
         if (r.c[a]) r.c[a][f] = rv;
@@ -299,9 +449,9 @@ __global__ void __launch_bounds__(256) k_norm2(VelBox boxes, Grid g, VelArrC<T> 
 {
     const int a = blockIdx.y;
     const Box box = boxes.b[a];
-    const long long n = (long long)box.ext[0] * box.ext[1] * box.ext[2];
+    const int n = box.ext[0] * box.ext[1] * box.ext[2];
     double acc = 0.0;
-    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
         int i, j, k;
         box_pos(box, t, i, j, k);
         const double w = (double)v.c[a][at(g, i, j, k)];
@@ -328,7 +478,7 @@ __global__ void __launch_bounds__(256) k_reduce_final(const double *__restrict__
 // ---------------------------------------------------------------------------
 // transfers
 // ---------------------------------------------------------------------------
-__device__ inline int rst_weights(int vert, int I, int *fq, double *w)
+__host__ __device__ inline int rst_weights(int vert, int I, int *fq, double *w)
 {
     if (vert) {
         fq[0] = 2 * I - 1; w[0] = 0.25;
@@ -343,7 +493,7 @@ __device__ inline int rst_weights(int vert, int I, int *fq, double *w)
     return 4;
 }
 
-__device__ inline int prl_weights(int vert, int f, int *cq, double *w)
+__host__ __device__ inline int prl_weights(int vert, int f, int *cq, double *w)
 {
     if (vert) {
         if ((f & 1) == 0) { cq[0] = f >> 1; w[0] = 1.0; return 1; }
@@ -357,74 +507,161 @@ __device__ inline int prl_weights(int vert, int f, int *cq, double *w)
     return 2;
 }
 
+// Per-axis taps of a transfer, resolved through the boundary rules once per
+// axis: index along the axis, sign, and weight (zero for a fixed face).
+struct AxisTaps {
+    int q[4];
+    double w[4];
+};
+
+template <int NT>
+__device__ inline void resolve_taps(const Grid &g, int d, int vert, int role, const int *raw, const double *wraw,
+                                    AxisTaps &t)
+{
+#pragma unroll
+    for (int a = 0; a < NT; ++a) {
+        int q = raw[a], s = 1;
+        const bool live = resolve(g, d, vert, role, q, s);
+        t.q[a] = live ? q : 0;
+        t.w[a] = live ? (s > 0 ? wraw[a] : -wraw[a]) : 0.0;
+    }
+}
+
+template <typename T, int D, int VM>
+__device__ inline double restrict_point(const Grid &gf, int role, const T *__restrict__ src, int I, int J, int K)
+{
+    constexpr int N0 = (VM & 1) ? 3 : 4;
+    constexpr int N1 = (VM & 2) ? 3 : 4;
+    constexpr int N2 = D == 3 ? ((VM & 4) ? 3 : 4) : 1;
+    const int Q[3] = {I, J, K};
+    AxisTaps t[3];
+    int raw[4];
+    double wr[4];
+    rst_weights(VM & 1, Q[0], raw, wr);
+    resolve_taps<N0>(gf, 0, VM & 1, role, raw, wr, t[0]);
+    rst_weights((VM >> 1) & 1, Q[1], raw, wr);
+    resolve_taps<N1>(gf, 1, (VM >> 1) & 1, role, raw, wr, t[1]);
+    if (D == 3) {
+        rst_weights((VM >> 2) & 1, Q[2], raw, wr);
+        resolve_taps<N2>(gf, 2, (VM >> 2) & 1, role, raw, wr, t[2]);
+    } else {
+        t[2].q[0] = 0;
+        t[2].w[0] = 1.0;
+    }
+    T v[N2][N1][N0];
+#pragma unroll
+    for (int c = 0; c < N2; ++c)
+#pragma unroll
+        for (int b = 0; b < N1; ++b)
+#pragma unroll
+            for (int a = 0; a < N0; ++a) v[c][b][a] = src[(t[2].q[c] * gf.NY + t[1].q[b]) * gf.NX + t[0].q[a]];
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < N2; ++c)
+#pragma unroll
+        for (int b = 0; b < N1; ++b) {
+            double rs = 0.0;
+#pragma unroll
+            for (int a = 0; a < N0; ++a) rs += t[0].w[a] * (double)v[c][b][a];
+            s += t[1].w[b] * t[2].w[c] * rs;
+        }
+    return s;
+}
+
+template <typename T, int D, int VM>
+__device__ inline double prolong_point(const Grid &gc, int role, const T *__restrict__ src, int i, int j, int k)
+{
+    constexpr int N2 = D == 3 ? 2 : 1;
+    const int q[3] = {i, j, k};
+    AxisTaps t[3];
+    int raw[2];
+    double wr[2];
+    for (int d = 0; d < D; ++d) {
+        const int vert = (VM >> d) & 1;
+        const int n = prl_weights(vert, q[d], raw, wr);
+        if (n == 1) { raw[1] = raw[0]; wr[1] = 0.0; }
+        resolve_taps<2>(gc, d, vert, role, raw, wr, t[d]);
+    }
+    if (D == 2) {
+        t[2].q[0] = 0;
+        t[2].w[0] = 1.0;
+    }
+    T v[N2][2][2];
+#pragma unroll
+    for (int c = 0; c < N2; ++c)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) v[c][b][a] = src[(t[2].q[c] * gc.NY + t[1].q[b]) * gc.NX + t[0].q[a]];
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < N2; ++c)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) s += t[0].w[a] * t[1].w[b] * t[2].w[c] * (double)v[c][b][a];
+    return s;
+}
+
+template <typename T, int D>
+__device__ inline double restrict_any(int vm, const Grid &gf, int role, const T *src, int I, int J, int K)
+{
+    switch (vm) {
+    case 0: return restrict_point<T, D, 0>(gf, role, src, I, J, K);
+    case 1: return restrict_point<T, D, 1>(gf, role, src, I, J, K);
+    case 2: return restrict_point<T, D, 2>(gf, role, src, I, J, K);
+    case 3: return restrict_point<T, D, 3>(gf, role, src, I, J, K);
+    case 4: return restrict_point<T, D, 4>(gf, role, src, I, J, K);
+    case 5: return restrict_point<T, D, 5>(gf, role, src, I, J, K);
+    case 6: return restrict_point<T, D, 6>(gf, role, src, I, J, K);
+    default: return restrict_point<T, D, 7>(gf, role, src, I, J, K);
+    }
+}
+
+template <typename T, int D>
+__device__ inline double prolong_any(int vm, const Grid &gc, int role, const T *src, int i, int j, int k)
+{
+    switch (vm) {
+    case 0: return prolong_point<T, D, 0>(gc, role, src, i, j, k);
+    case 1: return prolong_point<T, D, 1>(gc, role, src, i, j, k);
+    case 2: return prolong_point<T, D, 2>(gc, role, src, i, j, k);
+    case 3: return prolong_point<T, D, 3>(gc, role, src, i, j, k);
+    case 4: return prolong_point<T, D, 4>(gc, role, src, i, j, k);
+    case 5: return prolong_point<T, D, 5>(gc, role, src, i, j, k);
+    case 6: return prolong_point<T, D, 6>(gc, role, src, i, j, k);
+    default: return prolong_point<T, D, 7>(gc, role, src, i, j, k);
+    }
+}
+
 // coarse[c] = full-weighting restriction of fine[c] at every coarse unknown
-// (or every stored coarse position when `all_stored`, for coefficients)
-template <typename T>
-__global__ void __launch_bounds__(256) k_restrict(Grid gf, Grid gc, VelBox cboxes, int masks, int role, VelArrC<T> fine,
-                                                  VelArr<T> coarse, T scale)
+// (or every stored coarse position for coefficients); zero_x[c], when set,
+// is cleared at the same positions (the coarse correction starts at zero)
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_restrict(Grid gf, Grid gc, VelPBox parts, int masks, int role,
+                                                  VelArrC<T> fine, VelArr<T> coarse, T scale, VelArr<T> zero_x)
 {
     const int comp = blockIdx.y;
     const int vmask = (masks >> (4 * comp)) & 0xF;
-    const Box box = cboxes.b[comp];
     int I, J, K;
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (!box_pos(box, t, I, J, K)) return;
-    const int Q[3] = {I, J, K};
-    int fq[3][4];
-    double w[3][4];
-    int nf[3];
-    bool direct = true;
-    for (int d = 0; d < 3; ++d) {
-        if (d >= gf.D) { fq[d][0] = 0; w[d][0] = 1.0; nf[d] = 1; continue; }
-        const int vert = (vmask >> d) & 1;
-        nf[d] = rst_weights(vert, Q[d], fq[d], w[d]);
-        int lo, hi;
-        if (role == ROLE_C) { lo = 0; hi = stored_extent(gf, d, vert) - 1; }
-        else unk_range(gf, d, vert, lo, hi);
-        if (fq[d][0] < lo || fq[d][nf[d] - 1] > hi) direct = false;
-    }
-    const T *__restrict__ src = fine.c[comp];
-    double s = 0.0;
-    for (int c = 0; c < nf[2]; ++c)
-        for (int b = 0; b < nf[1]; ++b) {
-            const double wbc = w[1][b] * w[2][c];
-            for (int a = 0; a < nf[0]; ++a) {
-                double v;
-                if (direct) v = (double)src[at(gf, fq[0][a], fq[1][b], fq[2][c])];
-                else v = (double)load_ref(src, ref_at(gf, vmask, role, fq[0][a], fq[1][b], fq[2][c]));
-                s += w[0][a] * wbc * v;
-            }
-        }
-    coarse.c[comp][at(gc, I, J, K)] = (T)(s * (double)scale);
+    bool inner;
+    if (!pbox_pos(parts.p[comp], -1, blockIdx.x * blockDim.x + threadIdx.x, I, J, K, inner)) return;
+    const double s = restrict_any<T, D>(vmask, gf, role, fine.c[comp], I, J, K);
+    const long long e = at(gc, I, J, K);
+    coarse.c[comp][e] = (T)(s * (double)scale);
+    if (zero_x.c[comp]) zero_x.c[comp][e] = T(0);
 }
 
 // fine[c] += linear interpolation of coarse[c] at every fine unknown
-template <typename T>
-__global__ void __launch_bounds__(256) k_prolong_add(Grid gc, Grid gf, VelBox fboxes, int masks, int role,
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_prolong_add(Grid gc, Grid gf, VelPBox parts, int masks, int role,
                                                      VelArrC<T> coarse, VelArr<T> fine)
 {
     const int comp = blockIdx.y;
     const int vmask = (masks >> (4 * comp)) & 0xF;
-    const Box box = fboxes.b[comp];
     int i, j, k;
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (!box_pos(box, t, i, j, k)) return;
-    const int q[3] = {i, j, k};
-    int cq[3][2];
-    double w[3][2];
-    int nc[3];
-    for (int d = 0; d < 3; ++d) {
-        if (d >= gf.D) { cq[d][0] = 0; w[d][0] = 1.0; nc[d] = 1; continue; }
-        nc[d] = prl_weights((vmask >> d) & 1, q[d], cq[d], w[d]);
-    }
-    const T *__restrict__ src = coarse.c[comp];
-    double s = 0.0;
-    for (int c = 0; c < nc[2]; ++c)
-        for (int b = 0; b < nc[1]; ++b)
-            for (int a = 0; a < nc[0]; ++a)
-                s += w[0][a] * w[1][b] * w[2][c] *
-                     (double)load_ref(src, ref_at(gc, vmask, role, cq[0][a], cq[1][b], cq[2][c]));
-    fine.c[comp][at(gf, i, j, k)] += (T)s;
+    bool inner;
+    if (!pbox_pos(parts.p[comp], -1, blockIdx.x * blockDim.x + threadIdx.x, i, j, k, inner)) return;
+    fine.c[comp][at(gf, i, j, k)] += (T)prolong_any<T, D>(vmask, gc, role, coarse.c[comp], i, j, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -448,8 +685,8 @@ __global__ void __launch_bounds__(64) k_dense_inverse(Grid g, int velocity, int 
             const long long e = uidx[r];
             const int k = (int)(e / g.NXY), jj = (int)((e % g.NXY) / g.NX), i = (int)(e % g.NX);
             double Ax, dg;
-            if (velocity) u_row_slow<double>(g, tmp, cu, mass, cvisc, ucomp[r], i, jj, k, Ax, dg);
-            else p_row_slow<double>(g, tmp.c[0], cp, cvisc, i, jj, k, Ax, dg);
+            if (velocity) u_row_slow_any<double>(g, tmp, cu, mass, cvisc, ucomp[r], i, jj, k, Ax, dg);
+            else p_row_slow_any<double>(g, tmp.c[0], cp, cvisc, i, jj, k, Ax, dg);
             Aw[r * n + j] = Ax;
         }
         __syncthreads();
@@ -562,18 +799,31 @@ static inline long long box_count(const Box &b) { return (long long)b.ext[0] * b
 template <typename T>
 void launch_smooth_p(const Grid &g, const T *b, T *x, const CoefP<T> &cf, T cvisc, int colour, hipStream_t s)
 {
-    const Box box = unk_box(g, 0);
-    const long long n = (long long)((box.ext[0] + 1) / 2) * box.ext[1] * box.ext[2];
-    hipLaunchKernelGGL(k_smooth_p<T>, dim3(blocks_for(n)), dim3(256), 0, s, g, box, b, x, cf, cvisc, colour);
+    const PBox P = smoother_pbox(g, 0, false, true);
+    const int n = pbox_total(P);
+    if (n <= 0) return;
+    if (g.D == 3)
+        hipLaunchKernelGGL((k_smooth_p<T, 3>), dim3(blocks_for(n)), dim3(256), 0, s, g, P, b, x, cf, cvisc, colour);
+    else
+        hipLaunchKernelGGL((k_smooth_p<T, 2>), dim3(blocks_for(n)), dim3(256), 0, s, g, P, b, x, cf, cvisc, colour);
 }
 
 template <typename T>
 void launch_smooth_u(const Grid &g, int a, const T *b, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc,
                      int colour, hipStream_t s)
 {
-    const Box box = unk_box(g, face_mask(a));
-    const long long n = (long long)((box.ext[0] + 1) / 2) * box.ext[1] * box.ext[2];
-    hipLaunchKernelGGL(k_smooth_u<T>, dim3(blocks_for(n)), dim3(256), 0, s, g, box, a, b, x, cf, mass, cvisc, colour);
+    const PBox P = smoother_pbox(g, face_mask(a), true, true);
+    const int n = pbox_total(P);
+    if (n <= 0) return;
+    const dim3 grid(blocks_for(n)), blk(256);
+    if (g.D == 3) {
+        if (a == 0) hipLaunchKernelGGL((k_smooth_u<T, 3, 0>), grid, blk, 0, s, g, P, b, x, cf, mass, cvisc, colour);
+        else if (a == 1) hipLaunchKernelGGL((k_smooth_u<T, 3, 1>), grid, blk, 0, s, g, P, b, x, cf, mass, cvisc, colour);
+        else hipLaunchKernelGGL((k_smooth_u<T, 3, 2>), grid, blk, 0, s, g, P, b, x, cf, mass, cvisc, colour);
+    } else {
+        if (a == 0) hipLaunchKernelGGL((k_smooth_u<T, 2, 0>), grid, blk, 0, s, g, P, b, x, cf, mass, cvisc, colour);
+        else hipLaunchKernelGGL((k_smooth_u<T, 2, 1>), grid, blk, 0, s, g, P, b, x, cf, mass, cvisc, colour);
+    }
 }
 
 static inline unsigned stride_blocks(long long n)
@@ -586,9 +836,10 @@ template <typename T>
 int launch_resid_p(const Grid &g, const T *b, const T *x, const CoefP<T> &cf, T cvisc, T *r, double *partial,
                    hipStream_t s)
 {
-    const Box box = unk_box(g, 0);
-    const unsigned nb = stride_blocks(box_count(box));
-    hipLaunchKernelGGL(k_resid_p<T>, dim3(nb), dim3(256), 0, s, g, box, b, x, cf, cvisc, r, partial);
+    const PBox P = smoother_pbox(g, 0, false, false);
+    const unsigned nb = stride_blocks(pbox_total(P));
+    if (g.D == 3) hipLaunchKernelGGL((k_resid_p<T, 3>), dim3(nb), dim3(256), 0, s, g, P, b, x, cf, cvisc, r, partial);
+    else hipLaunchKernelGGL((k_resid_p<T, 2>), dim3(nb), dim3(256), 0, s, g, P, b, x, cf, cvisc, r, partial);
     return (int)nb;
 }
 
@@ -596,14 +847,21 @@ template <typename T>
 int launch_resid_u(const Grid &g, const VelArrC<T> &b, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc,
                    const VelArr<T> &r, double *partial, hipStream_t s)
 {
-    VelBox boxes;
+    VelPBox parts;
     long long mx = 0;
     for (int a = 0; a < 3; ++a) {
-        boxes.b[a] = a < g.D ? unk_box(g, face_mask(a)) : Box{{0, 0, 0}, {0, 0, 0}};
-        if (a < g.D && box_count(boxes.b[a]) > mx) mx = box_count(boxes.b[a]);
+        if (a < g.D) {
+            parts.p[a] = smoother_pbox(g, face_mask(a), true, false);
+            mx = pbox_total(parts.p[a]) > mx ? pbox_total(parts.p[a]) : mx;
+        } else {
+            parts.p[a] = parts.p[0];
+        }
     }
     const unsigned nb = stride_blocks(mx);
-    hipLaunchKernelGGL(k_resid_u<T>, dim3(nb, g.D), dim3(256), 0, s, g, boxes, b, x, cf, mass, cvisc, r, partial);
+    if (g.D == 3)
+        hipLaunchKernelGGL((k_resid_u<T, 3>), dim3(nb, 3), dim3(256), 0, s, g, parts, b, x, cf, mass, cvisc, r, partial);
+    else
+        hipLaunchKernelGGL((k_resid_u<T, 2>), dim3(nb, 2), dim3(256), 0, s, g, parts, b, x, cf, mass, cvisc, r, partial);
     return (int)nb * g.D;
 }
 
@@ -636,44 +894,118 @@ static inline Box stored_box(const Grid &g, int vmask)
     return b;
 }
 
+// valid index range of a lattice along d for a role (fine side of a transfer)
+static void valid_range(const Grid &g, int d, int vert, int role, int &lo, int &hi)
+{
+    if (role == ROLE_C) { lo = 0; hi = stored_extent(g, d, vert) - 1; }
+    else unk_range(g, d, vert, lo, hi);
+}
+
+// coarse positions of box `cb` whose restriction taps all sit in the valid
+// fine range, as the inner interval per axis
+static PBox restrict_pbox(const Grid &gf, const Box &cb, int vmask, int role)
+{
+    int ilo[3], ihi[3];
+    for (int d = 0; d < 3; ++d) {
+        ilo[d] = cb.lo[d];
+        ihi[d] = cb.lo[d] + cb.ext[d] - 1;
+        if (d >= gf.D) continue;
+        const int vert = (vmask >> d) & 1;
+        int lo, hi;
+        valid_range(gf, d, vert, role, lo, hi);
+        int first = 1 << 30, last = -(1 << 30);
+        for (int I = cb.lo[d]; I < cb.lo[d] + cb.ext[d]; ++I) {
+            const int t0 = 2 * I - 1, t1 = vert ? 2 * I + 1 : 2 * I + 2;
+            if (t0 >= lo && t1 <= hi) {
+                first = I < first ? I : first;
+                last = I > last ? I : last;
+            }
+        }
+        ilo[d] = first;
+        ihi[d] = last;
+    }
+    return make_pbox(gf, cb, ilo, ihi, false);
+}
+
+// fine unknowns of box `fb` whose prolongation taps all sit in the valid
+// coarse range
+static PBox prolong_pbox(const Grid &gc, const Box &fb, int vmask, int role)
+{
+    int ilo[3], ihi[3];
+    for (int d = 0; d < 3; ++d) {
+        ilo[d] = fb.lo[d];
+        ihi[d] = fb.lo[d] + fb.ext[d] - 1;
+        if (d >= gc.D) continue;
+        const int vert = (vmask >> d) & 1;
+        int lo, hi;
+        valid_range(gc, d, vert, role, lo, hi);
+        int first = 1 << 30, last = -(1 << 30);
+        for (int f = fb.lo[d]; f < fb.lo[d] + fb.ext[d]; ++f) {
+            int t0, t1;
+            if (vert) { t0 = (f - (f & 1)) / 2; t1 = (f + (f & 1)) / 2; }
+            else { t0 = (f >> 1) - 1; t1 = (f >> 1) + 1; }
+            if (t0 >= lo && t1 <= hi) {
+                first = f < first ? f : first;
+                last = f > last ? f : last;
+            }
+        }
+        ilo[d] = first;
+        ihi[d] = last;
+    }
+    return make_pbox(gc, fb, ilo, ihi, false);
+}
+
 template <typename T>
 void launch_restrict(const Grid &gf, const Grid &gc, int ncomp, const int *vmasks, int role, bool all_stored,
-                     const VelArrC<T> &fine, const VelArr<T> &coarse, T scale, hipStream_t s)
+                     const VelArrC<T> &fine, const VelArr<T> &coarse, T scale, hipStream_t s,
+                     const VelArr<T> *zero_x)
 {
-    VelBox boxes;
+    VelPBox parts;
     int masks = 0;
     long long mx = 0;
     for (int a = 0; a < 3; ++a) {
         if (a < ncomp) {
-            boxes.b[a] = all_stored ? stored_box(gc, vmasks[a]) : unk_box(gc, vmasks[a]);
+            const Box cb = all_stored ? stored_box(gc, vmasks[a]) : unk_box(gc, vmasks[a]);
+            parts.p[a] = restrict_pbox(gf, cb, vmasks[a], role);
             masks |= vmasks[a] << (4 * a);
-            mx = box_count(boxes.b[a]) > mx ? box_count(boxes.b[a]) : mx;
+            mx = pbox_total(parts.p[a]) > mx ? pbox_total(parts.p[a]) : mx;
         } else {
-            boxes.b[a] = Box{{0, 0, 0}, {0, 0, 0}};
+            parts.p[a] = parts.p[0];
         }
     }
-    hipLaunchKernelGGL(k_restrict<T>, dim3(blocks_for(mx), ncomp), dim3(256), 0, s, gf, gc, boxes, masks, role, fine,
-                       coarse, scale);
+    const VelArr<T> zx = zero_x ? *zero_x : VelArr<T>{{nullptr, nullptr, nullptr}};
+    if (mx <= 0) return;
+    if (gf.D == 3)
+        hipLaunchKernelGGL((k_restrict<T, 3>), dim3(blocks_for(mx), ncomp), dim3(256), 0, s, gf, gc, parts, masks, role,
+                           fine, coarse, scale, zx);
+    else
+        hipLaunchKernelGGL((k_restrict<T, 2>), dim3(blocks_for(mx), ncomp), dim3(256), 0, s, gf, gc, parts, masks, role,
+                           fine, coarse, scale, zx);
 }
 
 template <typename T>
 void launch_prolong_add(const Grid &gc, const Grid &gf, int ncomp, const int *vmasks, int role,
                         const VelArrC<T> &coarse, const VelArr<T> &fine, hipStream_t s)
 {
-    VelBox boxes;
+    VelPBox parts;
     int masks = 0;
     long long mx = 0;
     for (int a = 0; a < 3; ++a) {
         if (a < ncomp) {
-            boxes.b[a] = unk_box(gf, vmasks[a]);
+            parts.p[a] = prolong_pbox(gc, unk_box(gf, vmasks[a]), vmasks[a], role);
             masks |= vmasks[a] << (4 * a);
-            mx = box_count(boxes.b[a]) > mx ? box_count(boxes.b[a]) : mx;
+            mx = pbox_total(parts.p[a]) > mx ? pbox_total(parts.p[a]) : mx;
         } else {
-            boxes.b[a] = Box{{0, 0, 0}, {0, 0, 0}};
+            parts.p[a] = parts.p[0];
         }
     }
-    hipLaunchKernelGGL(k_prolong_add<T>, dim3(blocks_for(mx), ncomp), dim3(256), 0, s, gc, gf, boxes, masks, role,
-                       coarse, fine);
+    if (mx <= 0) return;
+    if (gf.D == 3)
+        hipLaunchKernelGGL((k_prolong_add<T, 3>), dim3(blocks_for(mx), ncomp), dim3(256), 0, s, gc, gf, parts, masks,
+                           role, coarse, fine);
+    else
+        hipLaunchKernelGGL((k_prolong_add<T, 2>), dim3(blocks_for(mx), ncomp), dim3(256), 0, s, gc, gf, parts, masks,
+                           role, coarse, fine);
 }
 
 void launch_dense_inverse(const Grid &g, int velocity, int n, const long long *uidx, const int *ucomp,
@@ -736,7 +1068,7 @@ void launch_add_correction(const Grid &g, int ncomp, const int *vmasks, const Ve
                                    const VelArr<T> &, double *, hipStream_t);                                       \
     template int launch_norm2<T>(const Grid &, int, const int *, const VelArrC<T> &, double *, hipStream_t);        \
     template void launch_restrict<T>(const Grid &, const Grid &, int, const int *, int, bool, const VelArrC<T> &,   \
-                                     const VelArr<T> &, T, hipStream_t);                                            \
+                                     const VelArr<T> &, T, hipStream_t, const VelArr<T> *);                         \
     template void launch_prolong_add<T>(const Grid &, const Grid &, int, const int *, int, const VelArrC<T> &,      \
                                         const VelArr<T> &, hipStream_t);                                            \
     template void launch_dense_apply<T>(int, const long long *, const int *, const double *, const VelArrC<T> &,    \

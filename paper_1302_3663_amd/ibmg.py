@@ -183,6 +183,15 @@ class Context:
         self._c(self.lib.ibb_spread(self.ctx, width, X.shape[1], _ptr(X), _ptr(F), _ptr(out)), "ibb_spread")
         return out
 
+    def profile_enable(self, enable=True):
+        self._c(self.lib.ibb_profile_enable(self.ctx, 1 if enable else 0), "ibb_profile_enable")
+
+    def profile_read(self, kernel_class):
+        n, ms, u = ctypes.c_longlong(), ctypes.c_double(), ctypes.c_longlong()
+        self._c(self.lib.ibb_profile_read(self.ctx, kernel_class, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(u)),
+                "ibb_profile_read")
+        return dict(launches=n.value, total_ms=ms.value, units=u.value)
+
     def level_info(self, level=0):
         nl = ctypes.c_int()
         n = (ctypes.c_int * 3)()
