@@ -185,10 +185,10 @@ Grid make_grid(const ibb_desc *d, int l)
         g.n[a] = a < d->dim ? d->n[a] >> l : 1;
         g.bc[a] = a < d->dim ? d->axis_bc[a] : 0;
     }
-    g.NX = g.n[0] + 1;
-    g.NY = g.n[1] + 1;
+    g.NX = g.n[0] + 3;
+    g.NY = g.n[1] + 3;
     g.NXY = (long long)g.NX * g.NY;
-    g.nel = g.NXY * (d->dim == 3 ? g.n[2] + 1 : 1);
+    g.nel = g.NXY * (d->dim == 3 ? g.n[2] + 3 : 1);
     g.h = d->h * (double)(1 << l);
     return g;
 }
@@ -442,11 +442,11 @@ void vcycle(ibb_ctx *c, bool vel, int l)
     if (l == c->L - 1) {
         const long long n = vel ? L.nu : L.np;
         if (n <= DENSE_MAX) {
-            if (vel) launch_dense_apply<T>((int)n, c->uidx_u, c->ucomp_u, c->Mu, cview(v.bu), v.xu, c->s);
+            if (vel) launch_dense_apply<T>(L.g, 1, (int)n, c->uidx_u, c->ucomp_u, c->Mu, cview(v.bu), v.xu, c->s);
             else {
                 VelArr<T> x{{v.xp, nullptr, nullptr}};
                 VelArrC<T> b{{v.bp, nullptr, nullptr}};
-                launch_dense_apply<T>((int)n, c->uidx_p, c->ucomp_p, c->Mp, b, x, c->s);
+                launch_dense_apply<T>(L.g, 0, (int)n, c->uidx_p, c->ucomp_p, c->Mp, b, x, c->s);
             }
         } else {
             for (int s = 0; s < c->d.nu1 + c->d.nu2; ++s) sweep<T>(c, vel, l);
@@ -513,23 +513,17 @@ ibb_status resid_norm(ibb_ctx *c, bool vel, double *out)
 
 void zero_unknowns(ibb_ctx *c, bool vel)
 {
-    // x(unknowns) = 0 through a cast from the zeroed FP64 residual scratch is
-    // avoided: write zeros with a cast of an all-zero array of the same level
     Level &L = c->lv[0];
     const int D = c->d.dim;
     int vm[3];
     vel_masks(D, vm);
     const int pm[3] = {0, 0, 0};
-    if (vel) {
-        for (int a = 0; a < D; ++a) launch_fill<double>(L.ru[a], L.g.nel, 0.0, c->s);
-        // x = x * 0 at unknowns: copy zeros from r into x at the unknown positions
-        launch_cast_unknowns<double, double>(L.g, D, vm, VelArrC<double>{{L.ru[0], L.ru[1], L.ru[2]}},
-                                             VelArr<double>{{L.xu[0], L.xu[1], L.xu[2]}}, c->s);
-    } else {
-        launch_fill<double>(L.rp, L.g.nel, 0.0, c->s);
-        launch_cast_unknowns<double, double>(L.g, 1, pm, VelArrC<double>{{L.rp, nullptr, nullptr}},
-                                             VelArr<double>{{L.xp, nullptr, nullptr}}, c->s);
-    }
+    if (vel)
+        launch_load_unknowns<double>(L.g, D, vm, VelArrC<double>{{nullptr, nullptr, nullptr}},
+                                     VelArr<double>{{L.xu[0], L.xu[1], L.xu[2]}}, c->s);
+    else
+        launch_load_unknowns<double>(L.g, 1, pm, VelArrC<double>{{nullptr, nullptr, nullptr}},
+                                     VelArr<double>{{L.xp, nullptr, nullptr}}, c->s);
 }
 
 struct SolveOut {
@@ -674,7 +668,14 @@ ibb_status rebuild_coefficients(ibb_ctx *c)
             }
             launch_restrict<double>(F.g, L.g, c->E, em3, ROLE_C, true, fe, ce, gm, c->s);
         }
-        for (int a = 0; a < D; ++a) launch_beta_face(L.g, a, L.rho[a], L.beta[a], c->s);
+        for (int a = 0; a < D; ++a) {
+            launch_beta_face(L.g, a, L.rho[a], L.beta[a], c->s);
+            launch_coef_ghosts<double>(L.g, face_mask(a), L.rho[a], c->s);
+            launch_coef_ghosts<double>(L.g, face_mask(a), L.beta[a], c->s);
+        }
+        launch_coef_ghosts<double>(L.g, 0, L.muc, c->s);
+        for (int e = 0; e < c->E; ++e)
+            launch_coef_ghosts<double>(L.g, edge_mask(D, c->edge_axis[e]), L.mue[c->edge_axis[e]], c->s);
         if (d->precision == IBB_FP32_REFINED) {
             for (int a = 0; a < D; ++a) {
                 launch_to_f32(L.rho[a], L.rho32[a], L.g.nel, c->s);
@@ -705,6 +706,10 @@ ibb_status remove_cell_mean(ibb_ctx *c, double *v)
     const int np = launch_sum_cells(L0.g, v, c->partial, c->s);
     launch_reduce_final(c->partial, np, c->scalar, c->s);
     launch_add_scalar_cells(L0.g, v, c->scalar, -1.0 / (double)L0.np, c->s);
+    // refresh the ghost images of the shifted field
+    const int pm[3] = {0, 0, 0};
+    launch_load_unknowns<double>(L0.g, 1, pm, VelArrC<double>{{v, nullptr, nullptr}}, VelArr<double>{{v, nullptr, nullptr}},
+                                 c->s);
     return IBB_OK;
 }
 
@@ -925,8 +930,11 @@ ibb_status ibb_projection_step(ibb_ctx *c, ibb_solve_stats *stats)
     const int D = c->d.dim;
     const long long n0 = L0.g.nel;
     View<double> v = view64(L0);
+    int vm[3];
+    vel_masks(D, vm);
+    const int pm[3] = {0, 0, 0};
     // momentum right-hand side and the viscous solve, warm start u^n
-    for (int a = 0; a < D; ++a) launch_copy(c->u[a], L0.xu[a], n0, c->s);
+    launch_load_unknowns<double>(L0.g, D, vm, VelArrC<double>{{c->u[0], c->u[1], c->u[2]}}, v.xu, c->s);
     launch_momentum_rhs(L0.g, c->ph, VelArrC<double>{{c->u[0], c->u[1], c->u[2]}}, v.cu,
                         VelArrC<double>{{c->f[0], c->f[1], c->f[2]}}, v.bu, c->s);
     HIPCHK(hipEventRecord(c->ev[0], c->s));
@@ -935,17 +943,17 @@ ibb_status ibb_projection_step(ibb_ctx *c, ibb_solve_stats *stats)
     if (st) return st;
     HIPCHK(hipEventRecord(c->ev[1], c->s));
     // pressure right-hand side and solve, warm start p^n
-    launch_pressure_div(L0.g, c->ph, cview(v.xu), L0.bp, c->s);
+    launch_pressure_div(L0.g, c->ph, cview(v.xu), VelArrC<double>{{c->u[0], c->u[1], c->u[2]}}, L0.bp, c->s);
     if (c->singular_p) remove_cell_mean(c, L0.bp);
-    launch_copy(c->p, L0.xp, n0, c->s);
+    launch_load_unknowns<double>(L0.g, 1, pm, VelArrC<double>{{c->p, nullptr, nullptr}},
+                                 VelArr<double>{{L0.xp, nullptr, nullptr}}, c->s);
     HIPCHK(hipEventRecord(c->ev[2], c->s));
     st = solve(c, false, c->d.max_cycles, 0, &sp);
     if (st) return st;
     HIPCHK(hipEventRecord(c->ev[3], c->s));
     if (c->singular_p) remove_cell_mean(c, L0.xp);
     launch_copy(L0.xp, c->p, n0, c->s);
-    // projection
-    for (int a = 0; a < D; ++a) launch_copy(L0.xu[a], c->u[a], n0, c->s);
+    // projection: the unknown faces of the state take u~ - (eps dt / sigma) beta G p
     launch_project(L0.g, c->ph, cview(v.xu), L0.xp, v.cp, VelArr<double>{{c->u[0], c->u[1], c->u[2]}}, c->s);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->s));
@@ -1040,7 +1048,8 @@ ibb_status ibb_pressure_rhs(ibb_ctx *c, const double *ut, double *bp)
     if (!c || !ut || !bp) return IBB_EINVAL;
     Level &L0 = c->lv[0];
     faces_in(c, ut, L0.ru);
-    launch_pressure_div(L0.g, c->ph, VelArrC<double>{{L0.ru[0], L0.ru[1], L0.ru[2]}}, L0.rp, c->s);
+    launch_pressure_div(L0.g, c->ph, VelArrC<double>{{L0.ru[0], L0.ru[1], L0.ru[2]}},
+                        VelArrC<double>{{L0.ru[0], L0.ru[1], L0.ru[2]}}, L0.rp, c->s);
     if (c->singular_p) remove_cell_mean(c, L0.rp);
     launch_layout(L0.g, 0, L0.rp, bp, false, c->s);
     HIPCHK(hipGetLastError());
@@ -1054,19 +1063,34 @@ ibb_status ibb_mg_solve(ibb_ctx *c, int which, const double *b, double *x, int m
     if (!c->have_coefs) return fail(c, IBB_ESTATE, "ibb_mg_solve: coefficients not built");
     Level &L0 = c->lv[0];
     const bool vel = which == 1;
+    int vm[3];
+    vel_masks(c->d.dim, vm);
+    const int pm[3] = {0, 0, 0};
+    // the initial guess enters through the unknowns only; the caller's values
+    // on fixed faces are handed back unchanged
     if (vel) {
         for (int a = 0; a < c->d.dim; ++a) launch_fill<double>(L0.bu[a], L0.g.nel, 0.0, c->s);
         faces_in(c, b, L0.bu);
-        faces_in(c, x, L0.xu);
+        faces_in(c, x, L0.ru);
+        launch_load_unknowns<double>(L0.g, c->d.dim, vm, VelArrC<double>{{L0.ru[0], L0.ru[1], L0.ru[2]}},
+                                     VelArr<double>{{L0.xu[0], L0.xu[1], L0.xu[2]}}, c->s);
     } else {
         launch_layout(L0.g, 0, b, L0.bp, true, c->s);
-        launch_layout(L0.g, 0, x, L0.xp, true, c->s);
+        launch_layout(L0.g, 0, x, L0.rp, true, c->s);
+        launch_load_unknowns<double>(L0.g, 1, pm, VelArrC<double>{{L0.rp, nullptr, nullptr}},
+                                     VelArr<double>{{L0.xp, nullptr, nullptr}}, c->s);
     }
     SolveOut o;
     ibb_status st = solve(c, vel, max_cycles_override > 0 ? max_cycles_override : c->d.max_cycles, ncycles_exact, &o);
     if (st) return st;
-    if (vel) faces_out(c, 0, L0.xu, x);
-    else launch_layout(L0.g, 0, L0.xp, x, false, c->s);
+    if (vel) {
+        faces_in(c, x, L0.ru);
+        launch_load_unknowns<double>(L0.g, c->d.dim, vm, VelArrC<double>{{L0.xu[0], L0.xu[1], L0.xu[2]}},
+                                     VelArr<double>{{L0.ru[0], L0.ru[1], L0.ru[2]}}, c->s);
+        faces_out(c, 0, L0.ru, x);
+    } else {
+        launch_layout(L0.g, 0, L0.xp, x, false, c->s);
+    }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->s));
     if (cycles) *cycles = o.cycles;
@@ -1081,10 +1105,12 @@ ibb_status ibb_project(ibb_ctx *c, const double *ut, const double *p, double *u)
     if (!c->have_coefs) return fail(c, IBB_ESTATE, "ibb_project: coefficients not built");
     Level &L0 = c->lv[0];
     View<double> v = view64(L0);
-    faces_in(c, ut, L0.xu);
-    launch_layout(L0.g, 0, p, L0.xp, true, c->s);
-    for (int a = 0; a < c->d.dim; ++a) launch_copy(L0.xu[a], L0.ru[a], L0.g.nel, c->s);
-    launch_project(L0.g, c->ph, cview(v.xu), L0.xp, v.cp, v.ru, c->s);
+    const int pm[3] = {0, 0, 0};
+    faces_in(c, ut, L0.ru);
+    launch_layout(L0.g, 0, p, L0.rp, true, c->s);
+    launch_load_unknowns<double>(L0.g, 1, pm, VelArrC<double>{{L0.rp, nullptr, nullptr}},
+                                 VelArr<double>{{L0.xp, nullptr, nullptr}}, c->s);
+    launch_project(L0.g, c->ph, cview(v.ru), L0.xp, v.cp, v.ru, c->s);
     faces_out(c, 0, L0.ru, u);
     HIPCHK(hipGetLastError());
     return IBB_OK;

@@ -24,9 +24,11 @@ enum { AX_PERIODIC = 0, AX_WALLS = 1, AX_INOUT = 2 };
 enum { ROLE_P = 0, ROLE_V = 1, ROLE_C = 3 };
 
 // One multigrid level.  Every field of the level (cell, face or edge
-// lattice) uses the same uniform array of (n[0]+1) x (n[1]+1) (x (n[2]+1))
-// entries, so that neighbouring positions of different lattices sit at fixed
-// offsets.  Lattice position (i, j, k) is entry at(i, j, k).
+// lattice) uses the same uniform array covering lattice indices -1 .. n[d]+1
+// along each axis ((n[0]+3) x (n[1]+3) (x (n[2]+3)) entries), so that
+// neighbouring positions of different lattices sit at fixed offsets and one
+// layer of ghost positions surrounds the domain.  Lattice position (i, j, k)
+// is entry at(i, j, k).
 struct Grid {
     int D;
     int n[3];
@@ -39,7 +41,16 @@ struct Grid {
 
 __host__ __device__ inline long long at(const Grid &g, int i, int j, int k)
 {
-    return ((long long)k * g.NY + j) * g.NX + i;
+    return ((long long)(k + (g.D == 3 ? 1 : 0)) * g.NY + (j + 1)) * g.NX + (i + 1);
+}
+
+// lattice index of entry e (inverse of at)
+__host__ __device__ inline void decode(const Grid &g, long long e, int &i, int &j, int &k)
+{
+    k = (int)(e / g.NXY) - (g.D == 3 ? 1 : 0);
+    const long long r = e % g.NXY;
+    j = (int)(r / g.NX) - 1;
+    i = (int)(r % g.NX) - 1;
 }
 
 __host__ __device__ inline long long stride_of(const Grid &g, int d)
@@ -133,6 +144,59 @@ __device__ inline T ld(const T *__restrict__ v, Ref r)
 {
     const T x = v[r.idx];
     return r.s == 0 ? T(0) : (r.s > 0 ? x : -x);
+}
+
+// Ghost positions along axis d whose value is (sign x) the value at q:
+// the inverse of resolve() for the positions the stencils read (at most two).
+__host__ __device__ inline int images_of(const Grid &g, int d, int vert, int role, int q, int *gq, int *gs)
+{
+    const int n = g.n[d], bc = g.bc[d];
+    int m = 0;
+    if (bc == AX_PERIODIC) {
+        if (q == 0) { gq[m] = n; gs[m++] = 1; }
+        if (q == n - 1) { gq[m] = -1; gs[m++] = 1; }
+        return m;
+    }
+    if (!vert) {
+        if (q == 0) { gq[m] = -1; gs[m++] = role == ROLE_V ? -1 : 1; }
+        if (q == n - 1) {
+            int s = 1;
+            if (role == ROLE_P && bc == AX_INOUT) s = -1;
+            if (role == ROLE_V && bc == AX_WALLS) s = -1;
+            gq[m] = n;
+            gs[m++] = s;
+        }
+        return m;
+    }
+    if (role == ROLE_C) {
+        if (q == 1) { gq[m] = -1; gs[m++] = 1; }
+        if (q == n - 1) { gq[m] = n + 1; gs[m++] = 1; }
+        return m;
+    }
+    if (role == ROLE_V && bc == AX_INOUT && q == n - 1) { gq[m] = n + 1; gs[m++] = 1; }
+    return m;
+}
+
+// write v (times the reflection sign) to every ghost image of (i, j, k)
+template <typename T>
+__device__ inline void write_images(const Grid &g, int vmask, int role, T *x, int i, int j, int k, T v)
+{
+    const int q[3] = {i, j, k};
+    int cq[3][3], cs[3][3], cn[3];
+    for (int d = 0; d < 3; ++d) {
+        cq[d][0] = q[d];
+        cs[d][0] = 1;
+        cn[d] = 1;
+        if (d < g.D) cn[d] += images_of(g, d, (vmask >> d) & 1, role, q[d], &cq[d][1], &cs[d][1]);
+    }
+    if (cn[0] == 1 && cn[1] == 1 && cn[2] == 1) return;
+    for (int c = 0; c < cn[2]; ++c)
+        for (int b = 0; b < cn[1]; ++b)
+            for (int a = 0; a < cn[0]; ++a) {
+                if ((a | b | c) == 0) continue;
+                const int s = cs[0][a] * cs[1][b] * cs[2][c];
+                x[at(g, cq[0][a], cq[1][b], cq[2][c])] = s > 0 ? v : -v;
+            }
 }
 
 // lattice masks

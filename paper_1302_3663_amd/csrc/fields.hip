@@ -184,9 +184,10 @@ void launch_momentum_rhs(const Grid &g, const Phys &ph, const VelArrC<double> &u
     hipLaunchKernelGGL(k_momentum_rhs, dim3(nblk(mx), g.D), dim3(256), 0, s, g, ph, u, cf, f, b, boxes);
 }
 
-// b_p = -(sigma / (eps dt)) D u~ at every cell (stored face values used,
-// periodic faces wrap)
-__global__ void __launch_bounds__(256) k_pressure_div(Grid g, double coef, VelArrC<double> ut, double *bp)
+// b_p = -(sigma / (eps dt)) D u~ at every cell: unknown faces from ut, fixed
+// faces (walls, inflow) from ubd, periodic faces wrap
+__global__ void __launch_bounds__(256) k_pressure_div(Grid g, double coef, VelArrC<double> ut, VelArrC<double> ubd,
+                                                      double *bp)
 {
     const int ext[3] = {g.n[0], g.n[1], g.D == 3 ? g.n[2] : 1};
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -198,15 +199,20 @@ __global__ void __launch_bounds__(256) k_pressure_div(Grid g, double coef, VelAr
         int qp[3] = {i, j, k};
         qp[a] += 1;
         if (g.bc[a] == AX_PERIODIC && qp[a] == g.n[a]) qp[a] = 0;
-        div += (ut.c[a][at(g, qp[0], qp[1], qp[2])] - ut.c[a][at(g, q[0], q[1], q[2])]) / g.h;
+        int lo, hi;
+        unk_range(g, a, 1, lo, hi);
+        const double up = (qp[a] >= lo && qp[a] <= hi ? ut.c[a] : ubd.c[a])[at(g, qp[0], qp[1], qp[2])];
+        const double um = (q[a] >= lo && q[a] <= hi ? ut.c[a] : ubd.c[a])[at(g, q[0], q[1], q[2])];
+        div += (up - um) / g.h;
     }
     bp[at(g, i, j, k)] = coef * div;
 }
 
-void launch_pressure_div(const Grid &g, const Phys &ph, const VelArrC<double> &ut, double *bp, hipStream_t s)
+void launch_pressure_div(const Grid &g, const Phys &ph, const VelArrC<double> &ut, const VelArrC<double> &ubd,
+                         double *bp, hipStream_t s)
 {
     const long long n = (long long)g.n[0] * g.n[1] * (g.D == 3 ? g.n[2] : 1);
-    hipLaunchKernelGGL(k_pressure_div, dim3(nblk(n)), dim3(256), 0, s, g, -ph.sigma / (ph.eps * ph.dt), ut, bp);
+    hipLaunchKernelGGL(k_pressure_div, dim3(nblk(n)), dim3(256), 0, s, g, -ph.sigma / (ph.eps * ph.dt), ut, ubd, bp);
 }
 
 // v(cells) += scale * sum[0]

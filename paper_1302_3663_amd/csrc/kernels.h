@@ -84,8 +84,16 @@ void launch_dense_inverse(const Grid &g, int velocity, int n, const long long *u
                           const CoefP<double> &cp, const CoefU<double> &cu, double mass, double cvisc,
                           const VelArr<double> &tmp, int singular, double *Aw, double *M, hipStream_t s);
 template <typename T>
-void launch_dense_apply(int n, const long long *uidx, const int *ucomp, const double *M, const VelArrC<T> &b,
-                        const VelArr<T> &x, hipStream_t s);
+void launch_dense_apply(const Grid &g, int velocity, int n, const long long *uidx, const int *ucomp, const double *M,
+                        const VelArrC<T> &b, const VelArr<T> &x, hipStream_t s);
+// dst = src at the unknowns of each lattice (src component may be null: zero),
+// with dst's ghost images written (velocity: face lattices, else cells)
+template <typename T>
+void launch_load_unknowns(const Grid &g, int ncomp, const int *vmasks, const VelArrC<T> &src, const VelArr<T> &dst,
+                          hipStream_t s);
+// fill the ghost layer of a coefficient field from its stored positions
+template <typename T>
+void launch_coef_ghosts(const Grid &g, int vmask, T *v, hipStream_t s);
 template <typename T>
 void launch_fill(T *p, long long n, T v, hipStream_t s);
 template <typename Ts, typename Td>
@@ -105,7 +113,8 @@ struct Phys {
 void launch_layout(const Grid &g, int vmask, const double *src, double *dst, bool to_uniform, hipStream_t s);
 void launch_momentum_rhs(const Grid &g, const Phys &ph, const VelArrC<double> &u, const CoefU<double> &cf,
                          const VelArrC<double> &f, const VelArr<double> &b, hipStream_t s);
-void launch_pressure_div(const Grid &g, const Phys &ph, const VelArrC<double> &ut, double *bp, hipStream_t s);
+void launch_pressure_div(const Grid &g, const Phys &ph, const VelArrC<double> &ut, const VelArrC<double> &ubd,
+                         double *bp, hipStream_t s);
 void launch_add_scalar_cells(const Grid &g, double *v, const double *sum, double scale, hipStream_t s);
 void launch_project(const Grid &g, const Phys &ph, const VelArrC<double> &ut, const double *p,
                     const CoefP<double> &beta, const VelArr<double> &u, hipStream_t s);

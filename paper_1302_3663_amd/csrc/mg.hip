@@ -192,6 +192,86 @@ __device__ inline void u_row_slow(const Grid &g, const VelArr<T> &x, const CoefU
     dg = m + cvisc * d;
 }
 
+// Rows read through the ghost layer: every neighbour sits at a fixed
+// offset.  Where the ghost across a boundary mirrors the point itself, the
+// diagonal gains the reflection: coefficient x (1 - sign) instead of the
+// coefficient alone.
+template <typename T, int D>
+__device__ inline void p_row(const Grid &g, const T *__restrict__ x, const CoefP<T> &cf, T cvisc, int i, int j, int k,
+                             T &Ax, T &dg)
+{
+    const int c = (int)at(g, i, j, k);
+    const int st[3] = {1, g.NX, (int)g.NXY};
+    T xn[2 * D], bt[2 * D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        xn[2 * a] = x[c + st[a]];
+        xn[2 * a + 1] = x[c - st[a]];
+        bt[2 * a] = cf.beta[a][c + st[a]];
+        bt[2 * a + 1] = cf.beta[a][c];
+    }
+    const T xc = x[c];
+    const int q[3] = {i, j, k};
+    T acc = 0, d = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        acc += bt[2 * a] * (xc - xn[2 * a]) + bt[2 * a + 1] * (xc - xn[2 * a + 1]);
+        d += bt[2 * a] + bt[2 * a + 1];
+        if (g.bc[a] != AX_PERIODIC) {
+            if (q[a] == 0) d -= bt[2 * a + 1];                                         // even mirror
+            if (q[a] == g.n[a] - 1) d += g.bc[a] == AX_INOUT ? bt[2 * a] : -bt[2 * a];  // odd at the outflow
+        }
+    }
+    Ax = acc * cvisc;
+    dg = d * cvisc;
+}
+
+template <typename T, int D, int A>
+__device__ inline void u_row(const Grid &g, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc, int i, int j,
+                             int k, T &Ax, T &dg)
+{
+    const int f = (int)at(g, i, j, k);
+    const int st[3] = {1, g.NX, (int)g.NXY};
+    const int sa = st[A];
+    const T *__restrict__ ua = x.c[A];
+    const T xf = ua[f];
+    const T cp = T(2) * cf.muc[f], cm = T(2) * cf.muc[f - sa];
+    const T vp = ua[f + sa], vm = ua[f - sa];
+    const T rho = cf.rho[A][f];
+    T mp[D - 1], mm[D - 1], ap[D - 1], am[D - 1], b0[D - 1], b1[D - 1], b2[D - 1], b3[D - 1];
+#pragma unroll
+    for (int bi = 0; bi < D - 1; ++bi) {
+        const int B = other_axis<A>(bi);
+        const int sb = st[B];
+        const T *__restrict__ ub = x.c[B];
+        const T *__restrict__ me = cf.mue[3 - A - B];
+        mp[bi] = me[f + sb];
+        mm[bi] = me[f];
+        ap[bi] = ua[f + sb];
+        am[bi] = ua[f - sb];
+        b0[bi] = ub[f + sb];
+        b1[bi] = ub[f + sb - sa];
+        b2[bi] = ub[f];
+        b3[bi] = ub[f - sa];
+    }
+    const int q[3] = {i, j, k};
+    T acc = cp * (vp - xf) - cm * (xf - vm);
+    T d = cp + cm;
+#pragma unroll
+    for (int bi = 0; bi < D - 1; ++bi) {
+        const int B = other_axis<A>(bi);
+        acc += mp[bi] * ((ap[bi] - xf) + (b0[bi] - b1[bi])) - mm[bi] * ((xf - am[bi]) + (b2[bi] - b3[bi]));
+        d += mp[bi] + mm[bi];
+        if (g.bc[B] != AX_PERIODIC) {
+            if (q[B] == 0) d += mm[bi];                                                  // odd mirror
+            if (q[B] == g.n[B] - 1) d += g.bc[B] == AX_WALLS ? mp[bi] : -mp[bi];          // even at the outflow
+        }
+    }
+    const T m = mass * rho;
+    Ax = m * xf - cvisc * acc;
+    dg = m + cvisc * d;
+}
+
 // runtime-dimension entry points (coarsest dense assembly)
 template <typename T>
 __device__ inline void p_row_slow_any(const Grid &g, const T *x, const CoefP<T> &cf, T cvisc, int i, int j, int k, T &Ax,
@@ -326,49 +406,36 @@ static PBox smoother_pbox(const Grid &g, int vmask, bool velocity, bool colour)
     return make_pbox(g, full, ilo, ihi, colour);
 }
 
-template <typename T, int D>
-__device__ inline void p_row_pos(const Grid &g, const T *__restrict__ x, const CoefP<T> &cf, T cvisc, int i, int j,
-                                 int k, bool inner, T &Ax, T &dg)
-{
-    if (inner) p_row_fast<T, D>(g, x, cf, cvisc, (int)at(g, i, j, k), Ax, dg);
-    else p_row_slow<T, D>(g, x, cf, cvisc, i, j, k, Ax, dg);
-}
-
-template <typename T, int D, int A>
-__device__ inline void u_row_pos(const Grid &g, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc, int i, int j,
-                                 int k, bool inner, T &Ax, T &dg)
-{
-    if (inner) u_row_fast<T, D, A>(g, x, cf, mass, cvisc, (int)at(g, i, j, k), Ax, dg);
-    else u_row_slow<T, D, A>(g, x, cf, mass, cvisc, i, j, k, Ax, dg);
-}
-
 // ---------------------------------------------------------------------------
-// smoothers
+// smoothers: one colour of one component; the updated value is also written
+// to its ghost images so that later passes read it at fixed offsets
 // ---------------------------------------------------------------------------
 template <typename T, int D>
-__global__ void __launch_bounds__(256) k_smooth_p(Grid g, PBox P, const T *__restrict__ b, T *x, CoefP<T> cf, T cvisc,
+__global__ void __launch_bounds__(256) k_smooth_p(Grid g, Box box, const T *__restrict__ b, T *x, CoefP<T> cf, T cvisc,
                                                   int colour)
 {
     int i, j, k;
-    bool inner;
-    if (!pbox_pos(P, colour, blockIdx.x * blockDim.x + threadIdx.x, i, j, k, inner)) return;
+    if (!box_colour_pos(box, colour, blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
     T Ax, dg;
-    p_row_pos<T, D>(g, x, cf, cvisc, i, j, k, inner, Ax, dg);
+    p_row<T, D>(g, x, cf, cvisc, i, j, k, Ax, dg);
     const long long c = at(g, i, j, k);
-    x[c] += (b[c] - Ax) / dg;
+    const T xn = x[c] + (b[c] - Ax) / dg;
+    x[c] = xn;
+    write_images(g, 0, ROLE_P, x, i, j, k, xn);
 }
 
 template <typename T, int D, int A>
-__global__ void __launch_bounds__(256) k_smooth_u(Grid g, PBox P, const T *__restrict__ b, VelArr<T> x, CoefU<T> cf,
+__global__ void __launch_bounds__(256) k_smooth_u(Grid g, Box box, const T *__restrict__ b, VelArr<T> x, CoefU<T> cf,
                                                   T mass, T cvisc, int colour)
 {
     int i, j, k;
-    bool inner;
-    if (!pbox_pos(P, colour, blockIdx.x * blockDim.x + threadIdx.x, i, j, k, inner)) return;
+    if (!box_colour_pos(box, colour, blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
     T Ax, dg;
-    u_row_pos<T, D, A>(g, x, cf, mass, cvisc, i, j, k, inner, Ax, dg);
+    u_row<T, D, A>(g, x, cf, mass, cvisc, i, j, k, Ax, dg);
     const long long f = at(g, i, j, k);
-    x.c[A][f] += (b[f] - Ax) / dg;
+    const T xn = x.c[A][f] + (b[f] - Ax) / dg;
+    x.c[A][f] = xn;
+    write_images(g, face_mask(A), ROLE_V, x.c[A], i, j, k, xn);
 }
 
 // ---------------------------------------------------------------------------
@@ -391,19 +458,18 @@ struct VelPBox {
 };
 
 // residual r = b - A x at every unknown (r may be null) and per-block
-// partial sums of r^2 (partial may be null); grid-stride over the partition
+// partial sums of r^2 (partial may be null); grid-stride over the box
 template <typename T, int D>
-__global__ void __launch_bounds__(256) k_resid_p(Grid g, PBox P, const T *__restrict__ b, const T *__restrict__ x,
+__global__ void __launch_bounds__(256) k_resid_p(Grid g, Box box, const T *__restrict__ b, const T *__restrict__ x,
                                                  CoefP<T> cf, T cvisc, T *r, double *partial)
 {
-    const int n = P.off[P.n];
+    const int n = box.ext[0] * box.ext[1] * box.ext[2];
     double acc = 0.0;
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
         int i, j, k;
-        bool inner;
-        pbox_pos(P, -1, t, i, j, k, inner);
+        box_pos(box, t, i, j, k);
         T Ax, dg;
-        p_row_pos<T, D>(g, x, cf, cvisc, i, j, k, inner, Ax, dg);
+        p_row<T, D>(g, x, cf, cvisc, i, j, k, Ax, dg);
         const long long c = at(g, i, j, k);
         const T rv = b[c] - Ax;
         if (r) r[c] = rv;
@@ -412,29 +478,21 @@ __global__ void __launch_bounds__(256) k_resid_p(Grid g, PBox P, const T *__rest
     if (partial) block_sum_store(acc, partial, blockIdx.x);
 }
 
-template <typename T, int D, int A>
-__device__ inline void u_row_dispatch(const Grid &g, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc, int i,
-                                      int j, int k, bool inner, T &Ax, T &dg)
-{
-    u_row_pos<T, D, A>(g, x, cf, mass, cvisc, i, j, k, inner, Ax, dg);
-}
-
 template <typename T, int D>
-__global__ void __launch_bounds__(256) k_resid_u(Grid g, VelPBox parts, VelArrC<T> b, VelArr<T> x, CoefU<T> cf, T mass,
+__global__ void __launch_bounds__(256) k_resid_u(Grid g, VelBox boxes, VelArrC<T> b, VelArr<T> x, CoefU<T> cf, T mass,
                                                  T cvisc, VelArr<T> r, double *partial)
 {
     const int a = blockIdx.y;
-    const PBox &P = parts.p[a];
-    const int n = P.off[P.n];
+    const Box box = boxes.b[a];
+    const int n = box.ext[0] * box.ext[1] * box.ext[2];
     double acc = 0.0;
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
         int i, j, k;
-        bool inner;
-        pbox_pos(P, -1, t, i, j, k, inner);
+        box_pos(box, t, i, j, k);
         T Ax, dg;
-        if (a == 0) u_row_dispatch<T, D, 0>(g, x, cf, mass, cvisc, i, j, k, inner, Ax, dg);
-        else if (a == 1) u_row_dispatch<T, D, 1>(g, x, cf, mass, cvisc, i, j, k, inner, Ax, dg);
-        else u_row_dispatch<T, D, (D == 3 ? 2 : 1)>(g, x, cf, mass, cvisc, i, j, k, inner, Ax, dg);
+        if (a == 0) u_row<T, D, 0>(g, x, cf, mass, cvisc, i, j, k, Ax, dg);
+        else if (a == 1) u_row<T, D, 1>(g, x, cf, mass, cvisc, i, j, k, Ax, dg);
+        else u_row<T, D, (D == 3 ? 2 : 1)>(g, x, cf, mass, cvisc, i, j, k, Ax, dg);
         const long long f = at(g, i, j, k);
         const T rv = b.c[a][f] - Ax;
         if (r.c[a]) r.c[a][f] = rv;
@@ -554,7 +612,7 @@ __device__ inline double restrict_point(const Grid &gf, int role, const T *__res
 #pragma unroll
         for (int b = 0; b < N1; ++b)
 #pragma unroll
-            for (int a = 0; a < N0; ++a) v[c][b][a] = src[(t[2].q[c] * gf.NY + t[1].q[b]) * gf.NX + t[0].q[a]];
+            for (int a = 0; a < N0; ++a) v[c][b][a] = src[at(gf, t[0].q[a], t[1].q[b], t[2].q[c])];
     double s = 0.0;
 #pragma unroll
     for (int c = 0; c < N2; ++c)
@@ -592,7 +650,7 @@ __device__ inline double prolong_point(const Grid &gc, int role, const T *__rest
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int a = 0; a < 2; ++a) v[c][b][a] = src[(t[2].q[c] * gc.NY + t[1].q[b]) * gc.NX + t[0].q[a]];
+            for (int a = 0; a < 2; ++a) v[c][b][a] = src[at(gc, t[0].q[a], t[1].q[b], t[2].q[c])];
     double s = 0.0;
 #pragma unroll
     for (int c = 0; c < N2; ++c)
@@ -648,7 +706,10 @@ __global__ void __launch_bounds__(256) k_restrict(Grid gf, Grid gc, VelPBox part
     const double s = restrict_any<T, D>(vmask, gf, role, fine.c[comp], I, J, K);
     const long long e = at(gc, I, J, K);
     coarse.c[comp][e] = (T)(s * (double)scale);
-    if (zero_x.c[comp]) zero_x.c[comp][e] = T(0);
+    if (zero_x.c[comp]) {
+        zero_x.c[comp][e] = T(0);
+        write_images(gc, vmask, role, zero_x.c[comp], I, J, K, T(0));
+    }
 }
 
 // fine[c] += linear interpolation of coarse[c] at every fine unknown
@@ -661,7 +722,10 @@ __global__ void __launch_bounds__(256) k_prolong_add(Grid gc, Grid gf, VelPBox p
     int i, j, k;
     bool inner;
     if (!pbox_pos(parts.p[comp], -1, blockIdx.x * blockDim.x + threadIdx.x, i, j, k, inner)) return;
-    fine.c[comp][at(gf, i, j, k)] += (T)prolong_any<T, D>(vmask, gc, role, coarse.c[comp], i, j, k);
+    const long long e = at(gf, i, j, k);
+    const T v = fine.c[comp][e] + (T)prolong_any<T, D>(vmask, gc, role, coarse.c[comp], i, j, k);
+    fine.c[comp][e] = v;
+    write_images(gf, vmask, role, fine.c[comp], i, j, k, v);
 }
 
 // ---------------------------------------------------------------------------
@@ -683,7 +747,8 @@ __global__ void __launch_bounds__(64) k_dense_inverse(Grid g, int velocity, int 
         __syncthreads();
         if (r < n) {
             const long long e = uidx[r];
-            const int k = (int)(e / g.NXY), jj = (int)((e % g.NXY) / g.NX), i = (int)(e % g.NX);
+            int i, jj, k;
+            decode(g, e, i, jj, k);
             double Ax, dg;
             if (velocity) u_row_slow_any<double>(g, tmp, cu, mass, cvisc, ucomp[r], i, jj, k, Ax, dg);
             else p_row_slow_any<double>(g, tmp.c[0], cp, cvisc, i, jj, k, Ax, dg);
@@ -740,9 +805,9 @@ __global__ void __launch_bounds__(64) k_dense_inverse(Grid g, int velocity, int 
     }
 }
 
-// x = M b over the coarsest unknowns (M in FP64)
+// x = M b over the coarsest unknowns (M in FP64), ghost images updated
 template <typename T>
-__global__ void __launch_bounds__(64) k_dense_apply(int n, const long long *__restrict__ uidx,
+__global__ void __launch_bounds__(64) k_dense_apply(Grid g, int velocity, int n, const long long *__restrict__ uidx,
                                                     const int *__restrict__ ucomp, const double *__restrict__ M,
                                                     VelArrC<T> b, VelArr<T> x)
 {
@@ -753,7 +818,11 @@ __global__ void __launch_bounds__(64) k_dense_apply(int n, const long long *__re
     if (r < n) {
         double s = 0.0;
         for (int j = 0; j < n; ++j) s += M[r * n + j] * bv[j];
-        x.c[ucomp[r]][uidx[r]] = (T)s;
+        const int c = ucomp[r];
+        x.c[c][uidx[r]] = (T)s;
+        int i, jj, k;
+        decode(g, uidx[r], i, jj, k);
+        write_images(g, velocity ? face_mask(c) : 0, velocity ? ROLE_V : ROLE_P, x.c[c], i, jj, k, (T)s);
     }
 }
 
@@ -779,15 +848,41 @@ __global__ void __launch_bounds__(256) k_cast_unknowns(Grid g, VelBox boxes, Vel
     dst.c[a][e] = (Td)src.c[a][e];
 }
 
-// x(unknowns) += (double) e(unknowns)
-__global__ void __launch_bounds__(256) k_add_correction(Grid g, VelBox boxes, VelArrC<float> e, VelArr<double> x)
+// x(unknowns) += (double) e(unknowns), ghost images of x updated (role:
+// velocity components or pressure)
+__global__ void __launch_bounds__(256) k_add_correction(Grid g, VelBox boxes, int velocity, VelArrC<float> e,
+                                                        VelArr<double> x)
 {
     const int a = blockIdx.y;
     int i, j, k;
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (!box_pos(boxes.b[a], t, i, j, k)) return;
+    if (!box_pos(boxes.b[a], blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
     const long long q = at(g, i, j, k);
-    x.c[a][q] += (double)e.c[a][q];
+    const double v = x.c[a][q] + (double)e.c[a][q];
+    x.c[a][q] = v;
+    write_images(g, velocity ? face_mask(a) : 0, velocity ? ROLE_V : ROLE_P, x.c[a], i, j, k, v);
+}
+
+// dst(unknowns) = src(unknowns) with the ghost images of dst written; fixed
+// positions of dst are left as they are (zero in solver arrays)
+template <typename T>
+__global__ void __launch_bounds__(256) k_load_unknowns(Grid g, VelBox boxes, int velocity, VelArrC<T> src, VelArr<T> dst)
+{
+    const int a = blockIdx.y;
+    int i, j, k;
+    if (!box_pos(boxes.b[a], blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
+    const long long q = at(g, i, j, k);
+    const T v = src.c[a] ? src.c[a][q] : T(0);
+    dst.c[a][q] = v;
+    write_images(g, velocity ? face_mask(a) : 0, velocity ? ROLE_V : ROLE_P, dst.c[a], i, j, k, v);
+}
+
+// coefficient ghost layer: every stored position writes its even images
+template <typename T>
+__global__ void __launch_bounds__(256) k_coef_ghosts(Grid g, Box box, int vmask, T *v)
+{
+    int i, j, k;
+    if (!box_pos(box, blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
+    write_images(g, vmask, ROLE_C, v, i, j, k, v[at(g, i, j, k)]);
 }
 
 // ---------------------------------------------------------------------------
@@ -799,8 +894,8 @@ static inline long long box_count(const Box &b) { return (long long)b.ext[0] * b
 template <typename T>
 void launch_smooth_p(const Grid &g, const T *b, T *x, const CoefP<T> &cf, T cvisc, int colour, hipStream_t s)
 {
-    const PBox P = smoother_pbox(g, 0, false, true);
-    const int n = pbox_total(P);
+    const Box P = unk_box(g, 0);
+    const long long n = (long long)((P.ext[0] + 1) / 2) * P.ext[1] * P.ext[2];
     if (n <= 0) return;
     if (g.D == 3)
         hipLaunchKernelGGL((k_smooth_p<T, 3>), dim3(blocks_for(n)), dim3(256), 0, s, g, P, b, x, cf, cvisc, colour);
@@ -812,8 +907,8 @@ template <typename T>
 void launch_smooth_u(const Grid &g, int a, const T *b, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc,
                      int colour, hipStream_t s)
 {
-    const PBox P = smoother_pbox(g, face_mask(a), true, true);
-    const int n = pbox_total(P);
+    const Box P = unk_box(g, face_mask(a));
+    const long long n = (long long)((P.ext[0] + 1) / 2) * P.ext[1] * P.ext[2];
     if (n <= 0) return;
     const dim3 grid(blocks_for(n)), blk(256);
     if (g.D == 3) {
@@ -836,8 +931,8 @@ template <typename T>
 int launch_resid_p(const Grid &g, const T *b, const T *x, const CoefP<T> &cf, T cvisc, T *r, double *partial,
                    hipStream_t s)
 {
-    const PBox P = smoother_pbox(g, 0, false, false);
-    const unsigned nb = stride_blocks(pbox_total(P));
+    const Box P = unk_box(g, 0);
+    const unsigned nb = stride_blocks(box_count(P));
     if (g.D == 3) hipLaunchKernelGGL((k_resid_p<T, 3>), dim3(nb), dim3(256), 0, s, g, P, b, x, cf, cvisc, r, partial);
     else hipLaunchKernelGGL((k_resid_p<T, 2>), dim3(nb), dim3(256), 0, s, g, P, b, x, cf, cvisc, r, partial);
     return (int)nb;
@@ -847,15 +942,11 @@ template <typename T>
 int launch_resid_u(const Grid &g, const VelArrC<T> &b, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc,
                    const VelArr<T> &r, double *partial, hipStream_t s)
 {
-    VelPBox parts;
+    VelBox parts;
     long long mx = 0;
     for (int a = 0; a < 3; ++a) {
-        if (a < g.D) {
-            parts.p[a] = smoother_pbox(g, face_mask(a), true, false);
-            mx = pbox_total(parts.p[a]) > mx ? pbox_total(parts.p[a]) : mx;
-        } else {
-            parts.p[a] = parts.p[0];
-        }
+        parts.b[a] = a < g.D ? unk_box(g, face_mask(a)) : Box{{0, 0, 0}, {0, 0, 0}};
+        if (a < g.D && box_count(parts.b[a]) > mx) mx = box_count(parts.b[a]);
     }
     const unsigned nb = stride_blocks(mx);
     if (g.D == 3)
@@ -1017,10 +1108,10 @@ void launch_dense_inverse(const Grid &g, int velocity, int n, const long long *u
 }
 
 template <typename T>
-void launch_dense_apply(int n, const long long *uidx, const int *ucomp, const double *M, const VelArrC<T> &b,
-                        const VelArr<T> &x, hipStream_t s)
+void launch_dense_apply(const Grid &g, int velocity, int n, const long long *uidx, const int *ucomp, const double *M,
+                        const VelArrC<T> &b, const VelArr<T> &x, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_dense_apply<T>, dim3(1), dim3(64), 0, s, n, uidx, ucomp, M, b, x);
+    hipLaunchKernelGGL(k_dense_apply<T>, dim3(1), dim3(64), 0, s, g, velocity, n, uidx, ucomp, M, b, x);
 }
 
 template <typename T>
@@ -1048,13 +1139,35 @@ void launch_cast_unknowns(const Grid &g, int ncomp, const int *vmasks, const Vel
 void launch_add_correction(const Grid &g, int ncomp, const int *vmasks, const VelArrC<float> &e,
                            const VelArr<double> &x, hipStream_t s)
 {
+    const int velocity = vmasks[0] != 0 ? 1 : 0;
     VelBox boxes;
     long long mx = 0;
     for (int a = 0; a < 3; ++a) {
         boxes.b[a] = a < ncomp ? unk_box(g, vmasks[a]) : Box{{0, 0, 0}, {0, 0, 0}};
         if (a < ncomp && box_count(boxes.b[a]) > mx) mx = box_count(boxes.b[a]);
     }
-    hipLaunchKernelGGL(k_add_correction, dim3(blocks_for(mx), ncomp), dim3(256), 0, s, g, boxes, e, x);
+    hipLaunchKernelGGL(k_add_correction, dim3(blocks_for(mx), ncomp), dim3(256), 0, s, g, boxes, velocity, e, x);
+}
+
+template <typename T>
+void launch_load_unknowns(const Grid &g, int ncomp, const int *vmasks, const VelArrC<T> &src, const VelArr<T> &dst,
+                          hipStream_t s)
+{
+    VelBox boxes;
+    long long mx = 0;
+    for (int a = 0; a < 3; ++a) {
+        boxes.b[a] = a < ncomp ? unk_box(g, vmasks[a]) : Box{{0, 0, 0}, {0, 0, 0}};
+        if (a < ncomp && box_count(boxes.b[a]) > mx) mx = box_count(boxes.b[a]);
+    }
+    const int velocity = vmasks[0] != 0 ? 1 : 0;
+    hipLaunchKernelGGL(k_load_unknowns<T>, dim3(blocks_for(mx), ncomp), dim3(256), 0, s, g, boxes, velocity, src, dst);
+}
+
+template <typename T>
+void launch_coef_ghosts(const Grid &g, int vmask, T *v, hipStream_t s)
+{
+    const Box box = stored_box(g, vmask);
+    hipLaunchKernelGGL(k_coef_ghosts<T>, dim3(blocks_for(box_count(box))), dim3(256), 0, s, g, box, vmask, v);
 }
 
 // explicit instantiations
@@ -1071,8 +1184,11 @@ void launch_add_correction(const Grid &g, int ncomp, const int *vmasks, const Ve
                                      const VelArr<T> &, T, hipStream_t, const VelArr<T> *);                         \
     template void launch_prolong_add<T>(const Grid &, const Grid &, int, const int *, int, const VelArrC<T> &,      \
                                         const VelArr<T> &, hipStream_t);                                            \
-    template void launch_dense_apply<T>(int, const long long *, const int *, const double *, const VelArrC<T> &,    \
-                                        const VelArr<T> &, hipStream_t);                                            \
+    template void launch_dense_apply<T>(const Grid &, int, int, const long long *, const int *, const double *,    \
+                                        const VelArrC<T> &, const VelArr<T> &, hipStream_t);                        \
+    template void launch_load_unknowns<T>(const Grid &, int, const int *, const VelArrC<T> &, const VelArr<T> &,    \
+                                          hipStream_t);                                                             \
+    template void launch_coef_ghosts<T>(const Grid &, int, T *, hipStream_t);                                       \
     template void launch_fill<T>(T *, long long, T, hipStream_t);
 INST(double)
 INST(float)
