@@ -1,0 +1,213 @@
+"""HIP path, FP32-refined solver and edge cases, against the FP64 oracle.
+
+Refined mode (FP32 V-cycles inside FP64 defect correction) must reach the
+1e-10 relative residual under the oracle's FP64 operator and stay within 1e-9
+of the exact discrete solution (a direct solve).  Edge cases: no nodes, no
+springs, a zero right-hand side, forced non-convergence, non-finite input,
+calls out of order, a capped hierarchy (pure relaxation), Peskin's kernel and
+a coarse viscosity scaling gamma != 1."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import oracle as O
+from oracle import step as S
+from paper_1302_3663_amd import _lib as L
+from paper_1302_3663_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def dev(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda:0").contiguous()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def ibmg():
+    from paper_1302_3663_amd import ibmg as m
+    return m
+
+
+def oracle_state(case):
+    st = S.State(case["params"], case["u0"], case["p0"], case["X"], case["ij"], case["rest"], case["K"])
+    S.setup(st)
+    return st
+
+
+def unknown_vector(H, p, vel, compact):
+    comp, pos = H.unknowns(vel)
+    if vel:
+        faces = O.split_faces(p, compact)
+        return np.array([faces[a][k, j, i] for a, (i, j, k) in zip(comp, pos)])
+    n = p["n"]
+    arr = compact.reshape((n[2], n[1], n[0]) if p["dim"] == 3 else (1, n[1], n[0]))
+    return np.array([arr[k, j, i] for (i, j, k) in pos])
+
+
+CASES = {
+    "2d_periodic_walls": lambda: synth.tiny_2d(),
+    "2d_inout_walls": lambda: synth.tiny_2d(inout=True),
+    "3d_tube": lambda: synth.tiny_3d(),
+    "channel2d_64x32": lambda: synth.channel_2d(seed=1),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("vel", [0, 1])
+@pytest.mark.parametrize("inner", [1, 2])
+def test_refined_solve(name, vel, inner, ibmg):
+    case = CASES[name]()
+    print("case", name, "velocity" if vel else "pressure", "inner", inner, flush=True)
+    p = case["params"]
+    ctx = ibmg.from_case(case, precision=L.IBB_FP32_REFINED, inner_cycles=inner)
+    st = oracle_state(case)
+    if vel:
+        b = O.momentum_rhs(p, st.u, st.rho, st.mu_c, st.mu_e, st.f)
+        x0 = st.u
+    else:
+        b = O.pressure_rhs(p, st.u + 0.01 * np.random.default_rng(4).standard_normal(st.u.size))
+        x0 = np.zeros(ctx.n_cell)
+    xg, ig = ctx.mg_solve(vel, dev(b), dev(x0))
+    xg = host(xg)
+    assert ig["relres"] <= p["rtol"]
+    # the oracle's FP64 operator agrees that the tolerance is met
+    assert st.hier.relres(bool(vel), b, xg) <= p["rtol"] * (1 + 1e-6)
+    # and the iterate is within 1e-9 of the exact discrete solution
+    A = st.hier.csr(bool(vel))
+    bu = unknown_vector(st.hier, p, bool(vel), b)
+    singular = (not vel) and not any(p["axis_bc"][a] == O.AX_INOUT for a in range(p["dim"]))
+    if singular:
+        Ad = A.toarray() + np.trace(A.toarray()) / A.shape[0] ** 2
+        xs = np.linalg.solve(Ad, bu)
+        xs -= xs.mean()
+        xu = unknown_vector(st.hier, p, False, xg)
+        xu -= xu.mean()
+    else:
+        xs = spla.spsolve(A.tocsc(), bu)
+        xu = unknown_vector(st.hier, p, bool(vel), xg)
+    assert rel(xu, xs) < 1e-9, rel(xu, xs)
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["3d_tube", "channel2d_64x32"])
+def test_refined_full_steps(name, ibmg):
+    case = CASES[name]()
+    print("case", name, flush=True)
+    ctx = ibmg.from_case(case, precision=L.IBB_FP32_REFINED, inner_cycles=2)
+    st = oracle_state(case)
+    for n in range(3):
+        sg = ctx.projection_step()
+        S.projection_step(st)
+        assert sg["relres_u"] <= 1e-10 and sg["relres_p"] <= 1e-10
+        ctx.lagrangian_update()
+        S.lagrangian_update(st)
+    u, pr = ctx.get_state()
+    X, _, _ = ctx.get_nodes()
+    # both solves stop at 1e-10; the trajectories agree to the error bound of
+    # the stopping test (conditioning times tolerance) rather than to rounding
+    assert rel(host(u), st.u) < 1e-8
+    assert rel(host(X), st.X) < 1e-10
+    ctx.close()
+
+
+def test_no_nodes_no_springs(ibmg):
+    case = synth.tiny_3d()
+    case["X"] = np.zeros((3, 0))
+    case["ij"] = np.zeros((2, 0), np.int32)
+    case["rest"] = np.zeros(0)
+    case["K"] = np.zeros(0)
+    p = case["params"]
+    ctx = ibmg.from_case(case)
+    f, rho, mc, me = [host(t) for t in ctx.get_fields(0)]
+    assert np.all(f == 0) and np.all(rho == p["rho0"]) and np.all(mc == p["mu_out"]) and np.all(me == p["mu_out"])
+    st = oracle_state(case)
+    sg = ctx.projection_step()
+    so = S.projection_step(st)
+    assert sg["cycles_u"] == so["u"]["cycles"] and sg["cycles_p"] == so["p"]["cycles"]
+    ctx.lagrangian_update()
+    u, _ = ctx.get_state()
+    assert rel(host(u), st.u) < TOL
+    ctx.close()
+
+
+def test_zero_rhs_gives_zero(ibmg):
+    case = synth.tiny_3d()
+    ctx = ibmg.from_case(case)
+    x0 = np.random.default_rng(1).standard_normal(ctx.n_cell)
+    x, info = ctx.mg_solve(0, dev(np.zeros(ctx.n_cell)), dev(x0))
+    assert info["cycles"] == 0 and np.all(host(x) == 0)
+    ctx.close()
+
+
+def test_forced_nonconvergence_and_nonfinite(ibmg):
+    case = synth.tiny_3d()
+    ctx = ibmg.from_case(case)
+    b = np.random.default_rng(2).standard_normal(ctx.n_face)
+    x, info = ctx.mg_solve(1, dev(b), dev(case["u0"]), max_cycles=1, check=False)
+    assert info["status"] == L.IBB_ENOCONV and info["cycles"] == 1 and info["relres"] > 1e-10
+    b[5] = np.nan
+    x, info = ctx.mg_solve(1, dev(b), dev(case["u0"]), check=False)
+    assert info["status"] == L.IBB_ENUMERIC
+    ctx.close()
+
+
+def test_out_of_order_and_bad_sizes(ibmg):
+    case = synth.tiny_2d()
+    p = case["params"]
+    ctx = ibmg.Context(p, 4, 4)
+    with pytest.raises(L.IbbError) as e:
+        ctx.projection_step()
+    assert e.value.status == L.IBB_ESTATE
+    with pytest.raises(L.IbbError) as e:
+        ctx.set_nodes(torch.zeros((2, 10), dtype=torch.float64, device="cuda:0"))
+    assert e.value.status == L.IBB_EINVAL
+    ctx.close()
+
+
+def test_capped_hierarchy_is_relaxation(ibmg):
+    case = synth.tiny_2d()
+    case["params"] = dict(case["params"], max_levels=1)
+    ctx = ibmg.from_case(case)
+    st = oracle_state(case)
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(ctx.n_face)
+    x0 = case["u0"] + 0.1 * rng.standard_normal(ctx.n_face)
+    xg, _ = ctx.mg_solve(1, dev(b), dev(x0), exact=3)
+    assert rel(host(xg), st.hier.vcycles(True, b, x0, 3)) < TOL
+    ctx.close()
+
+
+@pytest.mark.parametrize("variant", ["peskin", "gamma"])
+def test_kernel_and_gamma_variants(variant, ibmg):
+    case = synth.tiny_3d()
+    p = dict(case["params"])
+    if variant == "peskin":
+        p["kernel"] = 1
+    else:
+        p["gamma"] = [1.0, 0.8, 0.7] + [0.9] * 13
+    case["params"] = p
+    ctx = ibmg.from_case(case)
+    st = oracle_state(case)
+    f, rho, mc, me = [host(t) for t in ctx.get_fields(0)]
+    assert rel(rho, st.rho) < TOL and rel(mc, st.mu_c) < TOL
+    sg = ctx.projection_step()
+    so = S.projection_step(st)
+    assert sg["cycles_u"] == so["u"]["cycles"]
+    u, _ = ctx.get_state()
+    assert rel(host(u), st.u) < TOL
+    ctx.close()

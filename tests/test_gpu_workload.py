@@ -1,0 +1,114 @@
+"""The benchmark workload at full size (3D tube 64 x 64 x 128, 5 000 nodes),
+in the configuration bench.py times, checked through what the oracle can
+evaluate without its own multigrid:
+
+- the spread fields and the momentum right-hand side, every point;
+- the viscous solve: its residual under the oracle's FP64 operator, applied
+  to the GPU's full field with the boundary data;
+- the pressure right-hand side, every point;
+- the pressure solve: by the projection identity D(u~ - c beta G p) =
+  -c (b_p - A_p p) with c = eps dt / sigma, projecting the GPU's pressure with
+  the oracle's projection and taking the oracle's divergence gives the GPU
+  solve's residual under the oracle's operator;
+- the projection itself, every point;
+- the fused step (ibb_projection_step) equals the step taken piece by piece.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1302_3663_amd import _lib as L
+from paper_1302_3663_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda:0").contiguous()
+
+
+@pytest.fixture(scope="module")
+def workload():
+    return synth.WORKLOADS["tube3d_64x64x128"]()
+
+
+def unknown_mask(p, n_total):
+    unk = np.zeros(n_total, bool)
+    off = 0
+    for a in range(p["dim"]):
+        n_a, dims = O.lattice_dims(p, O.FACE, a)
+        m = np.zeros((dims[2], dims[1], dims[0]), bool)
+        sl = [slice(None)] * 3
+        if p["axis_bc"][a] == O.AX_WALLS:
+            sl[2 - a] = slice(1, dims[a] - 1)
+        elif p["axis_bc"][a] == O.AX_INOUT:
+            sl[2 - a] = slice(1, dims[a])
+        m[tuple(sl)] = True
+        unk[off:off + n_a] = m.ravel()
+        off += n_a
+    return unk
+
+
+@pytest.mark.parametrize("precision", [L.IBB_FP64, L.IBB_FP32_REFINED])
+def test_full_size_step(workload, precision):
+    from paper_1302_3663_amd import ibmg
+    case = workload
+    p = case["params"]
+    print("tube3d_64x64x128 precision", precision, flush=True)
+    ctx = ibmg.from_case(case, precision=precision, inner_cycles=2)
+    # spread fields
+    F_o, _, _ = O.springs(p, case["X"], case["ij"], case["rest"], case["K"], np.ones(case["ij"].shape[1], np.uint8),
+                          do_break=False)
+    rho_o, mc_o, me_o = O.density(p, case["X"]), O.viscosity_cells(p, case["X"]), O.viscosity_edges(p, case["X"])
+    f, rho, mc, me = [host(t) for t in ctx.get_fields(0)]
+    assert rel(rho, rho_o) < 1e-12 and rel(mc, mc_o) < 1e-12 and rel(me, me_o) < 1e-12
+    # the nodes start at rest, so the forces are rounding noise on both sides:
+    # compare against the force scale of a spring stretched by its own length
+    f_o = O.spread_vec(p, p["omega"], case["X"], F_o)
+    s_F = float(np.max(case["K"] * case["rest"]))
+    X_g, F_g, _ = ctx.get_nodes()
+    assert np.abs(host(F_g)).max() <= 1e-12 * s_F
+    scale_f = np.linalg.norm(O.spread_vec(p, p["omega"], case["X"], np.full(F_o.shape, s_F)))
+    assert np.linalg.norm(f - f_o) <= 1e-12 * scale_f
+    # momentum right-hand side
+    b = host(ctx.momentum_rhs())
+    b_o = O.momentum_rhs(p, case["u0"], rho_o, mc_o, me_o, f)
+    assert rel(b, b_o) < 1e-12
+    # viscous solve and its residual under the oracle's operator
+    ut, info = ctx.mg_solve(1, dev(b), dev(case["u0"]))
+    ut = host(ut)
+    assert info["relres"] <= 1e-10
+    unk = unknown_mask(p, ut.size)
+    b_without = O.momentum_rhs(p, case["u0"], rho_o, mc_o, me_o, f, with_boundary=False)
+    r = (b_without - O.momentum_apply_full(p, ut, rho_o, mc_o, me_o))[unk]
+    assert np.linalg.norm(r) / np.linalg.norm(b[unk]) <= 1e-10 * (1 + 1e-6)
+    # pressure right-hand side and solve
+    bp = host(ctx.pressure_rhs(dev(ut)))
+    assert rel(bp, O.pressure_rhs(p, ut)) < 1e-12
+    pres, pinfo = ctx.mg_solve(0, dev(bp), dev(np.zeros(ctx.n_cell)))
+    pres = host(pres)
+    assert pinfo["relres"] <= 1e-10
+    u_o = O.project(p, ut, pres, rho_o)
+    c = p["eps"] * p["dt"] / p["sigma"]
+    rp = np.linalg.norm(O.divergence(p, u_o)) / c
+    assert rp / np.linalg.norm(bp) <= 1e-10 * (1 + 1e-6)
+    # projection
+    u_g = host(ctx.project(dev(ut), dev(pres)))
+    assert rel(u_g, u_o) < 1e-12
+    # the fused step from the same state reproduces the pieces
+    s = ctx.projection_step()
+    u_step, p_step = [host(t) for t in ctx.get_state()]
+    assert s["relres_u"] <= 1e-10 and s["relres_p"] <= 1e-10
+    assert s["cycles_u"] == info["cycles"] and s["cycles_p"] == pinfo["cycles"]
+    assert rel(u_step, u_g) < 1e-12
+    ctx.close()
