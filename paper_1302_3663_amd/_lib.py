@@ -47,6 +47,7 @@ class Desc(ctypes.Structure):
         ("gamma", ctypes.c_double * 16),
         ("precision", ctypes.c_int),
         ("inner_cycles", ctypes.c_int),
+        ("wg_coarse_max", ctypes.c_int),
     ]
 
 
@@ -82,6 +83,7 @@ def make_desc(p, precision=IBB_FP64, inner_cycles=1):
         d.gamma[l] = g[l] if l < len(g) else 1.0
     d.precision = int(p.get("precision", precision))
     d.inner_cycles = int(p.get("inner_cycles", inner_cycles))
+    d.wg_coarse_max = int(p.get("wg_coarse_max", 0))
     return d
 
 

@@ -66,6 +66,10 @@ struct ibb_ctx {
     double *Mp = nullptr, *Mu = nullptr, *Aw = nullptr;
     // reductions
     double *partial = nullptr, *scalar = nullptr;
+    // level tables for the one-workgroup coarse cycle, and where it starts
+    LevTab<double> *tab64 = nullptr;
+    LevTab<float> *tab32 = nullptr;
+    int lc_u = MAXLEV, lc_p = MAXLEV;
     // nodes and springs
     long long eta_max = 0, m_max = 0;
     int eta = 0, m = 0;
@@ -273,6 +277,8 @@ size_t carve(ibb_ctx *c, char *base, bool dry)
     c->Mp = cv.take<double>(DENSE_MAX * DENSE_MAX);
     c->Mu = cv.take<double>(DENSE_MAX * DENSE_MAX);
     c->Aw = cv.take<double>(DENSE_MAX * DENSE_MAX);
+    c->tab64 = cv.take<LevTab<double>>(MAXLEV);
+    c->tab32 = cv.take<LevTab<float>>(MAXLEV);
     c->partial = cv.take<double>(3 * NORM_BLOCKS);
     c->scalar = cv.take<double>(8);
     const size_t em = (size_t)(c->eta_max > 0 ? c->eta_max : 1);
@@ -313,6 +319,23 @@ void setup_shapes(ibb_ctx *c, const ibb_desc *d, int64_t max_nodes, int64_t max_
     c->singular_p = true;
     for (int a = 0; a < d->dim; ++a)
         if (d->axis_bc[a] == IBB_AXIS_INOUT) c->singular_p = false;
+    // first level whose largest colour class fits one workgroup pass budget
+    const long long wgmax = d->wg_coarse_max == 0 ? 2048 : d->wg_coarse_max;
+    c->lc_u = c->lc_p = MAXLEV;
+    if (d->wg_coarse_max >= 0) {
+        // the sizes shrink with the level, so the first level that fits starts it
+        for (int l = 0; l < c->L; ++l) {
+            const Grid &g = c->lv[l].g;
+            long long mu = 0;
+            for (int a = 0; a < d->dim; ++a) {
+                const long long n = unknowns_of(g, face_mask(a));
+                mu = n > mu ? n : mu;
+            }
+            if ((mu + 1) / 2 <= wgmax) { c->lc_u = l; break; }
+        }
+        for (int l = 0; l < c->L; ++l)
+            if ((c->lv[l].np + 1) / 2 <= wgmax) { c->lc_p = l; break; }
+    }
     c->eta_max = max_nodes;
     c->m_max = max_springs;
     int nb[3];
@@ -431,6 +454,13 @@ int residual(ibb_ctx *c, bool vel, int l, double *partial)
 }
 
 template <typename T>
+const LevTab<T> *level_table(ibb_ctx *c);
+template <>
+const LevTab<double> *level_table<double>(ibb_ctx *c) { return c->tab64; }
+template <>
+const LevTab<float> *level_table<float>(ibb_ctx *c) { return c->tab32; }
+
+template <typename T>
 void vcycle(ibb_ctx *c, bool vel, int l)
 {
     Level &L = c->lv[l];
@@ -438,6 +468,14 @@ void vcycle(ibb_ctx *c, bool vel, int l)
     int vm[3];
     vel_masks(D, vm);
     const int pm[3] = {0, 0, 0};
+    if (l >= (vel ? c->lc_u : c->lc_p)) {
+        Level &LC = c->lv[c->L - 1];
+        const long long nc = vel ? LC.nu : LC.np;
+        const int ndense = nc <= DENSE_MAX ? (int)nc : 0;
+        launch_coarse_vcycle<T>(D, level_table<T>(c), l, c->L, vel ? 1 : 0, c->d.nu1, c->d.nu2, ndense,
+                                vel ? c->uidx_u : c->uidx_p, vel ? c->ucomp_u : c->ucomp_p, vel ? c->Mu : c->Mp, c->s);
+        return;
+    }
     View<T> v = view<T>(L);
     if (l == c->L - 1) {
         const long long n = vel ? L.nu : L.np;
@@ -823,6 +861,36 @@ ibb_status ibb_create(const ibb_desc *desc, int64_t max_nodes, int64_t max_sprin
         e = hipMemcpyAsync(c->uidx_u, iu.data(), iu.size() * sizeof(long long), hipMemcpyHostToDevice, c->s);
         if (e == hipSuccess) e = hipMemcpyAsync(c->ucomp_u, cu.data(), cu.size() * sizeof(int), hipMemcpyHostToDevice, c->s);
     }
+    // level tables for the one-workgroup coarse cycle
+    std::vector<LevTab<double>> t64(MAXLEV);
+    std::vector<LevTab<float>> t32(MAXLEV);
+    for (int l = 0; l < c->L; ++l) {
+        Level &L = c->lv[l];
+        LevTab<double> &a = t64[l];
+        LevTab<float> &b = t32[l];
+        a.g = b.g = L.g;
+        for (int k = 0; k < 3; ++k) {
+            a.xu[k] = L.xu[k]; a.bu[k] = L.bu[k]; a.ru[k] = L.ru[k];
+            a.rho[k] = L.rho[k]; a.beta[k] = L.beta[k]; a.mue[k] = L.mue[k];
+            b.xu[k] = L.xu32[k]; b.bu[k] = L.bu32[k]; b.ru[k] = L.ru32[k];
+            b.rho[k] = L.rho32[k]; b.beta[k] = L.beta32[k]; b.mue[k] = L.mue32[k];
+        }
+        a.xp = L.xp; a.bp = L.bp; a.rp = L.rp; a.muc = L.muc;
+        b.xp = L.xp32; b.bp = L.bp32; b.rp = L.rp32; b.muc = L.muc32;
+        const double h2 = L.g.h * L.g.h;
+        a.mass = desc->sigma / desc->dt;
+        a.cvu = desc->inv_re / h2;
+        a.cvp = 1.0 / h2;
+        b.mass = (float)(desc->sigma / desc->dt);
+        b.cvu = (float)(desc->inv_re / h2);
+        b.cvp = (float)(1.0 / h2);
+        a.nu = b.nu = L.nu;
+        a.np = b.np = L.np;
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->tab64, t64.data(), MAXLEV * sizeof(LevTab<double>), hipMemcpyHostToDevice, c->s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->tab32, t32.data(), MAXLEV * sizeof(LevTab<float>), hipMemcpyHostToDevice, c->s);
     for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&c->ev[i]);
     if (e == hipSuccess) e = hipStreamSynchronize(c->s);
     if (e == hipSuccess) e = hipGetLastError();

@@ -102,6 +102,24 @@ void launch_cast_unknowns(const Grid &g, int ncomp, const int *vmasks, const Vel
 void launch_add_correction(const Grid &g, int ncomp, const int *vmasks, const VelArrC<float> &e,
                            const VelArr<double> &x, hipStream_t s);
 
+// One level of the hierarchy as seen by the single-workgroup coarse cycle
+// (kept in device memory, written once when the context is created).
+template <typename T>
+struct LevTab {
+    Grid g;
+    T *xu[3], *bu[3], *ru[3];
+    T *xp, *bp, *rp;
+    const T *rho[3], *beta[3], *muc, *mue[3];
+    T mass, cvu, cvp;
+    long long nu, np;
+};
+
+// the V-cycle from level l0 down to the coarsest level and back inside one
+// workgroup; ndense > 0: the coarsest level is solved with the inverse M
+template <typename T>
+void launch_coarse_vcycle(int D, const LevTab<T> *tab, int l0, int L, int vel, int nu1, int nu2, int ndense,
+                          const long long *uidx, const int *ucomp, const double *M, hipStream_t s);
+
 // ---- fields (fields.hip) ----
 struct Phys {
     double sigma, eps, inv_re, force_coef, dt;

@@ -10,8 +10,14 @@
 // the inner cycles of the refined solver).  A point more than one cell away
 // from every boundary reads its neighbours at fixed offsets; points near a
 // boundary resolve each neighbour through the boundary rules of common.h.
+//
+// Multiply-adds are fused only inside one source expression, never across
+// statements, so a row computes the same bits in every kernel that inlines
+// it (the launched passes and the one-workgroup coarse cycle).
 #include "common.h"
 #include "kernels.h"
+
+#pragma clang fp contract(on)
 
 namespace ibmg {
 
@@ -886,6 +892,194 @@ __global__ void __launch_bounds__(256) k_coef_ghosts(Grid g, Box box, int vmask,
 }
 
 // ---------------------------------------------------------------------------
+// the coarse part of a V-cycle in one workgroup
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline CoefU<T> coef_u(const LevTab<T> &lt)
+{
+    CoefU<T> cf;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cf.rho[a] = lt.rho[a];
+        cf.mue[a] = lt.mue[a];
+    }
+    cf.muc = lt.muc;
+    return cf;
+}
+
+// A x and the diagonal of one row of the velocity (VEL) or pressure system
+template <typename T, int D, int VEL, int A>
+__device__ inline void wg_row(const LevTab<T> &lt, int i, int j, int k, T &Ax, T &dg)
+{
+    if (VEL) {
+        const VelArr<T> x{{lt.xu[0], lt.xu[1], lt.xu[2]}};
+        u_row<T, D, A>(lt.g, x, coef_u(lt), lt.mass, lt.cvu, i, j, k, Ax, dg);
+    } else {
+        const CoefP<T> cf{{lt.beta[0], lt.beta[1], lt.beta[2]}};
+        p_row<T, D>(lt.g, lt.xp, cf, lt.cvp, i, j, k, Ax, dg);
+    }
+}
+
+// one red-black Gauss-Seidel pass over the unknowns of component A, the
+// same update and order as the launched smoother
+template <typename T, int D, int VEL, int A>
+__device__ inline void wg_sweep_comp(const LevTab<T> &lt)
+{
+    const Grid &g = lt.g;
+    const int vmask = VEL ? face_mask(A) : 0;
+    const Box box = unk_box(g, vmask);
+    const int n = ((box.ext[0] + 1) >> 1) * box.ext[1] * box.ext[2];
+    T *x = VEL ? lt.xu[A] : lt.xp;
+    const T *b = VEL ? lt.bu[A] : lt.bp;
+    for (int colour = 0; colour < 2; ++colour) {
+        for (int t = threadIdx.x; t < n; t += blockDim.x) {
+            int i, j, k;
+            if (!box_colour_pos(box, colour, t, i, j, k)) continue;
+            T Ax, dg;
+            wg_row<T, D, VEL, A>(lt, i, j, k, Ax, dg);
+            const long long e = at(g, i, j, k);
+            const T xn = x[e] + (b[e] - Ax) / dg;
+            x[e] = xn;
+            write_images(g, vmask, VEL ? ROLE_V : ROLE_P, x, i, j, k, xn);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T, int D, int VEL>
+__device__ void wg_sweep(const LevTab<T> &lt)
+{
+    wg_sweep_comp<T, D, VEL, 0>(lt);
+    if (VEL) {
+        wg_sweep_comp<T, D, VEL, 1>(lt);
+        if (D == 3) wg_sweep_comp<T, D, VEL, (D == 3 ? 2 : 1)>(lt);
+    }
+}
+
+template <typename T, int D, int VEL, int A>
+__device__ inline void wg_residual_comp(const LevTab<T> &lt)
+{
+    const Box box = unk_box(lt.g, VEL ? face_mask(A) : 0);
+    const int n = box.ext[0] * box.ext[1] * box.ext[2];
+    T *r = VEL ? lt.ru[A] : lt.rp;
+    const T *b = VEL ? lt.bu[A] : lt.bp;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        int i, j, k;
+        box_pos(box, t, i, j, k);
+        T Ax, dg;
+        wg_row<T, D, VEL, A>(lt, i, j, k, Ax, dg);
+        const long long e = at(lt.g, i, j, k);
+        r[e] = b[e] - Ax;
+    }
+}
+
+// coarse right-hand side = restriction of the fine residual, coarse
+// correction cleared (with its images)
+template <typename T, int D, int VEL, int A>
+__device__ inline void wg_restrict_comp(const LevTab<T> &lt, const LevTab<T> &lc)
+{
+    const int vmask = VEL ? face_mask(A) : 0;
+    const int role = VEL ? ROLE_V : ROLE_P;
+    const Box box = unk_box(lc.g, vmask);
+    const int n = box.ext[0] * box.ext[1] * box.ext[2];
+    const T *src = VEL ? lt.ru[A] : lt.rp;
+    T *bc = VEL ? lc.bu[A] : lc.bp;
+    T *xc = VEL ? lc.xu[A] : lc.xp;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        int I, J, K;
+        box_pos(box, t, I, J, K);
+        const long long e = at(lc.g, I, J, K);
+        bc[e] = (T)restrict_any<T, D>(vmask, lt.g, role, src, I, J, K);
+        xc[e] = T(0);
+        write_images(lc.g, vmask, role, xc, I, J, K, T(0));
+    }
+}
+
+template <typename T, int D, int VEL, int A>
+__device__ inline void wg_prolong_comp(const LevTab<T> &lc, const LevTab<T> &lt)
+{
+    const int vmask = VEL ? face_mask(A) : 0;
+    const int role = VEL ? ROLE_V : ROLE_P;
+    const Box box = unk_box(lt.g, vmask);
+    const int n = box.ext[0] * box.ext[1] * box.ext[2];
+    const T *src = VEL ? lc.xu[A] : lc.xp;
+    T *x = VEL ? lt.xu[A] : lt.xp;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        int i, j, k;
+        box_pos(box, t, i, j, k);
+        const long long e = at(lt.g, i, j, k);
+        const T v = x[e] + (T)prolong_any<T, D>(vmask, lc.g, role, src, i, j, k);
+        x[e] = v;
+        write_images(lt.g, vmask, role, x, i, j, k, v);
+    }
+}
+
+// The part of a V-cycle from level l0 down to the coarsest level and back,
+// in one workgroup: the same passes, in the same order, as the launched
+// kernels, with a barrier where a launch boundary would be.
+template <typename T, int D, int VEL>
+__global__ void __launch_bounds__(1024) k_coarse_vcycle(const LevTab<T> *__restrict__ tab, int l0, int L, int nu1,
+                                                         int nu2, int ndense, const long long *__restrict__ uidx,
+                                                         const int *__restrict__ ucomp, const double *__restrict__ M)
+{
+    constexpr int A2 = D == 3 ? 2 : 1;
+    for (int l = l0; l < L - 1; ++l) {
+        const LevTab<T> lt = tab[l];
+        for (int s = 0; s < nu1; ++s) wg_sweep<T, D, VEL>(lt);
+        wg_residual_comp<T, D, VEL, 0>(lt);
+        if (VEL) {
+            wg_residual_comp<T, D, VEL, 1>(lt);
+            if (D == 3) wg_residual_comp<T, D, VEL, A2>(lt);
+        }
+        __syncthreads();
+        const LevTab<T> lc = tab[l + 1];
+        wg_restrict_comp<T, D, VEL, 0>(lt, lc);
+        if (VEL) {
+            wg_restrict_comp<T, D, VEL, 1>(lt, lc);
+            if (D == 3) wg_restrict_comp<T, D, VEL, A2>(lt, lc);
+        }
+        __syncthreads();
+    }
+    {
+        const LevTab<T> lt = tab[L - 1];
+        if (ndense > 0) {
+            __shared__ double bv[64];
+            const int r = threadIdx.x;
+            if (r < ndense) {
+                const int c = ucomp[r];
+                const T *b = VEL ? (c == 0 ? lt.bu[0] : (c == 1 ? lt.bu[1] : lt.bu[2])) : lt.bp;
+                bv[r] = (double)b[uidx[r]];
+            }
+            __syncthreads();
+            if (r < ndense) {
+                double sum = 0.0;
+                for (int j = 0; j < ndense; ++j) sum += M[r * ndense + j] * bv[j];
+                const int c = ucomp[r];
+                T *x = VEL ? (c == 0 ? lt.xu[0] : (c == 1 ? lt.xu[1] : lt.xu[2])) : lt.xp;
+                x[uidx[r]] = (T)sum;
+                int i, jj, k;
+                decode(lt.g, uidx[r], i, jj, k);
+                write_images(lt.g, VEL ? face_mask(c) : 0, VEL ? ROLE_V : ROLE_P, x, i, jj, k, (T)sum);
+            }
+            __syncthreads();
+        } else {
+            for (int s = 0; s < nu1 + nu2; ++s) wg_sweep<T, D, VEL>(lt);
+        }
+    }
+    for (int l = L - 2; l >= l0; --l) {
+        const LevTab<T> lt = tab[l];
+        const LevTab<T> lc = tab[l + 1];
+        wg_prolong_comp<T, D, VEL, 0>(lc, lt);
+        if (VEL) {
+            wg_prolong_comp<T, D, VEL, 1>(lc, lt);
+            if (D == 3) wg_prolong_comp<T, D, VEL, A2>(lc, lt);
+        }
+        __syncthreads();
+        for (int s = 0; s < nu2; ++s) wg_sweep<T, D, VEL>(lt);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 static inline unsigned blocks_for(long long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
@@ -1169,6 +1363,27 @@ void launch_coef_ghosts(const Grid &g, int vmask, T *v, hipStream_t s)
     const Box box = stored_box(g, vmask);
     hipLaunchKernelGGL(k_coef_ghosts<T>, dim3(blocks_for(box_count(box))), dim3(256), 0, s, g, box, vmask, v);
 }
+
+template <typename T>
+void launch_coarse_vcycle(int D, const LevTab<T> *tab, int l0, int L, int vel, int nu1, int nu2, int ndense,
+                          const long long *uidx, const int *ucomp, const double *M, hipStream_t s)
+{
+#define LAUNCH(DD, VV)                                                                                              \
+    hipLaunchKernelGGL((k_coarse_vcycle<T, DD, VV>), dim3(1), dim3(1024), 0, s, tab, l0, L, nu1, nu2, ndense, uidx, \
+                       ucomp, M)
+    if (D == 3) {
+        if (vel) LAUNCH(3, 1);
+        else LAUNCH(3, 0);
+    } else {
+        if (vel) LAUNCH(2, 1);
+        else LAUNCH(2, 0);
+    }
+#undef LAUNCH
+}
+template void launch_coarse_vcycle<double>(int, const LevTab<double> *, int, int, int, int, int, int,
+                                           const long long *, const int *, const double *, hipStream_t);
+template void launch_coarse_vcycle<float>(int, const LevTab<float> *, int, int, int, int, int, int,
+                                          const long long *, const int *, const double *, hipStream_t);
 
 // explicit instantiations
 #define INST(T)                                                                                                     \

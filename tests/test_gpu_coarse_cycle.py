@@ -1,0 +1,61 @@
+"""The coarse part of a V-cycle run inside one workgroup must take exactly the
+passes of the launched kernels: iterates agree bit for bit with the launched
+path (switch-over disabled), whatever level the switch happens at."""
+import numpy as np
+import pytest
+
+from paper_1302_3663_amd import _lib as L
+from paper_1302_3663_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda:0").contiguous()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+CASES = {
+    "2d_periodic_walls": lambda: synth.tiny_2d(),
+    "2d_inout_walls": lambda: synth.tiny_2d(inout=True),
+    "3d_tube": lambda: synth.tiny_3d(),
+    "3d_periodic_z": lambda: synth.tiny_3d(periodic_z=True),
+    "channel2d_64x32": lambda: synth.channel_2d(seed=1),
+}
+
+
+def run(case, wg, precision):
+    from paper_1302_3663_amd import ibmg
+    c = dict(case)
+    c["params"] = dict(case["params"], wg_coarse_max=wg)
+    ctx = ibmg.from_case(c, precision=precision, inner_cycles=2)
+    rng = np.random.default_rng(7)
+    out = []
+    for vel, n in ((1, ctx.n_face), (0, ctx.n_cell)):
+        b = rng.standard_normal(n)
+        x0 = case["u0"] if vel else np.zeros(n)
+        x, _ = ctx.mg_solve(vel, dev(b), dev(x0), exact=3)
+        out.append(host(x))
+    s = ctx.projection_step()
+    u, p = ctx.get_state()
+    out += [host(u), host(p)]
+    ctx.close()
+    return out, (s["cycles_u"], s["cycles_p"])
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("precision", [L.IBB_FP64, L.IBB_FP32_REFINED])
+@pytest.mark.parametrize("wg", [0, 64, 8])
+def test_workgroup_cycle_matches_launched(name, precision, wg):
+    print("case", name, "precision", precision, "wg", wg, flush=True)
+    case = CASES[name]()
+    ref, cyc_ref = run(case, -1, precision)
+    got, cyc = run(case, wg, precision)
+    assert cyc == cyc_ref
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b)
