@@ -224,6 +224,43 @@ ibb_status ibb_interp(ibb_ctx *ctx, double width, int64_t n, const double *X, co
  * `width` (eq:discrForceCouple); out is compact faces. */
 ibb_status ibb_spread(ibb_ctx *ctx, double width, int64_t n, const double *X, const double *F, double *out);
 
+/* --- groups: several contexts stepped together (serving) ------------------
+ *
+ * A group steps independent contexts (different grids, dimensions,
+ * coefficients, nodes) together so that their multigrid passes share
+ * launches: every smoothing, residual, restriction and prolongation pass of
+ * one level runs as one launch over all members of one dimension, and the
+ * coarse part of every member's V-cycle runs in one launch with one
+ * workgroup per member.  One tick of a solve (an FP64 V-cycle, or a refined
+ * outer iteration with its inner FP32 V-cycles, then the FP64 residual and
+ * its norm) is captured once as a HIP graph at creation and replayed; a
+ * member that has met its stopping test is switched off by a device flag.
+ * Each member follows exactly the sequence of operations of its own
+ * ibb_projection_step / ibb_lagrangian_update, so its results are the same
+ * as when it is stepped alone.
+ *
+ * Members must agree on precision, nu1, nu2 and (refined) inner_cycles
+ * (IBB_EINVAL otherwise) and may not repeat.  They must outlive the group and
+ * keep their workspaces; a member can still be used on its own between group
+ * calls.  The group's work runs on a stream of its own, ordered after each
+ * member's stream on entry, with each member's stream ordered after it on
+ * return.  The workspace (device memory, >= ibb_group_footprint_bytes,
+ * owned by the caller, kept until ibb_group_destroy) holds the launch
+ * tables, the member flags and the norms. */
+typedef struct ibb_group ibb_group;
+
+ibb_status ibb_group_footprint_bytes(ibb_ctx *const *ctxs, int n, size_t *bytes);
+ibb_status ibb_group_create(ibb_ctx *const *ctxs, int n, void *workspace, size_t bytes, ibb_group **out);
+ibb_status ibb_group_destroy(ibb_group *group);
+/* One projection step of every member (as ibb_projection_step); per_ctx
+ * (host, n entries, may be null) receives each member's statistics, with the
+ * group's solve times.  A member that did not converge is reported in its
+ * statistics and makes the call return its status; the others are stepped. */
+ibb_status ibb_group_projection_step(ibb_group *group, ibb_solve_stats *per_ctx);
+/* One Lagrangian update of every member (as ibb_lagrangian_update). */
+ibb_status ibb_group_lagrangian_update(ibb_group *group, ibb_lag_stats *per_ctx);
+const char *ibb_group_last_error(const ibb_group *group);
+
 /* --- diagnostics ----------------------------------------------------------- */
 
 /* Device timing of the finest-level multigrid kernels.  While enabled, every

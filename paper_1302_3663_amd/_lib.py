@@ -121,6 +121,13 @@ ABI_FUNCTIONS = {
     "ibb_profile_read": (ctypes.c_int, [CTX, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong),
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
     "ibb_level_info": (ctypes.c_int, [CTX, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "ibb_group_footprint_bytes": (ctypes.c_int, [ctypes.POINTER(CTX), ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    "ibb_group_create": (ctypes.c_int, [ctypes.POINTER(CTX), ctypes.c_int, VP, ctypes.c_size_t,
+                                        ctypes.POINTER(VP)]),
+    "ibb_group_destroy": (ctypes.c_int, [VP]),
+    "ibb_group_projection_step": (ctypes.c_int, [VP, ctypes.POINTER(SolveStats)]),
+    "ibb_group_lagrangian_update": (ctypes.c_int, [VP, ctypes.POINTER(LagStats)]),
+    "ibb_group_last_error": (ctypes.c_char_p, [VP]),
 }
 
 _lib = None

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -773,6 +774,78 @@ ibb_status faces_out(ibb_ctx *c, int level, double *const *src, double *dst)
     return IBB_OK;
 }
 
+// ---- the pieces of a step, shared by single contexts and groups --------
+
+// momentum right-hand side at u^n; the viscous iterate starts from u^n
+void proj_viscous_rhs(ibb_ctx *c)
+{
+    Level &L0 = c->lv[0];
+    View<double> v = view64(L0);
+    int vm[3];
+    vel_masks(c->d.dim, vm);
+    launch_load_unknowns<double>(L0.g, c->d.dim, vm, VelArrC<double>{{c->u[0], c->u[1], c->u[2]}}, v.xu, c->s);
+    launch_momentum_rhs(L0.g, c->ph, VelArrC<double>{{c->u[0], c->u[1], c->u[2]}}, v.cu,
+                        VelArrC<double>{{c->f[0], c->f[1], c->f[2]}}, v.bu, c->s);
+}
+
+// pressure right-hand side from u~; the pressure iterate starts from p^n
+void proj_pressure_rhs(ibb_ctx *c)
+{
+    Level &L0 = c->lv[0];
+    View<double> v = view64(L0);
+    const int pm[3] = {0, 0, 0};
+    launch_pressure_div(L0.g, c->ph, cview(v.xu), VelArrC<double>{{c->u[0], c->u[1], c->u[2]}}, L0.bp, c->s);
+    if (c->singular_p) remove_cell_mean(c, L0.bp);
+    launch_load_unknowns<double>(L0.g, 1, pm, VelArrC<double>{{c->p, nullptr, nullptr}},
+                                 VelArr<double>{{L0.xp, nullptr, nullptr}}, c->s);
+}
+
+// p^{n+1} into the state; the unknown faces of the state take
+// u~ - (eps dt / sigma) beta G p
+void proj_finish(ibb_ctx *c)
+{
+    Level &L0 = c->lv[0];
+    View<double> v = view64(L0);
+    if (c->singular_p) remove_cell_mean(c, L0.xp);
+    launch_copy(L0.xp, c->p, L0.g.nel, c->s);
+    launch_project(L0.g, c->ph, cview(v.xu), L0.xp, v.cp, VelArr<double>{{c->u[0], c->u[1], c->u[2]}}, c->s);
+}
+
+void fill_stats(ibb_ctx *c, const SolveOut &su, const SolveOut &sp, float tu, float tp, ibb_solve_stats *stats)
+{
+    if (!stats) return;
+    stats->status_u = su.status;
+    stats->status_p = sp.status;
+    stats->cycles_u = su.cycles;
+    stats->cycles_p = sp.cycles;
+    stats->vcycles_u = su.vcycles;
+    stats->vcycles_p = sp.vcycles;
+    stats->relres_u = su.relres;
+    stats->relres_p = sp.relres;
+    stats->t_u_ms = tu;
+    stats->t_p_ms = tp;
+    stats->dof_u = c->lv[0].nu;
+    stats->dof_p = c->lv[0].np;
+}
+
+// interpolation, node update, breakage, forces, spread and the coefficient
+// hierarchy; the counters (broken this step, alive) are left on the device
+ibb_status lag_launch(ibb_ctx *c)
+{
+    Level &L0 = c->lv[0];
+    const long long em = c->eta_max > 0 ? c->eta_max : 1;
+    launch_interp(L0.g, c->d.kernel, c->d.h, VelArrC<double>{{c->u[0], c->u[1], c->u[2]}}, c->X, em, c->eta, c->U,
+                  em, c->s);
+    launch_euler(L0.g, c->d.dt / c->d.sigma, c->U, c->X, em, c->eta, c->s);
+    launch_fill<int>(c->counters, 2, 0, c->s);
+    if (c->have_springs && c->m > 0)
+        launch_spring_break(L0.g, c->d.break_ratio, c->X, em, c->ij, c->m, c->rest, c->alive, c->counters, c->s);
+    ibb_status st = rebuild_coefficients(c);
+    if (st) return st;
+    if (c->have_springs) launch_count_alive(c->alive, c->m, c->counters + 1, c->s);
+    return IBB_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -994,54 +1067,26 @@ ibb_status ibb_projection_step(ibb_ctx *c, ibb_solve_stats *stats)
 {
     if (!c) return IBB_EINVAL;
     if (!c->have_coefs) return fail(c, IBB_ESTATE, "ibb_projection_step: coefficients not built");
-    Level &L0 = c->lv[0];
-    const int D = c->d.dim;
-    const long long n0 = L0.g.nel;
-    View<double> v = view64(L0);
-    int vm[3];
-    vel_masks(D, vm);
-    const int pm[3] = {0, 0, 0};
     // momentum right-hand side and the viscous solve, warm start u^n
-    launch_load_unknowns<double>(L0.g, D, vm, VelArrC<double>{{c->u[0], c->u[1], c->u[2]}}, v.xu, c->s);
-    launch_momentum_rhs(L0.g, c->ph, VelArrC<double>{{c->u[0], c->u[1], c->u[2]}}, v.cu,
-                        VelArrC<double>{{c->f[0], c->f[1], c->f[2]}}, v.bu, c->s);
+    proj_viscous_rhs(c);
     HIPCHK(hipEventRecord(c->ev[0], c->s));
     SolveOut su, sp;
     ibb_status st = solve(c, true, c->d.max_cycles, 0, &su);
     if (st) return st;
     HIPCHK(hipEventRecord(c->ev[1], c->s));
     // pressure right-hand side and solve, warm start p^n
-    launch_pressure_div(L0.g, c->ph, cview(v.xu), VelArrC<double>{{c->u[0], c->u[1], c->u[2]}}, L0.bp, c->s);
-    if (c->singular_p) remove_cell_mean(c, L0.bp);
-    launch_load_unknowns<double>(L0.g, 1, pm, VelArrC<double>{{c->p, nullptr, nullptr}},
-                                 VelArr<double>{{L0.xp, nullptr, nullptr}}, c->s);
+    proj_pressure_rhs(c);
     HIPCHK(hipEventRecord(c->ev[2], c->s));
     st = solve(c, false, c->d.max_cycles, 0, &sp);
     if (st) return st;
     HIPCHK(hipEventRecord(c->ev[3], c->s));
-    if (c->singular_p) remove_cell_mean(c, L0.xp);
-    launch_copy(L0.xp, c->p, n0, c->s);
-    // projection: the unknown faces of the state take u~ - (eps dt / sigma) beta G p
-    launch_project(L0.g, c->ph, cview(v.xu), L0.xp, v.cp, VelArr<double>{{c->u[0], c->u[1], c->u[2]}}, c->s);
+    proj_finish(c);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->s));
-    if (stats) {
-        float tu = 0, tp = 0;
-        (void)hipEventElapsedTime(&tu, c->ev[0], c->ev[1]);
-        (void)hipEventElapsedTime(&tp, c->ev[2], c->ev[3]);
-        stats->status_u = su.status;
-        stats->status_p = sp.status;
-        stats->cycles_u = su.cycles;
-        stats->cycles_p = sp.cycles;
-        stats->vcycles_u = su.vcycles;
-        stats->vcycles_p = sp.vcycles;
-        stats->relres_u = su.relres;
-        stats->relres_p = sp.relres;
-        stats->t_u_ms = tu;
-        stats->t_p_ms = tp;
-        stats->dof_u = L0.nu;
-        stats->dof_p = L0.np;
-    }
+    float tu = 0, tp = 0;
+    (void)hipEventElapsedTime(&tu, c->ev[0], c->ev[1]);
+    (void)hipEventElapsedTime(&tp, c->ev[2], c->ev[3]);
+    fill_stats(c, su, sp, tu, tp, stats);
     if (su.status) return fail(c, (ibb_status)su.status, "viscous solve did not converge");
     if (sp.status) return fail(c, (ibb_status)sp.status, "pressure solve did not converge");
     return IBB_OK;
@@ -1051,18 +1096,9 @@ ibb_status ibb_lagrangian_update(ibb_ctx *c, ibb_lag_stats *stats)
 {
     if (!c) return IBB_EINVAL;
     if (!c->have_coefs) return fail(c, IBB_ESTATE, "ibb_lagrangian_update: coefficients not built");
-    Level &L0 = c->lv[0];
-    const long long em = c->eta_max > 0 ? c->eta_max : 1;
     HIPCHK(hipEventRecord(c->ev[0], c->s));
-    launch_interp(L0.g, c->d.kernel, c->d.h, VelArrC<double>{{c->u[0], c->u[1], c->u[2]}}, c->X, em, c->eta, c->U,
-                  em, c->s);
-    launch_euler(L0.g, c->d.dt / c->d.sigma, c->U, c->X, em, c->eta, c->s);
-    launch_fill<int>(c->counters, 2, 0, c->s);
-    if (c->have_springs && c->m > 0)
-        launch_spring_break(L0.g, c->d.break_ratio, c->X, em, c->ij, c->m, c->rest, c->alive, c->counters, c->s);
-    ibb_status st = rebuild_coefficients(c);
+    ibb_status st = lag_launch(c);
     if (st) return st;
-    if (c->have_springs) launch_count_alive(c->alive, c->m, c->counters + 1, c->s);
     HIPCHK(hipEventRecord(c->ev[1], c->s));
     int cnt[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(cnt, c->counters, 2 * sizeof(int), hipMemcpyDeviceToHost, c->s));
@@ -1255,6 +1291,546 @@ ibb_status ibb_level_info(const ibb_ctx *c, int level, int *nlevels, int n[3])
         if (level < 0 || level >= c->L) return IBB_EINVAL;
         for (int d = 0; d < 3; ++d) n[d] = c->lv[level].g.n[d];
     }
+    return IBB_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// groups: several contexts stepped together on one stream.  Every pass of
+// the members' V-cycles that can share a launch does (one launch per pass,
+// level and dimension), and one tick of a solve (the V-cycle or refined
+// outer iteration, the residual and its norm) is captured once as a HIP
+// graph and replayed; members that have converged are switched off by a
+// device-side flag, so the graph never changes while the group lives.
+// ===========================================================================
+namespace {
+
+enum { GK_REDUCE = 10, GK_COARSE = 11 };
+
+struct GOp {
+    int kind;       // BK_* or GK_*
+    int prec;       // 0: FP64 tables, 1: FP32 tables
+    int D, vel, A, colour;
+    size_t off;     // first BEntry (or BCoarse) of the launch
+    unsigned n;     // blocks (or items)
+};
+
+struct Plan {
+    std::vector<BEntry> ent;
+    std::vector<BCoarse> cent;
+    std::vector<GOp> ops[2];   // tick of the pressure (0) and the viscous (1) solve
+};
+
+}  // namespace
+
+struct ibb_group {
+    std::vector<ibb_ctx *> m;
+    hipStream_t s = nullptr;
+    bool refined = false;
+    int inner = 1, nu1 = 2, nu2 = 2;
+    BEntry *ent = nullptr;
+    BCoarse *cent = nullptr;
+    int *flags = nullptr;
+    double *norms = nullptr;
+    int *counts = nullptr;
+    Plan plan;
+    hipGraphExec_t exec[2] = {};
+    std::vector<int> hflags, dflags;   // wanted flags, flags on the device
+    hipEvent_t ev[5] = {};
+    std::string err;
+};
+
+#define GCHK(expr)                                                                           \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            g->err = std::string(#expr) + ": " + hipGetErrorString(e_);                      \
+            return IBB_EDEVICE;                                                              \
+        }                                                                                    \
+    } while (0)
+
+namespace {
+
+// last level a member's V-cycle runs with launched passes (the coarse part,
+// from there down, runs in one workgroup per member)
+int coarse_start(const ibb_ctx *c, bool vel)
+{
+    const int lc = vel ? c->lc_u : c->lc_p;
+    return lc < c->L - 1 ? lc : c->L - 1;
+}
+
+const void *table_at(ibb_ctx *c, int prec, int l)
+{
+    return prec ? (const void *)(c->tab32 + l) : (const void *)(c->tab64 + l);
+}
+
+// one batched pass over the members listed in `who`, one launch per dimension
+void plan_pass(Plan &P, std::vector<GOp> &ops, const std::vector<ibb_ctx *> &m, const std::vector<int> &who, int kind,
+               int prec, bool vel, int A, int colour, int l, bool norm)
+{
+    for (int D = 2; D <= 3; ++D) {
+        GOp op{kind, prec, D, vel ? 1 : 0, A, colour, P.ent.size(), 0};
+        for (int i : who) {
+            ibb_ctx *c = m[i];
+            if (c->d.dim != D) continue;
+            if (kind == BK_SWEEP && vel && A >= D) continue;
+            const Grid &gl = c->lv[l].g;
+            const Grid &gc = l + 1 < c->L ? c->lv[l + 1].g : gl;
+            const int nb = batch_blocks(kind, gl, gc, vel ? 1 : 0, A);
+            BEntry e{};
+            e.tab = table_at(c, prec, l);
+            e.tab2 = table_at(c, 1, 0);
+            e.partial = norm ? c->partial : nullptr;
+            e.base = (int)op.n;
+            e.nb = nb;
+            e.ctx = i;
+            for (int b = 0; b < nb; ++b) P.ent.push_back(e);
+            op.n += nb;
+        }
+        if (op.n) ops.push_back(op);
+    }
+}
+
+void plan_sweeps(Plan &P, std::vector<GOp> &ops, const std::vector<ibb_ctx *> &m, const std::vector<int> &who, int prec,
+                 bool vel, int l)
+{
+    for (int A = 0; A < (vel ? 3 : 1); ++A)
+        for (int colour = 0; colour < 2; ++colour) plan_pass(P, ops, m, who, BK_SWEEP, prec, vel, A, colour, l, false);
+}
+
+// one V-cycle of every member, in each member's own order of passes
+void plan_vcycle(Plan &P, std::vector<GOp> &ops, const std::vector<ibb_ctx *> &m, int prec, bool vel, int nu1,
+                 int nu2)
+{
+    const int n = (int)m.size();
+    int maxl = 0;
+    for (ibb_ctx *c : m) maxl = std::max(maxl, coarse_start(c, vel));
+    auto members_above = [&](int l) {
+        std::vector<int> w;
+        for (int i = 0; i < n; ++i)
+            if (l < coarse_start(m[i], vel)) w.push_back(i);
+        return w;
+    };
+    for (int l = 0; l < maxl; ++l) {
+        const std::vector<int> w = members_above(l);
+        for (int s = 0; s < nu1; ++s) plan_sweeps(P, ops, m, w, prec, vel, l);
+        plan_pass(P, ops, m, w, BK_RESID, prec, vel, 0, 0, l, false);
+        plan_pass(P, ops, m, w, BK_RESTRICT, prec, vel, 0, 0, l, false);
+    }
+    for (int D = 2; D <= 3; ++D) {
+        GOp op{GK_COARSE, prec, D, vel ? 1 : 0, 0, 0, P.cent.size(), 0};
+        for (int i = 0; i < n; ++i) {
+            ibb_ctx *c = m[i];
+            if (c->d.dim != D) continue;
+            Level &LC = c->lv[c->L - 1];
+            const long long nc = vel ? LC.nu : LC.np;
+            BCoarse it{};
+            it.tab = table_at(c, prec, 0);
+            it.uidx = vel ? c->uidx_u : c->uidx_p;
+            it.ucomp = vel ? c->ucomp_u : c->ucomp_p;
+            it.M = vel ? c->Mu : c->Mp;
+            it.l0 = coarse_start(c, vel);
+            it.L = c->L;
+            it.ndense = nc <= DENSE_MAX ? (int)nc : 0;
+            it.ctx = i;
+            P.cent.push_back(it);
+            op.n++;
+        }
+        if (op.n) ops.push_back(op);
+    }
+    for (int l = maxl - 1; l >= 0; --l) {
+        const std::vector<int> w = members_above(l);
+        plan_pass(P, ops, m, w, BK_PROLONG, prec, vel, 0, 0, l, false);
+        for (int s = 0; s < nu2; ++s) plan_sweeps(P, ops, m, w, prec, vel, l);
+    }
+}
+
+// one tick: an FP64 V-cycle (or a refined outer iteration), then the FP64
+// residual with its norm
+void plan_tick(Plan &P, std::vector<GOp> &ops, const std::vector<ibb_ctx *> &m, bool refined, int inner, bool vel,
+               int nu1, int nu2)
+{
+    std::vector<int> all(m.size());
+    for (size_t i = 0; i < m.size(); ++i) all[i] = (int)i;
+    if (refined) {
+        plan_pass(P, ops, m, all, BK_PREP, 0, vel, 0, 0, 0, false);
+        for (int it = 0; it < inner; ++it) plan_vcycle(P, ops, m, 1, vel, nu1, nu2);
+        plan_pass(P, ops, m, all, BK_ADD, 0, vel, 0, 0, 0, false);
+    } else {
+        plan_vcycle(P, ops, m, 0, vel, nu1, nu2);
+    }
+    plan_pass(P, ops, m, all, BK_RESID, 0, vel, 0, 0, 0, true);
+    GOp red{GK_REDUCE, 0, 0, vel ? 1 : 0, 0, 0, P.ent.size(), 0};
+    for (size_t i = 0; i < m.size(); ++i) {
+        ibb_ctx *c = m[i];
+        BEntry e{};
+        e.partial = c->partial;
+        e.nb = batch_blocks(BK_RESID, c->lv[0].g, c->lv[0].g, vel ? 1 : 0, 0) * (vel ? c->d.dim : 1);
+        e.ctx = (int)i;
+        P.ent.push_back(e);
+        red.n++;
+    }
+    ops.push_back(red);
+}
+
+void build_plan(Plan &P, const std::vector<ibb_ctx *> &m, bool refined, int inner, int nu1, int nu2)
+{
+    for (int vel = 0; vel < 2; ++vel) plan_tick(P, P.ops[vel], m, refined, inner, vel == 1, nu1, nu2);
+}
+
+void emit_ops(ibb_group *g, const std::vector<GOp> &ops)
+{
+    for (const GOp &op : ops) {
+        switch (op.kind) {
+        case GK_REDUCE: launch_breduce(g->ent + op.off, op.n, g->flags, g->norms, g->s); break;
+        case GK_COARSE:
+            if (op.prec) launch_bcoarse<float>(op.D, op.vel, g->cent + op.off, op.n, g->flags, g->nu1, g->nu2, g->s);
+            else launch_bcoarse<double>(op.D, op.vel, g->cent + op.off, op.n, g->flags, g->nu1, g->nu2, g->s);
+            break;
+        default:
+            if (op.prec)
+                launch_bpass<float>(op.kind, op.D, op.vel, op.A, op.colour, g->ent + op.off, op.n, g->flags, g->s);
+            else
+                launch_bpass<double>(op.kind, op.D, op.vel, op.A, op.colour, g->ent + op.off, op.n, g->flags, g->s);
+        }
+    }
+}
+
+ibb_status check_members(ibb_ctx *const *ctxs, int n)
+{
+    if (!ctxs || n < 1) return IBB_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i]) return IBB_EINVAL;
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return IBB_EINVAL;
+        const ibb_desc &a = ctxs[0]->d, &b = ctxs[i]->d;
+        if (a.precision != b.precision || a.nu1 != b.nu1 || a.nu2 != b.nu2) return IBB_EINVAL;
+        if (a.precision == IBB_FP32_REFINED && a.inner_cycles != b.inner_cycles) return IBB_EINVAL;
+    }
+    return IBB_OK;
+}
+
+size_t group_bytes(const Plan &P, int n)
+{
+    Carver cv{nullptr, 0, true};
+    cv.take<BEntry>(P.ent.size());
+    cv.take<BCoarse>(P.cent.size());
+    cv.take<int>(n);
+    cv.take<double>(n);
+    cv.take<int>(2 * (size_t)n);
+    return cv.off + 256;
+}
+
+struct GroupSolve {
+    std::vector<SolveOut> out;
+    std::vector<double> nb, rel;
+    std::vector<char> done;
+};
+
+// both norms of a member's start (||b||, then ||b - A x0||) into its slot
+ibb_status group_norms(ibb_group *g, bool vel, bool resid, const std::vector<char> &skip, std::vector<double> &h)
+{
+    const int n = (int)g->m.size();
+    for (int i = 0; i < n; ++i) {
+        if (skip[i]) continue;
+        ibb_ctx *c = g->m[i];
+        Level &L = c->lv[0];
+        int np;
+        if (resid) {
+            np = residual<double>(c, vel, 0, c->partial);
+        } else {
+            int vm[3];
+            vel_masks(c->d.dim, vm);
+            const int pm[3] = {0, 0, 0};
+            if (vel)
+                np = launch_norm2<double>(L.g, c->d.dim, vm, VelArrC<double>{{L.bu[0], L.bu[1], L.bu[2]}},
+                                          c->partial, g->s);
+            else
+                np = launch_norm2<double>(L.g, 1, pm, VelArrC<double>{{L.bp, nullptr, nullptr}}, c->partial, g->s);
+        }
+        launch_reduce_final(c->partial, np, g->norms + i, g->s);
+    }
+    h.assign(n, 0.0);
+    GCHK(hipMemcpyAsync(h.data(), g->norms, n * sizeof(double), hipMemcpyDeviceToHost, g->s));
+    GCHK(hipStreamSynchronize(g->s));
+    return IBB_OK;
+}
+
+// the members' solves of one system, ticked together; each member follows
+// exactly the sequence of its own solve (same stopping test, same passes)
+ibb_status group_solve(ibb_group *g, bool vel, GroupSolve &R)
+{
+    const int n = (int)g->m.size();
+    R.out.assign(n, SolveOut());
+    R.nb.assign(n, 0.0);
+    R.rel.assign(n, 0.0);
+    R.done.assign(n, 0);
+    std::vector<double> h;
+    ibb_status st = group_norms(g, vel, false, R.done, h);
+    if (st) return st;
+    for (int i = 0; i < n; ++i) {
+        R.nb[i] = sqrt(h[i]);
+        if (R.nb[i] == 0.0) {
+            zero_unknowns(g->m[i], vel);
+            R.done[i] = 1;
+        }
+    }
+    if ((st = group_norms(g, vel, true, R.done, h))) return st;
+    for (int i = 0; i < n; ++i)
+        if (!R.done[i]) R.rel[i] = sqrt(h[i]) / R.nb[i];
+    for (;;) {
+        bool any = false;
+        for (int i = 0; i < n; ++i) {
+            g->hflags[i] = 0;
+            if (R.done[i]) continue;
+            const double rel = R.rel[i];
+            ibb_ctx *c = g->m[i];
+            if (rel <= c->d.rtol) { R.done[i] = 1; continue; }
+            if (!(rel == rel) || isinf(rel)) { R.out[i].status = IBB_ENUMERIC; R.done[i] = 1; continue; }
+            if (R.out[i].cycles >= c->d.max_cycles) { R.out[i].status = IBB_ENOCONV; R.done[i] = 1; continue; }
+            g->hflags[i] = 1;
+            any = true;
+        }
+        if (!any) break;
+        if (g->hflags != g->dflags) {
+            GCHK(hipMemcpyAsync(g->flags, g->hflags.data(), n * sizeof(int), hipMemcpyHostToDevice, g->s));
+            g->dflags = g->hflags;
+        }
+        GCHK(hipGraphLaunch(g->exec[vel ? 1 : 0], g->s));
+        h.assign(n, 0.0);
+        GCHK(hipMemcpyAsync(h.data(), g->norms, n * sizeof(double), hipMemcpyDeviceToHost, g->s));
+        GCHK(hipStreamSynchronize(g->s));
+        for (int i = 0; i < n; ++i) {
+            if (!g->hflags[i]) continue;
+            R.out[i].cycles++;
+            R.out[i].vcycles += g->refined ? g->inner : 1;
+            R.rel[i] = sqrt(h[i]) / R.nb[i];
+        }
+    }
+    for (int i = 0; i < n; ++i) R.out[i].relres = R.rel[i];
+    return IBB_OK;
+}
+
+// run the members on the group's stream for the duration of a call
+struct Borrow {
+    ibb_group *g;
+    std::vector<hipStream_t> saved;
+    explicit Borrow(ibb_group *gg) : g(gg)
+    {
+        for (ibb_ctx *c : g->m) {
+            saved.push_back(c->s);
+            c->s = g->s;
+        }
+    }
+    ~Borrow()
+    {
+        for (size_t i = 0; i < g->m.size(); ++i) g->m[i]->s = saved[i];
+    }
+};
+
+// order the group's stream after the members' streams (enter) and the
+// members' streams after the group's (leave)
+ibb_status join_in(ibb_group *g)
+{
+    for (ibb_ctx *c : g->m) {
+        GCHK(hipEventRecord(g->ev[4], c->s));
+        GCHK(hipStreamWaitEvent(g->s, g->ev[4], 0));
+    }
+    return IBB_OK;
+}
+
+ibb_status join_out(ibb_group *g, const std::vector<hipStream_t> &streams)
+{
+    GCHK(hipEventRecord(g->ev[4], g->s));
+    for (hipStream_t s : streams) GCHK(hipStreamWaitEvent(s, g->ev[4], 0));
+    return IBB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ibb_status ibb_group_footprint_bytes(ibb_ctx *const *ctxs, int n, size_t *bytes)
+{
+    ibb_status st = check_members(ctxs, n);
+    if (st) return st;
+    if (!bytes) return IBB_EINVAL;
+    std::vector<ibb_ctx *> m(ctxs, ctxs + n);
+    Plan P;
+    const ibb_desc &d = m[0]->d;
+    build_plan(P, m, d.precision == IBB_FP32_REFINED, d.inner_cycles, d.nu1, d.nu2);
+    *bytes = group_bytes(P, n);
+    return IBB_OK;
+}
+
+ibb_status ibb_group_create(ibb_ctx *const *ctxs, int n, void *workspace, size_t bytes, ibb_group **out)
+{
+    if (!out) return IBB_EINVAL;
+    *out = nullptr;
+    ibb_status st = check_members(ctxs, n);
+    if (st) return st;
+    if (!workspace) return IBB_EINVAL;
+    ibb_group *g = new ibb_group();
+    g->m.assign(ctxs, ctxs + n);
+    const ibb_desc &d = g->m[0]->d;
+    g->refined = d.precision == IBB_FP32_REFINED;
+    g->inner = d.inner_cycles > 0 ? d.inner_cycles : 1;
+    g->nu1 = d.nu1;
+    g->nu2 = d.nu2;
+    build_plan(g->plan, g->m, g->refined, g->inner, g->nu1, g->nu2);
+    if (bytes < group_bytes(g->plan, n)) {
+        delete g;
+        return IBB_ENOMEM;
+    }
+    Carver cv{(char *)workspace, 0, false};
+    g->ent = cv.take<BEntry>(g->plan.ent.size());
+    g->cent = cv.take<BCoarse>(g->plan.cent.size());
+    g->flags = cv.take<int>(n);
+    g->norms = cv.take<double>(n);
+    g->counts = cv.take<int>(2 * (size_t)n);
+    g->hflags.assign(n, 0);
+    g->dflags.assign(n, 0);
+    auto bail = [&](const char *what, hipError_t e) {
+        fprintf(stderr, "ibb_group_create: %s: %s\n", what, hipGetErrorString(e));
+        for (int v = 0; v < 2; ++v)
+            if (g->exec[v]) (void)hipGraphExecDestroy(g->exec[v]);
+        for (hipEvent_t &e2 : g->ev)
+            if (e2) (void)hipEventDestroy(e2);
+        if (g->s) (void)hipStreamDestroy(g->s);
+        delete g;
+        return IBB_EDEVICE;
+    };
+    hipError_t e = hipStreamCreateWithFlags(&g->s, hipStreamNonBlocking);
+    if (e != hipSuccess) return bail("stream", e);
+    for (hipEvent_t &ev : g->ev)
+        if ((e = hipEventCreate(&ev)) != hipSuccess) return bail("event", e);
+    // the members' pending work (their tables, coefficients) comes first
+    for (ibb_ctx *c : g->m) {
+        if ((e = hipEventRecord(g->ev[4], c->s)) != hipSuccess) return bail("event record", e);
+        if ((e = hipStreamWaitEvent(g->s, g->ev[4], 0)) != hipSuccess) return bail("stream wait", e);
+    }
+    if (!g->plan.ent.empty() &&
+        (e = hipMemcpyAsync(g->ent, g->plan.ent.data(), g->plan.ent.size() * sizeof(BEntry), hipMemcpyHostToDevice,
+                            g->s)) != hipSuccess)
+        return bail("entries", e);
+    if (!g->plan.cent.empty() &&
+        (e = hipMemcpyAsync(g->cent, g->plan.cent.data(), g->plan.cent.size() * sizeof(BCoarse),
+                            hipMemcpyHostToDevice, g->s)) != hipSuccess)
+        return bail("coarse entries", e);
+    if ((e = hipMemcpyAsync(g->flags, g->dflags.data(), n * sizeof(int), hipMemcpyHostToDevice, g->s)) != hipSuccess)
+        return bail("flags", e);
+    if ((e = hipStreamSynchronize(g->s)) != hipSuccess) return bail("sync", e);
+    for (int v = 0; v < 2; ++v) {
+        hipGraph_t graph = nullptr;
+        if ((e = hipStreamBeginCapture(g->s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return bail("begin capture", e);
+        emit_ops(g, g->plan.ops[v]);
+        e = hipStreamEndCapture(g->s, &graph);
+        if (e != hipSuccess) return bail("end capture", e);
+        e = hipGraphInstantiate(&g->exec[v], graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return bail("instantiate", e);
+    }
+    *out = g;
+    return IBB_OK;
+}
+
+ibb_status ibb_group_destroy(ibb_group *g)
+{
+    if (!g) return IBB_EINVAL;
+    (void)hipStreamSynchronize(g->s);
+    for (int v = 0; v < 2; ++v)
+        if (g->exec[v]) (void)hipGraphExecDestroy(g->exec[v]);
+    for (hipEvent_t &e : g->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (g->s) (void)hipStreamDestroy(g->s);
+    delete g;
+    return IBB_OK;
+}
+
+const char *ibb_group_last_error(const ibb_group *g) { return g ? g->err.c_str() : ""; }
+
+ibb_status ibb_group_projection_step(ibb_group *g, ibb_solve_stats *per_ctx)
+{
+    if (!g) return IBB_EINVAL;
+    for (ibb_ctx *c : g->m)
+        if (!c->have_coefs) {
+            g->err = "ibb_group_projection_step: coefficients not built";
+            return IBB_ESTATE;
+        }
+    ibb_status st = join_in(g);
+    if (st) return st;
+    GroupSolve su, sp;
+    std::vector<hipStream_t> streams;
+    for (ibb_ctx *c : g->m) streams.push_back(c->s);
+    {
+        Borrow b(g);
+        for (ibb_ctx *c : g->m) proj_viscous_rhs(c);
+        GCHK(hipEventRecord(g->ev[0], g->s));
+        if ((st = group_solve(g, true, su))) return st;
+        GCHK(hipEventRecord(g->ev[1], g->s));
+        for (ibb_ctx *c : g->m) proj_pressure_rhs(c);
+        GCHK(hipEventRecord(g->ev[2], g->s));
+        if ((st = group_solve(g, false, sp))) return st;
+        GCHK(hipEventRecord(g->ev[3], g->s));
+        for (ibb_ctx *c : g->m) proj_finish(c);
+        GCHK(hipGetLastError());
+        GCHK(hipStreamSynchronize(g->s));
+    }
+    if ((st = join_out(g, streams))) return st;
+    float tu = 0, tp = 0;
+    (void)hipEventElapsedTime(&tu, g->ev[0], g->ev[1]);
+    (void)hipEventElapsedTime(&tp, g->ev[2], g->ev[3]);
+    ibb_status worst = IBB_OK;
+    for (size_t i = 0; i < g->m.size(); ++i) {
+        fill_stats(g->m[i], su.out[i], sp.out[i], tu, tp, per_ctx ? per_ctx + i : nullptr);
+        if (!worst && su.out[i].status) worst = (ibb_status)su.out[i].status;
+        if (!worst && sp.out[i].status) worst = (ibb_status)sp.out[i].status;
+    }
+    if (worst) g->err = "a member's solve did not converge (see its statistics)";
+    return worst;
+}
+
+ibb_status ibb_group_lagrangian_update(ibb_group *g, ibb_lag_stats *per_ctx)
+{
+    if (!g) return IBB_EINVAL;
+    for (ibb_ctx *c : g->m)
+        if (!c->have_coefs) {
+            g->err = "ibb_group_lagrangian_update: coefficients not built";
+            return IBB_ESTATE;
+        }
+    ibb_status st = join_in(g);
+    if (st) return st;
+    const int n = (int)g->m.size();
+    std::vector<hipStream_t> streams;
+    for (ibb_ctx *c : g->m) streams.push_back(c->s);
+    std::vector<int> cnt(2 * (size_t)n, 0);
+    {
+        Borrow b(g);
+        GCHK(hipEventRecord(g->ev[0], g->s));
+        for (int i = 0; i < n; ++i) {
+            ibb_ctx *c = g->m[i];
+            if ((st = lag_launch(c))) {
+                g->err = c->err;
+                return st;
+            }
+            GCHK(hipMemcpyAsync(g->counts + 2 * i, c->counters, 2 * sizeof(int), hipMemcpyDeviceToDevice, g->s));
+        }
+        GCHK(hipEventRecord(g->ev[1], g->s));
+        GCHK(hipMemcpyAsync(cnt.data(), g->counts, 2 * n * sizeof(int), hipMemcpyDeviceToHost, g->s));
+        GCHK(hipGetLastError());
+        GCHK(hipStreamSynchronize(g->s));
+    }
+    if ((st = join_out(g, streams))) return st;
+    float t = 0;
+    (void)hipEventElapsedTime(&t, g->ev[0], g->ev[1]);
+    if (per_ctx)
+        for (int i = 0; i < n; ++i) {
+            per_ctx[i].n_broken = cnt[2 * i];
+            per_ctx[i].n_alive = cnt[2 * i + 1];
+            per_ctx[i].t_ms = t;
+        }
     return IBB_OK;
 }
 

@@ -120,6 +120,42 @@ template <typename T>
 void launch_coarse_vcycle(int D, const LevTab<T> *tab, int l0, int L, int vel, int nu1, int nu2, int ndense,
                           const long long *uidx, const int *ucomp, const double *M, hipStream_t s);
 
+// ---- batched passes over several contexts (mg.hip) ----
+// One entry per block of a batched launch: the context's level table(s) at
+// the pass's level, the first block of that context in the launch, and for
+// residual norms the context's partial-sum buffer and block count.
+struct BEntry {
+    const void *tab;    // LevTab<T> at the level of the pass (FP64 table for prep / add)
+    const void *tab2;   // FP32 level-0 table (prep / add)
+    double *partial;    // residual norms: per-block sums (null: none)
+    int base;           // first block of this context in the launch
+    int nb;             // residual: blocks of this context; reduce: partial sums
+    int ctx;            // member index (flag, norm slot)
+    int pad;
+};
+
+// the coarse part of a context's V-cycle (one workgroup)
+struct BCoarse {
+    const void *tab;    // LevTab<T> array of the context (all levels)
+    const long long *uidx;
+    const int *ucomp;
+    const double *M;
+    int l0, L, ndense, ctx;
+};
+
+// pass kinds
+enum { BK_SWEEP = 0, BK_RESID = 1, BK_RESTRICT = 2, BK_PROLONG = 3, BK_PREP = 4, BK_ADD = 5 };
+// blocks one context needs in a batched pass of kind `kind` on level grid g
+// (gc: the next coarser grid, for restriction); A: component of a sweep
+int batch_blocks(int kind, const Grid &g, const Grid &gc, int vel, int A);
+template <typename T>
+void launch_bpass(int kind, int D, int vel, int A, int colour, const BEntry *ent, unsigned nblocks, const int *flags,
+                  hipStream_t s);
+void launch_breduce(const BEntry *ent, unsigned nitems, const int *flags, double *norms, hipStream_t s);
+template <typename T>
+void launch_bcoarse(int D, int vel, const BCoarse *items, unsigned nitems, const int *flags, int nu1, int nu2,
+                    hipStream_t s);
+
 // ---- fields (fields.hip) ----
 struct Phys {
     double sigma, eps, inv_re, force_coef, dt;

@@ -14,6 +14,8 @@
 // Multiply-adds are fused only inside one source expression, never across
 // statements, so a row computes the same bits in every kernel that inlines
 // it (the launched passes and the one-workgroup coarse cycle).
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -920,28 +922,82 @@ __device__ inline void wg_row(const LevTab<T> &lt, int i, int j, int k, T &Ax, T
     }
 }
 
-// one red-black Gauss-Seidel pass over the unknowns of component A, the
-// same update and order as the launched smoother
+// ---- per-point bodies, shared by the one-workgroup cycle and the batched
+// passes; the arithmetic is that of the launched kernels
+
+// red-black Gauss-Seidel update of the t-th point of one colour
+template <typename T, int D, int VEL, int A>
+__device__ inline void sweep_at(const LevTab<T> &lt, const Box &box, int colour, int t)
+{
+    int i, j, k;
+    if (!box_colour_pos(box, colour, t, i, j, k)) return;
+    T Ax, dg;
+    wg_row<T, D, VEL, A>(lt, i, j, k, Ax, dg);
+    T *x = VEL ? lt.xu[A] : lt.xp;
+    const T *b = VEL ? lt.bu[A] : lt.bp;
+    const long long e = at(lt.g, i, j, k);
+    const T xn = x[e] + (b[e] - Ax) / dg;
+    x[e] = xn;
+    write_images(lt.g, VEL ? face_mask(A) : 0, VEL ? ROLE_V : ROLE_P, x, i, j, k, xn);
+}
+
+// r = b - A x at the t-th unknown of the box (t in range); returns r
+template <typename T, int D, int VEL, int A>
+__device__ inline T resid_at(const LevTab<T> &lt, const Box &box, int t)
+{
+    int i, j, k;
+    box_pos(box, t, i, j, k);
+    T Ax, dg;
+    wg_row<T, D, VEL, A>(lt, i, j, k, Ax, dg);
+    const long long e = at(lt.g, i, j, k);
+    const T rv = (VEL ? lt.bu[A] : lt.bp)[e] - Ax;
+    (VEL ? lt.ru[A] : lt.rp)[e] = rv;
+    return rv;
+}
+
+// coarse right-hand side = restriction of the fine residual at the t-th
+// coarse unknown; the coarse correction there is cleared with its images
+template <typename T, int D, int VEL, int A>
+__device__ inline void restrict_at(const LevTab<T> &lt, const LevTab<T> &lc, const Box &box, int t)
+{
+    const int vmask = VEL ? face_mask(A) : 0;
+    const int role = VEL ? ROLE_V : ROLE_P;
+    int I, J, K;
+    box_pos(box, t, I, J, K);
+    const long long e = at(lc.g, I, J, K);
+    (VEL ? lc.bu[A] : lc.bp)[e] = (T)restrict_any<T, D>(vmask, lt.g, role, VEL ? lt.ru[A] : lt.rp, I, J, K);
+    T *xc = VEL ? lc.xu[A] : lc.xp;
+    xc[e] = T(0);
+    write_images(lc.g, vmask, role, xc, I, J, K, T(0));
+}
+
+// fine x += prolongation of the coarse correction at the t-th fine unknown
+template <typename T, int D, int VEL, int A>
+__device__ inline void prolong_at(const LevTab<T> &lc, const LevTab<T> &lt, const Box &box, int t)
+{
+    const int vmask = VEL ? face_mask(A) : 0;
+    const int role = VEL ? ROLE_V : ROLE_P;
+    int i, j, k;
+    box_pos(box, t, i, j, k);
+    T *x = VEL ? lt.xu[A] : lt.xp;
+    const long long e = at(lt.g, i, j, k);
+    const T v = x[e] + (T)prolong_any<T, D>(vmask, lc.g, role, VEL ? lc.xu[A] : lc.xp, i, j, k);
+    x[e] = v;
+    write_images(lt.g, vmask, role, x, i, j, k, v);
+}
+
+__device__ inline int colour_count(const Box &b) { return ((b.ext[0] + 1) >> 1) * b.ext[1] * b.ext[2]; }
+__device__ inline int point_count(const Box &b) { return b.ext[0] * b.ext[1] * b.ext[2]; }
+
+// one red-black Gauss-Seidel pass over the unknowns of component A by the
+// whole workgroup, the same update and order as the launched smoother
 template <typename T, int D, int VEL, int A>
 __device__ inline void wg_sweep_comp(const LevTab<T> &lt)
 {
-    const Grid &g = lt.g;
-    const int vmask = VEL ? face_mask(A) : 0;
-    const Box box = unk_box(g, vmask);
-    const int n = ((box.ext[0] + 1) >> 1) * box.ext[1] * box.ext[2];
-    T *x = VEL ? lt.xu[A] : lt.xp;
-    const T *b = VEL ? lt.bu[A] : lt.bp;
+    const Box box = unk_box(lt.g, VEL ? face_mask(A) : 0);
+    const int n = colour_count(box);
     for (int colour = 0; colour < 2; ++colour) {
-        for (int t = threadIdx.x; t < n; t += blockDim.x) {
-            int i, j, k;
-            if (!box_colour_pos(box, colour, t, i, j, k)) continue;
-            T Ax, dg;
-            wg_row<T, D, VEL, A>(lt, i, j, k, Ax, dg);
-            const long long e = at(g, i, j, k);
-            const T xn = x[e] + (b[e] - Ax) / dg;
-            x[e] = xn;
-            write_images(g, vmask, VEL ? ROLE_V : ROLE_P, x, i, j, k, xn);
-        }
+        for (int t = threadIdx.x; t < n; t += blockDim.x) sweep_at<T, D, VEL, A>(lt, box, colour, t);
         __syncthreads();
     }
 }
@@ -960,67 +1016,33 @@ template <typename T, int D, int VEL, int A>
 __device__ inline void wg_residual_comp(const LevTab<T> &lt)
 {
     const Box box = unk_box(lt.g, VEL ? face_mask(A) : 0);
-    const int n = box.ext[0] * box.ext[1] * box.ext[2];
-    T *r = VEL ? lt.ru[A] : lt.rp;
-    const T *b = VEL ? lt.bu[A] : lt.bp;
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
-        int i, j, k;
-        box_pos(box, t, i, j, k);
-        T Ax, dg;
-        wg_row<T, D, VEL, A>(lt, i, j, k, Ax, dg);
-        const long long e = at(lt.g, i, j, k);
-        r[e] = b[e] - Ax;
-    }
+    const int n = point_count(box);
+    for (int t = threadIdx.x; t < n; t += blockDim.x) (void)resid_at<T, D, VEL, A>(lt, box, t);
 }
 
-// coarse right-hand side = restriction of the fine residual, coarse
-// correction cleared (with its images)
 template <typename T, int D, int VEL, int A>
 __device__ inline void wg_restrict_comp(const LevTab<T> &lt, const LevTab<T> &lc)
 {
-    const int vmask = VEL ? face_mask(A) : 0;
-    const int role = VEL ? ROLE_V : ROLE_P;
-    const Box box = unk_box(lc.g, vmask);
-    const int n = box.ext[0] * box.ext[1] * box.ext[2];
-    const T *src = VEL ? lt.ru[A] : lt.rp;
-    T *bc = VEL ? lc.bu[A] : lc.bp;
-    T *xc = VEL ? lc.xu[A] : lc.xp;
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
-        int I, J, K;
-        box_pos(box, t, I, J, K);
-        const long long e = at(lc.g, I, J, K);
-        bc[e] = (T)restrict_any<T, D>(vmask, lt.g, role, src, I, J, K);
-        xc[e] = T(0);
-        write_images(lc.g, vmask, role, xc, I, J, K, T(0));
-    }
+    const Box box = unk_box(lc.g, VEL ? face_mask(A) : 0);
+    const int n = point_count(box);
+    for (int t = threadIdx.x; t < n; t += blockDim.x) restrict_at<T, D, VEL, A>(lt, lc, box, t);
 }
 
 template <typename T, int D, int VEL, int A>
 __device__ inline void wg_prolong_comp(const LevTab<T> &lc, const LevTab<T> &lt)
 {
-    const int vmask = VEL ? face_mask(A) : 0;
-    const int role = VEL ? ROLE_V : ROLE_P;
-    const Box box = unk_box(lt.g, vmask);
-    const int n = box.ext[0] * box.ext[1] * box.ext[2];
-    const T *src = VEL ? lc.xu[A] : lc.xp;
-    T *x = VEL ? lt.xu[A] : lt.xp;
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
-        int i, j, k;
-        box_pos(box, t, i, j, k);
-        const long long e = at(lt.g, i, j, k);
-        const T v = x[e] + (T)prolong_any<T, D>(vmask, lc.g, role, src, i, j, k);
-        x[e] = v;
-        write_images(lt.g, vmask, role, x, i, j, k, v);
-    }
+    const Box box = unk_box(lt.g, VEL ? face_mask(A) : 0);
+    const int n = point_count(box);
+    for (int t = threadIdx.x; t < n; t += blockDim.x) prolong_at<T, D, VEL, A>(lc, lt, box, t);
 }
 
 // The part of a V-cycle from level l0 down to the coarsest level and back,
 // in one workgroup: the same passes, in the same order, as the launched
 // kernels, with a barrier where a launch boundary would be.
 template <typename T, int D, int VEL>
-__global__ void __launch_bounds__(1024) k_coarse_vcycle(const LevTab<T> *__restrict__ tab, int l0, int L, int nu1,
-                                                         int nu2, int ndense, const long long *__restrict__ uidx,
-                                                         const int *__restrict__ ucomp, const double *__restrict__ M)
+__device__ void coarse_cycle(const LevTab<T> *__restrict__ tab, int l0, int L, int nu1, int nu2, int ndense,
+                             const long long *__restrict__ uidx, const int *__restrict__ ucomp,
+                             const double *__restrict__ M)
 {
     constexpr int A2 = D == 3 ? 2 : 1;
     for (int l = l0; l < L - 1; ++l) {
@@ -1077,6 +1099,169 @@ __global__ void __launch_bounds__(1024) k_coarse_vcycle(const LevTab<T> *__restr
         __syncthreads();
         for (int s = 0; s < nu2; ++s) wg_sweep<T, D, VEL>(lt);
     }
+}
+
+template <typename T, int D, int VEL>
+__global__ void __launch_bounds__(1024) k_coarse_vcycle(const LevTab<T> *__restrict__ tab, int l0, int L, int nu1,
+                                                         int nu2, int ndense, const long long *__restrict__ uidx,
+                                                         const int *__restrict__ ucomp, const double *__restrict__ M)
+{
+    coarse_cycle<T, D, VEL>(tab, l0, L, nu1, nu2, ndense, uidx, ucomp, M);
+}
+
+// ---------------------------------------------------------------------------
+// batched passes: one launch covers the same pass of several contexts.
+// Block b of a launch works for the context described by ent[b]; a context
+// whose flag is clear is skipped.  Each point is updated exactly as by the
+// single-context kernels above.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline const LevTab<T> &tab_of(const void *p) { return *static_cast<const LevTab<T> *>(p); }
+
+template <typename T, int D, int VEL, int A>
+__global__ void __launch_bounds__(256) k_bsweep(const BEntry *__restrict__ ent, const int *__restrict__ flags,
+                                                int colour)
+{
+    const BEntry E = ent[blockIdx.x];
+    if (!flags[E.ctx]) return;
+    const LevTab<T> &lt = tab_of<T>(E.tab);
+    const Box box = unk_box(lt.g, VEL ? face_mask(A) : 0);
+    sweep_at<T, D, VEL, A>(lt, box, colour, (int)(blockIdx.x - E.base) * blockDim.x + threadIdx.x);
+}
+
+// residual of every component (blockIdx.y) with a grid-stride loop over the
+// context's nb blocks; with E.partial set, per-block sums of r^2 in the
+// layout of the single-context residual kernels
+template <typename T, int D, int VEL>
+__global__ void __launch_bounds__(256) k_bresid(const BEntry *__restrict__ ent, const int *__restrict__ flags)
+{
+    const BEntry E = ent[blockIdx.x];
+    if (!flags[E.ctx]) return;
+    const LevTab<T> &lt = tab_of<T>(E.tab);
+    const int a = blockIdx.y;
+    const int lb = blockIdx.x - E.base;
+    const Box box = unk_box(lt.g, VEL ? face_mask(a) : 0);
+    const int n = point_count(box);
+    double acc = 0.0;
+    for (int t = lb * blockDim.x + threadIdx.x; t < n; t += E.nb * blockDim.x) {
+        T rv;
+        if (a == 0) rv = resid_at<T, D, VEL, 0>(lt, box, t);
+        else if (a == 1) rv = resid_at<T, D, VEL, 1>(lt, box, t);
+        else rv = resid_at<T, D, VEL, (D == 3 ? 2 : 1)>(lt, box, t);
+        acc += (double)rv * (double)rv;
+    }
+    if (E.partial) block_sum_store(acc, E.partial, (long long)a * E.nb + lb);
+}
+
+// one block per context: norms[ctx] = sum of its E.nb partial sums, in the
+// order of the single-context final reduction
+__global__ void __launch_bounds__(256) k_breduce(const BEntry *__restrict__ ent, const int *__restrict__ flags,
+                                                 double *norms)
+{
+    const BEntry E = ent[blockIdx.x];
+    if (!flags[E.ctx]) return;
+    double acc = 0.0;
+    for (long long t = threadIdx.x; t < E.nb; t += blockDim.x) acc += E.partial[t];
+    __shared__ double red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) norms[E.ctx] = red[0];
+}
+
+// restriction to the next level (the context's table at l and l + 1)
+template <typename T, int D, int VEL>
+__global__ void __launch_bounds__(256) k_brestrict(const BEntry *__restrict__ ent, const int *__restrict__ flags)
+{
+    const BEntry E = ent[blockIdx.x];
+    if (!flags[E.ctx]) return;
+    const LevTab<T> *tp = static_cast<const LevTab<T> *>(E.tab);
+    const LevTab<T> &lt = tp[0];
+    const LevTab<T> &lc = tp[1];
+    const int a = blockIdx.y;
+    const Box box = unk_box(lc.g, VEL ? face_mask(a) : 0);
+    const int t = (blockIdx.x - E.base) * blockDim.x + threadIdx.x;
+    if (t >= point_count(box)) return;
+    if (a == 0) restrict_at<T, D, VEL, 0>(lt, lc, box, t);
+    else if (a == 1) restrict_at<T, D, VEL, 1>(lt, lc, box, t);
+    else restrict_at<T, D, VEL, (D == 3 ? 2 : 1)>(lt, lc, box, t);
+}
+
+template <typename T, int D, int VEL>
+__global__ void __launch_bounds__(256) k_bprolong(const BEntry *__restrict__ ent, const int *__restrict__ flags)
+{
+    const BEntry E = ent[blockIdx.x];
+    if (!flags[E.ctx]) return;
+    const LevTab<T> *tp = static_cast<const LevTab<T> *>(E.tab);
+    const LevTab<T> &lt = tp[0];
+    const LevTab<T> &lc = tp[1];
+    const int a = blockIdx.y;
+    const Box box = unk_box(lt.g, VEL ? face_mask(a) : 0);
+    const int t = (blockIdx.x - E.base) * blockDim.x + threadIdx.x;
+    if (t >= point_count(box)) return;
+    if (a == 0) prolong_at<T, D, VEL, 0>(lc, lt, box, t);
+    else if (a == 1) prolong_at<T, D, VEL, 1>(lc, lt, box, t);
+    else prolong_at<T, D, VEL, (D == 3 ? 2 : 1)>(lc, lt, box, t);
+}
+
+// refined solver, start of an outer iteration: FP32 right-hand side = the
+// FP64 residual at the unknowns, FP32 correction cleared (whole arrays)
+template <int VEL>
+__global__ void __launch_bounds__(256) k_bprep32(const BEntry *__restrict__ ent, const int *__restrict__ flags)
+{
+    const BEntry E = ent[blockIdx.x];
+    if (!flags[E.ctx]) return;
+    const LevTab<double> &l64 = tab_of<double>(E.tab);
+    const LevTab<float> &l32 = tab_of<float>(E.tab2);
+    const int t = (blockIdx.x - E.base) * blockDim.x + threadIdx.x;
+    const int ncomp = VEL ? l64.g.D : 1;
+    for (int a = 0; a < ncomp; ++a) {
+        float *x32 = VEL ? l32.xu[a] : l32.xp;
+        if (t < l64.g.nel) x32[t] = 0.0f;
+        const Box box = unk_box(l64.g, VEL ? face_mask(a) : 0);
+        int i, j, k;
+        if (t < point_count(box)) {
+            box_pos(box, t, i, j, k);
+            const long long e = at(l64.g, i, j, k);
+            (VEL ? l32.bu[a] : l32.bp)[e] = (float)(VEL ? l64.ru[a] : l64.rp)[e];
+        }
+    }
+}
+
+// refined solver, end of an outer iteration: x += (double) e at the unknowns
+template <int VEL>
+__global__ void __launch_bounds__(256) k_badd(const BEntry *__restrict__ ent, const int *__restrict__ flags)
+{
+    const BEntry E = ent[blockIdx.x];
+    if (!flags[E.ctx]) return;
+    const LevTab<double> &l64 = tab_of<double>(E.tab);
+    const LevTab<float> &l32 = tab_of<float>(E.tab2);
+    const int a = blockIdx.y;
+    const int vmask = VEL ? face_mask(a) : 0;
+    const Box box = unk_box(l64.g, vmask);
+    const int t = (blockIdx.x - E.base) * blockDim.x + threadIdx.x;
+    if (t >= point_count(box)) return;
+    int i, j, k;
+    box_pos(box, t, i, j, k);
+    const long long q = at(l64.g, i, j, k);
+    double *x = VEL ? l64.xu[a] : l64.xp;
+    const double v = x[q] + (double)(VEL ? l32.xu[a] : l32.xp)[q];
+    x[q] = v;
+    write_images(l64.g, vmask, VEL ? ROLE_V : ROLE_P, x, i, j, k, v);
+}
+
+// the coarse part of the V-cycle of every context, one workgroup each
+template <typename T, int D, int VEL>
+__global__ void __launch_bounds__(1024) k_bcoarse(const BCoarse *__restrict__ items, const int *__restrict__ flags,
+                                                  int nu1, int nu2)
+{
+    const BCoarse I = items[blockIdx.x];
+    if (!flags[I.ctx]) return;
+    coarse_cycle<T, D, VEL>(static_cast<const LevTab<T> *>(I.tab), I.l0, I.L, nu1, nu2, I.ndense, I.uidx, I.ucomp,
+                            I.M);
 }
 
 // ---------------------------------------------------------------------------
@@ -1384,6 +1569,111 @@ template void launch_coarse_vcycle<double>(int, const LevTab<double> *, int, int
                                            const long long *, const int *, const double *, hipStream_t);
 template void launch_coarse_vcycle<float>(int, const LevTab<float> *, int, int, int, int, int, int,
                                           const long long *, const int *, const double *, hipStream_t);
+
+int batch_blocks(int kind, const Grid &g, const Grid &gc, int vel, int A)
+{
+    const int nc = vel ? g.D : 1;
+    long long mx = 0;
+    switch (kind) {
+    case BK_SWEEP: {
+        const Box b = unk_box(g, vel ? face_mask(A) : 0);
+        return (int)blocks_for((long long)((b.ext[0] + 1) / 2) * b.ext[1] * b.ext[2]);
+    }
+    case BK_RESID:
+        for (int a = 0; a < nc; ++a) mx = std::max(mx, box_count(unk_box(g, vel ? face_mask(a) : 0)));
+        return (int)stride_blocks(mx);
+    case BK_RESTRICT:
+        for (int a = 0; a < nc; ++a) mx = std::max(mx, box_count(unk_box(gc, vel ? face_mask(a) : 0)));
+        return (int)blocks_for(mx);
+    case BK_PROLONG:
+    case BK_ADD:
+        for (int a = 0; a < nc; ++a) mx = std::max(mx, box_count(unk_box(g, vel ? face_mask(a) : 0)));
+        return (int)blocks_for(mx);
+    case BK_PREP: return (int)blocks_for(g.nel);
+    }
+    return 0;
+}
+
+template <typename T>
+void launch_bpass(int kind, int D, int vel, int A, int colour, const BEntry *ent, unsigned nblocks, const int *flags,
+                  hipStream_t s)
+{
+    if (nblocks == 0) return;
+    const dim3 blk(256);
+    const dim3 gc(nblocks, vel ? D : 1);
+#define PASS3(K, ...)                                                                                               \
+    do {                                                                                                            \
+        if (vel) hipLaunchKernelGGL((K<T, 3, 1>), gc, blk, 0, s, ent, flags);                                       \
+        else hipLaunchKernelGGL((K<T, 3, 0>), gc, blk, 0, s, ent, flags);                                           \
+    } while (0)
+#define PASS2(K)                                                                                                    \
+    do {                                                                                                            \
+        if (vel) hipLaunchKernelGGL((K<T, 2, 1>), gc, blk, 0, s, ent, flags);                                       \
+        else hipLaunchKernelGGL((K<T, 2, 0>), gc, blk, 0, s, ent, flags);                                           \
+    } while (0)
+    switch (kind) {
+    case BK_SWEEP: {
+        const dim3 g1(nblocks);
+        if (D == 3) {
+            if (!vel) hipLaunchKernelGGL((k_bsweep<T, 3, 0, 0>), g1, blk, 0, s, ent, flags, colour);
+            else if (A == 0) hipLaunchKernelGGL((k_bsweep<T, 3, 1, 0>), g1, blk, 0, s, ent, flags, colour);
+            else if (A == 1) hipLaunchKernelGGL((k_bsweep<T, 3, 1, 1>), g1, blk, 0, s, ent, flags, colour);
+            else hipLaunchKernelGGL((k_bsweep<T, 3, 1, 2>), g1, blk, 0, s, ent, flags, colour);
+        } else {
+            if (!vel) hipLaunchKernelGGL((k_bsweep<T, 2, 0, 0>), g1, blk, 0, s, ent, flags, colour);
+            else if (A == 0) hipLaunchKernelGGL((k_bsweep<T, 2, 1, 0>), g1, blk, 0, s, ent, flags, colour);
+            else hipLaunchKernelGGL((k_bsweep<T, 2, 1, 1>), g1, blk, 0, s, ent, flags, colour);
+        }
+        break;
+    }
+    case BK_RESID:
+        if (D == 3) PASS3(k_bresid);
+        else PASS2(k_bresid);
+        break;
+    case BK_RESTRICT:
+        if (D == 3) PASS3(k_brestrict);
+        else PASS2(k_brestrict);
+        break;
+    case BK_PROLONG:
+        if (D == 3) PASS3(k_bprolong);
+        else PASS2(k_bprolong);
+        break;
+    case BK_PREP:
+        if (vel) hipLaunchKernelGGL(k_bprep32<1>, dim3(nblocks), blk, 0, s, ent, flags);
+        else hipLaunchKernelGGL(k_bprep32<0>, dim3(nblocks), blk, 0, s, ent, flags);
+        break;
+    case BK_ADD:
+        if (vel) hipLaunchKernelGGL(k_badd<1>, gc, blk, 0, s, ent, flags);
+        else hipLaunchKernelGGL(k_badd<0>, gc, blk, 0, s, ent, flags);
+        break;
+    }
+#undef PASS3
+#undef PASS2
+}
+
+void launch_breduce(const BEntry *ent, unsigned nitems, const int *flags, double *norms, hipStream_t s)
+{
+    if (nitems) hipLaunchKernelGGL(k_breduce, dim3(nitems), dim3(256), 0, s, ent, flags, norms);
+}
+
+template <typename T>
+void launch_bcoarse(int D, int vel, const BCoarse *items, unsigned nitems, const int *flags, int nu1, int nu2,
+                    hipStream_t s)
+{
+    if (nitems == 0) return;
+    const dim3 g(nitems), b(1024);
+    if (D == 3) {
+        if (vel) hipLaunchKernelGGL((k_bcoarse<T, 3, 1>), g, b, 0, s, items, flags, nu1, nu2);
+        else hipLaunchKernelGGL((k_bcoarse<T, 3, 0>), g, b, 0, s, items, flags, nu1, nu2);
+    } else {
+        if (vel) hipLaunchKernelGGL((k_bcoarse<T, 2, 1>), g, b, 0, s, items, flags, nu1, nu2);
+        else hipLaunchKernelGGL((k_bcoarse<T, 2, 0>), g, b, 0, s, items, flags, nu1, nu2);
+    }
+}
+template void launch_bpass<double>(int, int, int, int, int, const BEntry *, unsigned, const int *, hipStream_t);
+template void launch_bpass<float>(int, int, int, int, int, const BEntry *, unsigned, const int *, hipStream_t);
+template void launch_bcoarse<double>(int, int, const BCoarse *, unsigned, const int *, int, int, hipStream_t);
+template void launch_bcoarse<float>(int, int, const BCoarse *, unsigned, const int *, int, int, hipStream_t);
 
 // explicit instantiations
 #define INST(T)                                                                                                     \

@@ -199,6 +199,64 @@ class Context:
         return nl.value, tuple(n)
 
 
+class Group:
+    """Several contexts stepped together: their multigrid passes share
+    launches and each solve tick is a replayed HIP graph.  The members must
+    stay open while the group lives."""
+
+    def __init__(self, contexts):
+        self.lib = L.load()
+        self.members = list(contexts)
+        n = len(self.members)
+        self._ctxs = (L.CTX * n)(*[c.ctx.value for c in self.members])
+        nbytes = ctypes.c_size_t()
+        st = self.lib.ibb_group_footprint_bytes(self._ctxs, n, ctypes.byref(nbytes))
+        _chk(self.lib, st, "ibb_group_footprint_bytes")
+        self.nbytes = nbytes.value
+        self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=self.members[0].device)
+        self.group = ctypes.c_void_p()
+        st = self.lib.ibb_group_create(self._ctxs, n, ctypes.c_void_p(self.workspace.data_ptr()), self.nbytes,
+                                       ctypes.byref(self.group))
+        _chk(self.lib, st, "ibb_group_create")
+
+    def _err(self, st, where):
+        if st != L.IBB_OK:
+            msg = self.lib.ibb_status_string(st).decode()
+            extra = self.lib.ibb_group_last_error(self.group) if self.group else None
+            if extra:
+                msg += ": " + extra.decode()
+            raise L.IbbError(st, where, msg)
+
+    def projection_step(self, check=True):
+        n = len(self.members)
+        stats = (L.SolveStats * n)()
+        st = self.lib.ibb_group_projection_step(self.group, stats)
+        if check:
+            self._err(st, "ibb_group_projection_step")
+        out = []
+        for s in stats:
+            d = {k: getattr(s, k) for k, _ in L.SolveStats._fields_}
+            out.append(d)
+        return out
+
+    def lagrangian_update(self):
+        n = len(self.members)
+        stats = (L.LagStats * n)()
+        self._err(self.lib.ibb_group_lagrangian_update(self.group, stats), "ibb_group_lagrangian_update")
+        return [{k: getattr(s, k) for k, _ in L.LagStats._fields_} for s in stats]
+
+    def close(self):
+        if self.group:
+            self.lib.ibb_group_destroy(self.group)
+            self.group = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def from_case(case, precision=L.IBB_FP64, inner_cycles=1, device="cuda:0", spare_nodes=0):
     """Context loaded with a synthetic case (dict from synth) and coefficients built."""
     p = case["params"]

@@ -281,6 +281,70 @@ def tiny_3d(seed=12, n=(8, 8, 16), eta=20, periodic_z=False):
     return out
 
 
+# --------------------------------------------------------------------------
+# serving stream
+# --------------------------------------------------------------------------
+SERVING_SIZES = [(32, 32), (64, 32), (128, 64), (32, 32, 32), (64, 64, 64), (64, 64, 128)]
+
+
+def jittered_mound(rng, H, s, cx, cz, Lz, spacing, eta, jitter=0.15):
+    """Up to eta points on a lattice of the given spacing, each moved by at
+    most jitter*spacing per axis, kept inside the Gaussian mound (so any two
+    points are at least (1 - 2 jitter) spacing apart); nearest the mound's
+    axis first."""
+    xs = np.arange(spacing / 2, 1.0, spacing)
+    ys = np.arange(spacing / 2, H, spacing)
+    zs = np.arange(spacing / 2, Lz, spacing)
+    P = np.stack(np.meshgrid(xs, ys, zs, indexing="ij"), axis=-1).reshape(-1, 3)
+    P = P + rng.uniform(-jitter * spacing, jitter * spacing, size=P.shape)
+    ok = (P[:, 1] >= 0) & (P[:, 1] <= H * np.exp(-((P[:, 0] - cx) ** 2 + (P[:, 2] - cz) ** 2) / (2 * s * s)))
+    P = P[ok & (P[:, 0] > 0) & (P[:, 0] < 1) & (P[:, 2] > 0) & (P[:, 2] < Lz)]
+    r2 = (P[:, 0] - cx) ** 2 + (P[:, 2] - cz) ** 2 + P[:, 1] ** 2
+    P = P[np.argsort(r2, kind="stable")][:eta]
+    return P.T.copy()
+
+
+def serving_request(j, steps=10):
+    """Request j of the serving stream (seed 1000 + j): a grid drawn from
+    SERVING_SIZES (2D as the channel, 3D as the tube), a log-uniform node
+    count in [100, 10000], a log-uniform viscosity ratio in [1, 1e3] and a
+    uniform density ratio in [1, 1.3].  Springs join nodes closer than 2.5
+    mean spacings (2D) or 2 lattice spacings (3D)."""
+    rng = np.random.default_rng(1000 + j)
+    size = SERVING_SIZES[int(rng.integers(len(SERVING_SIZES)))]
+    eta = int(round(10 ** rng.uniform(2.0, 4.0)))
+    mu_max = float(10 ** rng.uniform(0.0, 3.0))
+    rho_b = float(rng.uniform(1.0, 1.3)) - 1.0
+    if len(size) == 2:
+        nx, ny = size
+        h = 1.0 / ny
+        p = base_params(2, [nx, ny], [AX_PERIODIC, AX_WALLS], h)
+        ly = ny * h
+        p["body_force"] = [8.0 * p["mu_out"] * p["inv_re"] / (ly * ly), 0.0, 0.0]
+        p.update(rho_b=rho_b, mu_max=mu_max, omega=0.02, break_ratio=1.5)
+        radius = 0.25
+        X = half_disc_uniform(rng, eta, 0.5 * nx * h, radius)
+        area = 0.5 * math.pi * radius * radius
+        ij = spring_pairs(X, 2.5 * math.sqrt(area / eta))
+        out = _finish(p, X, ij, np.full(ij.shape[1], 1e2), area, rng)
+    else:
+        n = list(size)
+        h = 1.0 / n[0]
+        p = base_params(3, n, [AX_WALLS, AX_WALLS, AX_INOUT], h)
+        p.update(rho_b=rho_b, mu_max=mu_max, omega=0.01, break_ratio=2.0)
+        Lz = n[2] * h
+        H, sw = 0.3, 0.18
+        vol = _mound_volume(H, sw)
+        spacing = 0.9 * (vol / eta) ** (1.0 / 3.0)
+        X = jittered_mound(rng, H, sw, 0.5, 0.5 * Lz, Lz, spacing, eta)
+        ij = spring_pairs(X, 2.0 * spacing)
+        out = _finish(p, X, ij, np.full(ij.shape[1], 1e2), vol * X.shape[1] / eta, rng)
+    out["seed"] = 1000 + j
+    out["steps"] = steps
+    out["size"] = size
+    return out
+
+
 WORKLOADS = {
     "channel2d_64x32": lambda: channel_2d(seed=1),
     "tube3d_64x64x128": lambda: tube_3d(seed=2),

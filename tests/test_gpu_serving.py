@@ -1,0 +1,64 @@
+"""The serving loop: requests of different grids, dimensions and contrasts
+arrive over time, are admitted as slots free up (continuous batching) and
+stepped together; each one's result must equal the request run alone."""
+import numpy as np
+import pytest
+
+from paper_1302_3663_amd import _lib as L
+from paper_1302_3663_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def alone(case, steps, precision):
+    from paper_1302_3663_amd import ibmg
+    ctx = ibmg.from_case(case, precision=precision, inner_cycles=2)
+    for _ in range(steps):
+        ctx.projection_step()
+        ctx.lagrangian_update()
+    u, p = ctx.get_state()
+    X, F, alive = ctx.get_nodes()
+    torch.cuda.synchronize()
+    out = [t.cpu().numpy() for t in (u, p, X, F, alive)]
+    ctx.close()
+    return out
+
+
+def small_serving_requests(k):
+    out, j = [], 0
+    while len(out) < k:
+        r = synth.serving_request(j, steps=2)
+        if np.prod(r["size"]) <= 32 ** 3 and r["X"].shape[1] <= 2000:
+            out.append(r)
+        j += 1
+    return out
+
+
+@pytest.mark.parametrize("max_slots", [2, 8])
+def test_serving_results_equal_alone(max_slots):
+    from paper_1302_3663_amd import serve
+    cases = [synth.tiny_2d(), synth.tiny_3d(), synth.tiny_2d(inout=True), synth.channel_2d(seed=1),
+             synth.tiny_3d(periodic_z=True)] + small_serving_requests(3)
+    steps = [3, 2, 2, 1, 3, 2, 2, 2]
+    arrivals = [0.0, 0.0, 0.01, 0.02, 0.02, 0.05, 0.08, 0.2]
+    reqs = [serve.Request(i, a, c, k) for i, (a, c, k) in enumerate(zip(arrivals, cases, steps))]
+    srv = serve.Server(budget_bytes=8 << 30, max_slots=max_slots, precision=L.IBB_FP32_REFINED)
+    summary = srv.run(reqs, keep_state=True, log=lambda m: print(m, flush=True))
+    assert summary["requests"] == len(reqs) and summary["failed_steps"] == 0
+    assert summary["peak_resident"] <= max_slots
+    for r in reqs:
+        assert r.done == r.steps and len(r.step_ms) == r.steps
+        ref = alone(r.case, r.steps, L.IBB_FP32_REFINED)
+        assert all(np.array_equal(a, b) for a, b in zip(r.final, ref)), r.rid
+
+
+def test_budget_binds():
+    from paper_1302_3663_amd import serve
+    cases = [synth.tiny_3d(seed=s) for s in (21, 22, 23)]
+    srv = serve.Server(max_slots=8, precision=L.IBB_FP32_REFINED)
+    one = srv.footprint(cases[0])
+    srv.budget = int(1.5 * max(srv.footprint(c) for c in cases))
+    reqs = [serve.Request(i, 0.0, c, 2) for i, c in enumerate(cases)]
+    summary = srv.run(reqs)
+    assert summary["peak_resident"] == 1 and summary["requests"] == 3 and one > 0
