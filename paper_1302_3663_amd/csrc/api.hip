@@ -18,7 +18,7 @@ using namespace ibmg;
 
 namespace {
 
-constexpr int DENSE_MAX = 64;   // coarsest systems up to this size are inverted
+constexpr int DENSE_MAX = DENSE_LDS;   // coarsest systems up to this size are inverted
 constexpr int MAXLEV = 16;
 
 struct Level {
@@ -64,7 +64,8 @@ struct ibb_ctx {
     // coarsest dense inverses
     long long *uidx_p = nullptr, *uidx_u = nullptr;
     int *ucomp_p = nullptr, *ucomp_u = nullptr;
-    double *Mp = nullptr, *Mu = nullptr, *Aw = nullptr;
+    double *Mp = nullptr, *Mu = nullptr, *Aw = nullptr, *Atmp = nullptr;
+    int *scan_tmp = nullptr;   // block sums of the multi-block scan
     // reductions
     double *partial = nullptr, *scalar = nullptr;
     // level tables for the one-workgroup coarse cycle, and where it starts
@@ -278,6 +279,7 @@ size_t carve(ibb_ctx *c, char *base, bool dry)
     c->Mp = cv.take<double>(DENSE_MAX * DENSE_MAX);
     c->Mu = cv.take<double>(DENSE_MAX * DENSE_MAX);
     c->Aw = cv.take<double>(DENSE_MAX * DENSE_MAX);
+    c->Atmp = cv.take<double>((size_t)DENSE_MAX * 3 * (size_t)c->lv[c->L - 1].g.nel);
     c->tab64 = cv.take<LevTab<double>>(MAXLEV);
     c->tab32 = cv.take<LevTab<float>>(MAXLEV);
     c->partial = cv.take<double>(3 * NORM_BLOCKS);
@@ -300,6 +302,7 @@ size_t carve(ibb_ctx *c, char *base, bool dry)
     c->inc_count = cv.take<int>(em);
     c->inc_start = cv.take<int>(em + 1);
     c->counters = cv.take<int>(8);
+    c->scan_tmp = cv.take<int>(scan_scratch_ints((long long)std::max<size_t>((size_t)c->nbins_cap, em + 1)));
     return cv.off + 256;
 }
 
@@ -679,7 +682,7 @@ ibb_status rebuild_coefficients(ibb_ctx *c)
     Bins b = c->bins;
     bins_for_width(d, d->omega, b.nb, b.bs);
     b.nbins = b.nb[0] * b.nb[1] * b.nb[2];
-    launch_bin_nodes(L0.g, b, c->X, em, c->eta, c->s);
+    launch_bin_nodes(L0.g, b, c->X, em, c->eta, c->scan_tmp, c->s);
     for (int a = 0; a < D; ++a)
         launch_spread_face(L0.g, c->ph, b, c->X, c->F, em, a, d->omega, c->f[a], L0.rho[a], c->s);
     launch_spread_visc(L0.g, c->ph, b, c->X, em, 0, L0.muc, c->s);
@@ -731,10 +734,10 @@ ibb_status rebuild_coefficients(ibb_ctx *c)
     View<double> v = view64(LC);
     if (LC.np <= DENSE_MAX)
         launch_dense_inverse(LC.g, 0, (int)LC.np, c->uidx_p, c->ucomp_p, v.cp, v.cu, d->sigma / d->dt, 1.0 / hc2,
-                             VelArr<double>{{LC.rp, nullptr, nullptr}}, c->singular_p ? 1 : 0, c->Aw, c->Mp, c->s);
+                             c->Atmp, c->singular_p ? 1 : 0, c->Aw, c->Mp, c->s);
     if (LC.nu <= DENSE_MAX)
         launch_dense_inverse(LC.g, 1, (int)LC.nu, c->uidx_u, c->ucomp_u, v.cp, v.cu, d->sigma / d->dt,
-                             d->inv_re / hc2, VelArr<double>{{LC.ru[0], LC.ru[1], LC.ru[2]}}, 0, c->Aw, c->Mu, c->s);
+                             d->inv_re / hc2, c->Atmp, 0, c->Aw, c->Mu, c->s);
     c->have_coefs = true;
     return IBB_OK;
 }
@@ -1046,7 +1049,7 @@ ibb_status ibb_set_springs(ibb_ctx *c, int64_t m, const int32_t *ij, const doubl
         launch_incidence_keys(c->ij, (int)m, c->inc_keys, c->s);
     }
     launch_bucket_sort(c->inc_keys, (int)(2 * m), c->eta > 0 ? c->eta : 1, c->inc_count, c->inc_start, c->inc_list,
-                       (int)(m > 0 ? m : 1), c->s);
+                       (int)(m > 0 ? m : 1), c->scan_tmp, c->s);
     HIPCHK(hipGetLastError());
     c->have_springs = true;
     return IBB_OK;
@@ -1245,7 +1248,7 @@ ibb_status ibb_spread(ibb_ctx *c, double width, int64_t n, const double *X, cons
     Bins b = c->bins;
     bins_for_width(&c->d, width, b.nb, b.bs);
     b.nbins = b.nb[0] * b.nb[1] * b.nb[2];
-    launch_bin_nodes(L0.g, b, X, n > 0 ? n : 1, (int)n, c->s);
+    launch_bin_nodes(L0.g, b, X, n > 0 ? n : 1, (int)n, c->scan_tmp, c->s);
     for (int a = 0; a < c->d.dim; ++a)
         launch_spread_face(L0.g, c->ph, b, X, F, n > 0 ? n : 1, a, width, L0.ru[a], nullptr, c->s);
     faces_out(c, 0, L0.ru, out);

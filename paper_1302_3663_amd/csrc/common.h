@@ -146,56 +146,70 @@ __device__ inline T ld(const T *__restrict__ v, Ref r)
     return r.s == 0 ? T(0) : (r.s > 0 ? x : -x);
 }
 
-// Ghost positions along axis d whose value is (sign x) the value at q:
-// the inverse of resolve() for the positions the stencils read (at most two).
-__host__ __device__ inline int images_of(const Grid &g, int d, int vert, int role, int q, int *gq, int *gs)
+// Ghost positions along axis d whose value is (sign x) the value at q: the
+// inverse of resolve() for the positions the stencils read.  There are at
+// most two, one caused by each end of the axis; slot 0 holds the image
+// across the low end, slot 1 the one across the high end (sign 0: none).
+struct AxisImages {
+    int q[2];
+    int s[2];
+};
+
+__host__ __device__ inline AxisImages images_of(const Grid &g, int d, int vert, int role, int q)
 {
     const int n = g.n[d], bc = g.bc[d];
-    int m = 0;
+    AxisImages m{{0, 0}, {0, 0}};
     if (bc == AX_PERIODIC) {
-        if (q == 0) { gq[m] = n; gs[m++] = 1; }
-        if (q == n - 1) { gq[m] = -1; gs[m++] = 1; }
+        if (q == n - 1) { m.q[0] = -1; m.s[0] = 1; }
+        if (q == 0) { m.q[1] = n; m.s[1] = 1; }
         return m;
     }
     if (!vert) {
-        if (q == 0) { gq[m] = -1; gs[m++] = role == ROLE_V ? -1 : 1; }
+        if (q == 0) { m.q[0] = -1; m.s[0] = role == ROLE_V ? -1 : 1; }
         if (q == n - 1) {
             int s = 1;
             if (role == ROLE_P && bc == AX_INOUT) s = -1;
             if (role == ROLE_V && bc == AX_WALLS) s = -1;
-            gq[m] = n;
-            gs[m++] = s;
+            m.q[1] = n;
+            m.s[1] = s;
         }
         return m;
     }
     if (role == ROLE_C) {
-        if (q == 1) { gq[m] = -1; gs[m++] = 1; }
-        if (q == n - 1) { gq[m] = n + 1; gs[m++] = 1; }
+        if (q == 1) { m.q[0] = -1; m.s[0] = 1; }
+        if (q == n - 1) { m.q[1] = n + 1; m.s[1] = 1; }
         return m;
     }
-    if (role == ROLE_V && bc == AX_INOUT && q == n - 1) { gq[m] = n + 1; gs[m++] = 1; }
+    if (role == ROLE_V && bc == AX_INOUT && q == n - 1) { m.q[1] = n + 1; m.s[1] = 1; }
     return m;
 }
 
-// write v (times the reflection sign) to every ghost image of (i, j, k)
+// write v (times the reflection sign) to every ghost image of (i, j, k):
+// each axis contributes the position itself or one of its images
 template <typename T>
 __device__ inline void write_images(const Grid &g, int vmask, int role, T *x, int i, int j, int k, T v)
 {
     const int q[3] = {i, j, k};
-    int cq[3][3], cs[3][3], cn[3];
-    for (int d = 0; d < 3; ++d) {
-        cq[d][0] = q[d];
-        cs[d][0] = 1;
-        cn[d] = 1;
-        if (d < g.D) cn[d] += images_of(g, d, (vmask >> d) & 1, role, q[d], &cq[d][1], &cs[d][1]);
-    }
-    if (cn[0] == 1 && cn[1] == 1 && cn[2] == 1) return;
-    for (int c = 0; c < cn[2]; ++c)
-        for (int b = 0; b < cn[1]; ++b)
-            for (int a = 0; a < cn[0]; ++a) {
-                if ((a | b | c) == 0) continue;
-                const int s = cs[0][a] * cs[1][b] * cs[2][c];
-                x[at(g, cq[0][a], cq[1][b], cq[2][c])] = s > 0 ? v : -v;
+    AxisImages im[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        im[d] = d < g.D ? images_of(g, d, (vmask >> d) & 1, role, q[d]) : AxisImages{{0, 0}, {0, 0}};
+    if ((im[0].s[0] | im[0].s[1] | im[1].s[0] | im[1].s[1] | im[2].s[0] | im[2].s[1]) == 0) return;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (a == 0 && b == 0 && c == 0) continue;
+                const int sa = a ? im[0].s[a - 1] : 1;
+                const int sb = b ? im[1].s[b - 1] : 1;
+                const int sc = c ? im[2].s[c - 1] : 1;
+                if (sa == 0 || sb == 0 || sc == 0) continue;
+                const int qa = a ? im[0].q[a - 1] : i;
+                const int qb = b ? im[1].q[b - 1] : j;
+                const int qc = c ? im[2].q[c - 1] : k;
+                x[at(g, qa, qb, qc)] = sa * sb * sc > 0 ? v : -v;
             }
 }
 

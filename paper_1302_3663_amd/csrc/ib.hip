@@ -34,30 +34,63 @@ __global__ void k_count_keys(const int *__restrict__ keys, int n, int *count)
     if (t < n) atomicAdd(&count[keys[t]], 1);
 }
 
-// single workgroup exclusive scan of count[0..nb) into start[0..nb]
-__global__ void __launch_bounds__(1024) k_scan(const int *__restrict__ count, int nb, int *start)
+// exclusive scan of count[0..nb) into start[0..nb] in three passes over
+// tiles of SCAN_TILE buckets: tile sums, a scan of the tile sums, and a
+// scan inside every tile offset by its tile's start
+constexpr int SCAN_TILE = 1024;
+
+// inclusive scan of one int per thread across a 1024-thread block
+__device__ inline int block_incl_scan(int v, int *buf)
 {
-    __shared__ int part[1024];
     const int t = threadIdx.x;
-    const int chunk = (nb + blockDim.x - 1) / blockDim.x;
-    const int lo = t * chunk, hi = min(nb, lo + chunk);
-    int s = 0;
-    for (int i = lo; i < hi; ++i) s += count[i];
-    part[t] = s;
+    buf[t] = v;
     __syncthreads();
-    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-        const int v = t >= off ? part[t - off] : 0;
+    for (int off = 1; off < SCAN_TILE; off <<= 1) {
+        const int w = t >= off ? buf[t - off] : 0;
         __syncthreads();
-        part[t] += v;
+        buf[t] += w;
         __syncthreads();
     }
-    int run = t ? part[t - 1] : 0;
-    for (int i = lo; i < hi; ++i) {
-        start[i] = run;
-        run += count[i];
-    }
-    if (t == blockDim.x - 1) start[nb] = part[t];
+    const int r = buf[t];
+    __syncthreads();
+    return r;
 }
+
+__global__ void __launch_bounds__(1024) k_scan_tiles(const int *__restrict__ count, int nb, int *tsum)
+{
+    __shared__ int buf[SCAN_TILE];
+    const int i = blockIdx.x * SCAN_TILE + threadIdx.x;
+    const int r = block_incl_scan(i < nb ? count[i] : 0, buf);
+    if (threadIdx.x == SCAN_TILE - 1) tsum[blockIdx.x] = r;
+}
+
+// one block: tsum[0..nt) -> exclusive prefix in place; start[nb] = total
+__global__ void __launch_bounds__(1024) k_scan_tsum(int *tsum, int nt, int *start, int nb)
+{
+    __shared__ int buf[SCAN_TILE];
+    int carry = 0;
+    for (int base = 0; base < nt; base += SCAN_TILE) {
+        const int i = base + threadIdx.x;
+        const int v = i < nt ? tsum[i] : 0;
+        const int r = block_incl_scan(v, buf);
+        if (i < nt) tsum[i] = carry + r - v;
+        carry += buf[SCAN_TILE - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) start[nb] = carry;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_apply(const int *__restrict__ count, int nb, const int *__restrict__ tsum,
+                                                     int *start)
+{
+    __shared__ int buf[SCAN_TILE];
+    const int i = blockIdx.x * SCAN_TILE + threadIdx.x;
+    const int v = i < nb ? count[i] : 0;
+    const int r = block_incl_scan(v, buf);
+    if (i < nb) start[i] = tsum[blockIdx.x] + r - v;
+}
+
+int scan_scratch_ints(long long nb) { return (int)((nb + SCAN_TILE - 1) / SCAN_TILE) + 2; }
 
 __global__ void k_scatter_keys(const int *__restrict__ keys, int n, const int *__restrict__ start, int *cursor, int *ids)
 {
@@ -87,11 +120,15 @@ __global__ void k_sort_buckets(const int *__restrict__ start, int nb, int *ids, 
     }
 }
 
-void launch_bucket_sort(const int *keys, int n, int nbuckets, int *count, int *start, int *ids, int mod, hipStream_t s)
+void launch_bucket_sort(const int *keys, int n, int nbuckets, int *count, int *start, int *ids, int mod,
+                        int *scan_tmp, hipStream_t s)
 {
     launch_fill<int>(count, nbuckets, 0, s);
     if (n > 0) hipLaunchKernelGGL(k_count_keys, dim3(nblk(n)), dim3(256), 0, s, keys, n, count);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, count, nbuckets, start);
+    const int nt = (nbuckets + SCAN_TILE - 1) / SCAN_TILE;
+    hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(SCAN_TILE), 0, s, count, nbuckets, scan_tmp);
+    hipLaunchKernelGGL(k_scan_tsum, dim3(1), dim3(SCAN_TILE), 0, s, scan_tmp, nt, start, nbuckets);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(SCAN_TILE), 0, s, count, nbuckets, scan_tmp, start);
     launch_fill<int>(count, nbuckets, 0, s);
     if (n > 0) hipLaunchKernelGGL(k_scatter_keys, dim3(nblk(n)), dim3(256), 0, s, keys, n, start, count, ids);
     hipLaunchKernelGGL(k_sort_buckets, dim3(nblk(nbuckets)), dim3(256), 0, s, start, nbuckets, ids, mod);
@@ -123,10 +160,11 @@ __global__ void k_bin_of(Grid g, Bins bins, const double *__restrict__ X, long l
     bins.bin_of[s] = (b[2] * bins.nb[1] + b[1]) * bins.nb[0] + b[0];
 }
 
-void launch_bin_nodes(const Grid &g, const Bins &bins, const double *X, long long stride, int eta, hipStream_t s)
+void launch_bin_nodes(const Grid &g, const Bins &bins, const double *X, long long stride, int eta, int *scan_tmp,
+                      hipStream_t s)
 {
     if (eta > 0) hipLaunchKernelGGL(k_bin_of, dim3(nblk(eta)), dim3(256), 0, s, g, bins, X, stride, eta);
-    launch_bucket_sort(bins.bin_of, eta, bins.nbins, bins.count, bins.start, bins.sorted, 0, s);
+    launch_bucket_sort(bins.bin_of, eta, bins.nbins, bins.count, bins.start, bins.sorted, 0, scan_tmp, s);
 }
 
 // distinct neighbouring bins of a point along each axis
@@ -287,11 +325,17 @@ void launch_spread_visc(const Grid &g, const Phys &ph, const Bins &bins, const d
 // interpolation U_a(s) = sum_x u_a(x) delta~(x - X_s, w) h^D over the
 // closed-domain a-faces (fixed faces contribute the values they hold)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_interp(Grid g, int kernel, double width, VelArrC<double> u,
-                                                const double *__restrict__ X, long long xstride, int eta, double *U,
-                                                long long ustride)
+//
+// One workgroup per (node, component): each thread takes lattice points of
+// the support box, the partial sums are combined in a fixed tree order.
+constexpr int INTERP_BLOCK = 128;
+
+__global__ void __launch_bounds__(INTERP_BLOCK) k_interp(Grid g, int kernel, double width, VelArrC<double> u,
+                                                         const double *__restrict__ X, long long xstride, int eta,
+                                                         double *U, long long ustride)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.x;
+    const int a = blockIdx.y;
     if (s >= eta) return;
     const double inv_w = 1.0 / width;
     double scale = 1.0, hD = 1.0;
@@ -301,47 +345,51 @@ __global__ void __launch_bounds__(256) k_interp(Grid g, int kernel, double width
     }
     double Xs[3] = {0.0, 0.0, 0.0};
     for (int d = 0; d < g.D; ++d) Xs[d] = X[d * xstride + s];
-    for (int a = 0; a < g.D; ++a) {
-        const int vmask = face_mask(a);
-        int qlo[3], qhi[3];
-        for (int d = 0; d < 3; ++d) {
-            if (d >= g.D) { qlo[d] = qhi[d] = 0; continue; }
-            const double off = ((vmask >> d) & 1) ? 0.0 : 0.5;
-            qlo[d] = (int)floor((Xs[d] - 2.0 * width) / g.h - off);
-            qhi[d] = (int)ceil((Xs[d] + 2.0 * width) / g.h - off);
-        }
-        double acc = 0.0;
-        for (int k = qlo[2]; k <= qhi[2]; ++k)
-            for (int j = qlo[1]; j <= qhi[1]; ++j)
-                for (int i = qlo[0]; i <= qhi[0]; ++i) {
-                    const int q[3] = {i, j, k};
-                    int qs[3] = {0, 0, 0};
-                    double w = scale;
-                    bool keep = true;
-                    for (int d = 0; d < g.D; ++d) {
-                        const int vert = (vmask >> d) & 1;
-                        const double xc = vert ? q[d] * g.h : (q[d] + 0.5) * g.h;
-                        const double r = (xc - Xs[d]) * inv_w;
-                        if (!(fabs(r) < 2.0)) { keep = false; break; }
-                        int tq = q[d];
-                        const int ext = stored_extent(g, d, vert);
-                        if (g.bc[d] == AX_PERIODIC) tq = ((tq % g.n[d]) + g.n[d]) % g.n[d];
-                        else if (tq < 0 || tq >= ext) { keep = false; break; }
-                        qs[d] = tq;
-                        w *= phi_eval(kernel, r);
-                    }
-                    if (!keep) continue;
-                    acc += u.c[a][at(g, qs[0], qs[1], qs[2])] * w;
-                }
-        U[a * ustride + s] = acc * hD;
+    const int vmask = face_mask(a);
+    int qlo[3], ext[3];
+    for (int d = 0; d < 3; ++d) {
+        if (d >= g.D) { qlo[d] = 0; ext[d] = 1; continue; }
+        const double off = ((vmask >> d) & 1) ? 0.0 : 0.5;
+        qlo[d] = (int)floor((Xs[d] - 2.0 * width) / g.h - off);
+        ext[d] = (int)ceil((Xs[d] + 2.0 * width) / g.h - off) - qlo[d] + 1;
     }
+    const int ntap = ext[0] * ext[1] * ext[2];
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < ntap; t += blockDim.x) {
+        const int q[3] = {qlo[0] + t % ext[0], qlo[1] + (t / ext[0]) % ext[1], qlo[2] + t / (ext[0] * ext[1])};
+        int qs[3] = {0, 0, 0};
+        double w = scale;
+        bool keep = true;
+        for (int d = 0; d < g.D; ++d) {
+            const int vert = (vmask >> d) & 1;
+            const double xc = vert ? q[d] * g.h : (q[d] + 0.5) * g.h;
+            const double r = (xc - Xs[d]) * inv_w;
+            if (!(fabs(r) < 2.0)) { keep = false; break; }
+            int tq = q[d];
+            const int se = stored_extent(g, d, vert);
+            if (g.bc[d] == AX_PERIODIC) tq = ((tq % g.n[d]) + g.n[d]) % g.n[d];
+            else if (tq < 0 || tq >= se) { keep = false; break; }
+            qs[d] = tq;
+            w *= phi_eval(kernel, r);
+        }
+        if (keep) acc += u.c[a][at(g, qs[0], qs[1], qs[2])] * w;
+    }
+    __shared__ double red[INTERP_BLOCK];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = INTERP_BLOCK / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) U[a * ustride + s] = red[0] * hD;
 }
 
 void launch_interp(const Grid &g, int kernel, double width, const VelArrC<double> &u, const double *X,
                    long long xstride, int eta, double *U, long long ustride, hipStream_t s)
 {
     if (eta <= 0) return;
-    hipLaunchKernelGGL(k_interp, dim3(nblk(eta)), dim3(256), 0, s, g, kernel, width, u, X, xstride, eta, U, ustride);
+    hipLaunchKernelGGL(k_interp, dim3(eta, g.D), dim3(INTERP_BLOCK), 0, s, g, kernel, width, u, X, xstride, eta, U,
+                       ustride);
 }
 
 // X += c U, periodic axes wrapped back into [0, L)

@@ -80,9 +80,14 @@ void launch_restrict(const Grid &gf, const Grid &gc, int ncomp, const int *vmask
 template <typename T>
 void launch_prolong_add(const Grid &gc, const Grid &gf, int ncomp, const int *vmasks, int role,
                         const VelArrC<T> &coarse, const VelArr<T> &fine, hipStream_t s);
+// largest coarsest system that is inverted (its matrix is held in LDS)
+constexpr int DENSE_LDS = 64;
+// inverse M of the coarsest operator (n <= DENSE_LDS unknowns listed by
+// uidx/ucomp): column j is assembled by applying the operator to e_j in its
+// own scratch (tmp: n * ncomp * nel doubles), Aw receives A (n x n)
 void launch_dense_inverse(const Grid &g, int velocity, int n, const long long *uidx, const int *ucomp,
-                          const CoefP<double> &cp, const CoefU<double> &cu, double mass, double cvisc,
-                          const VelArr<double> &tmp, int singular, double *Aw, double *M, hipStream_t s);
+                          const CoefP<double> &cp, const CoefU<double> &cu, double mass, double cvisc, double *tmp,
+                          int singular, double *Aw, double *M, hipStream_t s);
 template <typename T>
 void launch_dense_apply(const Grid &g, int velocity, int n, const long long *uidx, const int *ucomp, const double *M,
                         const VelArrC<T> &b, const VelArr<T> &x, hipStream_t s);
@@ -115,7 +120,12 @@ struct LevTab {
 };
 
 // the V-cycle from level l0 down to the coarsest level and back inside one
-// workgroup; ndense > 0: the coarsest level is solved with the inverse M
+// workgroup of WG_THREADS threads; ndense > 0: the coarsest level is solved
+// with the inverse M
+// (512 threads leave each thread up to 256 registers, so the fully inlined
+// cycle does not spill)
+constexpr int WG_THREADS = 512;
+__host__ __device__ constexpr int wg_threads(int, int) { return WG_THREADS; }
 template <typename T>
 void launch_coarse_vcycle(int D, const LevTab<T> *tab, int l0, int L, int vel, int nu1, int nu2, int ndense,
                           const long long *uidx, const int *ucomp, const double *M, hipStream_t s);
@@ -187,7 +197,8 @@ struct Bins {
     int *start;         // [nbins + 1] exclusive prefix
     int *sorted;        // [eta] node ids grouped by bin, ascending within a bin
 };
-void launch_bin_nodes(const Grid &g, const Bins &bins, const double *X, long long stride, int eta, hipStream_t s);
+void launch_bin_nodes(const Grid &g, const Bins &bins, const double *X, long long stride, int eta, int *scan_tmp,
+                      hipStream_t s);
 // spread of the face force (F may be null) and density, or of the viscosity
 // max at cells and edges; kind: 0 faces (axis a), 1 cells, 2 edges (axis c)
 void launch_spread_face(const Grid &g, const Phys &ph, const Bins &bins, const double *X, const double *F,
@@ -205,7 +216,10 @@ void launch_spring_force(const Grid &g, const double *X, long long stride, int e
 // counting sort of keys[0..n) into buckets [0, nbuckets): start (exclusive
 // prefix, nbuckets + 1 entries) and ids grouped by bucket, ascending in
 // id % mod within a bucket (mod = 0: ascending id)
-void launch_bucket_sort(const int *keys, int n, int nbuckets, int *count, int *start, int *ids, int mod, hipStream_t s);
+// ints of scratch the bucket sort needs for nb buckets
+int scan_scratch_ints(long long nb);
+void launch_bucket_sort(const int *keys, int n, int nbuckets, int *count, int *start, int *ids, int mod,
+                        int *scan_tmp, hipStream_t s);
 void launch_incidence_keys(const int *ij, int m, int *keys, hipStream_t s);
 void launch_count_alive(const unsigned char *alive, int m, int *out, hipStream_t s);
 

@@ -642,6 +642,7 @@ __device__ inline double prolong_point(const Grid &gc, int role, const T *__rest
     AxisTaps t[3];
     int raw[2];
     double wr[2];
+#pragma unroll
     for (int d = 0; d < D; ++d) {
         const int vert = (VM >> d) & 1;
         const int n = prl_weights(vert, q[d], raw, wr);
@@ -740,77 +741,88 @@ __global__ void __launch_bounds__(256) k_prolong_add(Grid gc, Grid gf, VelPBox p
 // coarsest level: dense inverse, assembled by applying the stencil to unit
 // vectors, inverted by Gauss-Jordan with partial pivoting (one workgroup)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) k_dense_inverse(Grid g, int velocity, int n, const long long *__restrict__ uidx,
-                                                      const int *__restrict__ ucomp, CoefP<double> cp,
-                                                      CoefU<double> cu, double mass, double cvisc, VelArr<double> tmp,
-                                                      int singular, double *Aw, double *M)
+__global__ void __launch_bounds__(256) k_dense_assemble(Grid g, int velocity, int n, const long long *__restrict__ uidx,
+                                                        const int *__restrict__ ucomp, CoefP<double> cp,
+                                                        CoefU<double> cu, double mass, double cvisc, double *tmp,
+                                                        double *Aw)
 {
-    const int r = threadIdx.x;
-    // assemble A column by column into Aw (row-major n x n)
-    for (int j = 0; j < n; ++j) {
-        for (long long e = r; e < g.nel; e += blockDim.x)
-            for (int c = 0; c < (velocity ? g.D : 1); ++c) tmp.c[c][e] = 0.0;
-        __syncthreads();
-        if (r == 0) tmp.c[velocity ? ucomp[j] : 0][uidx[j]] = 1.0;
-        __syncthreads();
-        if (r < n) {
-            const long long e = uidx[r];
-            int i, jj, k;
-            decode(g, e, i, jj, k);
-            double Ax, dg;
-            if (velocity) u_row_slow_any<double>(g, tmp, cu, mass, cvisc, ucomp[r], i, jj, k, Ax, dg);
-            else p_row_slow_any<double>(g, tmp.c[0], cp, cvisc, i, jj, k, Ax, dg);
-            Aw[r * n + j] = Ax;
-        }
-        __syncthreads();
+    // block j: column j of A (row-major n x n) = A applied to the unit vector e_j
+    const int j = blockIdx.x;
+    const int nc = velocity ? g.D : 1;
+    const long long nel = g.nel;
+    double *base = tmp + (long long)j * nc * nel;
+    VelArr<double> x{{base, nc > 1 ? base + nel : nullptr, nc > 2 ? base + 2 * nel : nullptr}};
+    for (long long e = threadIdx.x; e < nc * nel; e += blockDim.x) base[e] = 0.0;
+    __syncthreads();
+    if (threadIdx.x == 0) x.c[velocity ? ucomp[j] : 0][uidx[j]] = 1.0;
+    __syncthreads();
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+        int i, jj, k;
+        decode(g, uidx[r], i, jj, k);
+        double Ax, dg;
+        if (velocity) u_row_slow_any<double>(g, x, cu, mass, cvisc, ucomp[r], i, jj, k, Ax, dg);
+        else p_row_slow_any<double>(g, x.c[0], cp, cvisc, i, jj, k, Ax, dg);
+        Aw[r * n + j] = Ax;
     }
-    // singular (all-Neumann/periodic pressure): add alpha 1 1^T, alpha = trace / n^2
+}
+
+// Gauss-Jordan with partial pivoting on [A | I] held in LDS, one workgroup;
+// singular (all-Neumann/periodic pressure): A + alpha 1 1^T, alpha = trace / n^2
+__global__ void __launch_bounds__(1024) k_dense_gj(int n, int singular, const double *__restrict__ Aw, double *M)
+{
+    __shared__ double A[DENSE_LDS][DENSE_LDS + 1], B[DENSE_LDS][DENSE_LDS + 1];
+    __shared__ double f[DENSE_LDS];
+    __shared__ double tr;
+    __shared__ int piv;
+    const int t = threadIdx.x;
+    for (int e = t; e < n * n; e += blockDim.x) {
+        const int r = e / n, c = e % n;
+        A[r][c] = Aw[e];
+        B[r][c] = r == c ? 1.0 : 0.0;
+    }
+    __syncthreads();
     if (singular) {
-        __shared__ double tr;
-        if (r == 0) {
+        if (t == 0) {
             double s = 0.0;
-            for (int i = 0; i < n; ++i) s += Aw[i * n + i];
+            for (int i = 0; i < n; ++i) s += A[i][i];
             tr = s / ((double)n * (double)n);
         }
         __syncthreads();
-        if (r < n)
-            for (int j = 0; j < n; ++j) Aw[r * n + j] += tr;
+        for (int e = t; e < n * n; e += blockDim.x) A[e / n][e % n] += tr;
         __syncthreads();
     }
-    if (r < n)
-        for (int j = 0; j < n; ++j) M[r * n + j] = (r == j) ? 1.0 : 0.0;
-    __syncthreads();
-    __shared__ int piv;
-    for (int kcol = 0; kcol < n; ++kcol) {
-        if (r == 0) {
-            int p = kcol;
-            for (int i = kcol + 1; i < n; ++i)
-                if (fabs(Aw[i * n + kcol]) > fabs(Aw[p * n + kcol])) p = i;
+    for (int k = 0; k < n; ++k) {
+        if (t == 0) {
+            int p = k;
+            for (int i = k + 1; i < n; ++i)
+                if (fabs(A[i][k]) > fabs(A[p][k])) p = i;
             piv = p;
         }
         __syncthreads();
         const int p = piv;
-        if (p != kcol && r < n) {
-            double t = Aw[kcol * n + r]; Aw[kcol * n + r] = Aw[p * n + r]; Aw[p * n + r] = t;
-            t = M[kcol * n + r]; M[kcol * n + r] = M[p * n + r]; M[p * n + r] = t;
+        if (p != k && t < n) {
+            double v = A[k][t]; A[k][t] = A[p][t]; A[p][t] = v;
+            v = B[k][t]; B[k][t] = B[p][t]; B[p][t] = v;
         }
         __syncthreads();
-        const double pv = Aw[kcol * n + kcol];
+        const double pv = A[k][k];
         __syncthreads();
-        if (r < n) {
-            Aw[kcol * n + r] /= pv;
-            M[kcol * n + r] /= pv;
+        if (t < n) {
+            A[k][t] /= pv;
+            B[k][t] /= pv;
         }
         __syncthreads();
-        if (r < n && r != kcol) {
-            const double f = Aw[r * n + kcol];
-            for (int j = 0; j < n; ++j) {
-                Aw[r * n + j] -= f * Aw[kcol * n + j];
-                M[r * n + j] -= f * M[kcol * n + j];
-            }
+        if (t < n) f[t] = A[t][k];
+        __syncthreads();
+        for (int e = t; e < n * n; e += blockDim.x) {
+            const int r = e / n, c = e % n;
+            if (r == k) continue;
+            A[r][c] -= f[r] * A[k][c];
+            B[r][c] -= f[r] * B[k][c];
         }
         __syncthreads();
     }
+    for (int e = t; e < n * n; e += blockDim.x) M[e] = B[e / n][e % n];
 }
 
 // x = M b over the coarsest unknowns (M in FP64), ghost images updated
@@ -989,15 +1001,26 @@ __device__ inline void prolong_at(const LevTab<T> &lc, const LevTab<T> &lt, cons
 __device__ inline int colour_count(const Box &b) { return ((b.ext[0] + 1) >> 1) * b.ext[1] * b.ext[2]; }
 __device__ inline int point_count(const Box &b) { return b.ext[0] * b.ext[1] * b.ext[2]; }
 
-// one red-black Gauss-Seidel pass over the unknowns of component A by the
-// whole workgroup, the same update and order as the launched smoother
 template <typename T, int D, int VEL, int A>
 __device__ inline void wg_sweep_comp(const LevTab<T> &lt)
 {
-    const Box box = unk_box(lt.g, VEL ? face_mask(A) : 0);
-    const int n = colour_count(box);
+    const Grid &g = lt.g;
+    const int vmask = VEL ? face_mask(A) : 0;
+    const Box box = unk_box(g, vmask);
+    const int n = ((box.ext[0] + 1) >> 1) * box.ext[1] * box.ext[2];
+    T *x = VEL ? lt.xu[A] : lt.xp;
+    const T *b = VEL ? lt.bu[A] : lt.bp;
     for (int colour = 0; colour < 2; ++colour) {
-        for (int t = threadIdx.x; t < n; t += blockDim.x) sweep_at<T, D, VEL, A>(lt, box, colour, t);
+        for (int t = threadIdx.x; t < n; t += blockDim.x) {
+            int i, j, k;
+            if (!box_colour_pos(box, colour, t, i, j, k)) continue;
+            T Ax, dg;
+            wg_row<T, D, VEL, A>(lt, i, j, k, Ax, dg);
+            const long long e = at(g, i, j, k);
+            const T xn = x[e] + (b[e] - Ax) / dg;
+            x[e] = xn;
+            write_images(g, vmask, VEL ? ROLE_V : ROLE_P, x, i, j, k, xn);
+        }
         __syncthreads();
     }
 }
@@ -1016,37 +1039,72 @@ template <typename T, int D, int VEL, int A>
 __device__ inline void wg_residual_comp(const LevTab<T> &lt)
 {
     const Box box = unk_box(lt.g, VEL ? face_mask(A) : 0);
-    const int n = point_count(box);
-    for (int t = threadIdx.x; t < n; t += blockDim.x) (void)resid_at<T, D, VEL, A>(lt, box, t);
+    const int n = box.ext[0] * box.ext[1] * box.ext[2];
+    T *r = VEL ? lt.ru[A] : lt.rp;
+    const T *b = VEL ? lt.bu[A] : lt.bp;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        int i, j, k;
+        box_pos(box, t, i, j, k);
+        T Ax, dg;
+        wg_row<T, D, VEL, A>(lt, i, j, k, Ax, dg);
+        const long long e = at(lt.g, i, j, k);
+        r[e] = b[e] - Ax;
+    }
 }
 
+// coarse right-hand side = restriction of the fine residual, coarse
+// correction cleared (with its images)
 template <typename T, int D, int VEL, int A>
 __device__ inline void wg_restrict_comp(const LevTab<T> &lt, const LevTab<T> &lc)
 {
-    const Box box = unk_box(lc.g, VEL ? face_mask(A) : 0);
-    const int n = point_count(box);
-    for (int t = threadIdx.x; t < n; t += blockDim.x) restrict_at<T, D, VEL, A>(lt, lc, box, t);
+    const int vmask = VEL ? face_mask(A) : 0;
+    const int role = VEL ? ROLE_V : ROLE_P;
+    const Box box = unk_box(lc.g, vmask);
+    const int n = box.ext[0] * box.ext[1] * box.ext[2];
+    const T *src = VEL ? lt.ru[A] : lt.rp;
+    T *bc = VEL ? lc.bu[A] : lc.bp;
+    T *xc = VEL ? lc.xu[A] : lc.xp;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        int I, J, K;
+        box_pos(box, t, I, J, K);
+        const long long e = at(lc.g, I, J, K);
+        bc[e] = (T)restrict_any<T, D>(vmask, lt.g, role, src, I, J, K);
+        xc[e] = T(0);
+        write_images(lc.g, vmask, role, xc, I, J, K, T(0));
+    }
 }
 
 template <typename T, int D, int VEL, int A>
 __device__ inline void wg_prolong_comp(const LevTab<T> &lc, const LevTab<T> &lt)
 {
-    const Box box = unk_box(lt.g, VEL ? face_mask(A) : 0);
-    const int n = point_count(box);
-    for (int t = threadIdx.x; t < n; t += blockDim.x) prolong_at<T, D, VEL, A>(lc, lt, box, t);
+    const int vmask = VEL ? face_mask(A) : 0;
+    const int role = VEL ? ROLE_V : ROLE_P;
+    const Box box = unk_box(lt.g, vmask);
+    const int n = box.ext[0] * box.ext[1] * box.ext[2];
+    const T *src = VEL ? lc.xu[A] : lc.xp;
+    T *x = VEL ? lt.xu[A] : lt.xp;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        int i, j, k;
+        box_pos(box, t, i, j, k);
+        const long long e = at(lt.g, i, j, k);
+        const T v = x[e] + (T)prolong_any<T, D>(vmask, lc.g, role, src, i, j, k);
+        x[e] = v;
+        write_images(lt.g, vmask, role, x, i, j, k, v);
+    }
 }
 
 // The part of a V-cycle from level l0 down to the coarsest level and back,
 // in one workgroup: the same passes, in the same order, as the launched
 // kernels, with a barrier where a launch boundary would be.
 template <typename T, int D, int VEL>
-__device__ void coarse_cycle(const LevTab<T> *__restrict__ tab, int l0, int L, int nu1, int nu2, int ndense,
-                             const long long *__restrict__ uidx, const int *__restrict__ ucomp,
-                             const double *__restrict__ M)
+__device__ __attribute__((always_inline)) inline void coarse_cycle(const LevTab<T> *__restrict__ tab, int l0, int L, int nu1,
+                                                                  int nu2, int ndense,
+                                    const long long *__restrict__ uidx, const int *__restrict__ ucomp,
+                                    const double *__restrict__ M)
 {
     constexpr int A2 = D == 3 ? 2 : 1;
     for (int l = l0; l < L - 1; ++l) {
-        const LevTab<T> lt = tab[l];
+        const LevTab<T> &lt = tab[l];
         for (int s = 0; s < nu1; ++s) wg_sweep<T, D, VEL>(lt);
         wg_residual_comp<T, D, VEL, 0>(lt);
         if (VEL) {
@@ -1054,7 +1112,7 @@ __device__ void coarse_cycle(const LevTab<T> *__restrict__ tab, int l0, int L, i
             if (D == 3) wg_residual_comp<T, D, VEL, A2>(lt);
         }
         __syncthreads();
-        const LevTab<T> lc = tab[l + 1];
+        const LevTab<T> &lc = tab[l + 1];
         wg_restrict_comp<T, D, VEL, 0>(lt, lc);
         if (VEL) {
             wg_restrict_comp<T, D, VEL, 1>(lt, lc);
@@ -1063,7 +1121,7 @@ __device__ void coarse_cycle(const LevTab<T> *__restrict__ tab, int l0, int L, i
         __syncthreads();
     }
     {
-        const LevTab<T> lt = tab[L - 1];
+        const LevTab<T> &lt = tab[L - 1];
         if (ndense > 0) {
             __shared__ double bv[64];
             const int r = threadIdx.x;
@@ -1089,8 +1147,8 @@ __device__ void coarse_cycle(const LevTab<T> *__restrict__ tab, int l0, int L, i
         }
     }
     for (int l = L - 2; l >= l0; --l) {
-        const LevTab<T> lt = tab[l];
-        const LevTab<T> lc = tab[l + 1];
+        const LevTab<T> &lt = tab[l];
+        const LevTab<T> &lc = tab[l + 1];
         wg_prolong_comp<T, D, VEL, 0>(lc, lt);
         if (VEL) {
             wg_prolong_comp<T, D, VEL, 1>(lc, lt);
@@ -1101,10 +1159,12 @@ __device__ void coarse_cycle(const LevTab<T> *__restrict__ tab, int l0, int L, i
     }
 }
 
+
 template <typename T, int D, int VEL>
-__global__ void __launch_bounds__(1024) k_coarse_vcycle(const LevTab<T> *__restrict__ tab, int l0, int L, int nu1,
-                                                         int nu2, int ndense, const long long *__restrict__ uidx,
-                                                         const int *__restrict__ ucomp, const double *__restrict__ M)
+__global__ void __launch_bounds__(wg_threads(D, VEL)) k_coarse_vcycle(const LevTab<T> *__restrict__ tab, int l0, int L, int nu1,
+                                                               int nu2, int ndense, const long long *__restrict__ uidx,
+                                                               const int *__restrict__ ucomp,
+                                                               const double *__restrict__ M)
 {
     coarse_cycle<T, D, VEL>(tab, l0, L, nu1, nu2, ndense, uidx, ucomp, M);
 }
@@ -1255,7 +1315,7 @@ __global__ void __launch_bounds__(256) k_badd(const BEntry *__restrict__ ent, co
 
 // the coarse part of the V-cycle of every context, one workgroup each
 template <typename T, int D, int VEL>
-__global__ void __launch_bounds__(1024) k_bcoarse(const BCoarse *__restrict__ items, const int *__restrict__ flags,
+__global__ void __launch_bounds__(wg_threads(D, VEL)) k_bcoarse(const BCoarse *__restrict__ items, const int *__restrict__ flags,
                                                   int nu1, int nu2)
 {
     const BCoarse I = items[blockIdx.x];
@@ -1479,11 +1539,13 @@ void launch_prolong_add(const Grid &gc, const Grid &gf, int ncomp, const int *vm
 }
 
 void launch_dense_inverse(const Grid &g, int velocity, int n, const long long *uidx, const int *ucomp,
-                          const CoefP<double> &cp, const CoefU<double> &cu, double mass, double cvisc,
-                          const VelArr<double> &tmp, int singular, double *Aw, double *M, hipStream_t s)
+                          const CoefP<double> &cp, const CoefU<double> &cu, double mass, double cvisc, double *tmp,
+                          int singular, double *Aw, double *M, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_dense_inverse, dim3(1), dim3(64), 0, s, g, velocity, n, uidx, ucomp, cp, cu, mass, cvisc, tmp,
-                       singular, Aw, M);
+    if (n <= 0 || n > DENSE_LDS) return;
+    hipLaunchKernelGGL(k_dense_assemble, dim3(n), dim3(256), 0, s, g, velocity, n, uidx, ucomp, cp, cu, mass, cvisc,
+                       tmp, Aw);
+    hipLaunchKernelGGL(k_dense_gj, dim3(1), dim3(1024), 0, s, n, singular, Aw, M);
 }
 
 template <typename T>
@@ -1554,7 +1616,7 @@ void launch_coarse_vcycle(int D, const LevTab<T> *tab, int l0, int L, int vel, i
                           const long long *uidx, const int *ucomp, const double *M, hipStream_t s)
 {
 #define LAUNCH(DD, VV)                                                                                              \
-    hipLaunchKernelGGL((k_coarse_vcycle<T, DD, VV>), dim3(1), dim3(1024), 0, s, tab, l0, L, nu1, nu2, ndense, uidx, \
+    hipLaunchKernelGGL((k_coarse_vcycle<T, DD, VV>), dim3(1), dim3(wg_threads(DD, VV)), 0, s, tab, l0, L, nu1, nu2, ndense, uidx, \
                        ucomp, M)
     if (D == 3) {
         if (vel) LAUNCH(3, 1);
@@ -1661,7 +1723,7 @@ void launch_bcoarse(int D, int vel, const BCoarse *items, unsigned nitems, const
                     hipStream_t s)
 {
     if (nitems == 0) return;
-    const dim3 g(nitems), b(1024);
+    const dim3 g(nitems), b(wg_threads(D, vel));
     if (D == 3) {
         if (vel) hipLaunchKernelGGL((k_bcoarse<T, 3, 1>), g, b, 0, s, items, flags, nu1, nu2);
         else hipLaunchKernelGGL((k_bcoarse<T, 3, 0>), g, b, 0, s, items, flags, nu1, nu2);
