@@ -264,13 +264,14 @@ const char *ibb_group_last_error(const ibb_group *group);
 /* --- diagnostics ----------------------------------------------------------- */
 
 /* Device timing of the finest-level multigrid kernels.  While enabled, every
- * launch of a finest-level smoother colour pass or residual is bracketed by
- * HIP events on the context's stream; the durations accumulate per kernel
- * class until read.  Classes: 0 viscous smoother FP64, 1 pressure smoother
- * FP64, 2 viscous smoother FP32, 3 pressure smoother FP32, 4 viscous
- * residual FP64, 5 pressure residual FP64.  ibb_profile_read (host outputs)
- * returns the launches, their summed device time and the summed number of
- * unknowns they updated or evaluated; enabling resets the totals. */
+ * launch of a finest-level smoother colour pass or residual carries a pair of
+ * HIP events that its dispatch records at the kernel's start and end (on the
+ * context's stream); the durations accumulate per kernel class until read.
+ * Classes: 0 viscous smoother FP64, 1 pressure smoother FP64, 2 viscous
+ * smoother FP32, 3 pressure smoother FP32, 4 viscous residual FP64,
+ * 5 pressure residual FP64.  ibb_profile_read (host outputs) returns the
+ * launches, their summed device time and the summed number of unknowns they
+ * updated or evaluated; enabling resets the totals. */
 ibb_status ibb_profile_enable(ibb_ctx *ctx, int enable);
 ibb_status ibb_profile_read(ibb_ctx *ctx, int kernel_class, long long *launches, double *total_ms,
                             long long *units);

@@ -116,20 +116,22 @@ ibb_status fail(ibb_ctx *c, ibb_status st, const char *msg)
 
 constexpr int PROF_PAIRS = 2048;
 
-// start a timed launch of class cls: returns the pair slot or -1
+// time the next launch (of class cls): its dispatch records the kernel's
+// start and end into the slot's event pair; returns the slot or -1
 int prof_begin(ibb_ctx *c, int cls, long long units)
 {
     if (!c->prof || c->pused >= PROF_PAIRS) return -1;
     const int k = c->pused++;
     c->pcls[k] = cls;
     c->punits[k] = units;
-    (void)hipEventRecord(c->pev[2 * k], c->s);
+    set_launch_events(c->pev[2 * k], c->pev[2 * k + 1]);
     return k;
 }
 
-void prof_end(ibb_ctx *c, int k)
+// disarm the pair if the launcher had nothing to launch
+void prof_end(ibb_ctx *, int k)
 {
-    if (k >= 0) (void)hipEventRecord(c->pev[2 * k + 1], c->s);
+    if (k >= 0) set_launch_events(nullptr, nullptr);
 }
 
 // fold the recorded pairs into the totals (synchronises on the last event)

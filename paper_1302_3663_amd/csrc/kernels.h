@@ -130,6 +130,10 @@ template <typename T>
 void launch_coarse_vcycle(int D, const LevTab<T> *tab, int l0, int L, int vel, int nu1, int nu2, int ndense,
                           const long long *uidx, const int *ucomp, const double *M, hipStream_t s);
 
+// Arm a start/stop event pair for the next smoother or residual launch of
+// this thread: the dispatch itself records the kernel's start and end.
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
+
 // ---- batched passes over several contexts (mg.hip) ----
 // One entry per block of a batched launch: the context's level table(s) at
 // the pass's level, the first block of that context in the launch, and for

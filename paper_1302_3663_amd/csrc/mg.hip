@@ -16,6 +16,8 @@
 // it (the launched passes and the one-workgroup coarse cycle).
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -1328,6 +1330,27 @@ __global__ void __launch_bounds__(wg_threads(D, VEL)) k_bcoarse(const BCoarse *_
 // host launchers
 // ---------------------------------------------------------------------------
 static inline unsigned blocks_for(long long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+
+// events armed for the next timed launch (set_launch_events): the kernel's
+// own start and end are recorded into them by the dispatch
+static thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+
+void set_launch_events(hipEvent_t start, hipEvent_t stop)
+{
+    t_ev_start = start;
+    t_ev_stop = stop;
+}
+
+template <typename K, typename... Args>
+static void launch_timed(K kernel, dim3 grid, dim3 block, hipStream_t s, Args... args)
+{
+    if (t_ev_start) {
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, t_ev_start, t_ev_stop, 0, args...);
+        t_ev_start = t_ev_stop = nullptr;
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+    }
+}
 static inline long long box_count(const Box &b) { return (long long)b.ext[0] * b.ext[1] * b.ext[2]; }
 
 template <typename T>
@@ -1337,9 +1360,9 @@ void launch_smooth_p(const Grid &g, const T *b, T *x, const CoefP<T> &cf, T cvis
     const long long n = (long long)((P.ext[0] + 1) / 2) * P.ext[1] * P.ext[2];
     if (n <= 0) return;
     if (g.D == 3)
-        hipLaunchKernelGGL((k_smooth_p<T, 3>), dim3(blocks_for(n)), dim3(256), 0, s, g, P, b, x, cf, cvisc, colour);
+        launch_timed(k_smooth_p<T, 3>, dim3(blocks_for(n)), dim3(256), s, g, P, b, x, cf, cvisc, colour);
     else
-        hipLaunchKernelGGL((k_smooth_p<T, 2>), dim3(blocks_for(n)), dim3(256), 0, s, g, P, b, x, cf, cvisc, colour);
+        launch_timed(k_smooth_p<T, 2>, dim3(blocks_for(n)), dim3(256), s, g, P, b, x, cf, cvisc, colour);
 }
 
 template <typename T>
@@ -1351,12 +1374,12 @@ void launch_smooth_u(const Grid &g, int a, const T *b, const VelArr<T> &x, const
     if (n <= 0) return;
     const dim3 grid(blocks_for(n)), blk(256);
     if (g.D == 3) {
-        if (a == 0) hipLaunchKernelGGL((k_smooth_u<T, 3, 0>), grid, blk, 0, s, g, P, b, x, cf, mass, cvisc, colour);
-        else if (a == 1) hipLaunchKernelGGL((k_smooth_u<T, 3, 1>), grid, blk, 0, s, g, P, b, x, cf, mass, cvisc, colour);
-        else hipLaunchKernelGGL((k_smooth_u<T, 3, 2>), grid, blk, 0, s, g, P, b, x, cf, mass, cvisc, colour);
+        if (a == 0) launch_timed(k_smooth_u<T, 3, 0>, grid, blk, s, g, P, b, x, cf, mass, cvisc, colour);
+        else if (a == 1) launch_timed(k_smooth_u<T, 3, 1>, grid, blk, s, g, P, b, x, cf, mass, cvisc, colour);
+        else launch_timed(k_smooth_u<T, 3, 2>, grid, blk, s, g, P, b, x, cf, mass, cvisc, colour);
     } else {
-        if (a == 0) hipLaunchKernelGGL((k_smooth_u<T, 2, 0>), grid, blk, 0, s, g, P, b, x, cf, mass, cvisc, colour);
-        else hipLaunchKernelGGL((k_smooth_u<T, 2, 1>), grid, blk, 0, s, g, P, b, x, cf, mass, cvisc, colour);
+        if (a == 0) launch_timed(k_smooth_u<T, 2, 0>, grid, blk, s, g, P, b, x, cf, mass, cvisc, colour);
+        else launch_timed(k_smooth_u<T, 2, 1>, grid, blk, s, g, P, b, x, cf, mass, cvisc, colour);
     }
 }
 
@@ -1372,8 +1395,8 @@ int launch_resid_p(const Grid &g, const T *b, const T *x, const CoefP<T> &cf, T 
 {
     const Box P = unk_box(g, 0);
     const unsigned nb = stride_blocks(box_count(P));
-    if (g.D == 3) hipLaunchKernelGGL((k_resid_p<T, 3>), dim3(nb), dim3(256), 0, s, g, P, b, x, cf, cvisc, r, partial);
-    else hipLaunchKernelGGL((k_resid_p<T, 2>), dim3(nb), dim3(256), 0, s, g, P, b, x, cf, cvisc, r, partial);
+    if (g.D == 3) launch_timed(k_resid_p<T, 3>, dim3(nb), dim3(256), s, g, P, b, x, cf, cvisc, r, partial);
+    else launch_timed(k_resid_p<T, 2>, dim3(nb), dim3(256), s, g, P, b, x, cf, cvisc, r, partial);
     return (int)nb;
 }
 
@@ -1389,9 +1412,9 @@ int launch_resid_u(const Grid &g, const VelArrC<T> &b, const VelArr<T> &x, const
     }
     const unsigned nb = stride_blocks(mx);
     if (g.D == 3)
-        hipLaunchKernelGGL((k_resid_u<T, 3>), dim3(nb, 3), dim3(256), 0, s, g, parts, b, x, cf, mass, cvisc, r, partial);
+        launch_timed(k_resid_u<T, 3>, dim3(nb, 3), dim3(256), s, g, parts, b, x, cf, mass, cvisc, r, partial);
     else
-        hipLaunchKernelGGL((k_resid_u<T, 2>), dim3(nb, 2), dim3(256), 0, s, g, parts, b, x, cf, mass, cvisc, r, partial);
+        launch_timed(k_resid_u<T, 2>, dim3(nb, 2), dim3(256), s, g, parts, b, x, cf, mass, cvisc, r, partial);
     return (int)nb * g.D;
 }
 
