@@ -17,6 +17,11 @@ wall-clock per step.  The dominant finest-level kernel is timed live with HIP
 events on the context's stream and set against the HBM roofline using its
 algorithmic bytes per unknown.  The CPU baseline times the FP64 oracle on a
 bounded sample of the same workload.
+
+`--workload serving` runs the serving stream instead: independent requests of
+mixed grids and contrasts arriving over time, admitted by slot cap and
+device-memory budget and stepped together; it prints its own line with the
+aggregate solve DOF/s and the p50/p99 step and request latencies.
 """
 import argparse
 import hashlib
@@ -140,6 +145,74 @@ def cpu_baseline(case, log):
                        f"same workload, {secs:.1f} s single-threaded")
 
 
+SERVING_METRIC = "serving: aggregate MG solve DOF/s and p50/p99 step latency, mixed request stream"
+
+
+def run_serving(args, log):
+    """The serving stream: args.requests requests (synth.serving_request)
+    arriving with exponential gaps at args.rate per second, admitted by slot
+    cap and device-memory budget, stepped together (serve.Server)."""
+    import torch
+
+    from paper_1302_3663_amd import _lib as L
+    from paper_1302_3663_amd import serve, synth
+    log(f"serving: generating {args.requests} requests")
+    cases = [synth.serving_request(j) for j in range(args.requests)]
+    arrivals = serve.poisson_arrivals(args.requests, args.rate, seed=4)
+    srv = serve.Server(budget_bytes=int(args.budget_gb * (1 << 30)), max_slots=args.slots,
+                       precision=L.IBB_FP32_REFINED, inner_cycles=args.inner)
+    # warmup: a few requests through the same loop (loads the code objects)
+    warm = [serve.Request(-1 - j, 0.0, cases[j], 1) for j in range(min(args.warmup, len(cases)))]
+    if warm:
+        srv.run(warm)
+    reqs = [serve.Request(j, a, c, c["steps"]) for j, (a, c) in enumerate(zip(arrivals, cases))]
+    k = [0]
+
+    def tick_log(m):
+        k[0] += 1
+        if k[0] % 10 == 0:
+            log(m)
+    torch.cuda.synchronize()
+    s = srv.run(reqs, log=tick_log)
+    sizes = {}
+    for c in cases:
+        key = "x".join(str(v) for v in c["size"])
+        sizes[key] = sizes.get(key, 0) + 1
+    steps = sum(r.done for r in reqs)
+    return {
+        "metric": SERVING_METRIC,
+        "value": round(s["solve_dof_per_s"], 1),
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": len(warm),
+        "ms_per_step": round(1e3 * s["busy_s"] / max(s["ticks"], 1), 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-inner/f64-outer",
+        "data": "synthetic",
+        "config": {"workload": "serving", "requests": args.requests, "rate_per_s": args.rate,
+                   "steps_per_request": cases[0]["steps"], "slots": args.slots, "budget_gb": args.budget_gb,
+                   "sizes": sizes, "inner_cycles": args.inner},
+        "p50_step_ms": round(s["p50_step_ms"], 3),
+        "p99_step_ms": round(s["p99_step_ms"], 3),
+        "p50_request_s": round(s["p50_request_s"], 3),
+        "p99_request_s": round(s["p99_request_s"], 3),
+        "p50_wait_s": round(s["p50_wait_s"], 3),
+        "p99_wait_s": round(s["p99_wait_s"], 3),
+        "wall_s": round(s["wall_s"], 3),
+        "ticks": s["ticks"],
+        "mean_resident": round(s["mean_resident"], 2),
+        "peak_resident": s["peak_resident"],
+        "peak_bytes": s["peak_bytes"],
+        "busy_dof_per_s": round(s["busy_dof_per_s"], 1),
+        "failed_steps": s["failed_steps"],
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,7 +220,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--inner", type=int, default=2, help="FP32 V-cycles per FP64 outer iteration")
     ap.add_argument("--modes", default="both", choices=["both", "fp64", "refined"])
-    ap.add_argument("--workload", default="tube3d_64x64x128")
+    ap.add_argument("--workload", default="tube3d_64x64x128",
+                    help="a synth.WORKLOADS entry, or 'serving' for the mixed request stream")
+    ap.add_argument("--requests", type=int, default=256, help="serving: number of requests")
+    ap.add_argument("--rate", type=float, default=40.0, help="serving: arrivals per second")
+    ap.add_argument("--slots", type=int, default=32, help="serving: resident request cap")
+    ap.add_argument("--budget-gb", type=float, default=32.0, help="serving: device-memory budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="also run a plain device copy of this size (counter calibration)")
@@ -168,6 +246,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "serving":
+        print(json.dumps(run_serving(args, log)), flush=True)
+        return
     log(f"workload {args.workload}: generating inputs")
     case = synth.WORKLOADS[args.workload]()
     p = case["params"]

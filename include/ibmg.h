@@ -103,7 +103,8 @@ typedef struct {
     int precision;      /* ibb_precision */
     int inner_cycles;   /* FP32 V-cycles per outer FP64 iteration (refined) */
     int wg_coarse_max;  /* levels whose largest colour class has at most this many points
-                           run the rest of the V-cycle in one workgroup; 0: 2048, < 0: never */
+                           run the rest of the V-cycle in one workgroup; 0: 512 (one point
+                           per thread of the workgroup), < 0: never */
 } ibb_desc;
 
 typedef struct {

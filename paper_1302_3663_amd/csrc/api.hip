@@ -326,7 +326,7 @@ void setup_shapes(ibb_ctx *c, const ibb_desc *d, int64_t max_nodes, int64_t max_
     for (int a = 0; a < d->dim; ++a)
         if (d->axis_bc[a] == IBB_AXIS_INOUT) c->singular_p = false;
     // first level whose largest colour class fits one workgroup pass budget
-    const long long wgmax = d->wg_coarse_max == 0 ? 2048 : d->wg_coarse_max;
+    const long long wgmax = d->wg_coarse_max == 0 ? WG_THREADS : d->wg_coarse_max;
     c->lc_u = c->lc_p = MAXLEV;
     if (d->wg_coarse_max >= 0) {
         // the sizes shrink with the level, so the first level that fits starts it

@@ -13,6 +13,7 @@ The paper's microscopy cell coordinates are not available, so node clouds are
 drawn from the shapes and spacings it describes (mounds and films on the
 bottom wall, about 1 um between cells, springs to neighbours within a few um).
 """
+import functools
 import math
 
 import numpy as np
@@ -40,16 +41,16 @@ def base_params(dim, n, axis_bc, h):
 # --------------------------------------------------------------------------
 def half_disc_uniform(rng, n, cx, r):
     """n points uniform in the half-disc of radius r centred at (cx, 0), y >= 0."""
-    pts = []
-    while len(pts) < n:
+    xs, ys, have = [], [], 0
+    while have < n:
         x = rng.uniform(-r, r, size=4 * n)
         y = rng.uniform(0.0, r, size=4 * n)
         ok = x * x + y * y < r * r
-        for a, b in zip(x[ok], y[ok]):
-            pts.append((cx + a, b))
-            if len(pts) == n:
-                break
-    return np.array(pts).T.copy()
+        take = min(n - have, int(ok.sum()))
+        xs.append(cx + x[ok][:take])
+        ys.append(y[ok][:take])
+        have += take
+    return np.array([np.concatenate(xs), np.concatenate(ys)])
 
 
 def poisson_disc(rng, inside, lo, hi, rmin, limit, seed_point, k=30):
@@ -132,6 +133,11 @@ def face_dims(p, a):
 def duct_profile(nx, ny, h, terms=199):
     """Laminar axial velocity in a square duct (Spiga-Morini double series),
     at cell centres of an nx x ny cross-section, scaled to 1 at the centre."""
+    return _duct_profile(int(nx), int(ny), float(h), int(terms)).copy()
+
+
+@functools.lru_cache(maxsize=16)
+def _duct_profile(nx, ny, h, terms):
     ax, ay = nx * h, ny * h
     x = (np.arange(nx) + 0.5) * h
     y = (np.arange(ny) + 0.5) * h
