@@ -105,6 +105,12 @@ typedef struct {
     int wg_coarse_max;  /* levels whose largest colour class has at most this many points
                            run the rest of the V-cycle in one workgroup; 0: 512 (one point
                            per thread of the workgroup), < 0: never */
+    /* detached fragments (see ibb_fragments): a node is anchored when, at the
+     * positions given to ibb_set_nodes, its coordinate along attach_axis is
+     * below attach_dist (the attachment wall is that axis's low wall) */
+    int track_fragments;   /* nonzero: ibb_lagrangian_update counts fragments */
+    int attach_axis;
+    double attach_dist;
 } ibb_desc;
 
 typedef struct {
@@ -120,6 +126,8 @@ typedef struct {
     int n_broken;  /* springs broken in this update */
     int n_alive;   /* springs alive afterwards */
     double t_ms;   /* device time of the update */
+    int n_fragments;  /* fragments after the update (-1: not tracked) */
+    int n_detached;   /* of them, fragments without an anchored node (-1: not tracked) */
 } ibb_lag_stats;
 
 typedef struct ibb_ctx ibb_ctx;
@@ -224,6 +232,16 @@ ibb_status ibb_interp(ibb_ctx *ctx, double width, int64_t n, const double *X, co
 /* Spread of node vectors F [dim][n] at X to the face lattices with width
  * `width` (eq:discrForceCouple); out is compact faces. */
 ibb_status ibb_spread(ibb_ctx *ctx, double width, int64_t n, const double *X, const double *F, double *out);
+
+/* Detached fragments (the results section observes pieces of biofilm
+ * breaking off; the paper gives no algorithm): the connected components of
+ * the graph of nodes joined by alive springs.  label (device, int32 [eta],
+ * may be null) receives for every node the smallest node id of its fragment;
+ * n_fragments and n_detached (host, may be null) receive the number of
+ * fragments and of those with no anchored node (desc.attach_axis,
+ * desc.attach_dist).  Exact integer results; IBB_ESTATE before nodes are
+ * set.  Synchronises the stream. */
+ibb_status ibb_fragments(ibb_ctx *ctx, int32_t *label, int *n_fragments, int *n_detached);
 
 /* --- groups: several contexts stepped together (serving) ------------------
  *

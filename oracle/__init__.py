@@ -100,6 +100,7 @@ def lib():
         L.orc_density.argtypes = [D, ctypes.c_long, dp, dp]
         L.orc_viscosity.argtypes = [D, ctypes.c_int, ctypes.c_long, dp, dp]
         L.orc_springs.argtypes = [D, ctypes.c_long, dp, ctypes.c_long, ip, dp, dp, u8, dp, ctypes.c_int, lp]
+        L.orc_fragments.argtypes = [ctypes.c_long, ctypes.c_long, ip, u8, u8, ip, lp, lp]
         L.orc_momentum_rhs.argtypes = [D, dp, dp, dp, dp, dp, dp, ctypes.c_int]
         L.orc_momentum_apply_full.argtypes = [D, dp, dp, dp, dp, dp]
         L.orc_pressure_rhs.argtypes = [D, dp, dp]
@@ -245,6 +246,30 @@ def springs(p, X, ij, rest, K, alive, do_break=True):
                              _d(rest), _d(K), al.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)), _d(F),
                              1 if do_break else 0, ctypes.byref(nb)), "springs")
     return F, al, nb.value
+
+
+def anchored_nodes(p, X0):
+    """Nodes within the attachment distance of the attachment wall at t = 0
+    (the low wall of axis attach_axis)."""
+    ax = int(p.get("attach_axis", 1))
+    return (np.asarray(X0, float)[ax] < float(p.get("attach_dist", 0.0))).astype(np.uint8)
+
+
+def fragments(ij, alive, anchored):
+    """Connected components of the alive springs: (label per node = smallest
+    node id of its fragment, number of fragments, number of detached ones)."""
+    ij = np.ascontiguousarray(ij, dtype=np.int32)
+    m = ij.shape[1]
+    anchored = np.ascontiguousarray(anchored, dtype=np.uint8)
+    eta = anchored.size
+    al = np.ascontiguousarray(alive, dtype=np.uint8)
+    label = np.zeros(eta, np.int32)
+    nf, nd = ctypes.c_long(0), ctypes.c_long(0)
+    u8p = ctypes.POINTER(ctypes.c_ubyte)
+    _check(lib().orc_fragments(eta, m, ij.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), al.ctypes.data_as(u8p),
+                               anchored.ctypes.data_as(u8p), label.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                               ctypes.byref(nf), ctypes.byref(nd)), "fragments")
+    return label, nf.value, nd.value
 
 
 # --------------------------------------------------------------------------

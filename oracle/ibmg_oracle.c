@@ -15,7 +15,9 @@
  *     (eq:discrForceCouple, eq:discrDensCouple, eq:discrVelCouple),
  *   - the viscosity field as a max over nodes (eq:ViscExp),
  *   - Hookean springs with breakage (eq:springF, eq:defineK and the
- *     twice-the-rest-length rule of the "Elastic Forces" section),
+ *     twice-the-rest-length rule of the "Elastic Forces" section), and the
+ *     detached fragments they leave (connected components, see
+ *     orc_fragments),
  *   - the projection step (eq:NSdis1-1, eq:divergenceGrad,
  *     eq:divergencePartial, eq:NSdis2, eq:NSdis4) on a staggered MAC grid,
  *   - geometric multigrid with red-black Gauss-Seidel, full-weighting
@@ -1456,6 +1458,58 @@ int orc_springs(const orc_desc *d, long eta, const double *X, long m, const int 
         }
     }
     if (n_broken) *n_broken = nb;
+    return ORC_OK;
+}
+
+/* Detached fragments (the "break off" observation of the results section;
+ * the paper gives no algorithm): the fragments are the connected components
+ * of the graph whose vertices are the nodes and whose edges are the alive
+ * springs.  Each fragment is labelled by its smallest node id.  A fragment is
+ * detached when none of its nodes was anchored (within the attachment
+ * distance of the attachment wall at t = 0).
+ *
+ * Plain breadth-first search from every unvisited node in increasing id
+ * order: the node a search starts from is the smallest id of its component,
+ * because every smaller id was visited by an earlier search. */
+int orc_fragments(long eta, long m, const int *ij, const unsigned char *alive, const unsigned char *anchored,
+                  int *label, long *n_fragments, long *n_detached)
+{
+    long *deg = calloc((size_t)eta + 1, sizeof(long));
+    long *adj = malloc(sizeof(long) * (size_t)(2 * m + 1));
+    long *fill = calloc((size_t)eta + 1, sizeof(long));
+    long *queue = malloc(sizeof(long) * (size_t)(eta + 1));
+    if (!deg || !adj || !fill || !queue) { free(deg); free(adj); free(fill); free(queue); return ORC_ENOMEM; }
+    for (long e = 0; e < m; ++e)
+        if (alive[e]) { deg[ij[e] + 1]++; deg[ij[m + e] + 1]++; }
+    for (long s = 0; s < eta; ++s) deg[s + 1] += deg[s];          /* row starts */
+    for (long e = 0; e < m; ++e) {
+        if (!alive[e]) continue;
+        long i = ij[e], j = ij[m + e];
+        adj[deg[i] + fill[i]++] = j;
+        adj[deg[j] + fill[j]++] = i;
+    }
+    for (long s = 0; s < eta; ++s) label[s] = -1;
+    long nf = 0, nd = 0;
+    for (long s = 0; s < eta; ++s) {
+        if (label[s] >= 0) continue;
+        long head = 0, tail = 0;
+        int anchored_any = 0;
+        label[s] = (int)s;
+        queue[tail++] = s;
+        while (head < tail) {
+            long v = queue[head++];
+            if (anchored[v]) anchored_any = 1;
+            for (long k = deg[v]; k < deg[v + 1]; ++k) {
+                long w = adj[k];
+                if (label[w] < 0) { label[w] = (int)s; queue[tail++] = w; }
+            }
+        }
+        ++nf;
+        if (!anchored_any) ++nd;
+    }
+    free(deg); free(adj); free(fill); free(queue);
+    *n_fragments = nf;
+    *n_detached = nd;
     return ORC_OK;
 }
 

@@ -9,13 +9,14 @@ Strategy" section (TEST INFRASTRUCTURE ONLY).
     U     <- J_h u^n+1 at X^n                                      (eq:discrVelCouple)
     X^n+1 <- X^n + (dt / sigma) U  (periodic axes wrap)
     springs: break those stretched past break_ratio x rest, then forces
+    fragments: connected components of the alive springs (when tracked)
     f, rho, mu <- spread at X^n+1                                  (eq:discrForceCouple,
                                                                     eq:discrDensCouple, eq:ViscExp)
 """
 import numpy as np
 
-from . import (AX_INOUT, AX_PERIODIC, Hierarchy, density, interp_vec, momentum_rhs, pressure_rhs, project,
-               spread_vec, springs, viscosity_cells, viscosity_edges)
+from . import (AX_INOUT, AX_PERIODIC, Hierarchy, anchored_nodes, density, fragments, interp_vec, momentum_rhs,
+               pressure_rhs, project, spread_vec, springs, viscosity_cells, viscosity_edges)
 
 
 class State:
@@ -34,6 +35,7 @@ class State:
         self.f = self.rho = self.mu_c = self.mu_e = None
         self.hier = None
         self.step = 0
+        self.anchored = anchored_nodes(p, self.X)   # at t = 0
 
 
 def update_coefficients(st, do_break):
@@ -87,7 +89,10 @@ def lagrangian_update(st):
     st.X = wrap_positions(p, st.X + (p["dt"] / p["sigma"]) * U)
     nb = update_coefficients(st, do_break=True)
     st.step += 1
-    return dict(U=U, n_broken=nb)
+    out = dict(U=U, n_broken=nb, n_alive=int(st.alive.sum()))
+    if p.get("track_fragments"):
+        out["label"], out["n_fragments"], out["n_detached"] = fragments(st.ij, st.alive, st.anchored)
+    return out
 
 
 def run(st, steps):

@@ -48,6 +48,9 @@ class Desc(ctypes.Structure):
         ("precision", ctypes.c_int),
         ("inner_cycles", ctypes.c_int),
         ("wg_coarse_max", ctypes.c_int),
+        ("track_fragments", ctypes.c_int),
+        ("attach_axis", ctypes.c_int),
+        ("attach_dist", ctypes.c_double),
     ]
 
 
@@ -63,7 +66,8 @@ class SolveStats(ctypes.Structure):
 
 
 class LagStats(ctypes.Structure):
-    _fields_ = [("n_broken", ctypes.c_int), ("n_alive", ctypes.c_int), ("t_ms", ctypes.c_double)]
+    _fields_ = [("n_broken", ctypes.c_int), ("n_alive", ctypes.c_int), ("t_ms", ctypes.c_double),
+                ("n_fragments", ctypes.c_int), ("n_detached", ctypes.c_int)]
 
 
 def make_desc(p, precision=IBB_FP64, inner_cycles=1):
@@ -84,6 +88,9 @@ def make_desc(p, precision=IBB_FP64, inner_cycles=1):
     d.precision = int(p.get("precision", precision))
     d.inner_cycles = int(p.get("inner_cycles", inner_cycles))
     d.wg_coarse_max = int(p.get("wg_coarse_max", 0))
+    d.track_fragments = int(p.get("track_fragments", 0))
+    d.attach_axis = int(p.get("attach_axis", 1))
+    d.attach_dist = float(p.get("attach_dist", 0.0))
     return d
 
 
@@ -121,6 +128,7 @@ ABI_FUNCTIONS = {
     "ibb_profile_read": (ctypes.c_int, [CTX, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong),
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
     "ibb_level_info": (ctypes.c_int, [CTX, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "ibb_fragments": (ctypes.c_int, [CTX, VP, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "ibb_group_footprint_bytes": (ctypes.c_int, [ctypes.POINTER(CTX), ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "ibb_group_create": (ctypes.c_int, [ctypes.POINTER(CTX), ctypes.c_int, VP, ctypes.c_size_t,
                                         ctypes.POINTER(VP)]),

@@ -82,7 +82,10 @@ struct ibb_ctx {
     double *rest = nullptr, *K = nullptr;
     unsigned char *alive = nullptr;
     int *inc_keys = nullptr, *inc_count = nullptr, *inc_start = nullptr, *inc_list = nullptr;
-    int *counters = nullptr;
+    int *counters = nullptr;   // [0] broken this update, [1] alive, [2] fragments, [3] detached
+    // detached fragments
+    unsigned char *anchored = nullptr;
+    int *frag_label = nullptr, *frag_root = nullptr, *frag_flag = nullptr;
     bool have_nodes = false, have_springs = false, have_coefs = false;
     hipEvent_t ev[4] = {};
     // finest-level kernel timing (ibb_profile_*)
@@ -164,6 +167,7 @@ ibb_status check_desc(const ibb_desc *d)
     if (d->nu1 < 0 || d->nu2 < 0 || d->nu1 + d->nu2 < 1 || d->max_cycles < 1) return IBB_EINVAL;
     if (d->precision != IBB_FP64 && d->precision != IBB_FP32_REFINED) return IBB_EINVAL;
     if (d->precision == IBB_FP32_REFINED && d->inner_cycles < 1) return IBB_EINVAL;
+    if (d->attach_axis < 0 || d->attach_axis >= d->dim || !(d->attach_dist >= 0)) return IBB_EINVAL;
     for (int a = 0; a < d->dim; ++a)
         if (d->axis_bc[a] == IBB_AXIS_PERIODIC && 4.0 * d->omega > d->n[a] * d->h) return IBB_EINVAL;
     return IBB_OK;
@@ -304,6 +308,10 @@ size_t carve(ibb_ctx *c, char *base, bool dry)
     c->inc_count = cv.take<int>(em);
     c->inc_start = cv.take<int>(em + 1);
     c->counters = cv.take<int>(8);
+    c->anchored = cv.take<unsigned char>(em);
+    c->frag_label = cv.take<int>(em);
+    c->frag_root = cv.take<int>(em);
+    c->frag_flag = cv.take<int>(4);
     c->scan_tmp = cv.take<int>(scan_scratch_ints((long long)std::max<size_t>((size_t)c->nbins_cap, em + 1)));
     return cv.off + 256;
 }
@@ -833,8 +841,28 @@ void fill_stats(ibb_ctx *c, const SolveOut &su, const SolveOut &sp, float tu, fl
     stats->dof_p = c->lv[0].np;
 }
 
+// connected components of the alive springs into frag_label, counts into
+// counters[2] (fragments) and counters[3] (detached); one host round trip per
+// hook-and-shortcut round until no label moves
+ibb_status frag_compute(ibb_ctx *c)
+{
+    const int eta = c->eta;
+    const int m = c->have_springs ? c->m : 0;
+    launch_frag_init(c->frag_label, eta, c->s);
+    for (int round = 0; round <= eta; ++round) {
+        launch_frag_round(c->ij, m, c->alive, c->frag_label, eta, c->frag_flag, c->s);
+        int changed = 0;
+        HIPCHK(hipMemcpyAsync(&changed, c->frag_flag, sizeof(int), hipMemcpyDeviceToHost, c->s));
+        HIPCHK(hipStreamSynchronize(c->s));
+        if (!changed) break;
+    }
+    launch_frag_count(c->frag_label, c->anchored, eta, c->frag_root, c->counters + 2, c->s);
+    return IBB_OK;
+}
+
 // interpolation, node update, breakage, forces, spread and the coefficient
-// hierarchy; the counters (broken this step, alive) are left on the device
+// hierarchy; the counters (broken this step, alive, and when tracked the
+// fragments and detached fragments) are left on the device
 ibb_status lag_launch(ibb_ctx *c)
 {
     Level &L0 = c->lv[0];
@@ -842,9 +870,13 @@ ibb_status lag_launch(ibb_ctx *c)
     launch_interp(L0.g, c->d.kernel, c->d.h, VelArrC<double>{{c->u[0], c->u[1], c->u[2]}}, c->X, em, c->eta, c->U,
                   em, c->s);
     launch_euler(L0.g, c->d.dt / c->d.sigma, c->U, c->X, em, c->eta, c->s);
-    launch_fill<int>(c->counters, 2, 0, c->s);
+    launch_fill<int>(c->counters, 4, 0, c->s);
     if (c->have_springs && c->m > 0)
         launch_spring_break(L0.g, c->d.break_ratio, c->X, em, c->ij, c->m, c->rest, c->alive, c->counters, c->s);
+    if (c->d.track_fragments) {
+        ibb_status fs = frag_compute(c);
+        if (fs) return fs;
+    }
     ibb_status st = rebuild_coefficients(c);
     if (st) return st;
     if (c->have_springs) launch_count_alive(c->alive, c->m, c->counters + 1, c->s);
@@ -1017,7 +1049,26 @@ ibb_status ibb_set_nodes(ibb_ctx *c, int64_t n, const double *X)
     for (int a = 0; a < c->d.dim; ++a)
         if (n > 0) HIPCHK(hipMemcpyAsync(c->X + a * em, X + a * n, n * sizeof(double), hipMemcpyDeviceToDevice, c->s));
     c->eta = (int)n;
+    launch_frag_anchor(c->lv[0].g, c->X, em, (int)n, c->d.attach_axis, c->d.attach_dist, c->anchored, c->s);
     c->have_nodes = true;
+    return IBB_OK;
+}
+
+ibb_status ibb_fragments(ibb_ctx *c, int32_t *label, int *n_fragments, int *n_detached)
+{
+    if (!c) return IBB_EINVAL;
+    if (!c->have_nodes) return fail(c, IBB_ESTATE, "ibb_fragments: set the nodes first");
+    launch_fill<int>(c->counters + 2, 2, 0, c->s);
+    ibb_status st = frag_compute(c);
+    if (st) return st;
+    if (label && c->eta > 0)
+        HIPCHK(hipMemcpyAsync(label, c->frag_label, c->eta * sizeof(int), hipMemcpyDeviceToDevice, c->s));
+    int cnt[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(cnt, c->counters + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->s));
+    if (n_fragments) *n_fragments = cnt[0];
+    if (n_detached) *n_detached = cnt[1];
     return IBB_OK;
 }
 
@@ -1105,8 +1156,8 @@ ibb_status ibb_lagrangian_update(ibb_ctx *c, ibb_lag_stats *stats)
     ibb_status st = lag_launch(c);
     if (st) return st;
     HIPCHK(hipEventRecord(c->ev[1], c->s));
-    int cnt[2] = {0, 0};
-    HIPCHK(hipMemcpyAsync(cnt, c->counters, 2 * sizeof(int), hipMemcpyDeviceToHost, c->s));
+    int cnt[4] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(cnt, c->counters, 4 * sizeof(int), hipMemcpyDeviceToHost, c->s));
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->s));
     if (stats) {
@@ -1115,6 +1166,8 @@ ibb_status ibb_lagrangian_update(ibb_ctx *c, ibb_lag_stats *stats)
         stats->n_broken = cnt[0];
         stats->n_alive = cnt[1];
         stats->t_ms = t;
+        stats->n_fragments = c->d.track_fragments ? cnt[2] : -1;
+        stats->n_detached = c->d.track_fragments ? cnt[3] : -1;
     }
     return IBB_OK;
 }
@@ -1523,7 +1576,7 @@ size_t group_bytes(const Plan &P, int n)
     cv.take<BCoarse>(P.cent.size());
     cv.take<int>(n);
     cv.take<double>(n);
-    cv.take<int>(2 * (size_t)n);
+    cv.take<int>(4 * (size_t)n);
     return cv.off + 256;
 }
 
@@ -1693,7 +1746,7 @@ ibb_status ibb_group_create(ibb_ctx *const *ctxs, int n, void *workspace, size_t
     g->cent = cv.take<BCoarse>(g->plan.cent.size());
     g->flags = cv.take<int>(n);
     g->norms = cv.take<double>(n);
-    g->counts = cv.take<int>(2 * (size_t)n);
+    g->counts = cv.take<int>(4 * (size_t)n);
     g->hflags.assign(n, 0);
     g->dflags.assign(n, 0);
     auto bail = [&](const char *what, hipError_t e) {
@@ -1810,7 +1863,7 @@ ibb_status ibb_group_lagrangian_update(ibb_group *g, ibb_lag_stats *per_ctx)
     const int n = (int)g->m.size();
     std::vector<hipStream_t> streams;
     for (ibb_ctx *c : g->m) streams.push_back(c->s);
-    std::vector<int> cnt(2 * (size_t)n, 0);
+    std::vector<int> cnt(4 * (size_t)n, 0);
     {
         Borrow b(g);
         GCHK(hipEventRecord(g->ev[0], g->s));
@@ -1820,10 +1873,10 @@ ibb_status ibb_group_lagrangian_update(ibb_group *g, ibb_lag_stats *per_ctx)
                 g->err = c->err;
                 return st;
             }
-            GCHK(hipMemcpyAsync(g->counts + 2 * i, c->counters, 2 * sizeof(int), hipMemcpyDeviceToDevice, g->s));
+            GCHK(hipMemcpyAsync(g->counts + 4 * i, c->counters, 4 * sizeof(int), hipMemcpyDeviceToDevice, g->s));
         }
         GCHK(hipEventRecord(g->ev[1], g->s));
-        GCHK(hipMemcpyAsync(cnt.data(), g->counts, 2 * n * sizeof(int), hipMemcpyDeviceToHost, g->s));
+        GCHK(hipMemcpyAsync(cnt.data(), g->counts, 4 * n * sizeof(int), hipMemcpyDeviceToHost, g->s));
         GCHK(hipGetLastError());
         GCHK(hipStreamSynchronize(g->s));
     }
@@ -1832,9 +1885,11 @@ ibb_status ibb_group_lagrangian_update(ibb_group *g, ibb_lag_stats *per_ctx)
     (void)hipEventElapsedTime(&t, g->ev[0], g->ev[1]);
     if (per_ctx)
         for (int i = 0; i < n; ++i) {
-            per_ctx[i].n_broken = cnt[2 * i];
-            per_ctx[i].n_alive = cnt[2 * i + 1];
+            per_ctx[i].n_broken = cnt[4 * i];
+            per_ctx[i].n_alive = cnt[4 * i + 1];
             per_ctx[i].t_ms = t;
+            per_ctx[i].n_fragments = g->m[i]->d.track_fragments ? cnt[4 * i + 2] : -1;
+            per_ctx[i].n_detached = g->m[i]->d.track_fragments ? cnt[4 * i + 3] : -1;
         }
     return IBB_OK;
 }

@@ -521,4 +521,102 @@ void launch_count_alive(const unsigned char *alive, int m, int *out, hipStream_t
     if (m > 0) hipLaunchKernelGGL(k_count_alive, dim3(nblk(m)), dim3(256), 0, s, alive, m, out);
 }
 
+// ---------------------------------------------------------------------------
+// detached fragments: connected components of the alive springs, each
+// labelled by its smallest node id.  Labels only decrease and always name a
+// node of the same component, so the fixed point does not depend on the
+// order of the atomic updates: every component ends with one root, which is
+// its smallest id.
+// ---------------------------------------------------------------------------
+__global__ void k_frag_anchor(Grid g, const double *__restrict__ X, long long stride, int eta, int axis, double dist,
+                              unsigned char *anchored)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < eta) anchored[s] = X[axis * stride + s] < dist ? 1 : 0;
+}
+
+__global__ void k_frag_init(int *label, int eta)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < eta) label[s] = s;
+}
+
+// hook: for an alive spring whose ends carry different labels, point the
+// larger label at the smaller one
+__global__ void k_frag_hook(const int *__restrict__ ij, int m, const unsigned char *__restrict__ alive, int *label,
+                            int *changed)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m || !alive[e]) return;
+    const int a = label[ij[e]], b = label[ij[m + e]];
+    if (a == b) return;
+    const int hi = a > b ? a : b, lo = a > b ? b : a;
+    if (atomicMin(&label[hi], lo) > lo) *changed = 1;
+}
+
+// shortcut: every node points straight at the end of its label chain
+__global__ void k_frag_jump(int *label, int eta, int *changed)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= eta) return;
+    const int l0 = label[s];
+    int l = l0;
+    while (true) {
+        const int n = label[l];
+        if (n == l) break;
+        l = n;
+    }
+    if (l != l0) {
+        label[s] = l;
+        *changed = 1;
+    }
+}
+
+__global__ void k_frag_mark(const int *__restrict__ label, const unsigned char *__restrict__ anchored, int eta,
+                            int *root_anchored)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < eta && anchored[s]) root_anchored[label[s]] = 1;
+}
+
+// counts[0] += fragments, counts[1] += detached fragments
+__global__ void k_frag_count(const int *__restrict__ label, const int *__restrict__ root_anchored, int eta,
+                             int *counts)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= eta || label[s] != s) return;
+    atomicAdd(&counts[0], 1);
+    if (!root_anchored[s]) atomicAdd(&counts[1], 1);
+}
+
+void launch_frag_anchor(const Grid &g, const double *X, long long stride, int eta, int axis, double dist,
+                        unsigned char *anchored, hipStream_t s)
+{
+    if (eta > 0)
+        hipLaunchKernelGGL(k_frag_anchor, dim3(nblk(eta)), dim3(256), 0, s, g, X, stride, eta, axis, dist, anchored);
+}
+
+void launch_frag_init(int *label, int eta, hipStream_t s)
+{
+    if (eta > 0) hipLaunchKernelGGL(k_frag_init, dim3(nblk(eta)), dim3(256), 0, s, label, eta);
+}
+
+void launch_frag_round(const int *ij, int m, const unsigned char *alive, int *label, int eta, int *changed,
+                       hipStream_t s)
+{
+    launch_fill<int>(changed, 1, 0, s);
+    if (m > 0) hipLaunchKernelGGL(k_frag_hook, dim3(nblk(m)), dim3(256), 0, s, ij, m, alive, label, changed);
+    if (eta > 0) hipLaunchKernelGGL(k_frag_jump, dim3(nblk(eta)), dim3(256), 0, s, label, eta, changed);
+}
+
+void launch_frag_count(const int *label, const unsigned char *anchored, int eta, int *root_anchored, int *counts,
+                       hipStream_t s)
+{
+    launch_fill<int>(counts, 2, 0, s);
+    if (eta <= 0) return;
+    launch_fill<int>(root_anchored, eta, 0, s);
+    hipLaunchKernelGGL(k_frag_mark, dim3(nblk(eta)), dim3(256), 0, s, label, anchored, eta, root_anchored);
+    hipLaunchKernelGGL(k_frag_count, dim3(nblk(eta)), dim3(256), 0, s, label, root_anchored, eta, counts);
+}
+
 }  // namespace ibmg

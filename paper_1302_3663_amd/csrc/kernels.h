@@ -220,6 +220,17 @@ void launch_spring_force(const Grid &g, const double *X, long long stride, int e
 // counting sort of keys[0..n) into buckets [0, nbuckets): start (exclusive
 // prefix, nbuckets + 1 entries) and ids grouped by bucket, ascending in
 // id % mod within a bucket (mod = 0: ascending id)
+// detached fragments (connected components of the alive springs)
+void launch_frag_anchor(const Grid &g, const double *X, long long stride, int eta, int axis, double dist,
+                        unsigned char *anchored, hipStream_t s);
+void launch_frag_init(int *label, int eta, hipStream_t s);
+// one hook + shortcut round; *changed (device) is set when a label moved
+void launch_frag_round(const int *ij, int m, const unsigned char *alive, int *label, int eta, int *changed,
+                       hipStream_t s);
+// counts[0] = fragments, counts[1] = fragments without an anchored node
+void launch_frag_count(const int *label, const unsigned char *anchored, int eta, int *root_anchored, int *counts,
+                       hipStream_t s);
+
 // ints of scratch the bucket sort needs for nb buckets
 int scan_scratch_ints(long long nb);
 void launch_bucket_sort(const int *keys, int n, int nbuckets, int *count, int *start, int *ids, int mod,

@@ -33,6 +33,7 @@ def base_params(dim, n, axis_bc, h):
         body_force=[0.0, 0.0, 0.0], rho0=1.0, rho_b=0.0, d0_pow_d=0.0,
         mu_out=1.0, mu_max=1.0, omega=0.02, kernel=0, break_ratio=2.0,
         nu1=2, nu2=2, max_levels=0, max_cycles=200, rtol=1e-10, gamma=[1.0] * 16,
+        track_fragments=0, attach_axis=1, attach_dist=0.0,
     )
 
 
@@ -194,6 +195,7 @@ def channel_2d(seed=1, nx=64, ny=32, eta=200, radius=0.25, cutoff=0.08):
     p["body_force"] = [8.0 * 1.0 * p["mu_out"] * p["inv_re"] / (ly * ly), 0.0, 0.0]
     p.update(rho_b=0.1, mu_max=10.0, omega=0.02, break_ratio=1.5)
     X = half_disc_uniform(rng, eta, 0.5 * nx * h, radius)
+    p["attach_dist"] = math.sqrt(0.5 * math.pi * radius * radius / eta)
     ij = spring_pairs(X, cutoff)
     K = np.full(ij.shape[1], 1e2)
     out = _finish(p, X, ij, K, 0.5 * math.pi * radius * radius, rng)
@@ -220,7 +222,7 @@ def tube_3d(seed=2, n=(64, 64, 128), eta=5000, spacing=0.02, cutoff=0.05, rho_b=
     rng = np.random.default_rng(seed)
     h = 1.0 / n[0]
     p = base_params(3, list(n), [AX_WALLS, AX_WALLS, AX_INOUT], h)
-    p.update(rho_b=rho_b, mu_max=mu_max, omega=omega, break_ratio=2.0, nu1=nu[0], nu2=nu[1])
+    p.update(rho_b=rho_b, mu_max=mu_max, omega=omega, break_ratio=2.0, nu1=nu[0], nu2=nu[1], attach_dist=spacing)
     Lz = n[2] * h
     per = int(math.ceil(eta / mounds))
     clouds = []
@@ -251,7 +253,7 @@ def tiny_2d(seed=11, nx=16, ny=8, eta=12, inout=False):
     p = base_params(2, [nx, ny], bc, h)
     if not inout:
         p["body_force"] = [8.0 * p["mu_out"] * p["inv_re"], 0.0, 0.0]
-    p.update(rho_b=0.1, mu_max=10.0, omega=0.12, break_ratio=1.5)
+    p.update(rho_b=0.1, mu_max=10.0, omega=0.12, break_ratio=1.5, attach_dist=0.1)
     X = half_disc_uniform(rng, eta, 0.5 * nx * h, 0.3)
     ij = spring_pairs(X, 0.2)
     K = np.full(ij.shape[1], 1e2)
@@ -275,7 +277,7 @@ def tiny_3d(seed=12, n=(8, 8, 16), eta=20, periodic_z=False):
     p = base_params(3, list(n), bc, h)
     if periodic_z:
         p["body_force"] = [0.0, 0.0, 1.0]
-    p.update(rho_b=0.05, mu_max=20.0, omega=0.15, break_ratio=2.0)
+    p.update(rho_b=0.05, mu_max=20.0, omega=0.15, break_ratio=2.0, attach_dist=0.09)
     Lz = n[2] * h
     inside = _mound_inside(0.4, 0.2, 0.5, 0.5 * Lz)
     X = poisson_disc(rng, inside, [0.1, 0.0, 0.5 * Lz - 0.6], [0.9, 0.4, 0.5 * Lz + 0.6], 0.09, eta,
@@ -331,6 +333,7 @@ def serving_request(j, steps=10):
         radius = 0.25
         X = half_disc_uniform(rng, eta, 0.5 * nx * h, radius)
         area = 0.5 * math.pi * radius * radius
+        p["attach_dist"] = math.sqrt(area / eta)
         ij = spring_pairs(X, 2.5 * math.sqrt(area / eta))
         out = _finish(p, X, ij, np.full(ij.shape[1], 1e2), area, rng)
     else:
@@ -343,6 +346,7 @@ def serving_request(j, steps=10):
         vol = _mound_volume(H, sw)
         spacing = 0.9 * (vol / eta) ** (1.0 / 3.0)
         X = jittered_mound(rng, H, sw, 0.5, 0.5 * Lz, Lz, spacing, eta)
+        p["attach_dist"] = spacing
         ij = spring_pairs(X, 2.0 * spacing)
         out = _finish(p, X, ij, np.full(ij.shape[1], 1e2), vol * X.shape[1] / eta, rng)
     out["seed"] = 1000 + j
