@@ -63,13 +63,15 @@ def poisson_disc(rng, inside, lo, hi, rmin, limit, seed_point, k=30):
     cs = rmin / math.sqrt(D)
     shape = np.maximum(1, np.ceil((hi - lo) / cs).astype(int))
     grid = -np.ones(tuple(shape), dtype=np.int64)
-    pts = [np.asarray(seed_point, float)]
-    grid[tuple(np.minimum(((pts[0] - lo) / cs).astype(int), shape - 1))] = 0
+    P = np.empty((max(int(limit), 1), D))
+    P[0] = np.asarray(seed_point, float)
+    n = 1
+    grid[tuple(np.minimum(((P[0] - lo) / cs).astype(int), shape - 1))] = 0
     active = [0]
     reach = int(math.ceil(math.sqrt(D))) + 1
-    while active and len(pts) < limit:
+    while active and n < limit:
         ai = rng.integers(len(active))
-        base = pts[active[ai]]
+        base = P[active[ai]]
         # k candidates in the shell [rmin, 2 rmin)
         dirs = rng.normal(size=(k, D))
         dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
@@ -86,17 +88,18 @@ def poisson_disc(rng, inside, lo, hi, rmin, limit, seed_point, k=30):
             near = grid[sl]
             near = near[near >= 0]
             if near.size:
-                dd = np.linalg.norm(np.asarray([pts[j] for j in near]) - c, axis=1)
+                dd = np.linalg.norm(P[near] - c, axis=1)
                 if np.any(dd < rmin):
                     continue
-            grid[tuple(gi)] = len(pts)
-            pts.append(c)
-            active.append(len(pts) - 1)
+            grid[tuple(gi)] = n
+            P[n] = c
+            active.append(n)
+            n += 1
             placed = True
             break
         if not placed:
             active.pop(ai)
-    return np.asarray(pts).T.copy()
+    return P[:n].T.copy()
 
 
 def spring_pairs(X, cutoff):
@@ -214,6 +217,18 @@ def _mound_volume(H, s):
     return H * 2.0 * math.pi * s * s
 
 
+def _union_volume(H, s, centres, Lz, nx=1024):
+    """Volume under the highest of several Gaussian mounds on [0,1] x [0,Lz]
+    (midpoint rule)."""
+    x = (np.arange(nx) + 0.5) / nx
+    nz = int(nx * Lz)
+    z = (np.arange(nz) + 0.5) * (Lz / nz)
+    top = np.zeros((nz, nx))
+    for cz in centres:
+        top = np.maximum(top, H * np.exp(-((x[None, :] - 0.5) ** 2 + (z[:, None] - cz) ** 2) / (2 * s * s)))
+    return float(top.sum() * (1.0 / nx) * (Lz / nz))
+
+
 def tube_3d(seed=2, n=(64, 64, 128), eta=5000, spacing=0.02, cutoff=0.05, rho_b=0.05, mu_max=100.0,
             omega=0.01, mounds=1, K_range=None, H=0.3, s=0.18, nu=(2, 2)):
     """3D square tube: walls in x and y, laminar inflow at z = 0 and a free
@@ -224,22 +239,36 @@ def tube_3d(seed=2, n=(64, 64, 128), eta=5000, spacing=0.02, cutoff=0.05, rho_b=
     p = base_params(3, list(n), [AX_WALLS, AX_WALLS, AX_INOUT], h)
     p.update(rho_b=rho_b, mu_max=mu_max, omega=omega, break_ratio=2.0, nu1=nu[0], nu2=nu[1], attach_dist=spacing)
     Lz = n[2] * h
-    per = int(math.ceil(eta / mounds))
-    clouds = []
-    for m in range(mounds):
-        cz = Lz * (m + 1) / (mounds + 1)
+    if mounds == 1:
+        cz = 0.5 * Lz
         inside = _mound_inside(H, s, 0.5, cz)
         lo = [max(0.0, 0.5 - 3 * s), 0.0, max(0.0, cz - 3 * s)]
         hi = [min(1.0, 0.5 + 3 * s), H, min(Lz, cz + 3 * s)]
-        pts = poisson_disc(rng, inside, lo, hi, spacing, per, [0.5, 0.25 * spacing, cz])
-        clouds.append(pts)
-    X = np.concatenate(clouds, axis=1)[:, :eta]
+        X = poisson_disc(rng, inside, lo, hi, spacing, eta, [0.5, 0.25 * spacing, cz])
+    else:
+        # overlapping mounds: one process over their union keeps the minimum
+        # spacing everywhere; it grows from the base of the middle mound
+        parts = [_mound_inside(H, s, 0.5, Lz * (m + 1) / (mounds + 1)) for m in range(mounds)]
+
+        def inside(P):
+            ok = parts[0](P)
+            for f in parts[1:]:
+                ok |= f(P)
+            return ok
+        X = poisson_disc(rng, inside, [0.0, 0.0, 0.0], [1.0, H, Lz], spacing, eta,
+                         [0.5, 0.25 * spacing, Lz * ((mounds + 1) // 2) / (mounds + 1)])
     ij = spring_pairs(X, cutoff)
     if K_range is None:
         K = np.full(ij.shape[1], 1e2)
     else:
         K = 10.0 ** rng.uniform(math.log10(K_range[0]), math.log10(K_range[1]), size=ij.shape[1])
-    vol = _mound_volume(H, s) * mounds * min(1.0, X.shape[1] / max(1, per * mounds))
+    if mounds == 1:
+        vol = _mound_volume(H, s)
+    else:
+        # the process stops at eta nodes: the biofilm is the part of the
+        # union it filled, measured by the nodes' own packing density
+        full = _union_volume(H, s, [Lz * (m + 1) / (mounds + 1) for m in range(mounds)], Lz)
+        vol = full * min(1.0, X.shape[1] / eta)
     out = _finish(p, X, ij, K, vol, rng)
     out["seed"] = seed
     return out
@@ -359,5 +388,5 @@ WORKLOADS = {
     "channel2d_64x32": lambda: channel_2d(seed=1),
     "tube3d_64x64x128": lambda: tube_3d(seed=2),
     "tube3d_128x128x256": lambda: tube_3d(seed=3, n=(128, 128, 256), eta=50000, mounds=3, rho_b=0.2,
-                                          mu_max=1e3, K_range=(1e1, 1e3), H=0.3, s=0.2, nu=(3, 3)),
+                                          mu_max=1e3, K_range=(1e1, 1e3), H=0.62, s=0.31, nu=(3, 3)),
 }

@@ -1,6 +1,7 @@
-"""The benchmark workload at full size (3D tube 64 x 64 x 128, 5 000 nodes),
-in the configuration bench.py times, checked through what the oracle can
-evaluate without its own multigrid:
+"""The tube workloads at full size, in the configuration bench.py times
+(64 x 64 x 128 with 5 000 nodes in both precisions; 128 x 128 x 256 with
+50 000 nodes, viscosity ratio 1e3 and V(3,3), refined), checked through what
+the oracle can evaluate without its own multigrid:
 
 - the spread fields and the momentum right-hand side, every point;
 - the viscous solve: its residual under the oracle's FP64 operator, applied
@@ -37,9 +38,14 @@ def dev(x):
     return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda:0").contiguous()
 
 
-@pytest.fixture(scope="module")
-def workload():
-    return synth.WORKLOADS["tube3d_64x64x128"]()
+_CASES = {}
+
+
+def workload_case(name):
+    if name not in _CASES:
+        print("generating", name, flush=True)
+        _CASES[name] = synth.WORKLOADS[name]()
+    return _CASES[name]
 
 
 def unknown_mask(p, n_total):
@@ -59,12 +65,14 @@ def unknown_mask(p, n_total):
     return unk
 
 
-@pytest.mark.parametrize("precision", [L.IBB_FP64, L.IBB_FP32_REFINED])
-def test_full_size_step(workload, precision):
+@pytest.mark.parametrize("name,precision", [("tube3d_64x64x128", L.IBB_FP64),
+                                            ("tube3d_64x64x128", L.IBB_FP32_REFINED),
+                                            ("tube3d_128x128x256", L.IBB_FP32_REFINED)])
+def test_full_size_step(name, precision):
     from paper_1302_3663_amd import ibmg
-    case = workload
+    case = workload_case(name)
     p = case["params"]
-    print("tube3d_64x64x128 precision", precision, flush=True)
+    print(name, "precision", precision, flush=True)
     ctx = ibmg.from_case(case, precision=precision, inner_cycles=2)
     # spread fields
     F_o, _, _ = O.springs(p, case["X"], case["ij"], case["rest"], case["K"], np.ones(case["ij"].shape[1], np.uint8),
