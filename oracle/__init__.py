@@ -112,6 +112,7 @@ def lib():
         L.orc_hier_levels.argtypes = [vp, ip, lp]
         L.orc_solve.argtypes = [vp, ctypes.c_int, dp, dp, ip, dp, dp, dp, ctypes.c_int]
         L.orc_vcycles.argtypes = [vp, ctypes.c_int, dp, dp, ctypes.c_int]
+        L.orc_solve_gcr.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, ip, dp]
         L.orc_smooth.argtypes = [vp, ctypes.c_int, dp, dp, ctypes.c_int]
         L.orc_relres.restype = ctypes.c_double
         L.orc_relres.argtypes = [vp, ctypes.c_int, dp, dp]
@@ -348,6 +349,15 @@ class Hierarchy:
                              ctypes.byref(wu), _d(hist), hist_len)
         return x, dict(status=st, cycles=cyc.value, relres=rel.value, work_units=wu.value,
                        hist=hist[:min(hist_len, cyc.value + 1)])
+
+    def solve_gcr(self, velocity, b, x0, m=8, kmax=0):
+        """V-cycle-preconditioned GCR(m); kmax > 0: exactly kmax iterations."""
+        x = _f64(x0).copy()
+        it = ctypes.c_int(0)
+        rel = ctypes.c_double(0)
+        st = lib().orc_solve_gcr(self.h, int(velocity), int(m), int(kmax), _d(_f64(b)), _d(x), ctypes.byref(it),
+                                 ctypes.byref(rel))
+        return x, dict(status=st, cycles=it.value, relres=rel.value)
 
     def vcycles(self, velocity, b, x0, k):
         x = _f64(x0).copy()
