@@ -82,10 +82,12 @@ def percentile(v, q):
     return float(np.percentile(np.asarray(v), q)) if v else None
 
 
-def run_mode(case, precision, inner, steps, warmup, log):
+def run_mode(case, precision, inner, steps, warmup, log, krylov=0):
     import torch
 
     from paper_1302_3663_amd import ibmg
+    if krylov:
+        case = dict(case, params=dict(case["params"], krylov_restart=krylov))
     ctx = ibmg.from_case(case, precision=precision, inner_cycles=inner)
     for _ in range(warmup):
         ctx.projection_step()
@@ -227,6 +229,8 @@ def main():
     ap.add_argument("--slots", type=int, default=32, help="serving: resident request cap")
     ap.add_argument("--budget-gb", type=float, default=32.0, help="serving: device-memory budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--krylov", type=int, default=8, metavar="M",
+                    help="also time the GCR(M)-accelerated solver in each mode (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -258,6 +262,12 @@ def main():
         log(f"mode {m}: {args.warmup} warmup + {args.steps} timed steps")
         res[m] = run_mode(case, pkg.IBB_FP32_REFINED if m == "refined" else pkg.IBB_FP64, args.inner, args.steps,
                           args.warmup, log)
+    gcr = {}
+    if args.krylov > 0:
+        for m in modes:
+            log(f"mode {m} with GCR({args.krylov}): {args.warmup} warmup + {args.steps} timed steps")
+            gcr[m] = run_mode(case, pkg.IBB_FP32_REFINED if m == "refined" else pkg.IBB_FP64, args.inner,
+                              args.steps, args.warmup, log, krylov=args.krylov)
     if args.calibrate_copy > 0:
         n = args.calibrate_copy * (1 << 20) // 4
         a = torch.empty(n, dtype=torch.float32, device="cuda:0").fill_(1.0)
@@ -322,6 +332,16 @@ def main():
                           for c, v in r["prof"].items() if v["launches"]})
     if "fp64" in res and "refined" in res:
         out["refined_over_fp64"] = round(res["refined"]["dof_per_s"] / res["fp64"]["dof_per_s"], 3)
+    if gcr:
+        out["gcr"] = {"restart": args.krylov}
+        for m, r in gcr.items():
+            out["gcr"][m] = dict(dof_per_s=round(r["dof_per_s"], 1), ms_per_step=round(r["ms_per_step"], 3),
+                                 solve_ms_per_step=round(r["solve_ms"] / args.steps, 3),
+                                 mean_cycles_u=float(np.mean(r["cycles_u"])),
+                                 mean_cycles_p=float(np.mean(r["cycles_p"])), max_relres=r["max_relres"],
+                                 p50_step_ms=round(percentile(r["step_ms"], 50), 3),
+                                 p99_step_ms=round(percentile(r["step_ms"], 99), 3),
+                                 speedup_vs_plain=round(r["dof_per_s"] / res[m]["dof_per_s"], 3))
     print(json.dumps(out), flush=True)
 
 

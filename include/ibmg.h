@@ -111,6 +111,13 @@ typedef struct {
     int track_fragments;   /* nonzero: ibb_lagrangian_update counts fragments */
     int attach_axis;
     double attach_dist;
+    /* 0: plain V-cycles (the paper's method).  m in 1..64: GCR(m) with one
+     * V-cycle (refined: inner_cycles FP32 V-cycles) from zero as the right
+     * preconditioner, modified Gram-Schmidt against the stored directions,
+     * restarted after m directions; the FP64 residual b - A x and the
+     * stopping test are those of the plain solver, and max_cycles caps the
+     * iterations.  Groups require 0. */
+    int krylov_restart;
 } ibb_desc;
 
 typedef struct {

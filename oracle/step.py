@@ -59,13 +59,21 @@ def pressure_singular(p):
     return all(p["axis_bc"][a] != AX_INOUT for a in range(p["dim"]))
 
 
+def solve(st, velocity, b, x0):
+    """Plain V-cycles, or V-cycle-preconditioned GCR(m) when krylov_restart = m > 0."""
+    m = int(st.p.get("krylov_restart", 0))
+    if m > 0:
+        return st.hier.solve_gcr(velocity, b, x0, m=m)
+    return st.hier.solve(velocity, b, x0)
+
+
 def projection_step(st):
     """Momentum solve, pressure solve and projection (returns solve stats)."""
     p = st.p
     b_u = momentum_rhs(p, st.u, st.rho, st.mu_c, st.mu_e, st.f)
-    ut, su = st.hier.solve(True, b_u, st.u)
+    ut, su = solve(st, True, b_u, st.u)
     b_p = pressure_rhs(p, ut)
-    pres, sp = st.hier.solve(False, b_p, st.pres)
+    pres, sp = solve(st, False, b_p, st.pres)
     if pressure_singular(p):
         pres = pres - pres.mean()
     st.u = project(p, ut, pres, st.rho)

@@ -51,6 +51,7 @@ class Desc(ctypes.Structure):
         ("track_fragments", ctypes.c_int),
         ("attach_axis", ctypes.c_int),
         ("attach_dist", ctypes.c_double),
+        ("krylov_restart", ctypes.c_int),
     ]
 
 
@@ -91,6 +92,7 @@ def make_desc(p, precision=IBB_FP64, inner_cycles=1):
     d.track_fragments = int(p.get("track_fragments", 0))
     d.attach_axis = int(p.get("attach_axis", 1))
     d.attach_dist = float(p.get("attach_dist", 0.0))
+    d.krylov_restart = int(p.get("krylov_restart", 0))
     return d
 
 

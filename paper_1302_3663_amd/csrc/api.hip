@@ -83,6 +83,11 @@ struct ibb_ctx {
     unsigned char *alive = nullptr;
     int *inc_keys = nullptr, *inc_count = nullptr, *inc_start = nullptr, *inc_list = nullptr;
     int *counters = nullptr;   // [0] broken this update, [1] alive, [2] fragments, [3] detached
+    // GCR on the finest level: right-hand side, iterate, residual, and the
+    // stored directions z_j, q_j (component arrays of the finest level)
+    double *gb[3] = {}, *gx[3] = {}, *gr[3] = {};
+    std::vector<double *> gz, gq;   // [m * 3]
+    double *gs = nullptr;           // scalars: (q_j, q_j) for j < m, then scratch
     // detached fragments
     unsigned char *anchored = nullptr;
     int *frag_label = nullptr, *frag_root = nullptr, *frag_flag = nullptr;
@@ -168,6 +173,7 @@ ibb_status check_desc(const ibb_desc *d)
     if (d->precision != IBB_FP64 && d->precision != IBB_FP32_REFINED) return IBB_EINVAL;
     if (d->precision == IBB_FP32_REFINED && d->inner_cycles < 1) return IBB_EINVAL;
     if (d->attach_axis < 0 || d->attach_axis >= d->dim || !(d->attach_dist >= 0)) return IBB_EINVAL;
+    if (d->krylov_restart < 0 || d->krylov_restart > 64) return IBB_EINVAL;
     for (int a = 0; a < d->dim; ++a)
         if (d->axis_bc[a] == IBB_AXIS_PERIODIC && 4.0 * d->omega > d->n[a] * d->h) return IBB_EINVAL;
     return IBB_OK;
@@ -308,6 +314,21 @@ size_t carve(ibb_ctx *c, char *base, bool dry)
     c->inc_count = cv.take<int>(em);
     c->inc_start = cv.take<int>(em + 1);
     c->counters = cv.take<int>(8);
+    if (d->krylov_restart > 0) {
+        const int m = d->krylov_restart;
+        c->gz.assign(3 * (size_t)m, nullptr);
+        c->gq.assign(3 * (size_t)m, nullptr);
+        for (int a = 0; a < D; ++a) {
+            c->gb[a] = cv.take<double>(n0);
+            c->gx[a] = cv.take<double>(n0);
+            c->gr[a] = cv.take<double>(n0);
+            for (int j = 0; j < m; ++j) {
+                c->gz[3 * j + a] = cv.take<double>(n0);
+                c->gq[3 * j + a] = cv.take<double>(n0);
+            }
+        }
+        c->gs = cv.take<double>((size_t)m + 8);
+    }
     c->anchored = cv.take<unsigned char>(em);
     c->frag_label = cv.take<int>(em);
     c->frag_root = cv.take<int>(em);
@@ -585,9 +606,149 @@ struct SolveOut {
     double relres = 0.0;
 };
 
+// component views of the GCR arrays for one system
+struct GView {
+    VelArr<double> b, x, r;
+};
+
+GView gcr_view(ibb_ctx *c, bool vel)
+{
+    GView v;
+    const int nc = vel ? c->d.dim : 1;
+    for (int a = 0; a < 3; ++a) {
+        v.b.c[a] = a < nc ? c->gb[a] : nullptr;
+        v.x.c[a] = a < nc ? c->gx[a] : nullptr;
+        v.r.c[a] = a < nc ? c->gr[a] : nullptr;
+    }
+    return v;
+}
+
+VelArr<double> gcr_dir(ibb_ctx *c, bool vel, bool q, int j)
+{
+    VelArr<double> v{{nullptr, nullptr, nullptr}};
+    const int nc = vel ? c->d.dim : 1;
+    for (int a = 0; a < nc; ++a) v.c[a] = q ? c->gq[3 * j + a] : c->gz[3 * j + a];
+    return v;
+}
+
+// dot product of two finest-level fields over the unknowns into gs[slot]
+void gcr_dot(ibb_ctx *c, bool vel, const VelArr<double> &x, const VelArr<double> &y, int slot)
+{
+    const int np = launch_dot(c->lv[0].g, vel ? 1 : 0, cview(x), cview(y), c->partial, c->s);
+    launch_reduce_final(c->partial, np, c->gs + slot, c->s);
+}
+
+// b - A x for the GCR iterate, its squared norm back on the host
+ibb_status gcr_residual(ibb_ctx *c, bool vel, const GView &g, double *rn)
+{
+    Level &L = c->lv[0];
+    View<double> v = view64(L);
+    const double cvp = 1.0 / (L.g.h * L.g.h), cvu = c->d.inv_re / (L.g.h * L.g.h), mass = c->d.sigma / c->d.dt;
+    int np;
+    if (vel) np = launch_resid_u<double>(L.g, cview(g.b), g.x, v.cu, mass, cvu, g.r, c->partial, c->s);
+    else np = launch_resid_p<double>(L.g, g.b.c[0], g.x.c[0], v.cp, cvp, g.r.c[0], c->partial, c->s);
+    double s2;
+    ibb_status st = read_scalar(c, np, &s2);
+    *rn = sqrt(s2);
+    return st;
+}
+
+// V-cycle-preconditioned GCR(m) on the finest level (b and x in the level-0
+// arrays on entry; x there on return).  Same stopping test as the V-cycle
+// loop below; exact > 0 runs exactly that many iterations.
+ibb_status solve_gcr(ibb_ctx *c, bool vel, int max_cycles, int exact, SolveOut *o)
+{
+    const bool refined = c->d.precision == IBB_FP32_REFINED;
+    const int m = c->d.krylov_restart;
+    const int D = c->d.dim;
+    int vm[3];
+    vel_masks(D, vm);
+    const int pm[3] = {0, 0, 0};
+    const int *masks = vel ? vm : pm;
+    const int nc = vel ? D : 1;
+    Level &L0 = c->lv[0];
+    View<double> v = view64(L0);
+    View<float> w = view32(L0);
+    VelArr<double> bl = vel ? v.bu : VelArr<double>{{v.bp, nullptr, nullptr}};
+    VelArr<double> xl = vel ? v.xu : VelArr<double>{{v.xp, nullptr, nullptr}};
+    VelArr<float> bl32 = vel ? w.bu : VelArr<float>{{w.bp, nullptr, nullptr}};
+    VelArr<float> xl32 = vel ? w.xu : VelArr<float>{{w.xp, nullptr, nullptr}};
+    const GView g = gcr_view(c, vel);
+    const double cvp = 1.0 / (L0.g.h * L0.g.h), cvu = c->d.inv_re / (L0.g.h * L0.g.h), mass = c->d.sigma / c->d.dt;
+    double nb;
+    ibb_status st = norm_b(c, vel, &nb);
+    if (st) return st;
+    o->cycles = o->vcycles = 0;
+    o->relres = 0.0;
+    o->status = IBB_OK;
+    if (nb == 0.0) {
+        zero_unknowns(c, vel);
+        return IBB_OK;
+    }
+    // the solve's own copies of b and of the iterate (with ghost images)
+    for (int a = 0; a < nc; ++a) {
+        launch_fill<double>(g.b.c[a], L0.g.nel, 0.0, c->s);
+        launch_fill<double>(g.x.c[a], L0.g.nel, 0.0, c->s);
+    }
+    launch_load_unknowns<double>(L0.g, nc, masks, cview(bl), g.b, c->s);
+    launch_load_unknowns<double>(L0.g, nc, masks, cview(xl), g.x, c->s);
+    double rn;
+    if ((st = gcr_residual(c, vel, g, &rn))) return st;
+    double rel = rn / nb;
+    int j = 0;
+    const int SLOT_T = m, SLOT_RQ = m + 1;
+    for (;;) {
+        if (exact > 0) {
+            if (o->cycles >= exact) break;
+        } else {
+            if (rel <= c->d.rtol) break;
+            if (!(rel == rel) || isinf(rel)) { o->status = IBB_ENUMERIC; break; }
+            if (o->cycles >= max_cycles) { o->status = IBB_ENOCONV; break; }
+        }
+        const VelArr<double> z = gcr_dir(c, vel, false, j), q = gcr_dir(c, vel, true, j);
+        // z = M r: V-cycles from zero on A z = r in the level-0 arrays
+        for (int a = 0; a < nc; ++a) launch_fill<double>(z.c[a], L0.g.nel, 0.0, c->s);
+        if (!refined) {
+            for (int a = 0; a < nc; ++a) launch_fill<double>(xl.c[a], L0.g.nel, 0.0, c->s);
+            launch_load_unknowns<double>(L0.g, nc, masks, cview(g.r), bl, c->s);
+            vcycle<double>(c, vel, 0);
+            o->vcycles++;
+            launch_load_unknowns<double>(L0.g, nc, masks, cview(xl), z, c->s);
+        } else {
+            for (int a = 0; a < nc; ++a) launch_fill<float>(xl32.c[a], L0.g.nel, 0.0f, c->s);
+            launch_cast_unknowns<double, float>(L0.g, nc, masks, cview(g.r), bl32, c->s);
+            for (int it = 0; it < c->d.inner_cycles; ++it) {
+                vcycle<float>(c, vel, 0);
+                o->vcycles++;
+            }
+            launch_add_correction(L0.g, nc, masks, cview(xl32), z, c->s);
+        }
+        // q = A z, then orthogonal to the stored q_i (modified Gram-Schmidt)
+        launch_apply(L0.g, vel ? 1 : 0, z, v.cp, v.cu, mass, vel ? cvu : cvp, q, c->s);
+        for (int i = 0; i < j; ++i) {
+            const VelArr<double> zi = gcr_dir(c, vel, false, i), qi = gcr_dir(c, vel, true, i);
+            gcr_dot(c, vel, q, qi, SLOT_T);
+            launch_gcr_axpy2(L0.g, vel ? 1 : 0, c->gs + SLOT_T, c->gs + i, cview(qi), cview(zi), q, z, c->s);
+        }
+        gcr_dot(c, vel, q, q, j);
+        gcr_dot(c, vel, g.r, q, SLOT_RQ);
+        launch_gcr_update(L0.g, vel ? 1 : 0, c->gs + SLOT_RQ, c->gs + j, cview(z), g.x, c->s);
+        if ((st = gcr_residual(c, vel, g, &rn))) return st;
+        rel = rn / nb;
+        o->cycles++;
+        j = j + 1 == m ? 0 : j + 1;
+    }
+    // the iterate back into the level-0 arrays, b restored
+    launch_load_unknowns<double>(L0.g, nc, masks, cview(g.x), xl, c->s);
+    launch_load_unknowns<double>(L0.g, nc, masks, cview(g.b), bl, c->s);
+    o->relres = rel;
+    return IBB_OK;
+}
+
 // V-cycles on level 0 arrays (b and x already in place)
 ibb_status solve(ibb_ctx *c, bool vel, int max_cycles, int exact, SolveOut *o)
 {
+    if (c->d.krylov_restart > 0) return solve_gcr(c, vel, max_cycles, exact, o);
     const bool refined = c->d.precision == IBB_FP32_REFINED;
     const int D = c->d.dim;
     int vm[3];
@@ -1565,6 +1726,7 @@ ibb_status check_members(ibb_ctx *const *ctxs, int n)
         const ibb_desc &a = ctxs[0]->d, &b = ctxs[i]->d;
         if (a.precision != b.precision || a.nu1 != b.nu1 || a.nu2 != b.nu2) return IBB_EINVAL;
         if (a.precision == IBB_FP32_REFINED && a.inner_cycles != b.inner_cycles) return IBB_EINVAL;
+        if (b.krylov_restart != 0) return IBB_EINVAL;
     }
     return IBB_OK;
 }

@@ -130,6 +130,18 @@ template <typename T>
 void launch_coarse_vcycle(int D, const LevTab<T> *tab, int l0, int L, int vel, int nu1, int nu2, int ndense,
                           const long long *uidx, const int *ucomp, const double *M, hipStream_t s);
 
+// GCR on the finest level (FP64): q = A z at the unknowns; per-block sums of
+// x . y (returns the number of partial sums); q -= (num/den) qi and
+// z -= (num/den) zi; x += (num/den) z with ghost images
+void launch_apply(const Grid &g, int velocity, const VelArr<double> &z, const CoefP<double> &cp,
+                  const CoefU<double> &cu, double mass, double cvisc, const VelArr<double> &q, hipStream_t s);
+int launch_dot(const Grid &g, int velocity, const VelArrC<double> &x, const VelArrC<double> &y, double *partial,
+               hipStream_t s);
+void launch_gcr_axpy2(const Grid &g, int velocity, const double *num, const double *den, const VelArrC<double> &qi,
+                      const VelArrC<double> &zi, const VelArr<double> &q, const VelArr<double> &z, hipStream_t s);
+void launch_gcr_update(const Grid &g, int velocity, const double *num, const double *den, const VelArrC<double> &z,
+                       const VelArr<double> &x, hipStream_t s);
+
 // Arm a start/stop event pair for the next smoother or residual launch of
 // this thread: the dispatch itself records the kernel's start and end.
 void set_launch_events(hipEvent_t start, hipEvent_t stop);

@@ -908,6 +908,81 @@ __global__ void __launch_bounds__(256) k_coef_ghosts(Grid g, Box box, int vmask,
 }
 
 // ---------------------------------------------------------------------------
+// V-cycle-preconditioned GCR on the finest level (FP64): operator apply,
+// inner products over the unknowns, and the two updates.  The scalar
+// coefficients stay on the device; every thread forms the same quotient.
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(256) k_apply_u(Grid g, VelBox boxes, VelArr<double> z, CoefU<double> cf,
+                                                 double mass, double cvisc, VelArr<double> q)
+{
+    const int a = blockIdx.y;
+    int i, j, k;
+    if (!box_pos(boxes.b[a], blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
+    double Ax, dg;
+    if (a == 0) u_row<double, D, 0>(g, z, cf, mass, cvisc, i, j, k, Ax, dg);
+    else if (a == 1) u_row<double, D, 1>(g, z, cf, mass, cvisc, i, j, k, Ax, dg);
+    else u_row<double, D, (D == 3 ? 2 : 1)>(g, z, cf, mass, cvisc, i, j, k, Ax, dg);
+    q.c[a][at(g, i, j, k)] = Ax;
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) k_apply_p(Grid g, Box box, const double *z, CoefP<double> cf, double cvisc,
+                                                 double *q)
+{
+    int i, j, k;
+    if (!box_pos(box, blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
+    double Ax, dg;
+    p_row<double, D>(g, z, cf, cvisc, i, j, k, Ax, dg);
+    q[at(g, i, j, k)] = Ax;
+}
+
+// per-block sums of x . y over the unknowns of every component (blockIdx.y)
+__global__ void __launch_bounds__(256) k_dot(VelBox boxes, Grid g, VelArrC<double> x, VelArrC<double> y,
+                                             double *partial)
+{
+    const int a = blockIdx.y;
+    const Box box = boxes.b[a];
+    const int n = box.ext[0] * box.ext[1] * box.ext[2];
+    double acc = 0.0;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+        int i, j, k;
+        box_pos(box, t, i, j, k);
+        const long long e = at(g, i, j, k);
+        acc += x.c[a][e] * y.c[a][e];
+    }
+    block_sum_store(acc, partial, (long long)blockIdx.y * gridDim.x + blockIdx.x);
+}
+
+// q -= s qi and z -= s zi at the unknowns, s = num / den
+__global__ void __launch_bounds__(256) k_gcr_axpy2(Grid g, VelBox boxes, const double *num, const double *den,
+                                                   VelArrC<double> qi, VelArrC<double> zi, VelArr<double> q,
+                                                   VelArr<double> z)
+{
+    const int a = blockIdx.y;
+    int i, j, k;
+    if (!box_pos(boxes.b[a], blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
+    const double sc = num[0] / den[0];
+    const long long e = at(g, i, j, k);
+    q.c[a][e] -= sc * qi.c[a][e];
+    z.c[a][e] -= sc * zi.c[a][e];
+}
+
+// x += s z at the unknowns (s = num / den), ghost images of x updated
+__global__ void __launch_bounds__(256) k_gcr_update(Grid g, VelBox boxes, int velocity, const double *num,
+                                                    const double *den, VelArrC<double> z, VelArr<double> x)
+{
+    const int a = blockIdx.y;
+    int i, j, k;
+    if (!box_pos(boxes.b[a], blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
+    const double sc = num[0] / den[0];
+    const long long e = at(g, i, j, k);
+    const double v = x.c[a][e] + sc * z.c[a][e];
+    x.c[a][e] = v;
+    write_images(g, velocity ? face_mask(a) : 0, velocity ? ROLE_V : ROLE_P, x.c[a], i, j, k, v);
+}
+
+// ---------------------------------------------------------------------------
 // the coarse part of a V-cycle in one workgroup
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -1759,6 +1834,69 @@ template void launch_bpass<double>(int, int, int, int, int, const BEntry *, unsi
 template void launch_bpass<float>(int, int, int, int, int, const BEntry *, unsigned, const int *, hipStream_t);
 template void launch_bcoarse<double>(int, int, const BCoarse *, unsigned, const int *, int, int, hipStream_t);
 template void launch_bcoarse<float>(int, int, const BCoarse *, unsigned, const int *, int, int, hipStream_t);
+
+static VelBox unknown_boxes(const Grid &g, int velocity, long long &mx)
+{
+    VelBox boxes;
+    mx = 0;
+    const int nc = velocity ? g.D : 1;
+    for (int a = 0; a < 3; ++a) {
+        boxes.b[a] = a < nc ? unk_box(g, velocity ? face_mask(a) : 0) : Box{{0, 0, 0}, {0, 0, 0}};
+        if (a < nc && box_count(boxes.b[a]) > mx) mx = box_count(boxes.b[a]);
+    }
+    return boxes;
+}
+
+void launch_apply(const Grid &g, int velocity, const VelArr<double> &z, const CoefP<double> &cp,
+                  const CoefU<double> &cu, double mass, double cvisc, const VelArr<double> &q, hipStream_t s)
+{
+    long long mx;
+    const VelBox boxes = unknown_boxes(g, velocity, mx);
+    if (mx <= 0) return;
+    if (velocity) {
+        const dim3 grid(blocks_for(mx), g.D);
+        if (g.D == 3) hipLaunchKernelGGL(k_apply_u<3>, grid, dim3(256), 0, s, g, boxes, z, cu, mass, cvisc, q);
+        else hipLaunchKernelGGL(k_apply_u<2>, grid, dim3(256), 0, s, g, boxes, z, cu, mass, cvisc, q);
+    } else {
+        if (g.D == 3)
+            hipLaunchKernelGGL(k_apply_p<3>, dim3(blocks_for(mx)), dim3(256), 0, s, g, boxes.b[0], z.c[0], cp, cvisc,
+                               q.c[0]);
+        else
+            hipLaunchKernelGGL(k_apply_p<2>, dim3(blocks_for(mx)), dim3(256), 0, s, g, boxes.b[0], z.c[0], cp, cvisc,
+                               q.c[0]);
+    }
+}
+
+int launch_dot(const Grid &g, int velocity, const VelArrC<double> &x, const VelArrC<double> &y, double *partial,
+               hipStream_t s)
+{
+    long long mx;
+    const VelBox boxes = unknown_boxes(g, velocity, mx);
+    const unsigned nb = stride_blocks(mx);
+    const int nc = velocity ? g.D : 1;
+    hipLaunchKernelGGL(k_dot, dim3(nb, nc), dim3(256), 0, s, boxes, g, x, y, partial);
+    return (int)nb * nc;
+}
+
+void launch_gcr_axpy2(const Grid &g, int velocity, const double *num, const double *den, const VelArrC<double> &qi,
+                      const VelArrC<double> &zi, const VelArr<double> &q, const VelArr<double> &z, hipStream_t s)
+{
+    long long mx;
+    const VelBox boxes = unknown_boxes(g, velocity, mx);
+    if (mx <= 0) return;
+    hipLaunchKernelGGL(k_gcr_axpy2, dim3(blocks_for(mx), velocity ? g.D : 1), dim3(256), 0, s, g, boxes, num, den,
+                       qi, zi, q, z);
+}
+
+void launch_gcr_update(const Grid &g, int velocity, const double *num, const double *den, const VelArrC<double> &z,
+                       const VelArr<double> &x, hipStream_t s)
+{
+    long long mx;
+    const VelBox boxes = unknown_boxes(g, velocity, mx);
+    if (mx <= 0) return;
+    hipLaunchKernelGGL(k_gcr_update, dim3(blocks_for(mx), velocity ? g.D : 1), dim3(256), 0, s, g, boxes, velocity,
+                       num, den, z, x);
+}
 
 // explicit instantiations
 #define INST(T)                                                                                                     \
