@@ -162,7 +162,8 @@ def run_serving(args, log):
     cases = [synth.serving_request(j) for j in range(args.requests)]
     arrivals = serve.poisson_arrivals(args.requests, args.rate, seed=4)
     srv = serve.Server(budget_bytes=int(args.budget_gb * (1 << 30)), max_slots=args.slots,
-                       precision=L.IBB_FP32_REFINED, inner_cycles=args.inner)
+                       precision=L.IBB_FP32_REFINED, inner_cycles=args.inner, krylov=args.krylov,
+                       krylov_ratio=args.krylov_ratio)
     # warmup: a few requests through the same loop (loads the code objects)
     warm = [serve.Request(-1 - j, 0.0, cases[j], 1) for j in range(min(args.warmup, len(cases)))]
     if warm:
@@ -196,7 +197,8 @@ def run_serving(args, log):
         "data": "synthetic",
         "config": {"workload": "serving", "requests": args.requests, "rate_per_s": args.rate,
                    "steps_per_request": cases[0]["steps"], "slots": args.slots, "budget_gb": args.budget_gb,
-                   "sizes": sizes, "inner_cycles": args.inner},
+                   "sizes": sizes, "inner_cycles": args.inner,
+                   "gcr": {"restart": args.krylov, "from_viscosity_ratio": args.krylov_ratio} if args.krylov else None},
         "p50_step_ms": round(s["p50_step_ms"], 3),
         "p99_step_ms": round(s["p99_step_ms"], 3),
         "p50_request_s": round(s["p50_request_s"], 3),
@@ -228,6 +230,8 @@ def main():
     ap.add_argument("--rate", type=float, default=40.0, help="serving: arrivals per second")
     ap.add_argument("--slots", type=int, default=32, help="serving: resident request cap")
     ap.add_argument("--budget-gb", type=float, default=32.0, help="serving: device-memory budget")
+    ap.add_argument("--krylov-ratio", type=float, default=100.0,
+                    help="serving: GCR for requests with at least this viscosity ratio (with --krylov > 0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--krylov", type=int, default=8, metavar="M",
                     help="also time the GCR(M)-accelerated solver in each mode (0: skip)")

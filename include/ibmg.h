@@ -116,7 +116,8 @@ typedef struct {
      * preconditioner, modified Gram-Schmidt against the stored directions,
      * restarted after m directions; the FP64 residual b - A x and the
      * stopping test are those of the plain solver, and max_cycles caps the
-     * iterations.  Groups require 0. */
+     * iterations.  In a group, such a member's solves run on their own
+     * rather than in the shared launches. */
     int krylov_restart;
 } ibb_desc;
 
@@ -266,7 +267,9 @@ ibb_status ibb_fragments(ibb_ctx *ctx, int32_t *label, int *n_fragments, int *n_
  * as when it is stepped alone.
  *
  * Members must agree on precision, nu1, nu2 and (refined) inner_cycles
- * (IBB_EINVAL otherwise) and may not repeat.  They must outlive the group and
+ * (IBB_EINVAL otherwise) and may not repeat.  Members with krylov_restart > 0
+ * are solved one by one (their GCR solves do not share launches); the other
+ * members share them.  They must outlive the group and
  * keep their workspaces; a member can still be used on its own between group
  * calls.  The group's work runs on a stream of its own, ordered after each
  * member's stream on entry, with each member's stream ordered after it on

@@ -1726,7 +1726,6 @@ ibb_status check_members(ibb_ctx *const *ctxs, int n)
         const ibb_desc &a = ctxs[0]->d, &b = ctxs[i]->d;
         if (a.precision != b.precision || a.nu1 != b.nu1 || a.nu2 != b.nu2) return IBB_EINVAL;
         if (a.precision == IBB_FP32_REFINED && a.inner_cycles != b.inner_cycles) return IBB_EINVAL;
-        if (b.krylov_restart != 0) return IBB_EINVAL;
     }
     return IBB_OK;
 }
@@ -1787,9 +1786,19 @@ ibb_status group_solve(ibb_group *g, bool vel, GroupSolve &R)
     R.rel.assign(n, 0.0);
     R.done.assign(n, 0);
     std::vector<double> h;
-    ibb_status st = group_norms(g, vel, false, R.done, h);
-    if (st) return st;
+    ibb_status st;
+    // members solved by GCR run their own solve (not batched); their flags
+    // stay clear in the captured ticks
     for (int i = 0; i < n; ++i) {
+        ibb_ctx *c = g->m[i];
+        if (c->d.krylov_restart <= 0) continue;
+        if ((st = solve_gcr(c, vel, c->d.max_cycles, 0, &R.out[i]))) return st;
+        R.done[i] = 1;
+        R.rel[i] = R.out[i].relres;
+    }
+    if ((st = group_norms(g, vel, false, R.done, h))) return st;
+    for (int i = 0; i < n; ++i) {
+        if (R.done[i]) continue;
         R.nb[i] = sqrt(h[i]);
         if (R.nb[i] == 0.0) {
             zero_unknowns(g->m[i], vel);

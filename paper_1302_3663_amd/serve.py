@@ -49,17 +49,28 @@ def poisson_arrivals(n, rate, seed=0):
 
 
 class Server:
+    """krylov > 0: requests whose viscosity ratio is at least krylov_ratio are
+    solved by V-cycle-preconditioned GCR(krylov); the rest by plain V-cycles,
+    which share launches across the resident requests."""
+
     def __init__(self, budget_bytes=32 << 30, max_slots=32, precision=L.IBB_FP32_REFINED, inner_cycles=2,
-                 device="cuda:0"):
+                 device="cuda:0", krylov=0, krylov_ratio=100.0):
         self.budget = int(budget_bytes)
         self.max_slots = int(max_slots)
         self.precision = precision
         self.inner = inner_cycles
         self.device = device
+        self.krylov = int(krylov)
+        self.krylov_ratio = float(krylov_ratio)
+
+    def request_case(self, case):
+        p = case["params"]
+        m = self.krylov if self.krylov > 0 and p["mu_max"] / p["mu_out"] >= self.krylov_ratio else 0
+        return dict(case, params=dict(p, krylov_restart=m))
 
     def footprint(self, case):
-        p = case["params"]
-        return ibmg.footprint_bytes(p, max(case["X"].shape[1], 1), max(case["ij"].shape[1], 1), self.precision,
+        c = self.request_case(case)
+        return ibmg.footprint_bytes(c["params"], max(c["X"].shape[1], 1), max(c["ij"].shape[1], 1), self.precision,
                                     self.inner)
 
     def run(self, requests, keep_state=False, log=None):
@@ -80,8 +91,8 @@ class Server:
             while (pending and pending[0].arrival <= now and len(live) < self.max_slots
                    and used + pending[0].footprint <= self.budget):
                 r = pending.pop(0)
-                r.ctx = ibmg.from_case(r.case, precision=self.precision, inner_cycles=self.inner,
-                                       device=self.device)
+                r.ctx = ibmg.from_case(self.request_case(r.case), precision=self.precision,
+                                       inner_cycles=self.inner, device=self.device)
                 r.admitted = time.perf_counter() - t0
                 r.dof = r.ctx.n_face + r.ctx.n_cell
                 used += r.footprint

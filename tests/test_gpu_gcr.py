@@ -144,10 +144,21 @@ def test_fewer_iterations_than_vcycles():
     gcr.close()
 
 
-def test_group_rejects_gcr_members():
+def test_group_with_gcr_member_equals_solo():
     from paper_1302_3663_amd import ibmg
-    _, ctx, _ = setup("3d_tube")
-    with pytest.raises(L.IbbError) as e:
-        ibmg.Group([ctx])
-    assert e.value.status == L.IBB_EINVAL
-    ctx.close()
+    _, solo_g, _ = setup("3d_tube_mu1e3")
+    solo_p = ibmg.from_case(CASES["channel2d_64x32"]())
+    s1, s2 = solo_g.projection_step(), solo_p.projection_step()
+    _, gg, _ = setup("3d_tube_mu1e3")
+    gp = ibmg.from_case(CASES["channel2d_64x32"]())
+    grp = ibmg.Group([gg, gp])
+    t1, t2 = grp.projection_step()
+    assert (t1["cycles_u"], t1["cycles_p"], t2["cycles_u"], t2["cycles_p"]) == \
+        (s1["cycles_u"], s1["cycles_p"], s2["cycles_u"], s2["cycles_p"])
+    for a, b in ((solo_g, gg), (solo_p, gp)):
+        ua, pa = a.get_state()
+        ub, pb = b.get_state()
+        assert np.array_equal(host(ua), host(ub)) and np.array_equal(host(pa), host(pb))
+    grp.close()
+    for c in (solo_g, solo_p, gg, gp):
+        c.close()

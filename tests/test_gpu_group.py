@@ -27,6 +27,9 @@ def cases():
         "channel2d_64x32": synth.channel_2d(seed=1),
         # a member whose V-cycle runs with launched passes down to its coarsest level
         "3d_tube_launched": dict(synth.tiny_3d(seed=5), params=dict(synth.tiny_3d(seed=5)["params"], wg_coarse_max=-1)),
+        # a high-contrast member solved by GCR (its solves run on their own)
+        "3d_tube_gcr": dict(synth.tiny_3d(seed=6), params=dict(synth.tiny_3d(seed=6)["params"], mu_max=1e3,
+                                                                 krylov_restart=6)),
     }
 
 
