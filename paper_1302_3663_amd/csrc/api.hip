@@ -72,6 +72,10 @@ struct ibb_ctx {
     LevTab<double> *tab64 = nullptr;
     LevTab<float> *tab32 = nullptr;
     int lc_u = MAXLEV, lc_p = MAXLEV;
+    // levels of the one-workgroup cycle kept in LDS, per precision (0: FP64,
+    // 1: FP32) and system (0: pressure, 1: velocity)
+    LdsLevel *ldslev[2][2] = {};
+    int lds_ls[2][2] = {}, lds_bytes[2][2] = {};
     // nodes and springs
     long long eta_max = 0, m_max = 0;
     int eta = 0, m = 0;
@@ -294,6 +298,8 @@ size_t carve(ibb_ctx *c, char *base, bool dry)
     c->Atmp = cv.take<double>((size_t)DENSE_MAX * 3 * (size_t)c->lv[c->L - 1].g.nel);
     c->tab64 = cv.take<LevTab<double>>(MAXLEV);
     c->tab32 = cv.take<LevTab<float>>(MAXLEV);
+    for (int pr = 0; pr < 2; ++pr)
+        for (int v = 0; v < 2; ++v) c->ldslev[pr][v] = cv.take<LdsLevel>(WG_MAXLEV);
     c->partial = cv.take<double>(3 * NORM_BLOCKS);
     c->scalar = cv.take<double>(8);
     const size_t em = (size_t)(c->eta_max > 0 ? c->eta_max : 1);
@@ -488,6 +494,65 @@ int residual(ibb_ctx *c, bool vel, int l, double *partial)
     return launch_resid_p<T>(L.g, v.bp, v.xp, v.cp, cvp, v.rp, partial, c->s);
 }
 
+// LDS plan of the one-workgroup cycle: the deepest levels whose arrays fit
+// the workgroup's LDS budget, laid out level by level
+void plan_lds(ibb_ctx *c, int prec, bool vel, std::vector<LdsLevel> &out)
+{
+    const int wsz = prec ? 4 : 8;
+    const int D = c->d.dim;
+    const int lc = std::min(vel ? c->lc_u : c->lc_p, c->L - 1);
+    const int budget = wg_lds_budget();
+    out.assign(WG_MAXLEV, LdsLevel{});
+    for (LdsLevel &o : out) {
+        for (int a = 0; a < 3; ++a) o.xu[a] = o.bu[a] = o.ru[a] = o.rho[a] = o.beta[a] = o.mue[a] = -1;
+        o.xp = o.bp = o.rp = o.muc = -1;
+    }
+    // bytes of one level's arrays in this system
+    auto level_bytes = [&](int l) {
+        const long long one = ((c->lv[l].g.nel * wsz + 15) / 16) * 16;
+        const int arrays = vel ? 4 * D + 1 + c->E : 3 + D;
+        return one * arrays;
+    };
+    // the level the cycle starts on holds the solve's b and x: only the
+    // coarser levels, scratch of one cycle, may move to LDS
+    int ls = c->L;
+    long long total = 0;
+    for (int l = c->L - 1; l > lc; --l) {
+        if (total + level_bytes(l) > budget) break;
+        total += level_bytes(l);
+        ls = l;
+    }
+    int off = 0;
+    for (int l = ls; l < c->L; ++l) {
+        const int one = (int)(((c->lv[l].g.nel * wsz + 15) / 16) * 16);
+        LdsLevel &o = out[l];
+        auto take = [&]() { const int r = off; off += one; return r; };
+        if (vel) {
+            for (int a = 0; a < D; ++a) {
+                o.xu[a] = take();
+                o.bu[a] = take();
+                o.ru[a] = take();
+                o.rho[a] = take();
+            }
+            o.muc = take();
+            for (int e = 0; e < c->E; ++e) o.mue[c->edge_axis[e]] = take();
+        } else {
+            o.xp = take();
+            o.bp = take();
+            o.rp = take();
+            for (int a = 0; a < D; ++a) o.beta[a] = take();
+        }
+    }
+    c->lds_ls[prec][vel ? 1 : 0] = ls;
+    c->lds_bytes[prec][vel ? 1 : 0] = off;
+}
+
+LdsPlan lds_plan(ibb_ctx *c, int prec, bool vel)
+{
+    const int v = vel ? 1 : 0;
+    return LdsPlan{c->ldslev[prec][v], c->lds_ls[prec][v], c->lds_bytes[prec][v]};
+}
+
 template <typename T>
 const LevTab<T> *level_table(ibb_ctx *c);
 template <>
@@ -508,7 +573,8 @@ void vcycle(ibb_ctx *c, bool vel, int l)
         const long long nc = vel ? LC.nu : LC.np;
         const int ndense = nc <= DENSE_MAX ? (int)nc : 0;
         launch_coarse_vcycle<T>(D, level_table<T>(c), l, c->L, vel ? 1 : 0, c->d.nu1, c->d.nu2, ndense,
-                                vel ? c->uidx_u : c->uidx_p, vel ? c->ucomp_u : c->ucomp_p, vel ? c->Mu : c->Mp, c->s);
+                                vel ? c->uidx_u : c->uidx_p, vel ? c->ucomp_u : c->ucomp_p, vel ? c->Mu : c->Mp,
+                                lds_plan(c, sizeof(T) == 4 ? 1 : 0, vel), c->s);
         return;
     }
     View<T> v = view<T>(L);
@@ -1158,6 +1224,14 @@ ibb_status ibb_create(const ibb_desc *desc, int64_t max_nodes, int64_t max_sprin
         a.nu = b.nu = L.nu;
         a.np = b.np = L.np;
     }
+    std::vector<LdsLevel> plans[2][2];
+    for (int pr = 0; pr < 2; ++pr)
+        for (int v = 0; v < 2; ++v) {
+            plan_lds(c, pr, v == 1, plans[pr][v]);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(c->ldslev[pr][v], plans[pr][v].data(), WG_MAXLEV * sizeof(LdsLevel),
+                                   hipMemcpyHostToDevice, c->s);
+        }
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->tab64, t64.data(), MAXLEV * sizeof(LevTab<double>), hipMemcpyHostToDevice, c->s);
     if (e == hipSuccess)
@@ -1533,6 +1607,7 @@ struct GOp {
     int D, vel, A, colour;
     size_t off;     // first BEntry (or BCoarse) of the launch
     unsigned n;     // blocks (or items)
+    int lds;        // coarse launches: LDS arena bytes
 };
 
 struct Plan {
@@ -1589,7 +1664,7 @@ void plan_pass(Plan &P, std::vector<GOp> &ops, const std::vector<ibb_ctx *> &m, 
                int prec, bool vel, int A, int colour, int l, bool norm)
 {
     for (int D = 2; D <= 3; ++D) {
-        GOp op{kind, prec, D, vel ? 1 : 0, A, colour, P.ent.size(), 0};
+        GOp op{kind, prec, D, vel ? 1 : 0, A, colour, P.ent.size(), 0, 0};
         for (int i : who) {
             ibb_ctx *c = m[i];
             if (c->d.dim != D) continue;
@@ -1638,7 +1713,7 @@ void plan_vcycle(Plan &P, std::vector<GOp> &ops, const std::vector<ibb_ctx *> &m
         plan_pass(P, ops, m, w, BK_RESTRICT, prec, vel, 0, 0, l, false);
     }
     for (int D = 2; D <= 3; ++D) {
-        GOp op{GK_COARSE, prec, D, vel ? 1 : 0, 0, 0, P.cent.size(), 0};
+        GOp op{GK_COARSE, prec, D, vel ? 1 : 0, 0, 0, P.cent.size(), 0, 0};
         for (int i = 0; i < n; ++i) {
             ibb_ctx *c = m[i];
             if (c->d.dim != D) continue;
@@ -1653,6 +1728,9 @@ void plan_vcycle(Plan &P, std::vector<GOp> &ops, const std::vector<ibb_ctx *> &m
             it.L = c->L;
             it.ndense = nc <= DENSE_MAX ? (int)nc : 0;
             it.ctx = i;
+            it.lds = c->ldslev[prec][vel ? 1 : 0];
+            it.lds_from = c->lds_ls[prec][vel ? 1 : 0];
+            op.lds = std::max(op.lds, c->lds_bytes[prec][vel ? 1 : 0]);
             P.cent.push_back(it);
             op.n++;
         }
@@ -1680,7 +1758,7 @@ void plan_tick(Plan &P, std::vector<GOp> &ops, const std::vector<ibb_ctx *> &m, 
         plan_vcycle(P, ops, m, 0, vel, nu1, nu2);
     }
     plan_pass(P, ops, m, all, BK_RESID, 0, vel, 0, 0, 0, true);
-    GOp red{GK_REDUCE, 0, 0, vel ? 1 : 0, 0, 0, P.ent.size(), 0};
+    GOp red{GK_REDUCE, 0, 0, vel ? 1 : 0, 0, 0, P.ent.size(), 0, 0};
     for (size_t i = 0; i < m.size(); ++i) {
         ibb_ctx *c = m[i];
         BEntry e{};
@@ -1704,8 +1782,10 @@ void emit_ops(ibb_group *g, const std::vector<GOp> &ops)
         switch (op.kind) {
         case GK_REDUCE: launch_breduce(g->ent + op.off, op.n, g->flags, g->norms, g->s); break;
         case GK_COARSE:
-            if (op.prec) launch_bcoarse<float>(op.D, op.vel, g->cent + op.off, op.n, g->flags, g->nu1, g->nu2, g->s);
-            else launch_bcoarse<double>(op.D, op.vel, g->cent + op.off, op.n, g->flags, g->nu1, g->nu2, g->s);
+            if (op.prec)
+                launch_bcoarse<float>(op.D, op.vel, g->cent + op.off, op.n, g->flags, g->nu1, g->nu2, op.lds, g->s);
+            else
+                launch_bcoarse<double>(op.D, op.vel, g->cent + op.off, op.n, g->flags, g->nu1, g->nu2, op.lds, g->s);
             break;
         default:
             if (op.prec)

@@ -126,9 +126,28 @@ struct LevTab {
 // cycle does not spill)
 constexpr int WG_THREADS = 512;
 __host__ __device__ constexpr int wg_threads(int, int) { return WG_THREADS; }
+// Where the one-workgroup cycle keeps a level: levels l >= ls live in the
+// workgroup's LDS arena (byte offsets of their arrays below; -1 means the
+// array is not used by the system), the others stay in global memory.  The
+// coefficient arrays are copied in and the solver arrays cleared when the
+// kernel starts; nothing of those levels is needed after it ends.
+struct LdsLevel {
+    int xu[3], bu[3], ru[3], rho[3], beta[3], mue[3];
+    int xp, bp, rp, muc;
+};
+constexpr int WG_MAXLEV = 16;
+struct LdsPlan {
+    const LdsLevel *lev;   // device array [WG_MAXLEV]
+    int ls;                // first level in LDS (L: none)
+    int bytes;             // arena size
+};
+
 template <typename T>
 void launch_coarse_vcycle(int D, const LevTab<T> *tab, int l0, int L, int vel, int nu1, int nu2, int ndense,
-                          const long long *uidx, const int *ucomp, const double *M, hipStream_t s);
+                          const long long *uidx, const int *ucomp, const double *M, const LdsPlan &plan,
+                          hipStream_t s);
+// largest LDS arena the coarse cycle may use on the current device (bytes)
+int wg_lds_budget();
 
 // GCR on the finest level (FP64): q = A z at the unknowns; per-block sums of
 // x . y (returns the number of partial sums); q -= (num/den) qi and
@@ -166,7 +185,9 @@ struct BCoarse {
     const long long *uidx;
     const int *ucomp;
     const double *M;
+    const LdsLevel *lds;   // the member's LDS plan (levels >= lds_from)
     int l0, L, ndense, ctx;
+    int lds_from, pad;
 };
 
 // pass kinds
@@ -180,7 +201,7 @@ void launch_bpass(int kind, int D, int vel, int A, int colour, const BEntry *ent
 void launch_breduce(const BEntry *ent, unsigned nitems, const int *flags, double *norms, hipStream_t s);
 template <typename T>
 void launch_bcoarse(int D, int vel, const BCoarse *items, unsigned nitems, const int *flags, int nu1, int nu2,
-                    hipStream_t s);
+                    int lds_bytes, hipStream_t s);
 
 // ---- fields (fields.hip) ----
 struct Phys {

@@ -1237,13 +1237,79 @@ __device__ __attribute__((always_inline)) inline void coarse_cycle(const LevTab<
 }
 
 
+template <typename T>
+__device__ inline T *arena_ptr(unsigned char *arena, int off)
+{
+    return off >= 0 ? reinterpret_cast<T *>(arena + off) : nullptr;
+}
+
+// The workgroup's table of levels: the global tables, with the levels from
+// ls down rebased into the LDS arena; their coefficients are copied in and
+// their solver arrays cleared.
+template <typename T, int D, int VEL>
+__device__ inline void stage_levels(const LevTab<T> *__restrict__ tab, int L, int ls, const LdsLevel *__restrict__ lev,
+                                    unsigned char *arena, LevTab<T> *wt)
+{
+    for (int l = threadIdx.x; l < L; l += blockDim.x) {
+        LevTab<T> t = tab[l];
+        if (l >= ls) {
+            const LdsLevel o = lev[l];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                t.xu[a] = arena_ptr<T>(arena, o.xu[a]);
+                t.bu[a] = arena_ptr<T>(arena, o.bu[a]);
+                t.ru[a] = arena_ptr<T>(arena, o.ru[a]);
+                t.rho[a] = arena_ptr<T>(arena, o.rho[a]);
+                t.beta[a] = arena_ptr<T>(arena, o.beta[a]);
+                t.mue[a] = arena_ptr<T>(arena, o.mue[a]);
+            }
+            t.xp = arena_ptr<T>(arena, o.xp);
+            t.bp = arena_ptr<T>(arena, o.bp);
+            t.rp = arena_ptr<T>(arena, o.rp);
+            t.muc = arena_ptr<T>(arena, o.muc);
+        }
+        wt[l] = t;
+    }
+    __syncthreads();
+    for (int l = ls; l < L; ++l) {
+        const LevTab<T> &src = tab[l];
+        const LevTab<T> &dst = wt[l];
+        const int nel = (int)src.g.nel;
+        for (int e = threadIdx.x; e < nel; e += blockDim.x) {
+            if (VEL) {
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    const_cast<T *>(dst.rho[a])[e] = src.rho[a][e];
+                    dst.xu[a][e] = T(0);
+                    dst.bu[a][e] = T(0);
+                    dst.ru[a][e] = T(0);
+                }
+                const_cast<T *>(dst.muc)[e] = src.muc[e];
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    if (dst.mue[a]) const_cast<T *>(dst.mue[a])[e] = src.mue[a][e];
+            } else {
+#pragma unroll
+                for (int a = 0; a < D; ++a) const_cast<T *>(dst.beta[a])[e] = src.beta[a][e];
+                dst.xp[e] = T(0);
+                dst.bp[e] = T(0);
+                dst.rp[e] = T(0);
+            }
+        }
+    }
+    __syncthreads();
+}
+
 template <typename T, int D, int VEL>
 __global__ void __launch_bounds__(wg_threads(D, VEL)) k_coarse_vcycle(const LevTab<T> *__restrict__ tab, int l0, int L, int nu1,
                                                                int nu2, int ndense, const long long *__restrict__ uidx,
                                                                const int *__restrict__ ucomp,
-                                                               const double *__restrict__ M)
+                                                               const double *__restrict__ M, LdsPlan plan)
 {
-    coarse_cycle<T, D, VEL>(tab, l0, L, nu1, nu2, ndense, uidx, ucomp, M);
+    extern __shared__ __align__(16) unsigned char wg_arena[];
+    __shared__ LevTab<T> wt[WG_MAXLEV];
+    stage_levels<T, D, VEL>(tab, L, plan.ls, plan.lev, wg_arena, wt);
+    coarse_cycle<T, D, VEL>(wt, l0, L, nu1, nu2, ndense, uidx, ucomp, M);
 }
 
 // ---------------------------------------------------------------------------
@@ -1397,8 +1463,10 @@ __global__ void __launch_bounds__(wg_threads(D, VEL)) k_bcoarse(const BCoarse *_
 {
     const BCoarse I = items[blockIdx.x];
     if (!flags[I.ctx]) return;
-    coarse_cycle<T, D, VEL>(static_cast<const LevTab<T> *>(I.tab), I.l0, I.L, nu1, nu2, I.ndense, I.uidx, I.ucomp,
-                            I.M);
+    extern __shared__ __align__(16) unsigned char wg_arena[];
+    __shared__ LevTab<T> wt[WG_MAXLEV];
+    stage_levels<T, D, VEL>(static_cast<const LevTab<T> *>(I.tab), I.L, I.lds_from, I.lds, wg_arena, wt);
+    coarse_cycle<T, D, VEL>(wt, I.l0, I.L, nu1, nu2, I.ndense, I.uidx, I.ucomp, I.M);
 }
 
 // ---------------------------------------------------------------------------
@@ -1709,13 +1777,43 @@ void launch_coef_ghosts(const Grid &g, int vmask, T *v, hipStream_t s)
     hipLaunchKernelGGL(k_coef_ghosts<T>, dim3(blocks_for(box_count(box))), dim3(256), 0, s, g, box, vmask, v);
 }
 
+int wg_lds_budget()
+{
+    static int budget = -1;
+    if (budget < 0) {
+        int dev = 0, v = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 65536;
+        // the kernel's own shared data: the level table and the coarsest right-hand side
+        budget = v - (int)(WG_MAXLEV * sizeof(LevTab<double>)) - 1024;
+        if (budget < 0) budget = 0;
+    }
+    return budget;
+}
+
+// allow a dynamic arena above the default limit (once per kernel)
+template <typename K>
+static void allow_lds(K kernel, int bytes)
+{
+    static int allowed = 0;
+    if (bytes > allowed) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                bytes) == hipSuccess)
+            allowed = bytes;
+    }
+}
+
 template <typename T>
 void launch_coarse_vcycle(int D, const LevTab<T> *tab, int l0, int L, int vel, int nu1, int nu2, int ndense,
-                          const long long *uidx, const int *ucomp, const double *M, hipStream_t s)
+                          const long long *uidx, const int *ucomp, const double *M, const LdsPlan &plan,
+                          hipStream_t s)
 {
 #define LAUNCH(DD, VV)                                                                                              \
-    hipLaunchKernelGGL((k_coarse_vcycle<T, DD, VV>), dim3(1), dim3(wg_threads(DD, VV)), 0, s, tab, l0, L, nu1, nu2, ndense, uidx, \
-                       ucomp, M)
+    do {                                                                                                            \
+        allow_lds(k_coarse_vcycle<T, DD, VV>, plan.bytes);                                                          \
+        hipLaunchKernelGGL((k_coarse_vcycle<T, DD, VV>), dim3(1), dim3(wg_threads(DD, VV)), plan.bytes, s, tab, l0, \
+                           L, nu1, nu2, ndense, uidx, ucomp, M, plan);                                              \
+    } while (0)
     if (D == 3) {
         if (vel) LAUNCH(3, 1);
         else LAUNCH(3, 0);
@@ -1726,9 +1824,11 @@ void launch_coarse_vcycle(int D, const LevTab<T> *tab, int l0, int L, int vel, i
 #undef LAUNCH
 }
 template void launch_coarse_vcycle<double>(int, const LevTab<double> *, int, int, int, int, int, int,
-                                           const long long *, const int *, const double *, hipStream_t);
+                                           const long long *, const int *, const double *, const LdsPlan &,
+                                           hipStream_t);
 template void launch_coarse_vcycle<float>(int, const LevTab<float> *, int, int, int, int, int, int,
-                                          const long long *, const int *, const double *, hipStream_t);
+                                          const long long *, const int *, const double *, const LdsPlan &,
+                                          hipStream_t);
 
 int batch_blocks(int kind, const Grid &g, const Grid &gc, int vel, int A)
 {
@@ -1818,22 +1918,28 @@ void launch_breduce(const BEntry *ent, unsigned nitems, const int *flags, double
 
 template <typename T>
 void launch_bcoarse(int D, int vel, const BCoarse *items, unsigned nitems, const int *flags, int nu1, int nu2,
-                    hipStream_t s)
+                    int lds_bytes, hipStream_t s)
 {
     if (nitems == 0) return;
     const dim3 g(nitems), b(wg_threads(D, vel));
+#define LAUNCH(DD, VV)                                                                                              \
+    do {                                                                                                            \
+        allow_lds(k_bcoarse<T, DD, VV>, lds_bytes);                                                                 \
+        hipLaunchKernelGGL((k_bcoarse<T, DD, VV>), g, b, lds_bytes, s, items, flags, nu1, nu2);                     \
+    } while (0)
     if (D == 3) {
-        if (vel) hipLaunchKernelGGL((k_bcoarse<T, 3, 1>), g, b, 0, s, items, flags, nu1, nu2);
-        else hipLaunchKernelGGL((k_bcoarse<T, 3, 0>), g, b, 0, s, items, flags, nu1, nu2);
+        if (vel) LAUNCH(3, 1);
+        else LAUNCH(3, 0);
     } else {
-        if (vel) hipLaunchKernelGGL((k_bcoarse<T, 2, 1>), g, b, 0, s, items, flags, nu1, nu2);
-        else hipLaunchKernelGGL((k_bcoarse<T, 2, 0>), g, b, 0, s, items, flags, nu1, nu2);
+        if (vel) LAUNCH(2, 1);
+        else LAUNCH(2, 0);
     }
+#undef LAUNCH
 }
 template void launch_bpass<double>(int, int, int, int, int, const BEntry *, unsigned, const int *, hipStream_t);
 template void launch_bpass<float>(int, int, int, int, int, const BEntry *, unsigned, const int *, hipStream_t);
-template void launch_bcoarse<double>(int, int, const BCoarse *, unsigned, const int *, int, int, hipStream_t);
-template void launch_bcoarse<float>(int, int, const BCoarse *, unsigned, const int *, int, int, hipStream_t);
+template void launch_bcoarse<double>(int, int, const BCoarse *, unsigned, const int *, int, int, int, hipStream_t);
+template void launch_bcoarse<float>(int, int, const BCoarse *, unsigned, const int *, int, int, int, hipStream_t);
 
 static VelBox unknown_boxes(const Grid &g, int velocity, long long &mx)
 {
