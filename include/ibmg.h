@@ -119,6 +119,12 @@ typedef struct {
      * iterations.  In a group, such a member's solves run on their own
      * rather than in the shared launches. */
     int krylov_restart;
+    /* launches per red-black sweep of a component on levels swept with
+     * launched passes: 0 or 2, one per colour; 1, one launch for both
+     * colours (LDS tiles with a redundant red ring, a second iterate
+     * buffer; needs nu1 + nu2 even, otherwise two).  Both give the same
+     * bits; two is faster on the workloads measured here. */
+    int smoother_passes;
 } ibb_desc;
 
 typedef struct {

@@ -32,6 +32,12 @@ struct Level {
     float *xp32 = nullptr, *bp32 = nullptr, *rp32 = nullptr;
     float *xu32[3] = {}, *bu32[3] = {}, *ru32[3] = {};
     float *rho32[3] = {}, *beta32[3] = {}, *muc32 = nullptr, *mue32[3] = {};
+    // second iterate buffers of the one-launch red-black sweep (swapped with
+    // x after every sweep; an even number of sweeps per V-cycle brings them
+    // back), and whether this level uses that sweep
+    double *xu_alt[3] = {}, *xp_alt = nullptr;
+    float *xu32_alt[3] = {}, *xp32_alt = nullptr;
+    bool fused = false;
 };
 
 struct Carver {
@@ -178,6 +184,7 @@ ibb_status check_desc(const ibb_desc *d)
     if (d->precision == IBB_FP32_REFINED && d->inner_cycles < 1) return IBB_EINVAL;
     if (d->attach_axis < 0 || d->attach_axis >= d->dim || !(d->attach_dist >= 0)) return IBB_EINVAL;
     if (d->krylov_restart < 0 || d->krylov_restart > 64) return IBB_EINVAL;
+    if (d->smoother_passes < 0 || d->smoother_passes > 2) return IBB_EINVAL;
     for (int a = 0; a < d->dim; ++a)
         if (d->axis_bc[a] == IBB_AXIS_PERIODIC && 4.0 * d->omega > d->n[a] * d->h) return IBB_EINVAL;
     return IBB_OK;
@@ -267,6 +274,14 @@ size_t carve(ibb_ctx *c, char *base, bool dry)
         }
         L.muc = cv.take<double>(n);
         for (int e = 0; e < c->E; ++e) L.mue[c->edge_axis[e]] = cv.take<double>(n);
+        if (L.fused) {
+            L.xp_alt = cv.take<double>(n);
+            for (int a = 0; a < D; ++a) L.xu_alt[a] = cv.take<double>(n);
+            if (refined) {
+                L.xp32_alt = cv.take<float>(n);
+                for (int a = 0; a < D; ++a) L.xu32_alt[a] = cv.take<float>(n);
+            }
+        }
         if (refined) {
             L.xp32 = cv.take<float>(n);
             L.bp32 = cv.take<float>(n);
@@ -377,6 +392,16 @@ void setup_shapes(ibb_ctx *c, const ibb_desc *d, int64_t max_nodes, int64_t max_
         for (int l = 0; l < c->L; ++l)
             if ((c->lv[l].np + 1) / 2 <= wgmax) { c->lc_p = l; break; }
     }
+    // levels swept with launched passes may use the one-launch red-black
+    // sweep: an even number of sweeps per cycle, even periodic extents
+    for (int l = 0; l < c->L; ++l) {
+        Level &L = c->lv[l];
+        bool ok = d->smoother_passes == 1 && (d->nu1 + d->nu2) % 2 == 0 && l < c->L - 1 &&
+                  l < std::max(c->lc_u, c->lc_p);
+        for (int a = 0; a < d->dim; ++a)
+            if (d->axis_bc[a] == IBB_AXIS_PERIODIC && L.g.n[a] % 2) ok = false;
+        L.fused = ok;
+    }
     c->eta_max = max_nodes;
     c->m_max = max_springs;
     int nb[3];
@@ -456,10 +481,40 @@ void vel_masks(int D, int *m)
     for (int a = 0; a < 3; ++a) m[a] = a < D ? face_mask(a) : 0;
 }
 
+// the two iterate buffers of a level in precision T
+template <typename T>
+T **cur_x(Level &L, bool vel, int a);
+template <>
+double **cur_x<double>(Level &L, bool vel, int a) { return vel ? &L.xu[a] : &L.xp; }
+template <>
+float **cur_x<float>(Level &L, bool vel, int a) { return vel ? &L.xu32[a] : &L.xp32; }
+template <typename T>
+T **alt_x(Level &L, bool vel, int a);
+template <>
+double **alt_x<double>(Level &L, bool vel, int a) { return vel ? &L.xu_alt[a] : &L.xp_alt; }
+template <>
+float **alt_x<float>(Level &L, bool vel, int a) { return vel ? &L.xu32_alt[a] : &L.xp32_alt; }
+
 template <typename T>
 void sweep(ibb_ctx *c, bool vel, int l)
 {
     Level &L = c->lv[l];
+    if (L.fused && l < (vel ? c->lc_u : c->lc_p)) {
+        const T cvp = (T)(1.0 / (L.g.h * L.g.h));
+        const T cvu = (T)(c->d.inv_re / (L.g.h * L.g.h));
+        const T mass = (T)(c->d.sigma / c->d.dt);
+        const int cls = (vel ? 0 : 1) + (sizeof(T) == 4 ? 2 : 0);
+        for (int a = 0; a < (vel ? c->d.dim : 1); ++a) {
+            View<T> v = view<T>(L);
+            const VelArrC<T> xin = vel ? cview(v.xu) : VelArrC<T>{{v.xp, nullptr, nullptr}};
+            const int k = l == 0 ? prof_begin(c, cls, unknowns_of(L.g, vel ? face_mask(a) : 0)) : -1;
+            launch_smooth_rb<T>(L.g, vel ? 1 : 0, a, xin, vel ? v.bu.c[a] : v.bp, v.cu, v.cp, mass, vel ? cvu : cvp,
+                                *alt_x<T>(L, vel, a), c->s);
+            prof_end(c, k);
+            std::swap(*cur_x<T>(L, vel, a), *alt_x<T>(L, vel, a));
+        }
+        return;
+    }
     View<T> v = view<T>(L);
     const T cvp = (T)(1.0 / (L.g.h * L.g.h));
     const T cvu = (T)(c->d.inv_re / (L.g.h * L.g.h));
@@ -605,6 +660,9 @@ void vcycle(ibb_ctx *c, bool vel, int l)
         launch_restrict<T>(L.g, C.g, 1, pm, ROLE_P, false, rf, bc, (T)1, c->s, &xc);
     }
     vcycle<T>(c, vel, l + 1);
+    // the one-launch sweep alternates a level's iterate buffers: look them up again
+    v = view<T>(L);
+    w = view<T>(C);
     if (vel) {
         launch_prolong_add<T>(C.g, L.g, D, vm, ROLE_V, cview(w.xu), v.xu, c->s);
     } else {

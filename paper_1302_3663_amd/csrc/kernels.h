@@ -161,6 +161,14 @@ void launch_gcr_axpy2(const Grid &g, int velocity, const double *num, const doub
 void launch_gcr_update(const Grid &g, int velocity, const double *num, const double *den, const VelArrC<double> &z,
                        const VelArr<double> &x, hipStream_t s);
 
+// One red-black sweep (red then black) of component a (vel) or of the
+// pressure in one launch: reads xin (all components), writes the updated
+// component, with its ghost images, to xout (a second buffer; the other
+// entries of xout must already hold the field's fixed values)
+template <typename T>
+void launch_smooth_rb(const Grid &g, int vel, int a, const VelArrC<T> &xin, const T *b, const CoefU<T> &cu,
+                      const CoefP<T> &cp, T mass, T cvisc, T *xout, hipStream_t s);
+
 // Arm a start/stop event pair for the next smoother or residual launch of
 // this thread: the dispatch itself records the kernel's start and end.
 void set_launch_events(hipEvent_t start, hipEvent_t stop);

@@ -449,6 +449,211 @@ __global__ void __launch_bounds__(256) k_smooth_u(Grid g, Box box, const T *__re
 }
 
 // ---------------------------------------------------------------------------
+// One full red-black sweep of one component in one launch.  Each workgroup
+// owns a tile of the component's unknowns and stages a window of the tile
+// plus two points on every side in LDS: the red points of the tile and of
+// the ring around it are updated from the old black values, then the black
+// points of the tile from those reds.  The red ring is computed again by
+// the neighbouring tiles with the same arithmetic.  The result goes to a
+// second buffer (x_out), so that no workgroup reads a value another one has
+// already updated.  Along periodic axes the window holds the wrapped points
+// themselves; along the other axes it holds the ghost images, which a red
+// update refreshes inside the window.
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+struct RBTile {
+    static constexpr int H = 2;
+    static constexpr int TX = D == 3 ? 8 : 16, TY = D == 3 ? 8 : 16, TZ = D == 3 ? (sizeof(T) == 8 ? 4 : 8) : 1;
+    static constexpr int WX = TX + 2 * H, WY = TY + 2 * H, WZ = D == 3 ? TZ + 2 * H : 1;
+    static constexpr int W = WX * WY * WZ;
+};
+
+// write v (times the sign) to the ghost images of (i, j, k) along the
+// non-periodic axes that fall inside the window [o, o + W)
+template <typename T, int D>
+__device__ inline void write_images_window(const Grid &g, int vmask, int role, T *x, int i, int j, int k, T v,
+                                           const int o[3], const int w[3])
+{
+    const int q[3] = {i, j, k};
+    AxisImages im[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        im[d] = d < D && g.bc[d] != AX_PERIODIC ? images_of(g, d, (vmask >> d) & 1, role, q[d])
+                                               : AxisImages{{0, 0}, {0, 0}};
+    if ((im[0].s[0] | im[0].s[1] | im[1].s[0] | im[1].s[1] | im[2].s[0] | im[2].s[1]) == 0) return;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (a == 0 && b == 0 && c == 0) continue;
+                const int sa = a ? im[0].s[a - 1] : 1;
+                const int sb = b ? im[1].s[b - 1] : 1;
+                const int sc = c ? im[2].s[c - 1] : 1;
+                if (sa == 0 || sb == 0 || sc == 0) continue;
+                const int qa = a ? im[0].q[a - 1] : i;
+                const int qb = b ? im[1].q[b - 1] : j;
+                const int qc = c ? im[2].q[c - 1] : k;
+                if (qa < o[0] || qa >= o[0] + w[0] || qb < o[1] || qb >= o[1] + w[1]) continue;
+                if (D == 3 && (qc < o[2] || qc >= o[2] + w[2])) continue;
+                x[at(g, qa, qb, qc)] = sa * sb * sc > 0 ? v : -v;
+            }
+}
+
+template <typename T, int D, int VEL, int A>
+__global__ void __launch_bounds__(256) k_smooth_rb(Grid g, Box box, VelArrC<T> xin, const T *__restrict__ b,
+                                                   CoefU<T> cu, CoefP<T> cp, T mass, T cvisc, T *xout)
+{
+    using TL = RBTile<T, D>;
+    constexpr int NARR = VEL ? 2 * D + 2 : D + 2;
+    constexpr int BS = 256;
+    __shared__ T w[NARR][TL::W];
+    const int vmask = VEL ? face_mask(A) : 0;
+    const int role = VEL ? ROLE_V : ROLE_P;
+    // this workgroup's tile and window origin (extended lattice coordinates)
+    const int ntx = (box.ext[0] + TL::TX - 1) / TL::TX, nty = (box.ext[1] + TL::TY - 1) / TL::TY;
+    const int tid = blockIdx.x;
+    const int t0 = tid % ntx, t1 = (tid / ntx) % nty, t2 = tid / (ntx * nty);
+    const int lo[3] = {box.lo[0] + t0 * TL::TX, box.lo[1] + t1 * TL::TY, D == 3 ? box.lo[2] + t2 * TL::TZ : 0};
+    const int o[3] = {lo[0] - TL::H, lo[1] - TL::H, D == 3 ? lo[2] - TL::H : 0};
+    const int wd[3] = {TL::WX, TL::WY, TL::WZ};
+    // the window as a grid: same axes and boundary kinds, window strides
+    Grid gw = g;
+    gw.NX = TL::WX;
+    gw.NY = TL::WY;
+    gw.NXY = (long long)TL::WX * TL::WY;
+    const long long shift = at(gw, o[0], o[1], o[2]);
+    // source arrays of the window, in the order of w
+    const T *src[NARR];
+    if (VEL) {
+        src[0] = xin.c[A];
+#pragma unroll
+        for (int bi = 0; bi < D - 1; ++bi) {
+            const int B = other_axis<A>(bi);
+            src[1 + bi] = xin.c[B];
+            src[D + 3 + bi] = cu.mue[3 - A - B];
+        }
+        src[D] = b;
+        src[D + 1] = cu.rho[A];
+        src[D + 2] = cu.muc;
+    } else {
+        src[0] = xin.c[0];
+        src[1] = b;
+#pragma unroll
+        for (int a = 0; a < D; ++a) src[2 + a] = cp.beta[a];
+    }
+    // stage the window: every load issued before the first store
+    constexpr int PER = (TL::W + BS - 1) / BS;
+    int eidx[PER];
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+        const int sidx = threadIdx.x + it * BS;
+        int q[3] = {o[0] + sidx % TL::WX, o[1] + (sidx / TL::WX) % TL::WY, D == 3 ? o[2] + sidx / (TL::WX * TL::WY) : 0};
+        bool ok = sidx < TL::W;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            if (g.bc[d] == AX_PERIODIC) {
+                if (q[d] < 0) q[d] += g.n[d];
+                while (q[d] >= g.n[d]) q[d] -= g.n[d];
+            } else if (q[d] < -1 || q[d] > g.n[d] + 1) {
+                ok = false;
+            }
+        }
+        eidx[it] = ok ? (int)at(g, q[0], q[1], q[2]) : -1;
+    }
+    T v[NARR][PER];
+#pragma unroll
+    for (int m = 0; m < NARR; ++m)
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            const T x = src[m][eidx[it] >= 0 ? eidx[it] : 0];
+            v[m][it] = eidx[it] >= 0 ? x : T(0);
+        }
+#pragma unroll
+    for (int m = 0; m < NARR; ++m)
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            const int sidx = threadIdx.x + it * BS;
+            if (sidx < TL::W) w[m][sidx] = v[m][it];
+        }
+    __syncthreads();
+    // window views shifted so that at(gw, i, j, k) indexes them
+    VelArr<T> xw{{nullptr, nullptr, nullptr}};
+    CoefU<T> cw = cu;
+    CoefP<T> pw = cp;
+    T *bw;
+    if (VEL) {
+        xw.c[A] = &w[0][0] - shift;
+#pragma unroll
+        for (int bi = 0; bi < D - 1; ++bi) {
+            const int B = other_axis<A>(bi);
+            xw.c[B] = &w[1 + bi][0] - shift;
+            cw.mue[3 - A - B] = &w[D + 3 + bi][0] - shift;
+        }
+        bw = &w[D][0] - shift;
+        cw.rho[A] = &w[D + 1][0] - shift;
+        cw.muc = &w[D + 2][0] - shift;
+    } else {
+        xw.c[0] = &w[0][0] - shift;
+        bw = &w[1][0] - shift;
+#pragma unroll
+        for (int a = 0; a < D; ++a) pw.beta[a] = &w[2 + a][0] - shift;
+    }
+    T *xa = xw.c[VEL ? A : 0];
+    int ulo[3], uhi[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) unk_range(g, d, (vmask >> d) & 1, ulo[d], uhi[d]);
+    // red: the tile and the ring around it, enumerated by colour
+    constexpr int RX = TL::TX + 2, RY = TL::TY + 2, RZ = D == 3 ? TL::TZ + 2 : 1, RH = RX / 2;
+    for (int t = threadIdx.x; t < RH * RY * RZ; t += BS) {
+        const int ih = t % RH, r = t / RH;
+        const int q1 = lo[1] - 1 + r % RY, q2 = D == 3 ? lo[2] - 1 + r / RY : 0;
+        const int q0 = lo[0] - 1 + 2 * ih + ((lo[0] - 1 + q1 + q2) & 1);
+        const int qq[3] = {q0, q1, q2};
+        bool unknown = true;
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            if (g.bc[d] != AX_PERIODIC && (qq[d] < ulo[d] || qq[d] > uhi[d])) unknown = false;
+        if (!unknown) continue;
+        T Ax, dg;
+        if (VEL) u_row<T, D, A>(gw, xw, cw, mass, cvisc, q0, q1, q2, Ax, dg);
+        else p_row<T, D>(gw, xa, pw, cvisc, q0, q1, q2, Ax, dg);
+        const long long f = at(gw, q0, q1, q2);
+        const T xn = xa[f] + (bw[f] - Ax) / dg;
+        xa[f] = xn;
+        write_images_window<T, D>(gw, vmask, role, xa, q0, q1, q2, xn, o, wd);
+    }
+    __syncthreads();
+    // black: the tile, enumerated by colour
+    constexpr int TH = TL::TX / 2;
+    for (int t = threadIdx.x; t < TH * TL::TY * TL::TZ; t += BS) {
+        const int ih = t % TH, r = t / TH;
+        const int q1 = lo[1] + r % TL::TY, q2 = D == 3 ? lo[2] + r / TL::TY : 0;
+        const int q0 = lo[0] + 2 * ih + ((lo[0] + q1 + q2 + 1) & 1);
+        if (q0 >= box.lo[0] + box.ext[0] || q1 >= box.lo[1] + box.ext[1]) continue;
+        if (D == 3 && q2 >= box.lo[2] + box.ext[2]) continue;
+        T Ax, dg;
+        if (VEL) u_row<T, D, A>(gw, xw, cw, mass, cvisc, q0, q1, q2, Ax, dg);
+        else p_row<T, D>(gw, xa, pw, cvisc, q0, q1, q2, Ax, dg);
+        const long long f = at(gw, q0, q1, q2);
+        xa[f] = xa[f] + (bw[f] - Ax) / dg;
+    }
+    __syncthreads();
+    // the tile's unknowns and their ghost images to the output buffer
+    constexpr int TT = TL::TX * TL::TY * TL::TZ;
+    for (int sidx = threadIdx.x; sidx < TT; sidx += BS) {
+        const int q0 = lo[0] + sidx % TL::TX, q1 = lo[1] + (sidx / TL::TX) % TL::TY;
+        const int q2 = D == 3 ? lo[2] + sidx / (TL::TX * TL::TY) : 0;
+        if (q0 >= box.lo[0] + box.ext[0] || q1 >= box.lo[1] + box.ext[1]) continue;
+        if (D == 3 && q2 >= box.lo[2] + box.ext[2]) continue;
+        const T val = xa[at(gw, q0, q1, q2)];
+        xout[at(g, q0, q1, q2)] = val;
+        write_images(g, vmask, role, xout, q0, q1, q2, val);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // block reduction of one double per thread into partial[slot] (fixed order)
 // ---------------------------------------------------------------------------
 __device__ inline void block_sum_store(double v, double *partial, long long slot)
@@ -1526,6 +1731,30 @@ void launch_smooth_u(const Grid &g, int a, const T *b, const VelArr<T> &x, const
     }
 }
 
+template <typename T>
+void launch_smooth_rb(const Grid &g, int vel, int a, const VelArrC<T> &xin, const T *b, const CoefU<T> &cu,
+                      const CoefP<T> &cp, T mass, T cvisc, T *xout, hipStream_t s)
+{
+    const Box P = unk_box(g, vel ? face_mask(a) : 0);
+    if (box_count(P) <= 0) return;
+    const int D = g.D;
+    const int TX = D == 3 ? 8 : 16, TY = D == 3 ? 8 : 16, TZ = D == 3 ? (sizeof(T) == 8 ? 4 : 8) : 1;
+    const unsigned nt = (unsigned)(((P.ext[0] + TX - 1) / TX) * ((P.ext[1] + TY - 1) / TY) * ((P.ext[2] + TZ - 1) / TZ));
+    const dim3 grid(nt), blk(256);
+#define RB(DD, VV, AA) launch_timed(k_smooth_rb<T, DD, VV, AA>, grid, blk, s, g, P, xin, b, cu, cp, mass, cvisc, xout)
+    if (D == 3) {
+        if (!vel) RB(3, 0, 0);
+        else if (a == 0) RB(3, 1, 0);
+        else if (a == 1) RB(3, 1, 1);
+        else RB(3, 1, 2);
+    } else {
+        if (!vel) RB(2, 0, 0);
+        else if (a == 0) RB(2, 1, 0);
+        else RB(2, 1, 1);
+    }
+#undef RB
+}
+
 static inline unsigned stride_blocks(long long n)
 {
     unsigned b = blocks_for(n);
@@ -2009,6 +2238,8 @@ void launch_gcr_update(const Grid &g, int velocity, const double *num, const dou
     template void launch_smooth_p<T>(const Grid &, const T *, T *, const CoefP<T> &, T, int, hipStream_t);          \
     template void launch_smooth_u<T>(const Grid &, int, const T *, const VelArr<T> &, const CoefU<T> &, T, T, int,  \
                                      hipStream_t);                                                                  \
+    template void launch_smooth_rb<T>(const Grid &, int, int, const VelArrC<T> &, const T *, const CoefU<T> &,      \
+                                      const CoefP<T> &, T, T, T *, hipStream_t);                                    \
     template int launch_resid_p<T>(const Grid &, const T *, const T *, const CoefP<T> &, T, T *, double *,          \
                                    hipStream_t);                                                                    \
     template int launch_resid_u<T>(const Grid &, const VelArrC<T> &, const VelArr<T> &, const CoefU<T> &, T, T,     \

@@ -59,3 +59,56 @@ def test_workgroup_cycle_matches_launched(name, precision, wg):
     assert cyc == cyc_ref
     for a, b in zip(got, ref):
         assert np.array_equal(a, b)
+
+
+def run_passes(case, passes, precision, nu=(2, 2)):
+    from paper_1302_3663_amd import ibmg
+    c = dict(case)
+    c["params"] = dict(case["params"], smoother_passes=passes, wg_coarse_max=8, nu1=nu[0], nu2=nu[1])
+    ctx = ibmg.from_case(c, precision=precision, inner_cycles=2)
+    rng = np.random.default_rng(9)
+    out = []
+    for vel, n in ((1, ctx.n_face), (0, ctx.n_cell)):
+        b = rng.standard_normal(n)
+        x0 = case["u0"] if vel else np.zeros(n)
+        x, _ = ctx.mg_solve(vel, dev(b), dev(x0), exact=2)
+        out.append(host(x))
+    for _ in range(2):
+        s = ctx.projection_step()
+        ctx.lagrangian_update()
+    u, p = ctx.get_state()
+    out += [host(u), host(p)]
+    ctx.close()
+    return out, (s["cycles_u"], s["cycles_p"])
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("precision", [L.IBB_FP64, L.IBB_FP32_REFINED])
+@pytest.mark.parametrize("nu", [(2, 2), (3, 3), (1, 3)])
+def test_one_launch_sweep_matches_two(name, precision, nu):
+    """The one-launch red-black sweep (LDS tiles, second buffer) gives the
+    bits of the two launches per sweep; a small workgroup budget keeps
+    several levels on launched passes.  An odd number of pre-smoothing sweeps
+    leaves the buffers exchanged during the coarse-grid correction."""
+    print("case", name, "precision", precision, "nu", nu, flush=True)
+    case = CASES[name]()
+    ref, cyc_ref = run_passes(case, 2, precision, nu)
+    got, cyc = run_passes(case, 1, precision, nu)
+    assert cyc == cyc_ref
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b)
+
+
+def test_one_launch_sweep_full_size():
+    from paper_1302_3663_amd import ibmg
+    case = synth.WORKLOADS["tube3d_64x64x128"]()
+    outs = []
+    for passes in (2, 1):
+        c = dict(case, params=dict(case["params"], smoother_passes=passes))
+        ctx = ibmg.from_case(c, precision=L.IBB_FP32_REFINED, inner_cycles=2)
+        s = ctx.projection_step()
+        u, p = ctx.get_state()
+        outs.append((host(u), host(p), s["cycles_u"], s["cycles_p"]))
+        ctx.close()
+    assert outs[0][2:] == outs[1][2:]
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
