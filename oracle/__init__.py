@@ -54,6 +54,7 @@ class Desc(ctypes.Structure):
         ("max_cycles", ctypes.c_int),
         ("rtol", ctypes.c_double),
         ("gamma", ctypes.c_double * 16),
+        ("decoupled", ctypes.c_int),
     ]
 
 
@@ -73,6 +74,7 @@ def make_desc(p):
     g = p.get("gamma", [1.0] * 16)
     for l in range(16):
         d.gamma[l] = g[l] if l < len(g) else 1.0
+    d.decoupled = int(p.get("decoupled", 0))
     return d
 
 

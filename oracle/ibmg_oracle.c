@@ -59,6 +59,7 @@ typedef struct {
     int nu1, nu2, max_levels, max_cycles;
     double rtol;
     double gamma[16];
+    int decoupled;      /* 1: constant-viscosity momentum operator, eq:NSdis1 */
 } orc_desc;
 
 enum { ORC_OK = 0, ORC_EINVAL = 1, ORC_ENOMEM = 2, ORC_ENOCONV = 3, ORC_ENUMERIC = 4 };
@@ -395,6 +396,7 @@ typedef struct {
     double *beta[3];  /* 1 / rho on the same faces */
     double *mu_c;     /* viscosity at cell centres */
     double *mu_e[3];  /* viscosity on edges parallel to axis c (2D: corners in [2]) */
+    double mu0;       /* the constant viscosity of the decoupled operator on this level */
     umap_t up, uu;
     csr_t Ap, Au;
 } level_t;
@@ -463,11 +465,32 @@ static double visc_at(const level_t *L, double *const *u, int a, const int q[3])
     return s / h2;
 }
 
-/* viscous operator A_u = (sigma rho / dt) I - Re^-1 V, eq:NSdis1-1 */
+/* constant viscosity: mu0 L_h u_a, the 2D + 1 point Laplacian of eq:NSdis1
+ * on the a-face lattice.  Each component only sees itself; the neighbours
+ * across a boundary come from the same ghost images as in visc_at. */
+static double lap_at(const level_t *L, double *const *u, int a, const int q[3])
+{
+    const grid_t *g = &L->g;
+    double h2 = g->h * g->h;
+    const double *ua = u[a];
+    long f = P3(g, q);
+    double s = 0.0;
+    for (int b = 0; b < g->D; ++b) {
+        int qp[3] = {q[0], q[1], q[2]}, qm[3] = {q[0], q[1], q[2]};
+        qp[b] += 1;
+        qm[b] -= 1;
+        s += (ua[P3(g, qp)] - ua[f]) - (ua[f] - ua[P3(g, qm)]);
+    }
+    return L->mu0 * s / h2;
+}
+
+/* viscous operator A_u = (sigma rho / dt) I - Re^-1 V, eq:NSdis1-1; with
+ * constant viscosity V is mu L_h applied to each component, eq:NSdis1 */
 static double apply_u_at(const level_t *L, const orc_desc *d, double *const *u, int a, const int q[3])
 {
     long f = P3(&L->g, q);
-    return d->sigma / d->dt * L->rho[a][f] * u[a][f] - d->inv_re * visc_at(L, u, a, q);
+    double v = d->decoupled ? lap_at(L, u, a, q) : visc_at(L, u, a, q);
+    return d->sigma / d->dt * L->rho[a][f] * u[a][f] - d->inv_re * v;
 }
 
 /* ------------------------------------------------------------------ */
@@ -732,6 +755,9 @@ static int desc_check(const orc_desc *d)
         if (d->axis_bc[a] < 0 || d->axis_bc[a] > 2) return ORC_EINVAL;
     }
     if (!(d->h > 0) || !(d->dt > 0) || !(d->sigma > 0)) return ORC_EINVAL;
+    if (d->decoupled != 0 && d->decoupled != 1) return ORC_EINVAL;
+    /* the decoupled form holds only where the viscosity is one constant */
+    if (d->decoupled && d->mu_max != d->mu_out) return ORC_EINVAL;
     return ORC_OK;
 }
 
@@ -785,9 +811,11 @@ void *orc_hier_create(const orc_desc *d, const double *rho_faces, const double *
         off += stored_count(&L0->g, edge_lat(c));
     }
     level_betas(L0);
+    L0->mu0 = d->mu_out;
     for (int l = 1; l < H->L; ++l) {
         level_t *F = &H->lv[l - 1], *C = &H->lv[l];
         double gm = d->gamma[l] > 0 ? d->gamma[l] : 1.0;
+        C->mu0 = F->mu0 * gm;
         for (int a = 0; a < d->dim; ++a) restrict_coef(&F->g, &C->g, face_lat(a), F->rho[a], C->rho[a], 1.0);
         restrict_coef(&F->g, &C->g, cell_lat(), F->mu_c, C->mu_c, gm);
         for (int c = edge_first(d->dim); c < 3; ++c) restrict_coef(&F->g, &C->g, edge_lat(c), F->mu_e[c], C->mu_e[c], gm);

@@ -33,7 +33,7 @@ def base_params(dim, n, axis_bc, h):
         body_force=[0.0, 0.0, 0.0], rho0=1.0, rho_b=0.0, d0_pow_d=0.0,
         mu_out=1.0, mu_max=1.0, omega=0.02, kernel=0, break_ratio=2.0,
         nu1=2, nu2=2, max_levels=0, max_cycles=200, rtol=1e-10, gamma=[1.0] * 16,
-        track_fragments=0, attach_axis=1, attach_dist=0.0,
+        track_fragments=0, attach_axis=1, attach_dist=0.0, decoupled=0,
     )
 
 
