@@ -18,6 +18,11 @@ events on the context's stream and set against the HBM roofline using its
 algorithmic bytes per unknown.  The CPU baseline times the FP64 oracle on a
 bounded sample of the same workload.
 
+With the viscosity made uniform (mu_max = mu_out) the bench also steps the
+same workload with the coupled viscous system and with the constant-viscosity
+form of eq:NSdis1 (each component solved on its own, one smoothing launch
+per colour for all components) and reports both (`constant_viscosity`).
+
 `--workload serving` runs the serving stream instead: independent requests of
 mixed grids and contrasts arriving over time, admitted by slot cap and
 device-memory budget and stepped together; it prints its own line with the
@@ -45,7 +50,9 @@ KERNEL_SYMBOLS = {0: "k_smooth_u<double>", 1: "k_smooth_p<double>", 2: "k_smooth
                   4: "k_resid_u<double>", 5: "k_resid_p<double>"}
 
 
-def words_per_unknown(cls, D):
+def words_per_unknown(cls, D, decoupled=False):
+    if decoupled and cls in (0, 2, 4):   # u_a read+write, b, rho
+        return 4
     if cls in (0, 2, 4):   # u_a read+write (residual: read + r write), b, rho, mu_c, D-1 mu_e, D-1 u_b
         return 5 + 2 * (D - 1)
     return 2 + 1 + D       # p read+write (residual: read + r write), b, D beta
@@ -235,6 +242,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--krylov", type=int, default=8, metavar="M",
                     help="also time the GCR(M)-accelerated solver in each mode (0: skip)")
+    ap.add_argument("--const-visc", type=int, default=1, choices=[0, 1],
+                    help="also step the workload at uniform viscosity, coupled and constant-viscosity form")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -272,6 +281,14 @@ def main():
             log(f"mode {m} with GCR({args.krylov}): {args.warmup} warmup + {args.steps} timed steps")
             gcr[m] = run_mode(case, pkg.IBB_FP32_REFINED if m == "refined" else pkg.IBB_FP64, args.inner,
                               args.steps, args.warmup, log, krylov=args.krylov)
+    const = {}
+    if args.const_visc:
+        for dec in (0, 1):
+            cp = dict(case["params"], mu_max=case["params"]["mu_out"], decoupled=dec)
+            log(f"uniform viscosity, {'constant-viscosity form' if dec else 'coupled form'}: "
+                f"{args.warmup} warmup + {args.steps} timed steps")
+            const[dec] = run_mode(dict(case, params=cp), pkg.IBB_FP32_REFINED if "refined" in modes else pkg.IBB_FP64,
+                                  args.inner, args.steps, args.warmup, log)
     if args.calibrate_copy > 0:
         n = args.calibrate_copy * (1 << 20) // 4
         a = torch.empty(n, dtype=torch.float32, device="cuda:0").fill_(1.0)
@@ -346,6 +363,25 @@ def main():
                                  p50_step_ms=round(percentile(r["step_ms"], 50), 3),
                                  p99_step_ms=round(percentile(r["step_ms"], 99), 3),
                                  speedup_vs_plain=round(r["dof_per_s"] / res[m]["dof_per_s"], 3))
+    if const:
+        sm = 2 if "refined" in modes else 0
+        cv = {"viscosity_ratio": 1.0, "precision": head_mode}
+        for dec, key in ((0, "coupled"), (1, "decoupled")):
+            r = const[dec]
+            pr = r["prof"][sm]
+            avg_ms = pr["total_ms"] / max(pr["launches"], 1)
+            bpl = words_per_unknown(sm, D, bool(dec)) * word_size(sm) * pr["units"] / max(pr["launches"], 1)
+            gbs = bpl / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+            cv[key] = dict(dof_per_s=round(r["dof_per_s"], 1), ms_per_step=round(r["ms_per_step"], 3),
+                           solve_ms_per_step=round(r["solve_ms"] / args.steps, 3),
+                           mean_cycles_u=float(np.mean(r["cycles_u"])), mean_cycles_p=float(np.mean(r["cycles_p"])),
+                           max_relres=r["max_relres"],
+                           smoother=dict(kernel="k_smooth_u_dec" if dec else KERNEL_SYMBOLS[sm],
+                                         launches=pr["launches"], avg_launch_us=round(avg_ms * 1e3, 2),
+                                         algorithmic_bytes_per_launch=int(bpl), achieved_gbs=round(gbs, 1),
+                                         frac=round(gbs / HBM_PEAK_GBS, 4)))
+        cv["decoupled_over_coupled"] = round(const[1]["dof_per_s"] / const[0]["dof_per_s"], 3)
+        out["constant_viscosity"] = cv
     print(json.dumps(out), flush=True)
 
 

@@ -125,6 +125,12 @@ typedef struct {
      * buffer; needs nu1 + nu2 even, otherwise two).  Both give the same
      * bits; two is faster on the workloads measured here. */
     int smoother_passes;
+    /* 0: the coupled viscous system of eq:NSdis1-1.  1: constant viscosity,
+     * eq:NSdis1: (sigma rho / dt) u_a - Re^-1 mu L_h u_a for each component
+     * on its own (mu = mu_out, times the product of gamma down to a coarse
+     * level); needs mu_max == mu_out, otherwise IBB_EINVAL.  The components'
+     * smoothing passes of one colour share a launch. */
+    int decoupled;
 } ibb_desc;
 
 typedef struct {

@@ -53,6 +53,7 @@ class Desc(ctypes.Structure):
         ("attach_dist", ctypes.c_double),
         ("krylov_restart", ctypes.c_int),
         ("smoother_passes", ctypes.c_int),
+        ("decoupled", ctypes.c_int),
     ]
 
 
@@ -95,6 +96,7 @@ def make_desc(p, precision=IBB_FP64, inner_cycles=1):
     d.attach_dist = float(p.get("attach_dist", 0.0))
     d.krylov_restart = int(p.get("krylov_restart", 0))
     d.smoother_passes = int(p.get("smoother_passes", 0))
+    d.decoupled = int(p.get("decoupled", 0))
     return d
 
 

@@ -38,6 +38,10 @@ struct Level {
     double *xu_alt[3] = {}, *xp_alt = nullptr;
     float *xu32_alt[3] = {}, *xp32_alt = nullptr;
     bool fused = false;
+    // Re^-1 / h^2 of the viscous rows; with constant viscosity (eq:NSdis1)
+    // times mu_out and the product of gamma down to this level
+    double cvu = 0;
+    int dec = 0;
 };
 
 struct Carver {
@@ -185,6 +189,9 @@ ibb_status check_desc(const ibb_desc *d)
     if (d->attach_axis < 0 || d->attach_axis >= d->dim || !(d->attach_dist >= 0)) return IBB_EINVAL;
     if (d->krylov_restart < 0 || d->krylov_restart > 64) return IBB_EINVAL;
     if (d->smoother_passes < 0 || d->smoother_passes > 2) return IBB_EINVAL;
+    // the decoupled form holds only where the viscosity is one constant
+    if (d->decoupled != 0 && d->decoupled != 1) return IBB_EINVAL;
+    if (d->decoupled && d->mu_max != d->mu_out) return IBB_EINVAL;
     for (int a = 0; a < d->dim; ++a)
         if (d->axis_bc[a] == IBB_AXIS_PERIODIC && 4.0 * d->omega > d->n[a] * d->h) return IBB_EINVAL;
     return IBB_OK;
@@ -365,12 +372,16 @@ void setup_shapes(ibb_ctx *c, const ibb_desc *d, int64_t max_nodes, int64_t max_
     c->E = d->dim == 3 ? 3 : 1;
     if (d->dim == 3) { c->edge_axis[0] = 0; c->edge_axis[1] = 1; c->edge_axis[2] = 2; }
     else c->edge_axis[0] = 2;
+    double mu = d->mu_out;
     for (int l = 0; l < c->L; ++l) {
         Level &L = c->lv[l];
         L.g = make_grid(d, l);
         L.np = unknowns_of(L.g, 0);
         L.nu = 0;
         for (int a = 0; a < d->dim; ++a) L.nu += unknowns_of(L.g, face_mask(a));
+        if (l > 0) mu *= d->gamma[l] > 0 ? d->gamma[l] : 1.0;
+        L.cvu = d->inv_re * (d->decoupled ? mu : 1.0) / (L.g.h * L.g.h);
+        L.dec = d->decoupled ? 1 : 0;
     }
     c->singular_p = true;
     for (int a = 0; a < d->dim; ++a)
@@ -396,7 +407,7 @@ void setup_shapes(ibb_ctx *c, const ibb_desc *d, int64_t max_nodes, int64_t max_
     // sweep: an even number of sweeps per cycle, even periodic extents
     for (int l = 0; l < c->L; ++l) {
         Level &L = c->lv[l];
-        bool ok = d->smoother_passes == 1 && (d->nu1 + d->nu2) % 2 == 0 && l < c->L - 1 &&
+        bool ok = d->smoother_passes == 1 && !d->decoupled && (d->nu1 + d->nu2) % 2 == 0 && l < c->L - 1 &&
                   l < std::max(c->lc_u, c->lc_p);
         for (int a = 0; a < d->dim; ++a)
             if (d->axis_bc[a] == IBB_AXIS_PERIODIC && L.g.n[a] % 2) ok = false;
@@ -448,6 +459,7 @@ View<double> view64(Level &L)
         v.cu.mue[a] = L.mue[a];
     }
     v.cu.muc = L.muc;
+    v.cu.dec = L.dec;
     return v;
 }
 
@@ -466,6 +478,7 @@ View<float> view32(Level &L)
         v.cu.mue[a] = L.mue32[a];
     }
     v.cu.muc = L.muc32;
+    v.cu.dec = L.dec;
     return v;
 }
 
@@ -501,7 +514,7 @@ void sweep(ibb_ctx *c, bool vel, int l)
     Level &L = c->lv[l];
     if (L.fused && l < (vel ? c->lc_u : c->lc_p)) {
         const T cvp = (T)(1.0 / (L.g.h * L.g.h));
-        const T cvu = (T)(c->d.inv_re / (L.g.h * L.g.h));
+        const T cvu = (T)L.cvu;
         const T mass = (T)(c->d.sigma / c->d.dt);
         const int cls = (vel ? 0 : 1) + (sizeof(T) == 4 ? 2 : 0);
         for (int a = 0; a < (vel ? c->d.dim : 1); ++a) {
@@ -517,10 +530,18 @@ void sweep(ibb_ctx *c, bool vel, int l)
     }
     View<T> v = view<T>(L);
     const T cvp = (T)(1.0 / (L.g.h * L.g.h));
-    const T cvu = (T)(c->d.inv_re / (L.g.h * L.g.h));
+    const T cvu = (T)L.cvu;
     const T mass = (T)(c->d.sigma / c->d.dt);
     const int cls = (vel ? 0 : 1) + (sizeof(T) == 4 ? 2 : 0);
-    if (vel) {
+    if (vel && L.dec) {
+        for (int colour = 0; colour < 2; ++colour) {
+            long long units = 0;
+            for (int a = 0; a < c->d.dim; ++a) units += unknowns_of(L.g, face_mask(a)) / 2;
+            const int k = l == 0 ? prof_begin(c, cls, units) : -1;
+            launch_smooth_u_dec<T>(L.g, cview(v.bu), v.xu, v.cu, mass, cvu, colour, c->s);
+            prof_end(c, k);
+        }
+    } else if (vel) {
         for (int a = 0; a < c->d.dim; ++a)
             for (int colour = 0; colour < 2; ++colour) {
                 const int k = l == 0 ? prof_begin(c, cls, unknowns_of(L.g, face_mask(a)) / 2) : -1;
@@ -543,7 +564,7 @@ int residual(ibb_ctx *c, bool vel, int l, double *partial)
     Level &L = c->lv[l];
     View<T> v = view<T>(L);
     const T cvp = (T)(1.0 / (L.g.h * L.g.h));
-    const T cvu = (T)(c->d.inv_re / (L.g.h * L.g.h));
+    const T cvu = (T)L.cvu;
     const T mass = (T)(c->d.sigma / c->d.dt);
     if (vel) return launch_resid_u<T>(L.g, cview(v.bu), v.xu, v.cu, mass, cvu, v.ru, partial, c->s);
     return launch_resid_p<T>(L.g, v.bp, v.xp, v.cp, cvp, v.rp, partial, c->s);
@@ -767,7 +788,7 @@ ibb_status gcr_residual(ibb_ctx *c, bool vel, const GView &g, double *rn)
 {
     Level &L = c->lv[0];
     View<double> v = view64(L);
-    const double cvp = 1.0 / (L.g.h * L.g.h), cvu = c->d.inv_re / (L.g.h * L.g.h), mass = c->d.sigma / c->d.dt;
+    const double cvp = 1.0 / (L.g.h * L.g.h), cvu = L.cvu, mass = c->d.sigma / c->d.dt;
     int np;
     if (vel) np = launch_resid_u<double>(L.g, cview(g.b), g.x, v.cu, mass, cvu, g.r, c->partial, c->s);
     else np = launch_resid_p<double>(L.g, g.b.c[0], g.x.c[0], v.cp, cvp, g.r.c[0], c->partial, c->s);
@@ -798,7 +819,7 @@ ibb_status solve_gcr(ibb_ctx *c, bool vel, int max_cycles, int exact, SolveOut *
     VelArr<float> bl32 = vel ? w.bu : VelArr<float>{{w.bp, nullptr, nullptr}};
     VelArr<float> xl32 = vel ? w.xu : VelArr<float>{{w.xp, nullptr, nullptr}};
     const GView g = gcr_view(c, vel);
-    const double cvp = 1.0 / (L0.g.h * L0.g.h), cvu = c->d.inv_re / (L0.g.h * L0.g.h), mass = c->d.sigma / c->d.dt;
+    const double cvp = 1.0 / (L0.g.h * L0.g.h), cvu = L0.cvu, mass = c->d.sigma / c->d.dt;
     double nb;
     ibb_status st = norm_b(c, vel, &nb);
     if (st) return st;
@@ -980,9 +1001,15 @@ ibb_status rebuild_coefficients(ibb_ctx *c)
     launch_bin_nodes(L0.g, b, c->X, em, c->eta, c->scan_tmp, c->s);
     for (int a = 0; a < D; ++a)
         launch_spread_face(L0.g, c->ph, b, c->X, c->F, em, a, d->omega, c->f[a], L0.rho[a], c->s);
-    launch_spread_visc(L0.g, c->ph, b, c->X, em, 0, L0.muc, c->s);
-    for (int e = 0; e < c->E; ++e)
-        launch_spread_visc(L0.g, c->ph, b, c->X, em, edge_mask(D, c->edge_axis[e]), L0.mue[c->edge_axis[e]], c->s);
+    // with constant viscosity (eq:NSdis1) no row reads the viscosity fields,
+    // which keep the fluid value they were created with
+    const bool visc = !d->decoupled;
+    if (visc) {
+        launch_spread_visc(L0.g, c->ph, b, c->X, em, 0, L0.muc, c->s);
+        for (int e = 0; e < c->E; ++e)
+            launch_spread_visc(L0.g, c->ph, b, c->X, em, edge_mask(D, c->edge_axis[e]), L0.mue[c->edge_axis[e]],
+                               c->s);
+    }
     // coarse levels: full weighting of rho, mu (times gamma)
     int fm[3], em3[3];
     vel_masks(D, fm);
@@ -995,32 +1022,38 @@ ibb_status rebuild_coefficients(ibb_ctx *c)
             const double gm = d->gamma[l] > 0 ? d->gamma[l] : 1.0;
             launch_restrict<double>(F.g, L.g, D, fm, ROLE_C, true, VelArrC<double>{{F.rho[0], F.rho[1], F.rho[2]}},
                                     VelArr<double>{{L.rho[0], L.rho[1], L.rho[2]}}, 1.0, c->s);
-            launch_restrict<double>(F.g, L.g, 1, cm, ROLE_C, true, VelArrC<double>{{F.muc, nullptr, nullptr}},
-                                    VelArr<double>{{L.muc, nullptr, nullptr}}, gm, c->s);
-            VelArrC<double> fe{{nullptr, nullptr, nullptr}};
-            VelArr<double> ce{{nullptr, nullptr, nullptr}};
-            for (int e = 0; e < c->E; ++e) {
-                fe.c[e] = F.mue[c->edge_axis[e]];
-                ce.c[e] = L.mue[c->edge_axis[e]];
+            if (visc) {
+                launch_restrict<double>(F.g, L.g, 1, cm, ROLE_C, true, VelArrC<double>{{F.muc, nullptr, nullptr}},
+                                        VelArr<double>{{L.muc, nullptr, nullptr}}, gm, c->s);
+                VelArrC<double> fe{{nullptr, nullptr, nullptr}};
+                VelArr<double> ce{{nullptr, nullptr, nullptr}};
+                for (int e = 0; e < c->E; ++e) {
+                    fe.c[e] = F.mue[c->edge_axis[e]];
+                    ce.c[e] = L.mue[c->edge_axis[e]];
+                }
+                launch_restrict<double>(F.g, L.g, c->E, em3, ROLE_C, true, fe, ce, gm, c->s);
             }
-            launch_restrict<double>(F.g, L.g, c->E, em3, ROLE_C, true, fe, ce, gm, c->s);
         }
         for (int a = 0; a < D; ++a) {
             launch_beta_face(L.g, a, L.rho[a], L.beta[a], c->s);
             launch_coef_ghosts<double>(L.g, face_mask(a), L.rho[a], c->s);
             launch_coef_ghosts<double>(L.g, face_mask(a), L.beta[a], c->s);
         }
-        launch_coef_ghosts<double>(L.g, 0, L.muc, c->s);
-        for (int e = 0; e < c->E; ++e)
-            launch_coef_ghosts<double>(L.g, edge_mask(D, c->edge_axis[e]), L.mue[c->edge_axis[e]], c->s);
+        if (visc) {
+            launch_coef_ghosts<double>(L.g, 0, L.muc, c->s);
+            for (int e = 0; e < c->E; ++e)
+                launch_coef_ghosts<double>(L.g, edge_mask(D, c->edge_axis[e]), L.mue[c->edge_axis[e]], c->s);
+        }
         if (d->precision == IBB_FP32_REFINED) {
             for (int a = 0; a < D; ++a) {
                 launch_to_f32(L.rho[a], L.rho32[a], L.g.nel, c->s);
                 launch_to_f32(L.beta[a], L.beta32[a], L.g.nel, c->s);
             }
-            launch_to_f32(L.muc, L.muc32, L.g.nel, c->s);
-            for (int e = 0; e < c->E; ++e)
-                launch_to_f32(L.mue[c->edge_axis[e]], L.mue32[c->edge_axis[e]], L.g.nel, c->s);
+            if (visc) {
+                launch_to_f32(L.muc, L.muc32, L.g.nel, c->s);
+                for (int e = 0; e < c->E; ++e)
+                    launch_to_f32(L.mue[c->edge_axis[e]], L.mue32[c->edge_axis[e]], L.g.nel, c->s);
+            }
         }
     }
     // coarsest inverses
@@ -1032,7 +1065,7 @@ ibb_status rebuild_coefficients(ibb_ctx *c)
                              c->Atmp, c->singular_p ? 1 : 0, c->Aw, c->Mp, c->s);
     if (LC.nu <= DENSE_MAX)
         launch_dense_inverse(LC.g, 1, (int)LC.nu, c->uidx_u, c->ucomp_u, v.cp, v.cu, d->sigma / d->dt,
-                             d->inv_re / hc2, c->Atmp, 0, c->Aw, c->Mu, c->s);
+                             LC.cvu, c->Atmp, 0, c->Aw, c->Mu, c->s);
     c->have_coefs = true;
     return IBB_OK;
 }
@@ -1274,13 +1307,14 @@ ibb_status ibb_create(const ibb_desc *desc, int64_t max_nodes, int64_t max_sprin
         b.xp = L.xp32; b.bp = L.bp32; b.rp = L.rp32; b.muc = L.muc32;
         const double h2 = L.g.h * L.g.h;
         a.mass = desc->sigma / desc->dt;
-        a.cvu = desc->inv_re / h2;
+        a.cvu = L.cvu;
         a.cvp = 1.0 / h2;
         b.mass = (float)(desc->sigma / desc->dt);
-        b.cvu = (float)(desc->inv_re / h2);
+        b.cvu = (float)L.cvu;
         b.cvp = (float)(1.0 / h2);
         a.nu = b.nu = L.nu;
         a.np = b.np = L.np;
+        a.dec = b.dec = L.dec;
     }
     std::vector<LdsLevel> plans[2][2];
     for (int pr = 0; pr < 2; ++pr)

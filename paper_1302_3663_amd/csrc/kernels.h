@@ -49,6 +49,7 @@ struct CoefU {
     const T *rho[3];
     const T *muc;
     const T *mue[3];
+    int dec;  // constant viscosity (eq:NSdis1): muc and mue are not read
 };
 
 template <typename T>
@@ -63,6 +64,10 @@ void launch_smooth_p(const Grid &g, const T *b, T *x, const CoefP<T> &cf, T cvis
 template <typename T>
 void launch_smooth_u(const Grid &g, int a, const T *b, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc,
                      int colour, hipStream_t s);
+// one colour of every component of the constant-viscosity system, one launch
+template <typename T>
+void launch_smooth_u_dec(const Grid &g, const VelArrC<T> &b, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc,
+                         int colour, hipStream_t s);
 template <typename T>
 int launch_resid_p(const Grid &g, const T *b, const T *x, const CoefP<T> &cf, T cvisc, T *r, double *partial,
                    hipStream_t s);
@@ -117,6 +122,7 @@ struct LevTab {
     const T *rho[3], *beta[3], *muc, *mue[3];
     T mass, cvu, cvp;
     long long nu, np;
+    int dec;  // constant viscosity, as CoefU::dec
 };
 
 // the V-cycle from level l0 down to the coarsest level and back inside one

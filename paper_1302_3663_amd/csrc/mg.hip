@@ -95,41 +95,32 @@ __device__ inline void p_row_slow(const Grid &g, const T *__restrict__ x, const 
     dg = d * cvisc;
 }
 
+// Constant viscosity, eq:NSdis1: the 2D + 1 point Laplacian of component A
+// alone with unit coefficients (the viscosity is folded into cvisc), every
+// neighbour resolved through the boundary rules.
 template <typename T, int D, int A>
-__device__ inline void u_row_fast(const Grid &g, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc, int f, T &Ax,
-                                  T &dg)
+__device__ inline void u_row_slow_dec(const Grid &g, const T *__restrict__ ua, const T *__restrict__ rho, T mass,
+                                      T cvisc, int i, int j, int k, T &Ax, T &dg)
 {
-    const int st[3] = {1, g.NX, (int)g.NXY};
-    const int sa = st[A];
-    const T *__restrict__ ua = x.c[A];
+    const long long f = at(g, i, j, k);
+    const int ma = face_mask(A);
+    Ref rp[D], rm[D];
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+        int qp[3] = {i, j, k}, qm[3] = {i, j, k};
+        qp[b] += 1;
+        qm[b] -= 1;
+        rp[b] = ref_at(g, ma, ROLE_V, qp[0], qp[1], qp[2]);
+        rm[b] = ref_at(g, ma, ROLE_V, qm[0], qm[1], qm[2]);
+    }
     const T xf = ua[f];
-    const T cp = T(2) * cf.muc[f], cm = T(2) * cf.muc[f - sa];
-    const T vp = ua[f + sa], vm = ua[f - sa];
-    const T rho = cf.rho[A][f];
-    T mp[D - 1], mm[D - 1], ap[D - 1], am[D - 1], b0[D - 1], b1[D - 1], b2[D - 1], b3[D - 1];
+    T acc = 0, d = 0;
 #pragma unroll
-    for (int bi = 0; bi < D - 1; ++bi) {
-        const int B = other_axis<A>(bi);
-        const int sb = st[B];
-        const T *__restrict__ ub = x.c[B];
-        const T *__restrict__ me = cf.mue[3 - A - B];
-        mp[bi] = me[f + sb];
-        mm[bi] = me[f];
-        ap[bi] = ua[f + sb];
-        am[bi] = ua[f - sb];
-        b0[bi] = ub[f + sb];
-        b1[bi] = ub[f + sb - sa];
-        b2[bi] = ub[f];
-        b3[bi] = ub[f - sa];
+    for (int b = 0; b < D; ++b) {
+        acc += (ld(ua, rp[b]) - xf) - (xf - ld(ua, rm[b]));
+        d += T(1 - self_sign(rp[b], f)) + T(1 - self_sign(rm[b], f));
     }
-    T acc = cp * (vp - xf) - cm * (xf - vm);
-    T d = cp + cm;
-#pragma unroll
-    for (int bi = 0; bi < D - 1; ++bi) {
-        acc += mp[bi] * ((ap[bi] - xf) + (b0[bi] - b1[bi])) - mm[bi] * ((xf - am[bi]) + (b2[bi] - b3[bi]));
-        d += mp[bi] + mm[bi];
-    }
-    const T m = mass * rho;
+    const T m = mass * rho[f];
     Ax = m * xf - cvisc * acc;
     dg = m + cvisc * d;
 }
@@ -138,6 +129,10 @@ template <typename T, int D, int A>
 __device__ inline void u_row_slow(const Grid &g, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc, int i, int j,
                                   int k, T &Ax, T &dg)
 {
+    if (cf.dec) {
+        u_row_slow_dec<T, D, A>(g, x.c[A], cf.rho[A], mass, cvisc, i, j, k, Ax, dg);
+        return;
+    }
     const int q[3] = {i, j, k};
     const long long f = at(g, i, j, k);
     const int ma = face_mask(A);
@@ -236,10 +231,45 @@ __device__ inline void p_row(const Grid &g, const T *__restrict__ x, const CoefP
     dg = d * cvisc;
 }
 
+// Constant viscosity through the ghost layer: component A alone, unit
+// coefficients; a mirrored self-reference adds to the diagonal as in u_row.
+template <typename T, int D, int A>
+__device__ inline void u_row_dec(const Grid &g, const T *__restrict__ ua, const T *__restrict__ rho, T mass, T cvisc,
+                                 int i, int j, int k, T &Ax, T &dg)
+{
+    const int f = (int)at(g, i, j, k);
+    const int st[3] = {1, g.NX, (int)g.NXY};
+    T vp[D], vm[D];
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+        vp[b] = ua[f + st[b]];
+        vm[b] = ua[f - st[b]];
+    }
+    const T xf = ua[f];
+    const T r = rho[f];
+    const int q[3] = {i, j, k};
+    T acc = 0, d = T(2 * D);
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+        acc += (vp[b] - xf) - (xf - vm[b]);
+        if (b != A && g.bc[b] != AX_PERIODIC) {
+            if (q[b] == 0) d += T(1);                                              // odd mirror
+            if (q[b] == g.n[b] - 1) d += g.bc[b] == AX_WALLS ? T(1) : T(-1);        // even at the outflow
+        }
+    }
+    const T m = mass * r;
+    Ax = m * xf - cvisc * acc;
+    dg = m + cvisc * d;
+}
+
 template <typename T, int D, int A>
 __device__ inline void u_row(const Grid &g, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc, int i, int j,
                              int k, T &Ax, T &dg)
 {
+    if (cf.dec) {
+        u_row_dec<T, D, A>(g, x.c[A], cf.rho[A], mass, cvisc, i, j, k, Ax, dg);
+        return;
+    }
     const int f = (int)at(g, i, j, k);
     const int st[3] = {1, g.NX, (int)g.NXY};
     const int sa = st[A];
@@ -446,6 +476,27 @@ __global__ void __launch_bounds__(256) k_smooth_u(Grid g, Box box, const T *__re
     const T xn = x.c[A][f] + (b[f] - Ax) / dg;
     x.c[A][f] = xn;
     write_images(g, face_mask(A), ROLE_V, x.c[A], i, j, k, xn);
+}
+
+// one colour of every component of the constant-viscosity system (eq:NSdis1)
+// in one launch: the components do not couple, so this is the sweep of the
+// components one after another.  blockIdx.y is the component.
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_smooth_u_dec(Grid g, VelBox boxes, VelArrC<T> b, VelArr<T> x, CoefU<T> cf,
+                                                      T mass, T cvisc, int colour)
+{
+    const int a = blockIdx.y;
+    int i, j, k;
+    if (!box_colour_pos(boxes.b[a], colour, blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
+    T Ax, dg;
+    if (a == 0) u_row_dec<T, D, 0>(g, x.c[0], cf.rho[0], mass, cvisc, i, j, k, Ax, dg);
+    else if (a == 1) u_row_dec<T, D, 1>(g, x.c[1], cf.rho[1], mass, cvisc, i, j, k, Ax, dg);
+    else u_row_dec<T, D, (D == 3 ? 2 : 1)>(g, x.c[2], cf.rho[2], mass, cvisc, i, j, k, Ax, dg);
+    const long long f = at(g, i, j, k);
+    T *xa = x.c[a];
+    const T xn = xa[f] + (b.c[a][f] - Ax) / dg;
+    xa[f] = xn;
+    write_images(g, face_mask(a), ROLE_V, xa, i, j, k, xn);
 }
 
 // ---------------------------------------------------------------------------
@@ -1200,6 +1251,7 @@ __device__ inline CoefU<T> coef_u(const LevTab<T> &lt)
         cf.mue[a] = lt.mue[a];
     }
     cf.muc = lt.muc;
+    cf.dec = lt.dec;
     return cf;
 }
 
@@ -1732,6 +1784,25 @@ void launch_smooth_u(const Grid &g, int a, const T *b, const VelArr<T> &x, const
 }
 
 template <typename T>
+void launch_smooth_u_dec(const Grid &g, const VelArrC<T> &b, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc,
+                         int colour, hipStream_t s)
+{
+    VelBox parts;
+    long long mx = 0;
+    for (int a = 0; a < 3; ++a) {
+        parts.b[a] = a < g.D ? unk_box(g, face_mask(a)) : Box{{0, 0, 0}, {0, 0, 0}};
+        if (a >= g.D) continue;
+        const Box &P = parts.b[a];
+        const long long n = (long long)((P.ext[0] + 1) / 2) * P.ext[1] * P.ext[2];
+        mx = n > mx ? n : mx;
+    }
+    if (mx <= 0) return;
+    const dim3 grid(blocks_for(mx), g.D), blk(256);
+    if (g.D == 3) launch_timed(k_smooth_u_dec<T, 3>, grid, blk, s, g, parts, b, x, cf, mass, cvisc, colour);
+    else launch_timed(k_smooth_u_dec<T, 2>, grid, blk, s, g, parts, b, x, cf, mass, cvisc, colour);
+}
+
+template <typename T>
 void launch_smooth_rb(const Grid &g, int vel, int a, const VelArrC<T> &xin, const T *b, const CoefU<T> &cu,
                       const CoefP<T> &cp, T mass, T cvisc, T *xout, hipStream_t s)
 {
@@ -2238,6 +2309,8 @@ void launch_gcr_update(const Grid &g, int velocity, const double *num, const dou
     template void launch_smooth_p<T>(const Grid &, const T *, T *, const CoefP<T> &, T, int, hipStream_t);          \
     template void launch_smooth_u<T>(const Grid &, int, const T *, const VelArr<T> &, const CoefU<T> &, T, T, int,  \
                                      hipStream_t);                                                                  \
+    template void launch_smooth_u_dec<T>(const Grid &, const VelArrC<T> &, const VelArr<T> &, const CoefU<T> &, T,  \
+                                         T, int, hipStream_t);                                                      \
     template void launch_smooth_rb<T>(const Grid &, int, int, const VelArrC<T> &, const T *, const CoefU<T> &,      \
                                       const CoefP<T> &, T, T, T *, hipStream_t);                                    \
     template int launch_resid_p<T>(const Grid &, const T *, const T *, const CoefP<T> &, T, T *, double *,          \

@@ -30,6 +30,12 @@ def cases():
         # a high-contrast member solved by GCR (its solves run on their own)
         "3d_tube_gcr": dict(synth.tiny_3d(seed=6), params=dict(synth.tiny_3d(seed=6)["params"], mu_max=1e3,
                                                                  krylov_restart=6)),
+        # constant viscosity (eq:NSdis1): alone, one launch per colour covers
+        # every component; in the group each component has its own pass
+        "3d_tube_dec": dict(synth.tiny_3d(seed=7), params=dict(synth.tiny_3d(seed=7)["params"], mu_max=1.0,
+                                                                 decoupled=1)),
+        "2d_inout_dec": dict(synth.tiny_2d(inout=True, seed=8),
+                             params=dict(synth.tiny_2d(inout=True, seed=8)["params"], mu_max=1.0, decoupled=1)),
     }
 
 

@@ -203,3 +203,23 @@ def test_refused_with_variable_viscosity():
     p["mu_max"] = 3.0
     with pytest.raises(Exception):
         hierarchy(p)
+
+
+def test_steps_stay_close_to_the_coupled_form():
+    """The two forms differ by Re^-1 mu D_a(div u~), and u~ is divergence-free
+    only up to the projection's correction, so whole steps of the two agree
+    closely but not to rounding."""
+    from oracle import step as S
+    base = synth.tiny_2d()
+    out = []
+    for dec in (0, 1):
+        p = dict(base["params"], decoupled=dec)
+        p["mu_max"] = p["mu_out"]
+        st = S.State(p, base["u0"], base["p0"], base["X"], base["ij"], base["rest"], base["K"])
+        S.setup(st)
+        for _ in range(3):
+            S.projection_step(st)
+            S.lagrangian_update(st)
+        out.append(st.u.copy())
+    d = np.linalg.norm(out[1] - out[0]) / np.linalg.norm(out[0])
+    assert 1e-12 < d < 1e-4
