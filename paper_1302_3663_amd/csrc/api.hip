@@ -107,6 +107,11 @@ struct ibb_ctx {
     int *frag_label = nullptr, *frag_root = nullptr, *frag_flag = nullptr;
     bool have_nodes = false, have_springs = false, have_coefs = false;
     hipEvent_t ev[4] = {};
+    // one solver iteration with the residual norm after it, per system
+    // (pressure, velocity), captured once on a private stream and replayed
+    // on the context's stream
+    hipStream_t cap = nullptr;
+    hipGraphExec_t tick[2] = {};
     // finest-level kernel timing (ibb_profile_*)
     bool prof = false;
     std::vector<hipEvent_t> pev;           // pairs: start, stop
@@ -583,24 +588,34 @@ void plan_lds(ibb_ctx *c, int prec, bool vel, std::vector<LdsLevel> &out)
         for (int a = 0; a < 3; ++a) o.xu[a] = o.bu[a] = o.ru[a] = o.rho[a] = o.beta[a] = o.mue[a] = -1;
         o.xp = o.bp = o.rp = o.muc = -1;
     }
-    // bytes of one level's arrays in this system
-    auto level_bytes = [&](int l) {
-        const long long one = ((c->lv[l].g.nel * wsz + 15) / 16) * 16;
-        const int arrays = vel ? 4 * D + 1 + c->E : 3 + D;
-        return one * arrays;
-    };
-    // the level the cycle starts on holds the solve's b and x: only the
-    // coarser levels, scratch of one cycle, may move to LDS
+    // bytes of one level's arrays in this system: solver arrays (x, b, r)
+    // and coefficients
+    auto one_bytes = [&](int l) { return ((c->lv[l].g.nel * wsz + 15) / 16) * 16; };
+    const int nsolve = vel ? 3 * D : 3, ncoef = vel ? D + 1 + c->E : D;
+    // the levels below the start level, deepest first, while they fit
     int ls = c->L;
     long long total = 0;
     for (int l = c->L - 1; l > lc; --l) {
-        if (total + level_bytes(l) > budget) break;
-        total += level_bytes(l);
+        const long long b = one_bytes(l) * (nsolve + ncoef);
+        if (total + b > budget) break;
+        total += b;
         ls = l;
+    }
+    // then the start level, whole or its solver arrays alone, when
+    // everything below it is staged
+    bool start_coefs = false;
+    if (ls == lc + 1) {
+        if (total + one_bytes(lc) * (nsolve + ncoef) <= budget) {
+            ls = lc;
+            start_coefs = true;
+        } else if (total + one_bytes(lc) * nsolve <= budget) {
+            ls = lc;
+        }
     }
     int off = 0;
     for (int l = ls; l < c->L; ++l) {
-        const int one = (int)(((c->lv[l].g.nel * wsz + 15) / 16) * 16);
+        const int one = (int)one_bytes(l);
+        const bool coefs = l > lc || start_coefs;
         LdsLevel &o = out[l];
         auto take = [&]() { const int r = off; off += one; return r; };
         if (vel) {
@@ -608,15 +623,18 @@ void plan_lds(ibb_ctx *c, int prec, bool vel, std::vector<LdsLevel> &out)
                 o.xu[a] = take();
                 o.bu[a] = take();
                 o.ru[a] = take();
-                o.rho[a] = take();
+                if (coefs) o.rho[a] = take();
             }
-            o.muc = take();
-            for (int e = 0; e < c->E; ++e) o.mue[c->edge_axis[e]] = take();
+            if (coefs) {
+                o.muc = take();
+                for (int e = 0; e < c->E; ++e) o.mue[c->edge_axis[e]] = take();
+            }
         } else {
             o.xp = take();
             o.bp = take();
             o.rp = take();
-            for (int a = 0; a < D; ++a) o.beta[a] = take();
+            if (coefs)
+                for (int a = 0; a < D; ++a) o.beta[a] = take();
         }
     }
     c->lds_ls[prec][vel ? 1 : 0] = ls;
@@ -694,11 +712,43 @@ void vcycle(ibb_ctx *c, bool vel, int l)
     for (int s = 0; s < c->d.nu2; ++s) sweep<T>(c, vel, l);
 }
 
+// the reduced scalar back on the host
+ibb_status fetch_scalar(ibb_ctx *c, double *out)
+{
+    HIPCHK(hipMemcpyAsync(out, c->scalar, sizeof(double), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    return IBB_OK;
+}
+
 ibb_status read_scalar(ibb_ctx *c, int nparts, double *out)
 {
     launch_reduce_final(c->partial, nparts, c->scalar, c->s);
-    HIPCHK(hipMemcpyAsync(out, c->scalar, sizeof(double), hipMemcpyDeviceToHost, c->s));
-    HIPCHK(hipStreamSynchronize(c->s));
+    return fetch_scalar(c, out);
+}
+
+// Capture launch() -- kernels only, no memset and no copy -- as the graph of
+// system vel, on the private stream: the launch helpers use c->s, which
+// points there while the capture runs.
+template <typename F>
+ibb_status ensure_tick(ibb_ctx *c, bool vel, F launch)
+{
+    const int v = vel ? 1 : 0;
+    if (c->tick[v]) return IBB_OK;
+    if (!c->cap) HIPCHK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    hipStream_t user = c->s;
+    HIPCHK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    c->s = c->cap;
+    launch();
+    c->s = user;
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamEndCapture(c->cap, &graph));
+    const hipError_t e = hipGraphInstantiate(&c->tick[v], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        c->tick[v] = nullptr;
+        c->err = std::string("hipGraphInstantiate: ") + hipGetErrorString(e);
+        return IBB_EDEVICE;
+    }
     return IBB_OK;
 }
 
@@ -914,7 +964,6 @@ ibb_status solve(ibb_ctx *c, bool vel, int max_cycles, int exact, SolveOut *o)
     auto one_iteration = [&]() {
         if (!refined) {
             vcycle<double>(c, vel, 0);
-            o->vcycles++;
             return;
         }
         // r64 already holds b - A x (from the last residual evaluation)
@@ -927,10 +976,7 @@ ibb_status solve(ibb_ctx *c, bool vel, int max_cycles, int exact, SolveOut *o)
                                                 VelArr<float>{{L0.bp32, nullptr, nullptr}}, c->s);
             launch_fill<float>(L0.xp32, L0.g.nel, 0.0f, c->s);
         }
-        for (int it = 0; it < c->d.inner_cycles; ++it) {
-            vcycle<float>(c, vel, 0);
-            o->vcycles++;
-        }
+        for (int it = 0; it < c->d.inner_cycles; ++it) vcycle<float>(c, vel, 0);
         if (vel)
             launch_add_correction(L0.g, D, vm, VelArrC<float>{{L0.xu32[0], L0.xu32[1], L0.xu32[2]}},
                                   VelArr<double>{{L0.xu[0], L0.xu[1], L0.xu[2]}}, c->s);
@@ -938,13 +984,35 @@ ibb_status solve(ibb_ctx *c, bool vel, int max_cycles, int exact, SolveOut *o)
             launch_add_correction(L0.g, 1, pm, VelArrC<float>{{L0.xp32, nullptr, nullptr}},
                                   VelArr<double>{{L0.xp, nullptr, nullptr}}, c->s);
     };
+    // Without kernel timing an iteration is one graph launch: the same
+    // kernels in the same order as the launches below, so the same bits.
+    const bool graph = !c->prof;
+    if (graph) {
+        st = ensure_tick(c, vel, [&]() {
+            one_iteration();
+            const int np = residual<double>(c, vel, 0, c->partial);
+            launch_reduce_final(c->partial, np, c->scalar, c->s);
+        });
+        if (st) return st;
+    }
+    auto iterate = [&](double *r) -> ibb_status {
+        o->vcycles += refined ? c->d.inner_cycles : 1;
+        if (!graph) {
+            one_iteration();
+            return resid_norm(c, vel, r);
+        }
+        HIPCHK(hipGraphLaunch(c->tick[vel ? 1 : 0], c->s));
+        double s2;
+        const ibb_status e = fetch_scalar(c, &s2);
+        *r = sqrt(s2);
+        return e;
+    };
     if ((st = resid_norm(c, vel, &rn))) return st;
     double rel = rn / nb;
     if (exact > 0) {
         for (int k = 0; k < exact; ++k) {
-            one_iteration();
+            if ((st = iterate(&rn))) return st;
             o->cycles++;
-            if ((st = resid_norm(c, vel, &rn))) return st;
         }
         o->relres = rn / nb;
         return IBB_OK;
@@ -952,9 +1020,8 @@ ibb_status solve(ibb_ctx *c, bool vel, int max_cycles, int exact, SolveOut *o)
     while (!(rel <= c->d.rtol)) {
         if (!(rel == rel) || isinf(rel)) { o->status = IBB_ENUMERIC; break; }
         if (o->cycles >= max_cycles) { o->status = IBB_ENOCONV; break; }
-        one_iteration();
+        if ((st = iterate(&rn))) return st;
         o->cycles++;
-        if ((st = resid_norm(c, vel, &rn))) return st;
         prof_flush(c);
         rel = rn / nb;
     }
@@ -1256,6 +1323,7 @@ ibb_status ibb_create(const ibb_desc *desc, int64_t max_nodes, int64_t max_sprin
     if (check_desc(desc) || !workspace || max_nodes < 0 || max_springs < 0 || max_nodes > INT32_MAX / 2 ||
         max_springs > INT32_MAX / 2)
         return IBB_EINVAL;
+    wg_prepare();
     ibb_ctx *c = new ibb_ctx();
     setup_shapes(c, desc, max_nodes, max_springs);
     const size_t need = carve(c, nullptr, true);
@@ -1347,6 +1415,9 @@ ibb_status ibb_destroy(ibb_ctx *c)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
     for (auto &e : c->pev)
         if (e) (void)hipEventDestroy(e);
+    for (auto &g : c->tick)
+        if (g) (void)hipGraphExecDestroy(g);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
     delete c;
     return IBB_OK;
 }

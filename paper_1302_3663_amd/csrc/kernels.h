@@ -132,11 +132,13 @@ struct LevTab {
 // cycle does not spill)
 constexpr int WG_THREADS = 512;
 __host__ __device__ constexpr int wg_threads(int, int) { return WG_THREADS; }
-// Where the one-workgroup cycle keeps a level: levels l >= ls live in the
-// workgroup's LDS arena (byte offsets of their arrays below; -1 means the
-// array is not used by the system), the others stay in global memory.  The
-// coefficient arrays are copied in and the solver arrays cleared when the
-// kernel starts; nothing of those levels is needed after it ends.
+// Where the one-workgroup cycle keeps a level: arrays of levels l >= ls
+// with an offset >= 0 below live in the workgroup's LDS arena (byte
+// offsets), every other array stays where it is in global memory.  Staged
+// coefficients are copied in and staged solver arrays cleared when the
+// kernel starts.  The start level may be staged too, then with at least its
+// solver arrays: its x and b are copied in and x is copied back at the end;
+// nothing else of the staged levels is needed after the kernel.
 struct LdsLevel {
     int xu[3], bu[3], ru[3], rho[3], beta[3], mue[3];
     int xp, bp, rp, muc;
@@ -148,6 +150,8 @@ struct LdsPlan {
     int bytes;             // arena size
 };
 
+// sets the dynamic-LDS limit of the one-workgroup kernels (once per process)
+void wg_prepare();
 template <typename T>
 void launch_coarse_vcycle(int D, const LevTab<T> *tab, int l0, int L, int vel, int nu1, int nu2, int ndense,
                           const long long *uidx, const int *ucomp, const double *M, const LdsPlan &plan,

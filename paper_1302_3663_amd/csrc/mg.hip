@@ -1494,18 +1494,21 @@ __device__ __attribute__((always_inline)) inline void coarse_cycle(const LevTab<
 }
 
 
+// an array of a staged level: its place in the arena, or (offset -1) the
+// array where it already is
 template <typename T>
-__device__ inline T *arena_ptr(unsigned char *arena, int off)
+__device__ inline T *arena_ptr(unsigned char *arena, int off, T *global)
 {
-    return off >= 0 ? reinterpret_cast<T *>(arena + off) : nullptr;
+    return off >= 0 ? reinterpret_cast<T *>(arena + off) : global;
 }
 
-// The workgroup's table of levels: the global tables, with the levels from
-// ls down rebased into the LDS arena; their coefficients are copied in and
-// their solver arrays cleared.
+// The workgroup's table of levels: the global tables, with the arrays of the
+// levels from ls down that the plan places in the LDS arena rebased there.
+// Staged coefficients are copied in.  Staged solver arrays are cleared,
+// except on the start level l0, whose x and b carry the cycle's input.
 template <typename T, int D, int VEL>
-__device__ inline void stage_levels(const LevTab<T> *__restrict__ tab, int L, int ls, const LdsLevel *__restrict__ lev,
-                                    unsigned char *arena, LevTab<T> *wt)
+__device__ inline void stage_levels(const LevTab<T> *__restrict__ tab, int l0, int L, int ls,
+                                    const LdsLevel *__restrict__ lev, unsigned char *arena, LevTab<T> *wt)
 {
     for (int l = threadIdx.x; l < L; l += blockDim.x) {
         LevTab<T> t = tab[l];
@@ -1513,17 +1516,17 @@ __device__ inline void stage_levels(const LevTab<T> *__restrict__ tab, int L, in
             const LdsLevel o = lev[l];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                t.xu[a] = arena_ptr<T>(arena, o.xu[a]);
-                t.bu[a] = arena_ptr<T>(arena, o.bu[a]);
-                t.ru[a] = arena_ptr<T>(arena, o.ru[a]);
-                t.rho[a] = arena_ptr<T>(arena, o.rho[a]);
-                t.beta[a] = arena_ptr<T>(arena, o.beta[a]);
-                t.mue[a] = arena_ptr<T>(arena, o.mue[a]);
+                t.xu[a] = arena_ptr<T>(arena, o.xu[a], t.xu[a]);
+                t.bu[a] = arena_ptr<T>(arena, o.bu[a], t.bu[a]);
+                t.ru[a] = arena_ptr<T>(arena, o.ru[a], t.ru[a]);
+                t.rho[a] = arena_ptr<T>(arena, o.rho[a], const_cast<T *>(t.rho[a]));
+                t.beta[a] = arena_ptr<T>(arena, o.beta[a], const_cast<T *>(t.beta[a]));
+                t.mue[a] = arena_ptr<T>(arena, o.mue[a], const_cast<T *>(t.mue[a]));
             }
-            t.xp = arena_ptr<T>(arena, o.xp);
-            t.bp = arena_ptr<T>(arena, o.bp);
-            t.rp = arena_ptr<T>(arena, o.rp);
-            t.muc = arena_ptr<T>(arena, o.muc);
+            t.xp = arena_ptr<T>(arena, o.xp, t.xp);
+            t.bp = arena_ptr<T>(arena, o.bp, t.bp);
+            t.rp = arena_ptr<T>(arena, o.rp, t.rp);
+            t.muc = arena_ptr<T>(arena, o.muc, const_cast<T *>(t.muc));
         }
         wt[l] = t;
     }
@@ -1531,30 +1534,51 @@ __device__ inline void stage_levels(const LevTab<T> *__restrict__ tab, int L, in
     for (int l = ls; l < L; ++l) {
         const LevTab<T> &src = tab[l];
         const LevTab<T> &dst = wt[l];
+        const bool start = l == l0;
         const int nel = (int)src.g.nel;
         for (int e = threadIdx.x; e < nel; e += blockDim.x) {
             if (VEL) {
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
-                    const_cast<T *>(dst.rho[a])[e] = src.rho[a][e];
-                    dst.xu[a][e] = T(0);
-                    dst.bu[a][e] = T(0);
+                    if (dst.rho[a] != src.rho[a]) const_cast<T *>(dst.rho[a])[e] = src.rho[a][e];
+                    dst.xu[a][e] = start ? src.xu[a][e] : T(0);
+                    dst.bu[a][e] = start ? src.bu[a][e] : T(0);
                     dst.ru[a][e] = T(0);
                 }
-                const_cast<T *>(dst.muc)[e] = src.muc[e];
+                if (dst.muc != src.muc) const_cast<T *>(dst.muc)[e] = src.muc[e];
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
-                    if (dst.mue[a]) const_cast<T *>(dst.mue[a])[e] = src.mue[a][e];
+                    if (dst.mue[a] && dst.mue[a] != src.mue[a]) const_cast<T *>(dst.mue[a])[e] = src.mue[a][e];
             } else {
 #pragma unroll
-                for (int a = 0; a < D; ++a) const_cast<T *>(dst.beta[a])[e] = src.beta[a][e];
-                dst.xp[e] = T(0);
-                dst.bp[e] = T(0);
+                for (int a = 0; a < D; ++a)
+                    if (dst.beta[a] != src.beta[a]) const_cast<T *>(dst.beta[a])[e] = src.beta[a][e];
+                dst.xp[e] = start ? src.xp[e] : T(0);
+                dst.bp[e] = start ? src.bp[e] : T(0);
                 dst.rp[e] = T(0);
             }
         }
     }
     __syncthreads();
+}
+
+// a staged start level hands its iterate (with its ghost images) back
+template <typename T, int D, int VEL>
+__device__ inline void unstage_start(const LevTab<T> *__restrict__ tab, int l0, int ls, const LevTab<T> *wt)
+{
+    if (l0 < ls) return;
+    __syncthreads();
+    const LevTab<T> &src = wt[l0];
+    const LevTab<T> &dst = tab[l0];
+    const int nel = (int)dst.g.nel;
+    for (int e = threadIdx.x; e < nel; e += blockDim.x) {
+        if (VEL) {
+#pragma unroll
+            for (int a = 0; a < D; ++a) dst.xu[a][e] = src.xu[a][e];
+        } else {
+            dst.xp[e] = src.xp[e];
+        }
+    }
 }
 
 template <typename T, int D, int VEL>
@@ -1565,8 +1589,9 @@ __global__ void __launch_bounds__(wg_threads(D, VEL)) k_coarse_vcycle(const LevT
 {
     extern __shared__ __align__(16) unsigned char wg_arena[];
     __shared__ LevTab<T> wt[WG_MAXLEV];
-    stage_levels<T, D, VEL>(tab, L, plan.ls, plan.lev, wg_arena, wt);
+    stage_levels<T, D, VEL>(tab, l0, L, plan.ls, plan.lev, wg_arena, wt);
     coarse_cycle<T, D, VEL>(wt, l0, L, nu1, nu2, ndense, uidx, ucomp, M);
+    unstage_start<T, D, VEL>(tab, l0, plan.ls, wt);
 }
 
 // ---------------------------------------------------------------------------
@@ -1722,8 +1747,10 @@ __global__ void __launch_bounds__(wg_threads(D, VEL)) k_bcoarse(const BCoarse *_
     if (!flags[I.ctx]) return;
     extern __shared__ __align__(16) unsigned char wg_arena[];
     __shared__ LevTab<T> wt[WG_MAXLEV];
-    stage_levels<T, D, VEL>(static_cast<const LevTab<T> *>(I.tab), I.L, I.lds_from, I.lds, wg_arena, wt);
+    const LevTab<T> *tab = static_cast<const LevTab<T> *>(I.tab);
+    stage_levels<T, D, VEL>(tab, I.l0, I.L, I.lds_from, I.lds, wg_arena, wt);
     coarse_cycle<T, D, VEL>(wt, I.l0, I.L, nu1, nu2, I.ndense, I.uidx, I.ucomp, I.M);
+    unstage_start<T, D, VEL>(tab, I.l0, I.lds_from, wt);
 }
 
 // ---------------------------------------------------------------------------
@@ -2101,6 +2128,22 @@ static void allow_lds(K kernel, int bytes)
                                 bytes) == hipSuccess)
             allowed = bytes;
     }
+}
+
+// raise the dynamic-LDS limit of every one-workgroup kernel to the full
+// budget once, so that no launch needs the attribute call (which has no
+// place inside a captured graph)
+void wg_prepare()
+{
+    const int b = wg_lds_budget();
+#define PREP(T, DD, VV)                              \
+    do {                                             \
+        allow_lds(k_coarse_vcycle<T, DD, VV>, b);    \
+        allow_lds(k_bcoarse<T, DD, VV>, b);          \
+    } while (0)
+    PREP(double, 2, 0); PREP(double, 2, 1); PREP(double, 3, 0); PREP(double, 3, 1);
+    PREP(float, 2, 0); PREP(float, 2, 1); PREP(float, 3, 0); PREP(float, 3, 1);
+#undef PREP
 }
 
 template <typename T>
