@@ -19,6 +19,11 @@ The studies here use the 2D channel (periodic in x, walls in y) of the
 workloads; every time step runs on the GPU, and only the error norms and the
 restriction that compares two grids are host arithmetic.
 
+Delta kernels (eq:PhiErrorUnity, eq:PhiErrorFirstMomentum): how far the
+spread of one node misses the unity and first-moment conditions, for phi_1
+and phi_2 over a range of mesh widths at a fixed spread width, measured with
+the GPU spread (delta_errors).
+
     python -m paper_1302_3663_amd.studies [--out FILE]
 """
 import argparse
@@ -178,6 +183,58 @@ def channel(ny, seed=1, eta=30, mu_max=1.0, rho_b=0.0, krylov=0):
     return case
 
 
+def delta_errors(kernel, omega, h, nsamp=17):
+    """eq:PhiErrorUnity and eq:PhiErrorFirstMomentum through the GPU spread.
+
+    One node with unit x-force is spread on a periodic 2D grid.  It sits at
+    offset t from an x-face lattice point along both axes (x-faces sit at
+    x = i h, y = (j + 1/2) h), so the 2D sums factor into two equal 1D sums:
+    sum f h^2 = s(t)^2 and sum (x - X) f h^2 = m(t) s(t), with s and m the 1D
+    sums of the paper's metrics.  t runs over [0, h]; returns the maxima of
+    |s - 1| and |m| and the per-sample values."""
+    from . import ibmg
+    import torch
+    m = int(math.ceil(2.0 * omega / h)) + 4
+    n = 2 * m + (2 * m) % 2
+    p = synth.base_params(2, [n, n], [AX_PERIODIC, AX_PERIODIC], h)
+    p.update(kernel=kernel, omega=omega, rho_b=0.0, mu_max=p["mu_out"])
+    nf = sum(synth.face_dims(p, a)[0] * synth.face_dims(p, a)[1] for a in range(2))
+    c = m * h
+    case = dict(params=p, u0=np.zeros(nf), p0=np.zeros(n * n), X=np.array([[c], [c + 0.5 * h]]),
+                ij=np.zeros((2, 0), np.int32), rest=np.zeros(0), K=np.zeros(0))
+    ctx = ibmg.from_case(case)
+    xs = np.arange(n) * h
+    su, mo = [], []
+    try:
+        F = torch.tensor([[1.0], [0.0]], dtype=torch.float64, device="cuda:0")
+        for t in np.linspace(0.0, h, nsamp):
+            X = torch.tensor([[c + t], [c + 0.5 * h + t]], dtype=torch.float64, device="cuda:0")
+            f = ctx.spread(omega, X, F).cpu().numpy()
+            fx = f[:n * n].reshape(n, n)
+            S = float(fx.sum() * h * h)
+            M = float(((xs[None, :] - (c + t)) * fx).sum() * h * h)
+            s1 = math.sqrt(S)
+            su.append(s1 - 1.0)
+            mo.append(M / s1)
+    finally:
+        ctx.close()
+    return dict(eps_unity=float(np.max(np.abs(su))), eps_mom=float(np.max(np.abs(mo))), unity=su, moment=mo)
+
+
+def delta_sweep(omega=0.01, hs=None, nsamp=17):
+    """Fig. ComarePhi: both metrics for phi_1 and phi_2 at spread width omega
+    over mesh widths from omega/10 down to about omega/1024 * 100 and the
+    exact divisors omega/z."""
+    if hs is None:
+        hs = sorted({omega / z for z in (1, 2, 3, 4, 5, 8, 10)} |
+                    {1.0 / n for n in (100, 128, 160, 200, 256, 320, 400, 512, 640, 800, 1024)}, reverse=True)
+    out = {"omega": omega, "h": hs}
+    for name, k in (("phi1", 1), ("phi2", 0)):
+        r = [delta_errors(k, omega, h, nsamp) for h in hs]
+        out[name] = {"eps_unity": [x["eps_unity"] for x in r], "eps_mom": [x["eps_mom"] for x in r]}
+    return out
+
+
 STUDIES = {
     # name: (kind, case (temporal) or case maker of ny (spatial), refinements)
     "temporal": ("temporal", lambda: channel(32), [4e-4, 2e-4, 1e-4, 5e-5, 2.5e-5]),
@@ -202,7 +259,9 @@ def main():
     ap.add_argument("--only", default=None, help="comma-separated study names")
     args = ap.parse_args()
     names = args.only.split(",") if args.only else list(STUDIES)
-    res = {n: run_study(n, args.T) for n in names}
+    res = {n: run_study(n, args.T) for n in names if n in STUDIES}
+    if args.only is None or "delta" in names:
+        res["delta"] = delta_sweep()
     text = json.dumps(res, indent=1)
     if args.out:
         with open(args.out, "w") as f:
