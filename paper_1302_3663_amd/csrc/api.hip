@@ -112,6 +112,9 @@ struct ibb_ctx {
     // on the context's stream
     hipStream_t cap = nullptr;
     hipGraphExec_t tick[2] = {};
+    // GCR: one graph per system and position in the restart window (the
+    // number of Gram-Schmidt steps depends on it)
+    std::vector<hipGraphExec_t> gtick[2];
     // finest-level kernel timing (ibb_profile_*)
     bool prof = false;
     std::vector<hipEvent_t> pev;           // pairs: start, stop
@@ -726,14 +729,13 @@ ibb_status read_scalar(ibb_ctx *c, int nparts, double *out)
     return fetch_scalar(c, out);
 }
 
-// Capture launch() -- kernels only, no memset and no copy -- as the graph of
-// system vel, on the private stream: the launch helpers use c->s, which
-// points there while the capture runs.
+// Capture launch() -- kernels only, no memset and no copy -- into *slot
+// (once), on the private stream: the launch helpers use c->s, which points
+// there while the capture runs.
 template <typename F>
-ibb_status ensure_tick(ibb_ctx *c, bool vel, F launch)
+ibb_status ensure_graph(ibb_ctx *c, hipGraphExec_t *slot, F launch)
 {
-    const int v = vel ? 1 : 0;
-    if (c->tick[v]) return IBB_OK;
+    if (*slot) return IBB_OK;
     if (!c->cap) HIPCHK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
     hipStream_t user = c->s;
     HIPCHK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
@@ -742,14 +744,24 @@ ibb_status ensure_tick(ibb_ctx *c, bool vel, F launch)
     c->s = user;
     hipGraph_t graph = nullptr;
     HIPCHK(hipStreamEndCapture(c->cap, &graph));
-    const hipError_t e = hipGraphInstantiate(&c->tick[v], graph, nullptr, nullptr, 0);
+    const hipError_t e = hipGraphInstantiate(slot, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) {
-        c->tick[v] = nullptr;
+        *slot = nullptr;
         c->err = std::string("hipGraphInstantiate: ") + hipGetErrorString(e);
         return IBB_EDEVICE;
     }
     return IBB_OK;
+}
+
+// replay a captured iteration and read the squared norm it reduced
+ibb_status replay_norm(ibb_ctx *c, hipGraphExec_t exec, double *rn)
+{
+    HIPCHK(hipGraphLaunch(exec, c->s));
+    double s2;
+    const ibb_status e = fetch_scalar(c, &s2);
+    *rn = sqrt(s2);
+    return e;
 }
 
 // ||b|| over the unknowns of level 0 (FP64)
@@ -834,7 +846,8 @@ void gcr_dot(ibb_ctx *c, bool vel, const VelArr<double> &x, const VelArr<double>
 }
 
 // b - A x for the GCR iterate, its squared norm back on the host
-ibb_status gcr_residual(ibb_ctx *c, bool vel, const GView &g, double *rn)
+// b - A x for the GCR iterate and its squared norm reduced into c->scalar
+void gcr_residual_launch(ibb_ctx *c, bool vel, const GView &g)
 {
     Level &L = c->lv[0];
     View<double> v = view64(L);
@@ -842,8 +855,14 @@ ibb_status gcr_residual(ibb_ctx *c, bool vel, const GView &g, double *rn)
     int np;
     if (vel) np = launch_resid_u<double>(L.g, cview(g.b), g.x, v.cu, mass, cvu, g.r, c->partial, c->s);
     else np = launch_resid_p<double>(L.g, g.b.c[0], g.x.c[0], v.cp, cvp, g.r.c[0], c->partial, c->s);
+    launch_reduce_final(c->partial, np, c->scalar, c->s);
+}
+
+ibb_status gcr_residual(ibb_ctx *c, bool vel, const GView &g, double *rn)
+{
+    gcr_residual_launch(c, vel, g);
     double s2;
-    ibb_status st = read_scalar(c, np, &s2);
+    ibb_status st = fetch_scalar(c, &s2);
     *rn = sqrt(s2);
     return st;
 }
@@ -900,35 +919,47 @@ ibb_status solve_gcr(ibb_ctx *c, bool vel, int max_cycles, int exact, SolveOut *
             if (!(rel == rel) || isinf(rel)) { o->status = IBB_ENUMERIC; break; }
             if (o->cycles >= max_cycles) { o->status = IBB_ENOCONV; break; }
         }
-        const VelArr<double> z = gcr_dir(c, vel, false, j), q = gcr_dir(c, vel, true, j);
-        // z = M r: V-cycles from zero on A z = r in the level-0 arrays
-        for (int a = 0; a < nc; ++a) launch_fill<double>(z.c[a], L0.g.nel, 0.0, c->s);
-        if (!refined) {
-            for (int a = 0; a < nc; ++a) launch_fill<double>(xl.c[a], L0.g.nel, 0.0, c->s);
-            launch_load_unknowns<double>(L0.g, nc, masks, cview(g.r), bl, c->s);
-            vcycle<double>(c, vel, 0);
-            o->vcycles++;
-            launch_load_unknowns<double>(L0.g, nc, masks, cview(xl), z, c->s);
-        } else {
-            for (int a = 0; a < nc; ++a) launch_fill<float>(xl32.c[a], L0.g.nel, 0.0f, c->s);
-            launch_cast_unknowns<double, float>(L0.g, nc, masks, cview(g.r), bl32, c->s);
-            for (int it = 0; it < c->d.inner_cycles; ++it) {
-                vcycle<float>(c, vel, 0);
-                o->vcycles++;
+        // one iteration at window position j, with the fresh residual and its
+        // squared norm reduced into c->scalar
+        auto iteration = [&]() {
+            const VelArr<double> z = gcr_dir(c, vel, false, j), q = gcr_dir(c, vel, true, j);
+            // z = M r: V-cycles from zero on A z = r in the level-0 arrays
+            for (int a = 0; a < nc; ++a) launch_fill<double>(z.c[a], L0.g.nel, 0.0, c->s);
+            if (!refined) {
+                for (int a = 0; a < nc; ++a) launch_fill<double>(xl.c[a], L0.g.nel, 0.0, c->s);
+                launch_load_unknowns<double>(L0.g, nc, masks, cview(g.r), bl, c->s);
+                vcycle<double>(c, vel, 0);
+                launch_load_unknowns<double>(L0.g, nc, masks, cview(xl), z, c->s);
+            } else {
+                for (int a = 0; a < nc; ++a) launch_fill<float>(xl32.c[a], L0.g.nel, 0.0f, c->s);
+                launch_cast_unknowns<double, float>(L0.g, nc, masks, cview(g.r), bl32, c->s);
+                for (int it = 0; it < c->d.inner_cycles; ++it) vcycle<float>(c, vel, 0);
+                launch_add_correction(L0.g, nc, masks, cview(xl32), z, c->s);
             }
-            launch_add_correction(L0.g, nc, masks, cview(xl32), z, c->s);
+            // q = A z, then orthogonal to the stored q_i (modified Gram-Schmidt)
+            launch_apply(L0.g, vel ? 1 : 0, z, v.cp, v.cu, mass, vel ? cvu : cvp, q, c->s);
+            for (int i = 0; i < j; ++i) {
+                const VelArr<double> zi = gcr_dir(c, vel, false, i), qi = gcr_dir(c, vel, true, i);
+                gcr_dot(c, vel, q, qi, SLOT_T);
+                launch_gcr_axpy2(L0.g, vel ? 1 : 0, c->gs + SLOT_T, c->gs + i, cview(qi), cview(zi), q, z, c->s);
+            }
+            gcr_dot(c, vel, q, q, j);
+            gcr_dot(c, vel, g.r, q, SLOT_RQ);
+            launch_gcr_update(L0.g, vel ? 1 : 0, c->gs + SLOT_RQ, c->gs + j, cview(z), g.x, c->s);
+            gcr_residual_launch(c, vel, g);
+        };
+        o->vcycles += refined ? c->d.inner_cycles : 1;
+        if (c->prof) {
+            iteration();
+            double s2;
+            if ((st = fetch_scalar(c, &s2))) return st;
+            rn = sqrt(s2);
+        } else {
+            std::vector<hipGraphExec_t> &gt = c->gtick[vel ? 1 : 0];
+            if ((int)gt.size() < m) gt.assign(m, nullptr);
+            if ((st = ensure_graph(c, &gt[j], iteration))) return st;
+            if ((st = replay_norm(c, gt[j], &rn))) return st;
         }
-        // q = A z, then orthogonal to the stored q_i (modified Gram-Schmidt)
-        launch_apply(L0.g, vel ? 1 : 0, z, v.cp, v.cu, mass, vel ? cvu : cvp, q, c->s);
-        for (int i = 0; i < j; ++i) {
-            const VelArr<double> zi = gcr_dir(c, vel, false, i), qi = gcr_dir(c, vel, true, i);
-            gcr_dot(c, vel, q, qi, SLOT_T);
-            launch_gcr_axpy2(L0.g, vel ? 1 : 0, c->gs + SLOT_T, c->gs + i, cview(qi), cview(zi), q, z, c->s);
-        }
-        gcr_dot(c, vel, q, q, j);
-        gcr_dot(c, vel, g.r, q, SLOT_RQ);
-        launch_gcr_update(L0.g, vel ? 1 : 0, c->gs + SLOT_RQ, c->gs + j, cview(z), g.x, c->s);
-        if ((st = gcr_residual(c, vel, g, &rn))) return st;
         rel = rn / nb;
         o->cycles++;
         j = j + 1 == m ? 0 : j + 1;
@@ -988,7 +1019,7 @@ ibb_status solve(ibb_ctx *c, bool vel, int max_cycles, int exact, SolveOut *o)
     // kernels in the same order as the launches below, so the same bits.
     const bool graph = !c->prof;
     if (graph) {
-        st = ensure_tick(c, vel, [&]() {
+        st = ensure_graph(c, &c->tick[vel ? 1 : 0], [&]() {
             one_iteration();
             const int np = residual<double>(c, vel, 0, c->partial);
             launch_reduce_final(c->partial, np, c->scalar, c->s);
@@ -1001,11 +1032,7 @@ ibb_status solve(ibb_ctx *c, bool vel, int max_cycles, int exact, SolveOut *o)
             one_iteration();
             return resid_norm(c, vel, r);
         }
-        HIPCHK(hipGraphLaunch(c->tick[vel ? 1 : 0], c->s));
-        double s2;
-        const ibb_status e = fetch_scalar(c, &s2);
-        *r = sqrt(s2);
-        return e;
+        return replay_norm(c, c->tick[vel ? 1 : 0], r);
     };
     if ((st = resid_norm(c, vel, &rn))) return st;
     double rel = rn / nb;
@@ -1417,6 +1444,9 @@ ibb_status ibb_destroy(ibb_ctx *c)
         if (e) (void)hipEventDestroy(e);
     for (auto &g : c->tick)
         if (g) (void)hipGraphExecDestroy(g);
+    for (auto &v : c->gtick)
+        for (auto &g : v)
+            if (g) (void)hipGraphExecDestroy(g);
     if (c->cap) (void)hipStreamDestroy(c->cap);
     delete c;
     return IBB_OK;

@@ -1,7 +1,8 @@
 """Solver iterations replayed as HIP graphs (the default) against the same
 iterations launched one kernel at a time (the path taken while kernel timing
 is on): identical bits and cycle counts over several steps, with the step's
-own eager work and synchronisations between the replays."""
+own eager work and synchronisations between the replays.  Covers plain
+V-cycles, refined outer iterations and GCR windows."""
 import numpy as np
 import pytest
 
@@ -27,6 +28,12 @@ CASES = {
     "3d_tube_one_launch_sweep": lambda: dict(synth.tiny_3d(seed=6),
                                              params=dict(synth.tiny_3d(seed=6)["params"], smoother_passes=1,
                                                          wg_coarse_max=8)),
+    # GCR with a short restart window: every window position has its own
+    # graph, and each is replayed several times within a solve
+    "3d_tube_gcr3": lambda: dict(synth.tiny_3d(seed=7),
+                                 params=dict(synth.tiny_3d(seed=7)["params"], mu_max=1e3, krylov_restart=3)),
+    "channel2d_gcr8": lambda: dict(synth.channel_2d(seed=1),
+                                   params=dict(synth.channel_2d(seed=1)["params"], krylov_restart=8)),
 }
 
 
