@@ -869,17 +869,32 @@ ibb_status gcr_residual(ibb_ctx *c, bool vel, const GView &g, double *rn)
 
 // V-cycle-preconditioned GCR(m) on the finest level (b and x in the level-0
 // arrays on entry; x there on return).  Same stopping test as the V-cycle
-// loop below; exact > 0 runs exactly that many iterations.
-ibb_status solve_gcr(ibb_ctx *c, bool vel, int max_cycles, int exact, SolveOut *o)
+// loop below; exact > 0 runs exactly that many iterations.  The solve is cut
+// into resumable pieces so that a group can advance several such solves in
+// lock step, each on its own stream: begin, then while more: launch, the
+// norm back on the host, account; then finish.
+struct GcrRun {
+    ibb_ctx *c = nullptr;
+    bool vel = false;
+    int max_cycles = 0, exact = 0;
+    SolveOut *o = nullptr;
+    double nb = 0.0, rel = 0.0;
+    int j = 0;          // position in the restart window
+    bool done = false;  // stopping test met (or nothing to solve)
+};
+
+// one iteration at window position j: z = M r, q = A z made orthogonal to
+// the stored q_i, x += alpha z, then the fresh residual with its squared
+// norm reduced into c->scalar (kernels only)
+void gcr_iteration_launches(ibb_ctx *c, bool vel, int j)
 {
     const bool refined = c->d.precision == IBB_FP32_REFINED;
     const int m = c->d.krylov_restart;
-    const int D = c->d.dim;
     int vm[3];
-    vel_masks(D, vm);
+    vel_masks(c->d.dim, vm);
     const int pm[3] = {0, 0, 0};
     const int *masks = vel ? vm : pm;
-    const int nc = vel ? D : 1;
+    const int nc = vel ? c->d.dim : 1;
     Level &L0 = c->lv[0];
     View<double> v = view64(L0);
     View<float> w = view32(L0);
@@ -889,17 +904,62 @@ ibb_status solve_gcr(ibb_ctx *c, bool vel, int max_cycles, int exact, SolveOut *
     VelArr<float> xl32 = vel ? w.xu : VelArr<float>{{w.xp, nullptr, nullptr}};
     const GView g = gcr_view(c, vel);
     const double cvp = 1.0 / (L0.g.h * L0.g.h), cvu = L0.cvu, mass = c->d.sigma / c->d.dt;
-    double nb;
-    ibb_status st = norm_b(c, vel, &nb);
+    const int SLOT_T = m, SLOT_RQ = m + 1;
+    const VelArr<double> z = gcr_dir(c, vel, false, j), q = gcr_dir(c, vel, true, j);
+    // z = M r: V-cycles from zero on A z = r in the level-0 arrays
+    for (int a = 0; a < nc; ++a) launch_fill<double>(z.c[a], L0.g.nel, 0.0, c->s);
+    if (!refined) {
+        for (int a = 0; a < nc; ++a) launch_fill<double>(xl.c[a], L0.g.nel, 0.0, c->s);
+        launch_load_unknowns<double>(L0.g, nc, masks, cview(g.r), bl, c->s);
+        vcycle<double>(c, vel, 0);
+        launch_load_unknowns<double>(L0.g, nc, masks, cview(xl), z, c->s);
+    } else {
+        for (int a = 0; a < nc; ++a) launch_fill<float>(xl32.c[a], L0.g.nel, 0.0f, c->s);
+        launch_cast_unknowns<double, float>(L0.g, nc, masks, cview(g.r), bl32, c->s);
+        for (int it = 0; it < c->d.inner_cycles; ++it) vcycle<float>(c, vel, 0);
+        launch_add_correction(L0.g, nc, masks, cview(xl32), z, c->s);
+    }
+    // q = A z, then orthogonal to the stored q_i (modified Gram-Schmidt)
+    launch_apply(L0.g, vel ? 1 : 0, z, v.cp, v.cu, mass, vel ? cvu : cvp, q, c->s);
+    for (int i = 0; i < j; ++i) {
+        const VelArr<double> zi = gcr_dir(c, vel, false, i), qi = gcr_dir(c, vel, true, i);
+        gcr_dot(c, vel, q, qi, SLOT_T);
+        launch_gcr_axpy2(L0.g, vel ? 1 : 0, c->gs + SLOT_T, c->gs + i, cview(qi), cview(zi), q, z, c->s);
+    }
+    gcr_dot(c, vel, q, q, j);
+    gcr_dot(c, vel, g.r, q, SLOT_RQ);
+    launch_gcr_update(L0.g, vel ? 1 : 0, c->gs + SLOT_RQ, c->gs + j, cview(z), g.x, c->s);
+    gcr_residual_launch(c, vel, g);
+}
+
+// ||b||, the solve's own copies of b and x, the first residual (syncs c->s)
+ibb_status gcr_begin(GcrRun &R)
+{
+    ibb_ctx *c = R.c;
+    const bool vel = R.vel;
+    int vm[3];
+    vel_masks(c->d.dim, vm);
+    const int pm[3] = {0, 0, 0};
+    const int *masks = vel ? vm : pm;
+    const int nc = vel ? c->d.dim : 1;
+    Level &L0 = c->lv[0];
+    View<double> v = view64(L0);
+    VelArr<double> bl = vel ? v.bu : VelArr<double>{{v.bp, nullptr, nullptr}};
+    VelArr<double> xl = vel ? v.xu : VelArr<double>{{v.xp, nullptr, nullptr}};
+    const GView g = gcr_view(c, vel);
+    ibb_status st = norm_b(c, vel, &R.nb);
     if (st) return st;
-    o->cycles = o->vcycles = 0;
-    o->relres = 0.0;
-    o->status = IBB_OK;
-    if (nb == 0.0) {
+    R.o->cycles = R.o->vcycles = 0;
+    R.o->relres = 0.0;
+    R.o->status = IBB_OK;
+    R.j = 0;
+    R.rel = 0.0;
+    R.done = false;
+    if (R.nb == 0.0) {
         zero_unknowns(c, vel);
+        R.done = true;
         return IBB_OK;
     }
-    // the solve's own copies of b and of the iterate (with ghost images)
     for (int a = 0; a < nc; ++a) {
         launch_fill<double>(g.b.c[a], L0.g.nel, 0.0, c->s);
         launch_fill<double>(g.x.c[a], L0.g.nel, 0.0, c->s);
@@ -908,66 +968,94 @@ ibb_status solve_gcr(ibb_ctx *c, bool vel, int max_cycles, int exact, SolveOut *
     launch_load_unknowns<double>(L0.g, nc, masks, cview(xl), g.x, c->s);
     double rn;
     if ((st = gcr_residual(c, vel, g, &rn))) return st;
-    double rel = rn / nb;
-    int j = 0;
-    const int SLOT_T = m, SLOT_RQ = m + 1;
-    for (;;) {
-        if (exact > 0) {
-            if (o->cycles >= exact) break;
-        } else {
-            if (rel <= c->d.rtol) break;
-            if (!(rel == rel) || isinf(rel)) { o->status = IBB_ENUMERIC; break; }
-            if (o->cycles >= max_cycles) { o->status = IBB_ENOCONV; break; }
-        }
-        // one iteration at window position j, with the fresh residual and its
-        // squared norm reduced into c->scalar
-        auto iteration = [&]() {
-            const VelArr<double> z = gcr_dir(c, vel, false, j), q = gcr_dir(c, vel, true, j);
-            // z = M r: V-cycles from zero on A z = r in the level-0 arrays
-            for (int a = 0; a < nc; ++a) launch_fill<double>(z.c[a], L0.g.nel, 0.0, c->s);
-            if (!refined) {
-                for (int a = 0; a < nc; ++a) launch_fill<double>(xl.c[a], L0.g.nel, 0.0, c->s);
-                launch_load_unknowns<double>(L0.g, nc, masks, cview(g.r), bl, c->s);
-                vcycle<double>(c, vel, 0);
-                launch_load_unknowns<double>(L0.g, nc, masks, cview(xl), z, c->s);
-            } else {
-                for (int a = 0; a < nc; ++a) launch_fill<float>(xl32.c[a], L0.g.nel, 0.0f, c->s);
-                launch_cast_unknowns<double, float>(L0.g, nc, masks, cview(g.r), bl32, c->s);
-                for (int it = 0; it < c->d.inner_cycles; ++it) vcycle<float>(c, vel, 0);
-                launch_add_correction(L0.g, nc, masks, cview(xl32), z, c->s);
-            }
-            // q = A z, then orthogonal to the stored q_i (modified Gram-Schmidt)
-            launch_apply(L0.g, vel ? 1 : 0, z, v.cp, v.cu, mass, vel ? cvu : cvp, q, c->s);
-            for (int i = 0; i < j; ++i) {
-                const VelArr<double> zi = gcr_dir(c, vel, false, i), qi = gcr_dir(c, vel, true, i);
-                gcr_dot(c, vel, q, qi, SLOT_T);
-                launch_gcr_axpy2(L0.g, vel ? 1 : 0, c->gs + SLOT_T, c->gs + i, cview(qi), cview(zi), q, z, c->s);
-            }
-            gcr_dot(c, vel, q, q, j);
-            gcr_dot(c, vel, g.r, q, SLOT_RQ);
-            launch_gcr_update(L0.g, vel ? 1 : 0, c->gs + SLOT_RQ, c->gs + j, cview(z), g.x, c->s);
-            gcr_residual_launch(c, vel, g);
-        };
-        o->vcycles += refined ? c->d.inner_cycles : 1;
-        if (c->prof) {
-            iteration();
-            double s2;
-            if ((st = fetch_scalar(c, &s2))) return st;
-            rn = sqrt(s2);
-        } else {
-            std::vector<hipGraphExec_t> &gt = c->gtick[vel ? 1 : 0];
-            if ((int)gt.size() < m) gt.assign(m, nullptr);
-            if ((st = ensure_graph(c, &gt[j], iteration))) return st;
-            if ((st = replay_norm(c, gt[j], &rn))) return st;
-        }
-        rel = rn / nb;
-        o->cycles++;
-        j = j + 1 == m ? 0 : j + 1;
+    R.rel = rn / R.nb;
+    return IBB_OK;
+}
+
+// whether another iteration is due (the stopping test; records the outcome)
+bool gcr_more(GcrRun &R)
+{
+    if (R.done) return false;
+    SolveOut *o = R.o;
+    if (R.exact > 0) {
+        if (o->cycles >= R.exact) R.done = true;
+    } else if (R.rel <= R.c->d.rtol) {
+        R.done = true;
+    } else if (!(R.rel == R.rel) || isinf(R.rel)) {
+        o->status = IBB_ENUMERIC;
+        R.done = true;
+    } else if (o->cycles >= R.max_cycles) {
+        o->status = IBB_ENOCONV;
+        R.done = true;
     }
-    // the iterate back into the level-0 arrays, b restored
+    return !R.done;
+}
+
+// launch the next iteration on c->s: a graph replay (captured once per
+// window position), or kernel by kernel while kernel timing is on
+ibb_status gcr_launch(GcrRun &R)
+{
+    ibb_ctx *c = R.c;
+    const bool vel = R.vel;
+    const int j = R.j;
+    R.o->vcycles += c->d.precision == IBB_FP32_REFINED ? c->d.inner_cycles : 1;
+    if (c->prof) {
+        gcr_iteration_launches(c, vel, j);
+        return IBB_OK;
+    }
+    std::vector<hipGraphExec_t> &gt = c->gtick[vel ? 1 : 0];
+    if ((int)gt.size() < c->d.krylov_restart) gt.assign(c->d.krylov_restart, nullptr);
+    ibb_status st = ensure_graph(c, &gt[j], [&]() { gcr_iteration_launches(c, vel, j); });
+    if (st) return st;
+    HIPCHK(hipGraphLaunch(gt[j], c->s));
+    return IBB_OK;
+}
+
+void gcr_account(GcrRun &R, double rn)
+{
+    R.rel = rn / R.nb;
+    R.o->cycles++;
+    R.j = R.j + 1 == R.c->d.krylov_restart ? 0 : R.j + 1;
+}
+
+// the iterate back into the level-0 arrays, b restored
+void gcr_finish(GcrRun &R)
+{
+    ibb_ctx *c = R.c;
+    const bool vel = R.vel;
+    R.o->relres = R.rel;
+    if (R.nb == 0.0) return;
+    int vm[3];
+    vel_masks(c->d.dim, vm);
+    const int pm[3] = {0, 0, 0};
+    const int *masks = vel ? vm : pm;
+    const int nc = vel ? c->d.dim : 1;
+    Level &L0 = c->lv[0];
+    View<double> v = view64(L0);
+    VelArr<double> bl = vel ? v.bu : VelArr<double>{{v.bp, nullptr, nullptr}};
+    VelArr<double> xl = vel ? v.xu : VelArr<double>{{v.xp, nullptr, nullptr}};
+    const GView g = gcr_view(c, vel);
     launch_load_unknowns<double>(L0.g, nc, masks, cview(g.x), xl, c->s);
     launch_load_unknowns<double>(L0.g, nc, masks, cview(g.b), bl, c->s);
-    o->relres = rel;
+}
+
+ibb_status solve_gcr(ibb_ctx *c, bool vel, int max_cycles, int exact, SolveOut *o)
+{
+    GcrRun R;
+    R.c = c;
+    R.vel = vel;
+    R.max_cycles = max_cycles;
+    R.exact = exact;
+    R.o = o;
+    ibb_status st = gcr_begin(R);
+    if (st) return st;
+    while (gcr_more(R)) {
+        if ((st = gcr_launch(R))) return st;
+        double s2;
+        if ((st = fetch_scalar(c, &s2))) return st;
+        gcr_account(R, sqrt(s2));
+    }
+    gcr_finish(R);
     return IBB_OK;
 }
 
@@ -1825,6 +1913,10 @@ struct ibb_group {
     hipGraphExec_t exec[2] = {};
     std::vector<int> hflags, dflags;   // wanted flags, flags on the device
     hipEvent_t ev[5] = {};
+    // side streams (default priority) for members solved by GCR, which
+    // advance in lock step with the shared ticks, and one event each
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> sev;
     std::string err;
 };
 
@@ -2050,7 +2142,12 @@ ibb_status group_norms(ibb_group *g, bool vel, bool resid, const std::vector<cha
 }
 
 // the members' solves of one system, ticked together; each member follows
-// exactly the sequence of its own solve (same stopping test, same passes)
+// exactly the sequence of its own solve (same stopping test, same passes).
+// Members solved by GCR run their own iterations, each on a side stream, in
+// lock step with the shared ticks: one round launches every active member's
+// next iteration and reads all norms back at once.
+constexpr int GROUP_SIDE_STREAMS = 4;
+
 ibb_status group_solve(ibb_group *g, bool vel, GroupSolve &R)
 {
     const int n = (int)g->m.size();
@@ -2060,14 +2157,37 @@ ibb_status group_solve(ibb_group *g, bool vel, GroupSolve &R)
     R.done.assign(n, 0);
     std::vector<double> h;
     ibb_status st;
-    // members solved by GCR run their own solve (not batched); their flags
-    // stay clear in the captured ticks
-    for (int i = 0; i < n; ++i) {
-        ibb_ctx *c = g->m[i];
-        if (c->d.krylov_restart <= 0) continue;
-        if ((st = solve_gcr(c, vel, c->d.max_cycles, 0, &R.out[i]))) return st;
-        R.done[i] = 1;
-        R.rel[i] = R.out[i].relres;
+    // GCR members: their flags stay clear in the captured ticks
+    std::vector<GcrRun> gr(n);
+    std::vector<int> side(n, -1);
+    int ngcr = 0;
+    for (int i = 0; i < n; ++i)
+        if (g->m[i]->d.krylov_restart > 0) side[i] = ngcr++ % GROUP_SIDE_STREAMS;
+    const int nside = ngcr < GROUP_SIDE_STREAMS ? ngcr : GROUP_SIDE_STREAMS;
+    while ((int)g->side.size() < nside) {
+        hipStream_t sd;
+        hipEvent_t ev;
+        GCHK(hipStreamCreateWithFlags(&sd, hipStreamNonBlocking));
+        g->side.push_back(sd);
+        GCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        g->sev.push_back(ev);
+    }
+    if (ngcr) {
+        // the side streams start after the group stream's work so far
+        GCHK(hipEventRecord(g->ev[4], g->s));
+        for (int k = 0; k < nside; ++k) GCHK(hipStreamWaitEvent(g->side[k], g->ev[4], 0));
+        for (int i = 0; i < n; ++i) {
+            if (side[i] < 0) continue;
+            ibb_ctx *c = g->m[i];
+            c->s = g->side[side[i]];
+            gr[i].c = c;
+            gr[i].vel = vel;
+            gr[i].max_cycles = c->d.max_cycles;
+            gr[i].exact = 0;
+            gr[i].o = &R.out[i];
+            if ((st = gcr_begin(gr[i]))) return st;
+            R.done[i] = 1;
+        }
     }
     if ((st = group_norms(g, vel, false, R.done, h))) return st;
     for (int i = 0; i < n; ++i) {
@@ -2081,10 +2201,19 @@ ibb_status group_solve(ibb_group *g, bool vel, GroupSolve &R)
     if ((st = group_norms(g, vel, true, R.done, h))) return st;
     for (int i = 0; i < n; ++i)
         if (!R.done[i]) R.rel[i] = sqrt(h[i]) / R.nb[i];
+    std::vector<char> ran(n, 0);
     for (;;) {
-        bool any = false;
+        bool any = false, anyg = false;
         for (int i = 0; i < n; ++i) {
             g->hflags[i] = 0;
+            ran[i] = 0;
+            if (side[i] >= 0) {
+                if (gcr_more(gr[i])) {
+                    ran[i] = 1;
+                    anyg = true;
+                }
+                continue;
+            }
             if (R.done[i]) continue;
             const double rel = R.rel[i];
             ibb_ctx *c = g->m[i];
@@ -2094,23 +2223,54 @@ ibb_status group_solve(ibb_group *g, bool vel, GroupSolve &R)
             g->hflags[i] = 1;
             any = true;
         }
-        if (!any) break;
-        if (g->hflags != g->dflags) {
-            GCHK(hipMemcpyAsync(g->flags, g->hflags.data(), n * sizeof(int), hipMemcpyHostToDevice, g->s));
-            g->dflags = g->hflags;
+        if (!any && !anyg) break;
+        if (any) {
+            if (g->hflags != g->dflags) {
+                GCHK(hipMemcpyAsync(g->flags, g->hflags.data(), n * sizeof(int), hipMemcpyHostToDevice, g->s));
+                g->dflags = g->hflags;
+            }
+            GCHK(hipGraphLaunch(g->exec[vel ? 1 : 0], g->s));
         }
-        GCHK(hipGraphLaunch(g->exec[vel ? 1 : 0], g->s));
+        if (anyg) {
+            for (int i = 0; i < n; ++i) {
+                if (!ran[i]) continue;
+                ibb_ctx *c = g->m[i];
+                if ((st = gcr_launch(gr[i]))) return st;
+                GCHK(hipMemcpyAsync(g->norms + i, c->scalar, sizeof(double), hipMemcpyDeviceToDevice, c->s));
+            }
+            for (int k = 0; k < nside; ++k) {
+                GCHK(hipEventRecord(g->sev[k], g->side[k]));
+                GCHK(hipStreamWaitEvent(g->s, g->sev[k], 0));
+            }
+        }
         h.assign(n, 0.0);
         GCHK(hipMemcpyAsync(h.data(), g->norms, n * sizeof(double), hipMemcpyDeviceToHost, g->s));
         GCHK(hipStreamSynchronize(g->s));
         for (int i = 0; i < n; ++i) {
+            if (ran[i]) {
+                gcr_account(gr[i], sqrt(h[i]));
+                continue;
+            }
             if (!g->hflags[i]) continue;
             R.out[i].cycles++;
             R.out[i].vcycles += g->refined ? g->inner : 1;
             R.rel[i] = sqrt(h[i]) / R.nb[i];
         }
     }
-    for (int i = 0; i < n; ++i) R.out[i].relres = R.rel[i];
+    if (ngcr) {
+        for (int i = 0; i < n; ++i) {
+            if (side[i] < 0) continue;
+            gcr_finish(gr[i]);
+            R.rel[i] = gr[i].rel;
+            g->m[i]->s = g->s;
+        }
+        for (int k = 0; k < nside; ++k) {
+            GCHK(hipEventRecord(g->sev[k], g->side[k]));
+            GCHK(hipStreamWaitEvent(g->s, g->sev[k], 0));
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        if (side[i] < 0) R.out[i].relres = R.rel[i];
     return IBB_OK;
 }
 
@@ -2245,6 +2405,12 @@ ibb_status ibb_group_destroy(ibb_group *g)
     for (int v = 0; v < 2; ++v)
         if (g->exec[v]) (void)hipGraphExecDestroy(g->exec[v]);
     for (hipEvent_t &e : g->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (hipStream_t sd : g->side) {
+        (void)hipStreamSynchronize(sd);
+        (void)hipStreamDestroy(sd);
+    }
+    for (hipEvent_t e : g->sev)
         if (e) (void)hipEventDestroy(e);
     if (g->s) (void)hipStreamDestroy(g->s);
     delete g;
