@@ -102,6 +102,34 @@ def poisson_disc(rng, inside, lo, hi, rmin, limit, seed_point, k=30):
     return P[:n].T.copy()
 
 
+def poisson_disc_batched(rng, inside, lo, hi, rmin, limit, batch=400000, max_rounds=400):
+    """Random sequential addition in batches (for large node counts): each
+    round draws uniform candidates in the box, keeps those inside the region
+    and at least rmin from every accepted point, drops the later one of every
+    pair of candidates closer than rmin, and accepts the rest; stops at
+    `limit` points or after max_rounds.  Points end up at least rmin apart."""
+    from scipy.spatial import cKDTree
+    lo, hi = np.asarray(lo, float), np.asarray(hi, float)
+    D = lo.size
+    acc = np.empty((0, D))
+    for _ in range(max_rounds):
+        if len(acc) >= limit:
+            break
+        cand = lo + (hi - lo) * rng.random((batch, D))
+        cand = cand[inside(cand)]
+        if len(acc) and len(cand):
+            d, _ = cKDTree(acc).query(cand, k=1, distance_upper_bound=rmin)
+            cand = cand[~(d < rmin)]
+        if len(cand) > 1:
+            pairs = cKDTree(cand).query_pairs(rmin, output_type="ndarray")
+            if len(pairs):
+                keep = np.ones(len(cand), bool)
+                keep[pairs.max(axis=1)] = False
+                cand = cand[keep]
+        acc = np.vstack([acc, cand[:limit - len(acc)]])
+    return acc.T.copy()
+
+
 def spring_pairs(X, cutoff):
     """All node pairs closer than cutoff (strictly), as int32 [2][m], i < j."""
     from scipy.spatial import cKDTree
@@ -321,6 +349,58 @@ def tiny_3d(seed=12, n=(8, 8, 16), eta=20, periodic_z=False):
     return out
 
 
+def rough_thickness(rng, modes, mean, amp, Lx, Lz):
+    """Film thickness mean * (1 + amp * xi(x, z)) with xi a sum of `modes`
+    random Fourier modes (integer wavenumbers up to 4 across the wall, random
+    phases and weights), scaled so that max |xi| = 1 on a fine sample."""
+    kx = rng.integers(0, 5, size=modes)
+    kz = rng.integers(1, 9, size=modes)
+    ph = rng.uniform(0.0, 2.0 * math.pi, size=modes)
+    wt = rng.uniform(0.5, 1.0, size=modes)
+
+    def raw(x, z):
+        v = np.zeros(np.broadcast(x, z).shape)
+        for a, b, c, w in zip(kx, kz, ph, wt):
+            v += w * np.cos(2.0 * math.pi * (a * x / Lx + b * z / Lz) + c)
+        return v
+    xs = np.linspace(0.0, Lx, 257)
+    zs = np.linspace(0.0, Lz, 513)
+    scale = np.max(np.abs(raw(xs[None, :], zs[:, None])))
+
+    def thickness(x, z):
+        return mean * (1.0 + amp * raw(x, z) / scale)
+    return thickness
+
+
+def film_3d(seed=5, n=(256, 256, 512), eta=200000, spacing=0.008, rho_b=0.3, mu_max=1e3, omega=0.01,
+            gamma_2h=0.7):
+    """3D tube (walls in x and y, laminar inflow at z = 0, free outflow) with
+    a rough biofilm film on the bottom wall y = 0: thickness 20 h (1 + xi / 2)
+    with xi an 8-mode random Fourier field in [-1, 1], Poisson-disc nodes at
+    the given spacing filling it, springs within 2.5 spacings, fragments
+    tracked."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n[0]
+    p = base_params(3, list(n), [AX_WALLS, AX_WALLS, AX_INOUT], h)
+    p.update(rho_b=rho_b, mu_max=mu_max, omega=omega, break_ratio=2.0, attach_dist=spacing, track_fragments=1)
+    p["gamma"] = [1.0, gamma_2h] + [1.0] * 14
+    Lz = n[2] * h
+    top = rough_thickness(rng, 8, 20.0 * h, 0.5, 1.0, Lz)
+
+    def inside(P):
+        return (P[:, 1] >= 0.0) & (P[:, 1] <= top(P[:, 0], P[:, 2]))
+    X = poisson_disc_batched(rng, inside, [0.0, 0.0, 0.0], [1.0, 1.5 * 20.0 * h, Lz], spacing, eta)
+    ij = spring_pairs(X, 2.5 * spacing)
+    K = np.full(ij.shape[1], 1e2)
+    xs = (np.arange(512) + 0.5) / 512
+    zs = (np.arange(1024) + 0.5) * (Lz / 1024)
+    film = float(np.mean(top(xs[None, :], zs[:, None])) * Lz)
+    out = _finish(p, X, ij, K, film * min(1.0, X.shape[1] / eta), rng)
+    out["seed"] = seed
+    out["film_volume"] = film
+    return out
+
+
 # --------------------------------------------------------------------------
 # serving stream
 # --------------------------------------------------------------------------
@@ -394,4 +474,5 @@ WORKLOADS = {
     "tube3d_64x64x128": lambda: tube_3d(seed=2, gamma_2h=0.7),
     "tube3d_128x128x256": lambda: tube_3d(seed=3, n=(128, 128, 256), eta=50000, mounds=3, rho_b=0.2,
                                           mu_max=1e3, K_range=(1e1, 1e3), H=0.62, s=0.31, nu=(3, 3), gamma_2h=0.7),
+    "film3d_256x256x512": lambda: film_3d(),
 }

@@ -120,3 +120,79 @@ def test_full_size_step(name, precision):
     assert s["cycles_u"] == info["cycles"] and s["cycles_p"] == pinfo["cycles"]
     assert rel(u_step, u_g) < 1e-12
     ctx.close()
+
+
+def test_film_full_size_sampled():
+    """The rough film (256 x 256 x 512, 200 000 nodes, viscosity ratio 1e3,
+    refined) at full size, checked on samples and through properties:
+    - density and viscosity at 3 000 sampled lattice points against the
+      paper's formulas (eq:discrDensCouple, eq:ViscExp) summed here over the
+      nodes near each point with the oracle's phi;
+    - the viscous solve's residual under the oracle's FP64 operator, applied
+      to the GPU's full field with the GPU's (sampled-checked) coefficients;
+    - the pressure solve through the projection identity, as above."""
+    from scipy.spatial import cKDTree
+    from paper_1302_3663_amd import ibmg
+    case = workload_case("film3d_256x256x512")
+    p = case["params"]
+    h, om, D = p["h"], p["omega"], 3
+    print("film: context", flush=True)
+    ctx = ibmg.from_case(case, precision=L.IBB_FP32_REFINED, inner_cycles=2)
+    _, rho, mc, _ = [None if t is None else host(t) for t in ctx.get_fields(0)]
+    X = case["X"].T
+    tree = cKDTree(X)
+    rng = np.random.default_rng(3)
+    reach = 2.0 * om * np.sqrt(3.0) + 1e-12
+
+    def weights(pts):
+        out = []
+        for q, nb in zip(pts, tree.query_ball_point(pts, reach)):
+            nb = np.asarray(nb, int)
+            w = np.ones(len(nb))
+            for d in range(D):
+                w *= O.phi(p["kernel"], (q[d] - X[nb, d]) / om) / om
+            out.append(w)
+        return out
+    # y-faces (normal to the wall) near the film: x = (i + 1/2) h, y = j h, z = (k + 1/2) h
+    n = p["n"]
+    nfx = (n[0] + 1) * n[1] * n[2]
+    ii = rng.integers(0, n[0], 1500)
+    jj = rng.integers(1, 40, 1500)
+    kk = rng.integers(0, n[2], 1500)
+    pts = np.stack([(ii + 0.5) * h, jj * h, (kk + 0.5) * h], axis=1)
+    got = rho[nfx + (kk * (n[1] + 1) + jj) * n[0] + ii]
+    want = np.array([p["rho0"] + p["rho_b"] * p["d0_pow_d"] * w.sum() for w in weights(pts)])
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(want)
+    assert np.max(want) > p["rho0"] * 1.01
+    # cell centres
+    ii = rng.integers(0, n[0], 1500)
+    jj = rng.integers(0, 40, 1500)
+    kk = rng.integers(0, n[2], 1500)
+    pts = np.stack([(ii + 0.5) * h, (jj + 0.5) * h, (kk + 0.5) * h], axis=1)
+    got = mc[(kk * n[1] + jj) * n[0] + ii]
+    sc = (2.0 * om) ** D * (p["mu_max"] - p["mu_out"])
+    want = np.array([max(p["mu_out"], (sc * w + p["mu_out"]).max()) if len(w) else p["mu_out"]
+                     for w in weights(pts)])
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(want)
+    assert np.max(want) > 10 * p["mu_out"]
+    # one step's solves, checked under the oracle's operators
+    print("film: solves", flush=True)
+    b = host(ctx.momentum_rhs())
+    ut, info = ctx.mg_solve(1, dev(b), dev(case["u0"]))
+    ut = host(ut)
+    assert info["relres"] <= 1e-10
+    _, _, mc_g, me_g = [None if t is None else host(t) for t in ctx.get_fields(0)]
+    unk = unknown_mask(p, ut.size)
+    b_without = b - (O.momentum_rhs(p, case["u0"], rho, mc_g, me_g, np.zeros_like(b)) -
+                     O.momentum_rhs(p, case["u0"], rho, mc_g, me_g, np.zeros_like(b), with_boundary=False))
+    r = (b_without - O.momentum_apply_full(p, ut, rho, mc_g, me_g))[unk]
+    assert np.linalg.norm(r) / np.linalg.norm(b[unk]) <= 1e-10 * (1 + 1e-6)
+    bp = host(ctx.pressure_rhs(dev(ut)))
+    assert rel(bp, O.pressure_rhs(p, ut)) < 1e-12
+    pres, pinfo = ctx.mg_solve(0, dev(bp), dev(np.zeros(ctx.n_cell)))
+    pres = host(pres)
+    assert pinfo["relres"] <= 1e-10
+    u_o = O.project(p, ut, pres, rho)
+    c = p["eps"] * p["dt"] / p["sigma"]
+    assert np.linalg.norm(O.divergence(p, u_o)) / c / np.linalg.norm(bp) <= 1e-10 * (1 + 1e-6)
+    ctx.close()
