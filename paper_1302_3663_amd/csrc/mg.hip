@@ -447,15 +447,36 @@ static PBox smoother_pbox(const Grid &g, int vmask, bool velocity, bool colour)
 }
 
 // ---------------------------------------------------------------------------
+// Workgroups go to the chip's 8 XCDs in turn (workgroup b to XCD b mod 8),
+// and each XCD has its own L2.  Renumbered so that each XCD works through one
+// contiguous range of the index space, the rows and planes that neighbouring
+// points share stay in one L2.  A bijection of [0, gridDim.x); remap = 0
+// keeps the hardware order.  Measured on the smoothers: 10% faster on arrays
+// of 4.4 M entries, 5-7% slower on 34.5 M, where a plane's reuse window no
+// longer fits an XCD's L2 and the shared last-level cache did better with
+// every XCD on neighbouring rows; hence the size limit below.
+// ---------------------------------------------------------------------------
+constexpr long long XCD_REMAP_MAX_NEL = 16ll << 20;
+
+__device__ inline unsigned xcd_block(int remap)
+{
+    constexpr unsigned NXCD = 8;
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    if (!remap) return b;
+    const unsigned q = nb / NXCD, r = nb % NXCD, x = b % NXCD;
+    return x * q + (x < r ? x : r) + b / NXCD;
+}
+
+// ---------------------------------------------------------------------------
 // smoothers: one colour of one component; the updated value is also written
 // to its ghost images so that later passes read it at fixed offsets
 // ---------------------------------------------------------------------------
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_smooth_p(Grid g, Box box, const T *__restrict__ b, T *x, CoefP<T> cf, T cvisc,
-                                                  int colour)
+                                                  int colour, int remap)
 {
     int i, j, k;
-    if (!box_colour_pos(box, colour, blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
+    if (!box_colour_pos(box, colour, xcd_block(remap) * blockDim.x + threadIdx.x, i, j, k)) return;
     T Ax, dg;
     p_row<T, D>(g, x, cf, cvisc, i, j, k, Ax, dg);
     const long long c = at(g, i, j, k);
@@ -466,10 +487,10 @@ __global__ void __launch_bounds__(256) k_smooth_p(Grid g, Box box, const T *__re
 
 template <typename T, int D, int A>
 __global__ void __launch_bounds__(256) k_smooth_u(Grid g, Box box, const T *__restrict__ b, VelArr<T> x, CoefU<T> cf,
-                                                  T mass, T cvisc, int colour)
+                                                  T mass, T cvisc, int colour, int remap)
 {
     int i, j, k;
-    if (!box_colour_pos(box, colour, blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
+    if (!box_colour_pos(box, colour, xcd_block(remap) * blockDim.x + threadIdx.x, i, j, k)) return;
     T Ax, dg;
     u_row<T, D, A>(g, x, cf, mass, cvisc, i, j, k, Ax, dg);
     const long long f = at(g, i, j, k);
@@ -483,11 +504,11 @@ __global__ void __launch_bounds__(256) k_smooth_u(Grid g, Box box, const T *__re
 // components one after another.  blockIdx.y is the component.
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_smooth_u_dec(Grid g, VelBox boxes, VelArrC<T> b, VelArr<T> x, CoefU<T> cf,
-                                                      T mass, T cvisc, int colour)
+                                                      T mass, T cvisc, int colour, int remap)
 {
     const int a = blockIdx.y;
     int i, j, k;
-    if (!box_colour_pos(boxes.b[a], colour, blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
+    if (!box_colour_pos(boxes.b[a], colour, xcd_block(remap) * blockDim.x + threadIdx.x, i, j, k)) return;
     T Ax, dg;
     if (a == 0) u_row_dec<T, D, 0>(g, x.c[0], cf.rho[0], mass, cvisc, i, j, k, Ax, dg);
     else if (a == 1) u_row_dec<T, D, 1>(g, x.c[1], cf.rho[1], mass, cvisc, i, j, k, Ax, dg);
@@ -1786,10 +1807,11 @@ void launch_smooth_p(const Grid &g, const T *b, T *x, const CoefP<T> &cf, T cvis
     const Box P = unk_box(g, 0);
     const long long n = (long long)((P.ext[0] + 1) / 2) * P.ext[1] * P.ext[2];
     if (n <= 0) return;
+    const int remap = g.nel <= XCD_REMAP_MAX_NEL;
     if (g.D == 3)
-        launch_timed(k_smooth_p<T, 3>, dim3(blocks_for(n)), dim3(256), s, g, P, b, x, cf, cvisc, colour);
+        launch_timed(k_smooth_p<T, 3>, dim3(blocks_for(n)), dim3(256), s, g, P, b, x, cf, cvisc, colour, remap);
     else
-        launch_timed(k_smooth_p<T, 2>, dim3(blocks_for(n)), dim3(256), s, g, P, b, x, cf, cvisc, colour);
+        launch_timed(k_smooth_p<T, 2>, dim3(blocks_for(n)), dim3(256), s, g, P, b, x, cf, cvisc, colour, remap);
 }
 
 template <typename T>
@@ -1800,13 +1822,14 @@ void launch_smooth_u(const Grid &g, int a, const T *b, const VelArr<T> &x, const
     const long long n = (long long)((P.ext[0] + 1) / 2) * P.ext[1] * P.ext[2];
     if (n <= 0) return;
     const dim3 grid(blocks_for(n)), blk(256);
+    const int remap = g.nel <= XCD_REMAP_MAX_NEL;
     if (g.D == 3) {
-        if (a == 0) launch_timed(k_smooth_u<T, 3, 0>, grid, blk, s, g, P, b, x, cf, mass, cvisc, colour);
-        else if (a == 1) launch_timed(k_smooth_u<T, 3, 1>, grid, blk, s, g, P, b, x, cf, mass, cvisc, colour);
-        else launch_timed(k_smooth_u<T, 3, 2>, grid, blk, s, g, P, b, x, cf, mass, cvisc, colour);
+        if (a == 0) launch_timed(k_smooth_u<T, 3, 0>, grid, blk, s, g, P, b, x, cf, mass, cvisc, colour, remap);
+        else if (a == 1) launch_timed(k_smooth_u<T, 3, 1>, grid, blk, s, g, P, b, x, cf, mass, cvisc, colour, remap);
+        else launch_timed(k_smooth_u<T, 3, 2>, grid, blk, s, g, P, b, x, cf, mass, cvisc, colour, remap);
     } else {
-        if (a == 0) launch_timed(k_smooth_u<T, 2, 0>, grid, blk, s, g, P, b, x, cf, mass, cvisc, colour);
-        else launch_timed(k_smooth_u<T, 2, 1>, grid, blk, s, g, P, b, x, cf, mass, cvisc, colour);
+        if (a == 0) launch_timed(k_smooth_u<T, 2, 0>, grid, blk, s, g, P, b, x, cf, mass, cvisc, colour, remap);
+        else launch_timed(k_smooth_u<T, 2, 1>, grid, blk, s, g, P, b, x, cf, mass, cvisc, colour, remap);
     }
 }
 
@@ -1825,8 +1848,9 @@ void launch_smooth_u_dec(const Grid &g, const VelArrC<T> &b, const VelArr<T> &x,
     }
     if (mx <= 0) return;
     const dim3 grid(blocks_for(mx), g.D), blk(256);
-    if (g.D == 3) launch_timed(k_smooth_u_dec<T, 3>, grid, blk, s, g, parts, b, x, cf, mass, cvisc, colour);
-    else launch_timed(k_smooth_u_dec<T, 2>, grid, blk, s, g, parts, b, x, cf, mass, cvisc, colour);
+    const int remap = g.nel <= XCD_REMAP_MAX_NEL;
+    if (g.D == 3) launch_timed(k_smooth_u_dec<T, 3>, grid, blk, s, g, parts, b, x, cf, mass, cvisc, colour, remap);
+    else launch_timed(k_smooth_u_dec<T, 2>, grid, blk, s, g, parts, b, x, cf, mass, cvisc, colour, remap);
 }
 
 template <typename T>
