@@ -83,3 +83,34 @@ def test_status_strings():
     lib = L.load()
     for s in range(7):
         assert lib.ibb_status_string(s)
+
+
+@pytest.mark.parametrize("cname,pycls", [("ibb_desc", "Desc"), ("ibb_solve_stats", "SolveStats"),
+                                         ("ibb_lag_stats", "LagStats")])
+def test_struct_layouts_match_header(cname, pycls, tmp_path):
+    """Every field of the binding's ctypes mirror sits at the offset the C
+    compiler gives it from include/ibmg.h, and the sizes agree."""
+    import subprocess
+    cls = getattr(L, pycls)
+    names = [f[0] for f in cls._fields_]
+    src = tmp_path / "layout.c"
+    body = "\n".join(f'    printf("{n} %zu\\n", offsetof({cname}, {n}));' for n in names)
+    src.write_text(f'#include <stdio.h>\n#include <stddef.h>\n#include "ibmg.h"\nint main(void) {{\n'
+                   f'    printf("sizeof %zu\\n", sizeof({cname}));\n{body}\n    return 0;\n}}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                       text=True).stdout.splitlines())
+    assert int(out["sizeof"]) == ctypes.sizeof(cls)
+    for n in names:
+        assert int(out[n]) == getattr(cls, n).offset, n
+
+
+def test_decoupled_needs_constant_viscosity():
+    lib = L.load()
+    p = dict(synth.tiny_2d()["params"], decoupled=1)
+    n = ctypes.c_size_t()
+    assert p["mu_max"] != p["mu_out"]
+    assert lib.ibb_footprint_bytes(ctypes.byref(L.make_desc(p)), 10, 10, ctypes.byref(n)) == L.IBB_EINVAL
+    p["mu_max"] = p["mu_out"]
+    assert lib.ibb_footprint_bytes(ctypes.byref(L.make_desc(p)), 10, 10, ctypes.byref(n)) == L.IBB_OK
