@@ -78,7 +78,8 @@ typedef enum { IBB_FP64 = 0, IBB_FP32_REFINED = 1 } ibb_precision;
 
 typedef struct {
     int dim;            /* 2 or 3 */
-    int n[3];           /* cells per axis, each even; n[2] ignored in 2D */
+    int n[3];           /* cells per axis, each even; n[2] ignored in 2D; the product of
+                           (n + 3) over the axes below 2^31 */
     int axis_bc[3];     /* ibb_axis_bc per axis */
     double h;           /* mesh width (isotropic) */
     double sigma;       /* Strouhal number */

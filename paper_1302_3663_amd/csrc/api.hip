@@ -202,6 +202,11 @@ ibb_status check_desc(const ibb_desc *d)
     if (d->decoupled && d->mu_max != d->mu_out) return IBB_EINVAL;
     for (int a = 0; a < d->dim; ++a)
         if (d->axis_bc[a] == IBB_AXIS_PERIODIC && 4.0 * d->omega > d->n[a] * d->h) return IBB_EINVAL;
+    // array indices are formed in 32-bit arithmetic: every padded array
+    // (n + 3 entries per axis) must hold fewer than 2^31 entries
+    long long nel = 1;
+    for (int a = 0; a < d->dim; ++a) nel *= (long long)d->n[a] + 3;
+    if (nel >= (1ll << 31)) return IBB_EINVAL;
     return IBB_OK;
 }
 
@@ -2148,6 +2153,20 @@ ibb_status group_norms(ibb_group *g, bool vel, bool resid, const std::vector<cha
 // next iteration and reads all norms back at once.
 constexpr int GROUP_SIDE_STREAMS = 4;
 
+// on every way out of a group solve, the group's stream waits for the work
+// queued on the side streams
+struct SideJoin {
+    ibb_group *g;
+    int n = 0;
+    ~SideJoin()
+    {
+        for (int k = 0; k < n; ++k)
+            if (hipEventRecord(g->sev[k], g->side[k]) != hipSuccess ||
+                hipStreamWaitEvent(g->s, g->sev[k], 0) != hipSuccess)
+                (void)hipStreamSynchronize(g->side[k]);
+    }
+};
+
 ibb_status group_solve(ibb_group *g, bool vel, GroupSolve &R)
 {
     const int n = (int)g->m.size();
@@ -2172,6 +2191,7 @@ ibb_status group_solve(ibb_group *g, bool vel, GroupSolve &R)
         GCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         g->sev.push_back(ev);
     }
+    SideJoin join{g, nside};
     if (ngcr) {
         // the side streams start after the group stream's work so far
         GCHK(hipEventRecord(g->ev[4], g->s));
@@ -2257,17 +2277,11 @@ ibb_status group_solve(ibb_group *g, bool vel, GroupSolve &R)
             R.rel[i] = sqrt(h[i]) / R.nb[i];
         }
     }
-    if (ngcr) {
-        for (int i = 0; i < n; ++i) {
-            if (side[i] < 0) continue;
-            gcr_finish(gr[i]);
-            R.rel[i] = gr[i].rel;
-            g->m[i]->s = g->s;
-        }
-        for (int k = 0; k < nside; ++k) {
-            GCHK(hipEventRecord(g->sev[k], g->side[k]));
-            GCHK(hipStreamWaitEvent(g->s, g->sev[k], 0));
-        }
+    for (int i = 0; i < n; ++i) {
+        if (side[i] < 0) continue;
+        gcr_finish(gr[i]);
+        R.rel[i] = gr[i].rel;
+        g->m[i]->s = g->s;
     }
     for (int i = 0; i < n; ++i)
         if (side[i] < 0) R.out[i].relres = R.rel[i];

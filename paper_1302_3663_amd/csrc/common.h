@@ -39,9 +39,12 @@ struct Grid {
     double h;
 };
 
+// every array holds fewer than 2^31 entries (checked when a context is
+// created), so the index is formed in 32-bit arithmetic
 __host__ __device__ inline long long at(const Grid &g, int i, int j, int k)
 {
-    return ((long long)(k + (g.D == 3 ? 1 : 0)) * g.NY + (j + 1)) * g.NX + (i + 1);
+    const unsigned kk = (unsigned)(k + (g.D == 3 ? 1 : 0));
+    return (long long)((kk * (unsigned)g.NY + (unsigned)(j + 1)) * (unsigned)g.NX + (unsigned)(i + 1));
 }
 
 // lattice index of entry e (inverse of at)

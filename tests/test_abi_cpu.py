@@ -114,3 +114,16 @@ def test_decoupled_needs_constant_viscosity():
     assert lib.ibb_footprint_bytes(ctypes.byref(L.make_desc(p)), 10, 10, ctypes.byref(n)) == L.IBB_EINVAL
     p["mu_max"] = p["mu_out"]
     assert lib.ibb_footprint_bytes(ctypes.byref(L.make_desc(p)), 10, 10, ctypes.byref(n)) == L.IBB_OK
+
+
+def test_oversized_grid_rejected():
+    """Array indices are formed in 32-bit arithmetic: a grid whose padded
+    arrays would hold 2^31 entries or more is refused."""
+    lib = L.load()
+    p = dict(synth.tiny_3d()["params"])
+    n = ctypes.c_size_t()
+    p["n"] = [1290, 1290, 1290]
+    assert lib.ibb_footprint_bytes(ctypes.byref(L.make_desc(p)), 1, 1, ctypes.byref(n)) == L.IBB_EINVAL
+    p["n"] = [1024, 1024, 1024]
+    assert lib.ibb_footprint_bytes(ctypes.byref(L.make_desc(p)), 1, 1, ctypes.byref(n)) == L.IBB_OK
+
