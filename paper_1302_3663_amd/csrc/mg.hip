@@ -233,9 +233,10 @@ __device__ inline void p_row(const Grid &g, const T *__restrict__ x, const CoefP
 
 // Constant viscosity through the ghost layer: component A alone, unit
 // coefficients; a mirrored self-reference adds to the diagonal as in u_row.
+// (r: the density at the face, read by the caller)
 template <typename T, int D, int A>
-__device__ inline void u_row_dec(const Grid &g, const T *__restrict__ ua, const T *__restrict__ rho, T mass, T cvisc,
-                                 int i, int j, int k, T &Ax, T &dg)
+__device__ inline void u_row_dec_r(const Grid &g, const T *__restrict__ ua, T r, T mass, T cvisc, int i, int j, int k,
+                                   T &Ax, T &dg)
 {
     const int f = (int)at(g, i, j, k);
     const int st[3] = {1, g.NX, (int)g.NXY};
@@ -246,7 +247,6 @@ __device__ inline void u_row_dec(const Grid &g, const T *__restrict__ ua, const 
         vm[b] = ua[f - st[b]];
     }
     const T xf = ua[f];
-    const T r = rho[f];
     const int q[3] = {i, j, k};
     T acc = 0, d = T(2 * D);
 #pragma unroll
@@ -263,21 +263,29 @@ __device__ inline void u_row_dec(const Grid &g, const T *__restrict__ ua, const 
 }
 
 template <typename T, int D, int A>
+__device__ inline void u_row_dec(const Grid &g, const T *__restrict__ ua, const T *__restrict__ rho, T mass, T cvisc,
+                                 int i, int j, int k, T &Ax, T &dg)
+{
+    u_row_dec_r<T, D, A>(g, ua, rho[at(g, i, j, k)], mass, cvisc, i, j, k, Ax, dg);
+}
+
+template <typename T, int D, int A>
 __device__ inline void u_row(const Grid &g, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc, int i, int j,
                              int k, T &Ax, T &dg)
 {
+    const int f = (int)at(g, i, j, k);
+    // read before the branch, which both forms take it in
+    const T rho = cf.rho[A][f];
     if (cf.dec) {
-        u_row_dec<T, D, A>(g, x.c[A], cf.rho[A], mass, cvisc, i, j, k, Ax, dg);
+        u_row_dec_r<T, D, A>(g, x.c[A], rho, mass, cvisc, i, j, k, Ax, dg);
         return;
     }
-    const int f = (int)at(g, i, j, k);
     const int st[3] = {1, g.NX, (int)g.NXY};
     const int sa = st[A];
     const T *__restrict__ ua = x.c[A];
     const T xf = ua[f];
     const T cp = T(2) * cf.muc[f], cm = T(2) * cf.muc[f - sa];
     const T vp = ua[f + sa], vm = ua[f - sa];
-    const T rho = cf.rho[A][f];
     T mp[D - 1], mm[D - 1], ap[D - 1], am[D - 1], b0[D - 1], b1[D - 1], b2[D - 1], b3[D - 1];
 #pragma unroll
     for (int bi = 0; bi < D - 1; ++bi) {
@@ -469,7 +477,9 @@ __device__ inline unsigned xcd_block(int remap)
 
 // ---------------------------------------------------------------------------
 // smoothers: one colour of one component; the updated value is also written
-// to its ghost images so that later passes read it at fixed offsets
+// to its ghost images so that later passes read it at fixed offsets.  Each
+// point reads its own x and b before its row, so that all of its loads are
+// in flight together (read after the row, they cost a second round trip).
 // ---------------------------------------------------------------------------
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_smooth_p(Grid g, Box box, const T *__restrict__ b, T *x, CoefP<T> cf, T cvisc,
@@ -477,10 +487,11 @@ __global__ void __launch_bounds__(256) k_smooth_p(Grid g, Box box, const T *__re
 {
     int i, j, k;
     if (!box_colour_pos(box, colour, xcd_block(remap) * blockDim.x + threadIdx.x, i, j, k)) return;
+    const long long c = at(g, i, j, k);
+    const T bc = b[c], xc = x[c];
     T Ax, dg;
     p_row<T, D>(g, x, cf, cvisc, i, j, k, Ax, dg);
-    const long long c = at(g, i, j, k);
-    const T xn = x[c] + (b[c] - Ax) / dg;
+    const T xn = xc + (bc - Ax) / dg;
     x[c] = xn;
     write_images(g, 0, ROLE_P, x, i, j, k, xn);
 }
@@ -491,10 +502,11 @@ __global__ void __launch_bounds__(256) k_smooth_u(Grid g, Box box, const T *__re
 {
     int i, j, k;
     if (!box_colour_pos(box, colour, xcd_block(remap) * blockDim.x + threadIdx.x, i, j, k)) return;
+    const long long f = at(g, i, j, k);
+    const T bf = b[f], xf = x.c[A][f];
     T Ax, dg;
     u_row<T, D, A>(g, x, cf, mass, cvisc, i, j, k, Ax, dg);
-    const long long f = at(g, i, j, k);
-    const T xn = x.c[A][f] + (b[f] - Ax) / dg;
+    const T xn = xf + (bf - Ax) / dg;
     x.c[A][f] = xn;
     write_images(g, face_mask(A), ROLE_V, x.c[A], i, j, k, xn);
 }
@@ -509,13 +521,14 @@ __global__ void __launch_bounds__(256) k_smooth_u_dec(Grid g, VelBox boxes, VelA
     const int a = blockIdx.y;
     int i, j, k;
     if (!box_colour_pos(boxes.b[a], colour, xcd_block(remap) * blockDim.x + threadIdx.x, i, j, k)) return;
+    const long long f = at(g, i, j, k);
+    T *xa = x.c[a];
+    const T bf = b.c[a][f], xf = xa[f];
     T Ax, dg;
     if (a == 0) u_row_dec<T, D, 0>(g, x.c[0], cf.rho[0], mass, cvisc, i, j, k, Ax, dg);
     else if (a == 1) u_row_dec<T, D, 1>(g, x.c[1], cf.rho[1], mass, cvisc, i, j, k, Ax, dg);
     else u_row_dec<T, D, (D == 3 ? 2 : 1)>(g, x.c[2], cf.rho[2], mass, cvisc, i, j, k, Ax, dg);
-    const long long f = at(g, i, j, k);
-    T *xa = x.c[a];
-    const T xn = xa[f] + (b.c[a][f] - Ax) / dg;
+    const T xn = xf + (bf - Ax) / dg;
     xa[f] = xn;
     write_images(g, face_mask(a), ROLE_V, xa, i, j, k, xn);
 }
@@ -755,10 +768,11 @@ __global__ void __launch_bounds__(256) k_resid_p(Grid g, Box box, const T *__res
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
         int i, j, k;
         box_pos(box, t, i, j, k);
+        const long long c = at(g, i, j, k);
+        const T bc = b[c];
         T Ax, dg;
         p_row<T, D>(g, x, cf, cvisc, i, j, k, Ax, dg);
-        const long long c = at(g, i, j, k);
-        const T rv = b[c] - Ax;
+        const T rv = bc - Ax;
         if (r) r[c] = rv;
         acc += (double)rv * (double)rv;
     }
@@ -776,12 +790,13 @@ __global__ void __launch_bounds__(256) k_resid_u(Grid g, VelBox boxes, VelArrC<T
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
         int i, j, k;
         box_pos(box, t, i, j, k);
+        const long long f = at(g, i, j, k);
+        const T bf = b.c[a][f];
         T Ax, dg;
         if (a == 0) u_row<T, D, 0>(g, x, cf, mass, cvisc, i, j, k, Ax, dg);
         else if (a == 1) u_row<T, D, 1>(g, x, cf, mass, cvisc, i, j, k, Ax, dg);
         else u_row<T, D, (D == 3 ? 2 : 1)>(g, x, cf, mass, cvisc, i, j, k, Ax, dg);
-        const long long f = at(g, i, j, k);
-        const T rv = b.c[a][f] - Ax;
+        const T rv = bf - Ax;
         if (r.c[a]) r.c[a][f] = rv;
         acc += (double)rv * (double)rv;
     }
@@ -1011,7 +1026,8 @@ __global__ void __launch_bounds__(256) k_prolong_add(Grid gc, Grid gf, VelPBox p
     bool inner;
     if (!pbox_pos(parts.p[comp], -1, blockIdx.x * blockDim.x + threadIdx.x, i, j, k, inner)) return;
     const long long e = at(gf, i, j, k);
-    const T v = fine.c[comp][e] + (T)prolong_any<T, D>(vmask, gc, role, coarse.c[comp], i, j, k);
+    const T xe = fine.c[comp][e];
+    const T v = xe + (T)prolong_any<T, D>(vmask, gc, role, coarse.c[comp], i, j, k);
     fine.c[comp][e] = v;
     write_images(gf, vmask, role, fine.c[comp], i, j, k, v);
 }
@@ -1298,12 +1314,13 @@ __device__ inline void sweep_at(const LevTab<T> &lt, const Box &box, int colour,
 {
     int i, j, k;
     if (!box_colour_pos(box, colour, t, i, j, k)) return;
-    T Ax, dg;
-    wg_row<T, D, VEL, A>(lt, i, j, k, Ax, dg);
     T *x = VEL ? lt.xu[A] : lt.xp;
     const T *b = VEL ? lt.bu[A] : lt.bp;
     const long long e = at(lt.g, i, j, k);
-    const T xn = x[e] + (b[e] - Ax) / dg;
+    const T be = b[e], xe = x[e];
+    T Ax, dg;
+    wg_row<T, D, VEL, A>(lt, i, j, k, Ax, dg);
+    const T xn = xe + (be - Ax) / dg;
     x[e] = xn;
     write_images(lt.g, VEL ? face_mask(A) : 0, VEL ? ROLE_V : ROLE_P, x, i, j, k, xn);
 }
@@ -1314,10 +1331,11 @@ __device__ inline T resid_at(const LevTab<T> &lt, const Box &box, int t)
 {
     int i, j, k;
     box_pos(box, t, i, j, k);
+    const long long e = at(lt.g, i, j, k);
+    const T be = (VEL ? lt.bu[A] : lt.bp)[e];
     T Ax, dg;
     wg_row<T, D, VEL, A>(lt, i, j, k, Ax, dg);
-    const long long e = at(lt.g, i, j, k);
-    const T rv = (VEL ? lt.bu[A] : lt.bp)[e] - Ax;
+    const T rv = be - Ax;
     (VEL ? lt.ru[A] : lt.rp)[e] = rv;
     return rv;
 }
@@ -1348,7 +1366,8 @@ __device__ inline void prolong_at(const LevTab<T> &lc, const LevTab<T> &lt, cons
     box_pos(box, t, i, j, k);
     T *x = VEL ? lt.xu[A] : lt.xp;
     const long long e = at(lt.g, i, j, k);
-    const T v = x[e] + (T)prolong_any<T, D>(vmask, lc.g, role, VEL ? lc.xu[A] : lc.xp, i, j, k);
+    const T xe = x[e];
+    const T v = xe + (T)prolong_any<T, D>(vmask, lc.g, role, VEL ? lc.xu[A] : lc.xp, i, j, k);
     x[e] = v;
     write_images(lt.g, vmask, role, x, i, j, k, v);
 }
@@ -1357,8 +1376,9 @@ __device__ inline int colour_count(const Box &b) { return ((b.ext[0] + 1) >> 1) 
 __device__ inline int point_count(const Box &b) { return b.ext[0] * b.ext[1] * b.ext[2]; }
 
 template <typename T, int D, int VEL, int A>
-__device__ inline void wg_sweep_comp(const LevTab<T> &lt)
+__device__ inline void wg_sweep_comp(const LevTab<T> &ltr)
 {
+    const LevTab<T> lt = ltr;
     const Grid &g = lt.g;
     const int vmask = VEL ? face_mask(A) : 0;
     const Box box = unk_box(g, vmask);
@@ -1369,10 +1389,11 @@ __device__ inline void wg_sweep_comp(const LevTab<T> &lt)
         for (int t = threadIdx.x; t < n; t += blockDim.x) {
             int i, j, k;
             if (!box_colour_pos(box, colour, t, i, j, k)) continue;
+            const long long e = at(g, i, j, k);
+            const T be = b[e], xe = x[e];
             T Ax, dg;
             wg_row<T, D, VEL, A>(lt, i, j, k, Ax, dg);
-            const long long e = at(g, i, j, k);
-            const T xn = x[e] + (b[e] - Ax) / dg;
+            const T xn = xe + (be - Ax) / dg;
             x[e] = xn;
             write_images(g, vmask, VEL ? ROLE_V : ROLE_P, x, i, j, k, xn);
         }
@@ -1391,8 +1412,9 @@ __device__ void wg_sweep(const LevTab<T> &lt)
 }
 
 template <typename T, int D, int VEL, int A>
-__device__ inline void wg_residual_comp(const LevTab<T> &lt)
+__device__ inline void wg_residual_comp(const LevTab<T> &ltr)
 {
+    const LevTab<T> lt = ltr;
     const Box box = unk_box(lt.g, VEL ? face_mask(A) : 0);
     const int n = box.ext[0] * box.ext[1] * box.ext[2];
     T *r = VEL ? lt.ru[A] : lt.rp;
@@ -1400,18 +1422,20 @@ __device__ inline void wg_residual_comp(const LevTab<T> &lt)
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
         int i, j, k;
         box_pos(box, t, i, j, k);
+        const long long e = at(lt.g, i, j, k);
+        const T be = b[e];
         T Ax, dg;
         wg_row<T, D, VEL, A>(lt, i, j, k, Ax, dg);
-        const long long e = at(lt.g, i, j, k);
-        r[e] = b[e] - Ax;
+        r[e] = be - Ax;
     }
 }
 
 // coarse right-hand side = restriction of the fine residual, coarse
 // correction cleared (with its images)
 template <typename T, int D, int VEL, int A>
-__device__ inline void wg_restrict_comp(const LevTab<T> &lt, const LevTab<T> &lc)
+__device__ inline void wg_restrict_comp(const LevTab<T> &ltr, const LevTab<T> &lcr)
 {
+    const LevTab<T> lt = ltr, lc = lcr;
     const int vmask = VEL ? face_mask(A) : 0;
     const int role = VEL ? ROLE_V : ROLE_P;
     const Box box = unk_box(lc.g, vmask);
@@ -1430,8 +1454,9 @@ __device__ inline void wg_restrict_comp(const LevTab<T> &lt, const LevTab<T> &lc
 }
 
 template <typename T, int D, int VEL, int A>
-__device__ inline void wg_prolong_comp(const LevTab<T> &lc, const LevTab<T> &lt)
+__device__ inline void wg_prolong_comp(const LevTab<T> &lcr, const LevTab<T> &ltr)
 {
+    const LevTab<T> lc = lcr, lt = ltr;
     const int vmask = VEL ? face_mask(A) : 0;
     const int role = VEL ? ROLE_V : ROLE_P;
     const Box box = unk_box(lt.g, vmask);
@@ -1442,7 +1467,8 @@ __device__ inline void wg_prolong_comp(const LevTab<T> &lc, const LevTab<T> &lt)
         int i, j, k;
         box_pos(box, t, i, j, k);
         const long long e = at(lt.g, i, j, k);
-        const T v = x[e] + (T)prolong_any<T, D>(vmask, lc.g, role, src, i, j, k);
+        const T xe = x[e];
+        const T v = xe + (T)prolong_any<T, D>(vmask, lc.g, role, src, i, j, k);
         x[e] = v;
         write_images(lt.g, vmask, role, x, i, j, k, v);
     }
@@ -1476,7 +1502,7 @@ __device__ __attribute__((always_inline)) inline void coarse_cycle(const LevTab<
         __syncthreads();
     }
     {
-        const LevTab<T> &lt = tab[L - 1];
+        const LevTab<T> lt = tab[L - 1];
         if (ndense > 0) {
             __shared__ double bv[64];
             const int r = threadIdx.x;
@@ -1553,8 +1579,8 @@ __device__ inline void stage_levels(const LevTab<T> *__restrict__ tab, int l0, i
     }
     __syncthreads();
     for (int l = ls; l < L; ++l) {
-        const LevTab<T> &src = tab[l];
-        const LevTab<T> &dst = wt[l];
+        const LevTab<T> src = tab[l];
+        const LevTab<T> dst = wt[l];
         const bool start = l == l0;
         const int nel = (int)src.g.nel;
         for (int e = threadIdx.x; e < nel; e += blockDim.x) {
@@ -1589,8 +1615,8 @@ __device__ inline void unstage_start(const LevTab<T> *__restrict__ tab, int l0, 
 {
     if (l0 < ls) return;
     __syncthreads();
-    const LevTab<T> &src = wt[l0];
-    const LevTab<T> &dst = tab[l0];
+    const LevTab<T> src = wt[l0];
+    const LevTab<T> dst = tab[l0];
     const int nel = (int)dst.g.nel;
     for (int e = threadIdx.x; e < nel; e += blockDim.x) {
         if (VEL) {
@@ -1630,7 +1656,7 @@ __global__ void __launch_bounds__(256) k_bsweep(const BEntry *__restrict__ ent, 
 {
     const BEntry E = ent[blockIdx.x];
     if (!flags[E.ctx]) return;
-    const LevTab<T> &lt = tab_of<T>(E.tab);
+    const LevTab<T> lt = tab_of<T>(E.tab);
     const Box box = unk_box(lt.g, VEL ? face_mask(A) : 0);
     sweep_at<T, D, VEL, A>(lt, box, colour, (int)(blockIdx.x - E.base) * blockDim.x + threadIdx.x);
 }
@@ -1643,7 +1669,7 @@ __global__ void __launch_bounds__(256) k_bresid(const BEntry *__restrict__ ent, 
 {
     const BEntry E = ent[blockIdx.x];
     if (!flags[E.ctx]) return;
-    const LevTab<T> &lt = tab_of<T>(E.tab);
+    const LevTab<T> lt = tab_of<T>(E.tab);
     const int a = blockIdx.y;
     const int lb = blockIdx.x - E.base;
     const Box box = unk_box(lt.g, VEL ? face_mask(a) : 0);
@@ -1685,8 +1711,8 @@ __global__ void __launch_bounds__(256) k_brestrict(const BEntry *__restrict__ en
     const BEntry E = ent[blockIdx.x];
     if (!flags[E.ctx]) return;
     const LevTab<T> *tp = static_cast<const LevTab<T> *>(E.tab);
-    const LevTab<T> &lt = tp[0];
-    const LevTab<T> &lc = tp[1];
+    const LevTab<T> lt = tp[0];
+    const LevTab<T> lc = tp[1];
     const int a = blockIdx.y;
     const Box box = unk_box(lc.g, VEL ? face_mask(a) : 0);
     const int t = (blockIdx.x - E.base) * blockDim.x + threadIdx.x;
@@ -1702,8 +1728,8 @@ __global__ void __launch_bounds__(256) k_bprolong(const BEntry *__restrict__ ent
     const BEntry E = ent[blockIdx.x];
     if (!flags[E.ctx]) return;
     const LevTab<T> *tp = static_cast<const LevTab<T> *>(E.tab);
-    const LevTab<T> &lt = tp[0];
-    const LevTab<T> &lc = tp[1];
+    const LevTab<T> lt = tp[0];
+    const LevTab<T> lc = tp[1];
     const int a = blockIdx.y;
     const Box box = unk_box(lt.g, VEL ? face_mask(a) : 0);
     const int t = (blockIdx.x - E.base) * blockDim.x + threadIdx.x;
