@@ -1583,26 +1583,66 @@ __device__ inline void stage_levels(const LevTab<T> *__restrict__ tab, int l0, i
         const LevTab<T> dst = wt[l];
         const bool start = l == l0;
         const int nel = (int)src.g.nel;
-        for (int e = threadIdx.x; e < nel; e += blockDim.x) {
+        // two elements per round, every load before any store, so that a
+        // round costs one trip to global memory
+        constexpr int U = 2;
+        for (int e0 = threadIdx.x; e0 < nel; e0 += U * blockDim.x) {
             if (VEL) {
+                T rh[U][3], xv[U][3], bv[U][3], mc[U], me[U][3];
 #pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    if (dst.rho[a] != src.rho[a]) const_cast<T *>(dst.rho[a])[e] = src.rho[a][e];
-                    dst.xu[a][e] = start ? src.xu[a][e] : T(0);
-                    dst.bu[a][e] = start ? src.bu[a][e] : T(0);
-                    dst.ru[a][e] = T(0);
+                for (int u = 0; u < U; ++u) {
+                    const int e = e0 + u * blockDim.x;
+                    if (e >= nel) break;
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        if (dst.rho[a] != src.rho[a]) rh[u][a] = src.rho[a][e];
+                        xv[u][a] = start ? src.xu[a][e] : T(0);
+                        bv[u][a] = start ? src.bu[a][e] : T(0);
+                    }
+                    if (dst.muc != src.muc) mc[u] = src.muc[e];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+                        if (dst.mue[a] && dst.mue[a] != src.mue[a]) me[u][a] = src.mue[a][e];
                 }
-                if (dst.muc != src.muc) const_cast<T *>(dst.muc)[e] = src.muc[e];
 #pragma unroll
-                for (int a = 0; a < 3; ++a)
-                    if (dst.mue[a] && dst.mue[a] != src.mue[a]) const_cast<T *>(dst.mue[a])[e] = src.mue[a][e];
+                for (int u = 0; u < U; ++u) {
+                    const int e = e0 + u * blockDim.x;
+                    if (e >= nel) break;
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        if (dst.rho[a] != src.rho[a]) const_cast<T *>(dst.rho[a])[e] = rh[u][a];
+                        dst.xu[a][e] = xv[u][a];
+                        dst.bu[a][e] = bv[u][a];
+                        dst.ru[a][e] = T(0);
+                    }
+                    if (dst.muc != src.muc) const_cast<T *>(dst.muc)[e] = mc[u];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+                        if (dst.mue[a] && dst.mue[a] != src.mue[a]) const_cast<T *>(dst.mue[a])[e] = me[u][a];
+                }
             } else {
+                T bt[U][3], xv[U], bv[U];
 #pragma unroll
-                for (int a = 0; a < D; ++a)
-                    if (dst.beta[a] != src.beta[a]) const_cast<T *>(dst.beta[a])[e] = src.beta[a][e];
-                dst.xp[e] = start ? src.xp[e] : T(0);
-                dst.bp[e] = start ? src.bp[e] : T(0);
-                dst.rp[e] = T(0);
+                for (int u = 0; u < U; ++u) {
+                    const int e = e0 + u * blockDim.x;
+                    if (e >= nel) break;
+#pragma unroll
+                    for (int a = 0; a < D; ++a)
+                        if (dst.beta[a] != src.beta[a]) bt[u][a] = src.beta[a][e];
+                    xv[u] = start ? src.xp[e] : T(0);
+                    bv[u] = start ? src.bp[e] : T(0);
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int e = e0 + u * blockDim.x;
+                    if (e >= nel) break;
+#pragma unroll
+                    for (int a = 0; a < D; ++a)
+                        if (dst.beta[a] != src.beta[a]) const_cast<T *>(dst.beta[a])[e] = bt[u][a];
+                    dst.xp[e] = xv[u];
+                    dst.bp[e] = bv[u];
+                    dst.rp[e] = T(0);
+                }
             }
         }
     }
