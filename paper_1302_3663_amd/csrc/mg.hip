@@ -384,14 +384,31 @@ __host__ __device__ inline bool box_colour_pos(const Box &b, int colour, int t, 
 
 // position of thread t in a partitioned box; inner is true for part 0 when
 // the partition has an inner box.  colour < 0: every point.
-__host__ __device__ inline bool pbox_pos(const PBox &P, int colour, int t, int &i, int &j, int &k, bool &inner)
+// The part is found with a fixed sequence of selects rather than a search
+// loop: every entry of P is then read at a fixed place, which lets the
+// table (a kernel argument) come in through scalar loads all at once
+// instead of one dependent vector load per step of the search.
+__host__ __device__ inline bool pbox_pos(const PBox &Pr, int colour, int t, int &i, int &j, int &k, bool &inner)
 {
-    if (t >= P.off[P.n]) return false;
-    int p = 0;
-    while (p + 1 < P.n && t >= P.off[p + 1]) ++p;
+    const PBox P = Pr;
+    const int n = P.n;
+    int total = P.off[0];
+#pragma unroll
+    for (int q = 1; q < 8; ++q)
+        if (q == n) total = P.off[q];
+    if (t >= total) return false;
+    int p = 0, base = P.off[0];
+    Box B = P.b[0];
+#pragma unroll
+    for (int q = 1; q < 7; ++q)
+        if (q < n && t >= P.off[q]) {
+            p = q;
+            base = P.off[q];
+            B = P.b[q];
+        }
     inner = p == 0 && P.inner;
-    const int tl = t - P.off[p];
-    return colour < 0 ? box_pos(P.b[p], tl, i, j, k) : box_colour_pos(P.b[p], colour, tl, i, j, k);
+    const int tl = t - base;
+    return colour < 0 ? box_pos(B, tl, i, j, k) : box_colour_pos(B, colour, tl, i, j, k);
 }
 
 // Split `full` into the inner box [ilo, ihi] (clipped) and boundary slabs.
