@@ -69,7 +69,7 @@ CASES = {
 
 @pytest.mark.parametrize("name", sorted(CASES))
 @pytest.mark.parametrize("vel", [0, 1])
-@pytest.mark.parametrize("inner", [1, 2])
+@pytest.mark.parametrize("inner", [1, 2, 4])
 def test_refined_solve(name, vel, inner, ibmg):
     case = CASES[name]()
     print("case", name, "velocity" if vel else "pressure", "inner", inner, flush=True)

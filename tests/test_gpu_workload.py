@@ -73,7 +73,8 @@ def test_full_size_step(name, precision):
     case = workload_case(name)
     p = case["params"]
     print(name, "precision", precision, flush=True)
-    ctx = ibmg.from_case(case, precision=precision, inner_cycles=2)
+    # the inner cycle count bench.py uses for these workloads
+    ctx = ibmg.from_case(case, precision=precision, inner_cycles=4)
     # spread fields
     F_o, _, _ = O.springs(p, case["X"], case["ij"], case["rest"], case["K"], np.ones(case["ij"].shape[1], np.uint8),
                           do_break=False)
@@ -137,7 +138,7 @@ def test_film_full_size_sampled():
     p = case["params"]
     h, om, D = p["h"], p["omega"], 3
     print("film: context", flush=True)
-    ctx = ibmg.from_case(case, precision=L.IBB_FP32_REFINED, inner_cycles=2)
+    ctx = ibmg.from_case(case, precision=L.IBB_FP32_REFINED, inner_cycles=4)
     _, rho, mc, _ = [None if t is None else host(t) for t in ctx.get_fields(0)]
     X = case["X"].T
     tree = cKDTree(X)
