@@ -17,17 +17,6 @@ struct VelBox {
     Box b[3];
 };
 
-// A box split into an inner box (part 0: every neighbour of every point is
-// reached at a fixed offset) and up to six boundary slabs.  off[p] counts the
-// threads of parts before p; a launch covers off[n] threads, so the
-// wavefronts of the inner part never take the boundary path.
-struct PBox {
-    Box b[7];
-    int off[8];   // off[n] is the total thread count
-    int n;        // parts in use
-    int inner;    // part 0 is the inner box
-};
-
 template <typename T>
 struct VelArr {
     T *c[3];

@@ -344,7 +344,7 @@ __device__ inline void u_row_slow_any(const Grid &g, const VelArr<T> &x, const C
 }
 
 // ---------------------------------------------------------------------------
-// index helpers: unknown boxes, their colour classes and partitions
+// index helpers: unknown boxes and their colour classes
 // ---------------------------------------------------------------------------
 __host__ __device__ inline Box unk_box(const Grid &g, int vmask)
 {
@@ -380,95 +380,6 @@ __host__ __device__ inline bool box_colour_pos(const Box &b, int colour, int t, 
     k = b.lo[2] + t / b.ext[1];
     i = b.lo[0] + 2 * ih + ((b.lo[0] + j + k + colour) & 1);
     return i < b.lo[0] + b.ext[0];
-}
-
-// position of thread t in a partitioned box; inner is true for part 0 when
-// the partition has an inner box.  colour < 0: every point.
-// The part is found with a fixed sequence of selects rather than a search
-// loop: every entry of P is then read at a fixed place, which lets the
-// table (a kernel argument) come in through scalar loads all at once
-// instead of one dependent vector load per step of the search.
-__host__ __device__ inline bool pbox_pos(const PBox &Pr, int colour, int t, int &i, int &j, int &k, bool &inner)
-{
-    const PBox P = Pr;
-    const int n = P.n;
-    int total = P.off[0];
-#pragma unroll
-    for (int q = 1; q < 8; ++q)
-        if (q == n) total = P.off[q];
-    if (t >= total) return false;
-    int p = 0, base = P.off[0];
-    Box B = P.b[0];
-#pragma unroll
-    for (int q = 1; q < 7; ++q)
-        if (q < n && t >= P.off[q]) {
-            p = q;
-            base = P.off[q];
-            B = P.b[q];
-        }
-    inner = p == 0 && P.inner;
-    const int tl = t - base;
-    return colour < 0 ? box_pos(B, tl, i, j, k) : box_colour_pos(B, colour, tl, i, j, k);
-}
-
-// Split `full` into the inner box [ilo, ihi] (clipped) and boundary slabs.
-static PBox make_pbox(const Grid &g, const Box &full, const int ilo[3], const int ihi[3], bool colour)
-{
-    PBox P;
-    for (int p = 0; p < 7; ++p) P.b[p] = Box{{0, 0, 0}, {0, 0, 0}};
-    P.n = 0;
-    P.inner = 0;
-    for (int p = 0; p < 8; ++p) P.off[p] = 0;
-    int flo[3], fhi[3], lo[3], hi[3];
-    bool empty = false;
-    for (int d = 0; d < 3; ++d) {
-        flo[d] = full.lo[d];
-        fhi[d] = full.lo[d] + full.ext[d] - 1;
-        if (d >= g.D) { lo[d] = flo[d]; hi[d] = fhi[d]; continue; }
-        lo[d] = ilo[d] > flo[d] ? ilo[d] : flo[d];
-        hi[d] = ihi[d] < fhi[d] ? ihi[d] : fhi[d];
-        if (hi[d] < lo[d]) empty = true;
-    }
-    if (full.ext[0] <= 0 || full.ext[1] <= 0 || full.ext[2] <= 0) return P;
-    auto add = [&](int x0, int x1, int y0, int y1, int z0, int z1) {
-        if (x1 < x0 || y1 < y0 || z1 < z0) return;
-        P.b[P.n++] = Box{{x0, y0, z0}, {x1 - x0 + 1, y1 - y0 + 1, z1 - z0 + 1}};
-    };
-    bool inner = !empty;
-    if (inner) {
-        add(lo[0], hi[0], lo[1], hi[1], lo[2], hi[2]);
-        add(flo[0], fhi[0], flo[1], fhi[1], flo[2], lo[2] - 1);
-        add(flo[0], fhi[0], flo[1], fhi[1], hi[2] + 1, fhi[2]);
-        add(flo[0], fhi[0], flo[1], lo[1] - 1, lo[2], hi[2]);
-        add(flo[0], fhi[0], hi[1] + 1, fhi[1], lo[2], hi[2]);
-        add(flo[0], lo[0] - 1, lo[1], hi[1], lo[2], hi[2]);
-        add(hi[0] + 1, fhi[0], lo[1], hi[1], lo[2], hi[2]);
-    } else {
-        add(flo[0], fhi[0], flo[1], fhi[1], flo[2], fhi[2]);
-    }
-    int acc = 0;
-    for (int p = 0; p < P.n; ++p) {
-        P.off[p] = acc;
-        const Box &b = P.b[p];
-        acc += (colour ? (b.ext[0] + 1) / 2 : b.ext[0]) * b.ext[1] * b.ext[2];
-    }
-    for (int p = P.n; p < 8; ++p) P.off[p] = acc;
-    P.inner = inner ? 1 : 0;
-    return P;
-}
-
-static inline int pbox_total(const PBox &P) { return P.off[P.n]; }
-
-// inner ranges: velocity rows read two layers (2 .. n-2), pressure rows one (1 .. n-2)
-static PBox smoother_pbox(const Grid &g, int vmask, bool velocity, bool colour)
-{
-    const Box full = unk_box(g, vmask);
-    int ilo[3], ihi[3];
-    for (int d = 0; d < 3; ++d) {
-        ilo[d] = velocity ? 2 : 1;
-        ihi[d] = d < g.D ? g.n[d] - 2 : 0;
-    }
-    return make_pbox(g, full, ilo, ihi, colour);
 }
 
 // ---------------------------------------------------------------------------
@@ -770,10 +681,6 @@ __device__ inline void block_sum_store(double v, double *partial, long long slot
     if (threadIdx.x == 0) partial[slot] = red[0];
 }
 
-struct VelPBox {
-    PBox p[3];
-};
-
 // residual r = b - A x at every unknown (r may be null) and per-block
 // partial sums of r^2 (partial may be null); grid-stride over the box
 template <typename T, int D>
@@ -1015,14 +922,13 @@ __device__ inline double prolong_any(int vm, const Grid &gc, int role, const T *
 // (or every stored coarse position for coefficients); zero_x[c], when set,
 // is cleared at the same positions (the coarse correction starts at zero)
 template <typename T, int D>
-__global__ void __launch_bounds__(256) k_restrict(Grid gf, Grid gc, VelPBox parts, int masks, int role,
+__global__ void __launch_bounds__(256) k_restrict(Grid gf, Grid gc, VelBox boxes, int masks, int role,
                                                   VelArrC<T> fine, VelArr<T> coarse, T scale, VelArr<T> zero_x)
 {
     const int comp = blockIdx.y;
     const int vmask = (masks >> (4 * comp)) & 0xF;
     int I, J, K;
-    bool inner;
-    if (!pbox_pos(parts.p[comp], -1, blockIdx.x * blockDim.x + threadIdx.x, I, J, K, inner)) return;
+    if (!box_pos(boxes.b[comp], blockIdx.x * blockDim.x + threadIdx.x, I, J, K)) return;
     const double s = restrict_any<T, D>(vmask, gf, role, fine.c[comp], I, J, K);
     const long long e = at(gc, I, J, K);
     coarse.c[comp][e] = (T)(s * (double)scale);
@@ -1034,14 +940,13 @@ __global__ void __launch_bounds__(256) k_restrict(Grid gf, Grid gc, VelPBox part
 
 // fine[c] += linear interpolation of coarse[c] at every fine unknown
 template <typename T, int D>
-__global__ void __launch_bounds__(256) k_prolong_add(Grid gc, Grid gf, VelPBox parts, int masks, int role,
+__global__ void __launch_bounds__(256) k_prolong_add(Grid gc, Grid gf, VelBox boxes, int masks, int role,
                                                      VelArrC<T> coarse, VelArr<T> fine)
 {
     const int comp = blockIdx.y;
     const int vmask = (masks >> (4 * comp)) & 0xF;
     int i, j, k;
-    bool inner;
-    if (!pbox_pos(parts.p[comp], -1, blockIdx.x * blockDim.x + threadIdx.x, i, j, k, inner)) return;
+    if (!box_pos(boxes.b[comp], blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
     const long long e = at(gf, i, j, k);
     const T xe = fine.c[comp][e];
     const T v = xe + (T)prolong_any<T, D>(vmask, gc, role, coarse.c[comp], i, j, k);
@@ -2024,83 +1929,21 @@ static inline Box stored_box(const Grid &g, int vmask)
     return b;
 }
 
-// valid index range of a lattice along d for a role (fine side of a transfer)
-static void valid_range(const Grid &g, int d, int vert, int role, int &lo, int &hi)
-{
-    if (role == ROLE_C) { lo = 0; hi = stored_extent(g, d, vert) - 1; }
-    else unk_range(g, d, vert, lo, hi);
-}
-
-// coarse positions of box `cb` whose restriction taps all sit in the valid
-// fine range, as the inner interval per axis
-static PBox restrict_pbox(const Grid &gf, const Box &cb, int vmask, int role)
-{
-    int ilo[3], ihi[3];
-    for (int d = 0; d < 3; ++d) {
-        ilo[d] = cb.lo[d];
-        ihi[d] = cb.lo[d] + cb.ext[d] - 1;
-        if (d >= gf.D) continue;
-        const int vert = (vmask >> d) & 1;
-        int lo, hi;
-        valid_range(gf, d, vert, role, lo, hi);
-        int first = 1 << 30, last = -(1 << 30);
-        for (int I = cb.lo[d]; I < cb.lo[d] + cb.ext[d]; ++I) {
-            const int t0 = 2 * I - 1, t1 = vert ? 2 * I + 1 : 2 * I + 2;
-            if (t0 >= lo && t1 <= hi) {
-                first = I < first ? I : first;
-                last = I > last ? I : last;
-            }
-        }
-        ilo[d] = first;
-        ihi[d] = last;
-    }
-    return make_pbox(gf, cb, ilo, ihi, false);
-}
-
-// fine unknowns of box `fb` whose prolongation taps all sit in the valid
-// coarse range
-static PBox prolong_pbox(const Grid &gc, const Box &fb, int vmask, int role)
-{
-    int ilo[3], ihi[3];
-    for (int d = 0; d < 3; ++d) {
-        ilo[d] = fb.lo[d];
-        ihi[d] = fb.lo[d] + fb.ext[d] - 1;
-        if (d >= gc.D) continue;
-        const int vert = (vmask >> d) & 1;
-        int lo, hi;
-        valid_range(gc, d, vert, role, lo, hi);
-        int first = 1 << 30, last = -(1 << 30);
-        for (int f = fb.lo[d]; f < fb.lo[d] + fb.ext[d]; ++f) {
-            int t0, t1;
-            if (vert) { t0 = (f - (f & 1)) / 2; t1 = (f + (f & 1)) / 2; }
-            else { t0 = (f >> 1) - 1; t1 = (f >> 1) + 1; }
-            if (t0 >= lo && t1 <= hi) {
-                first = f < first ? f : first;
-                last = f > last ? f : last;
-            }
-        }
-        ilo[d] = first;
-        ihi[d] = last;
-    }
-    return make_pbox(gc, fb, ilo, ihi, false);
-}
-
 template <typename T>
 void launch_restrict(const Grid &gf, const Grid &gc, int ncomp, const int *vmasks, int role, bool all_stored,
                      const VelArrC<T> &fine, const VelArr<T> &coarse, T scale, hipStream_t s,
                      const VelArr<T> *zero_x)
 {
-    VelPBox parts;
+    VelBox parts;
     int masks = 0;
     long long mx = 0;
     for (int a = 0; a < 3; ++a) {
         if (a < ncomp) {
-            const Box cb = all_stored ? stored_box(gc, vmasks[a]) : unk_box(gc, vmasks[a]);
-            parts.p[a] = restrict_pbox(gf, cb, vmasks[a], role);
+            parts.b[a] = all_stored ? stored_box(gc, vmasks[a]) : unk_box(gc, vmasks[a]);
             masks |= vmasks[a] << (4 * a);
-            mx = pbox_total(parts.p[a]) > mx ? pbox_total(parts.p[a]) : mx;
+            mx = box_count(parts.b[a]) > mx ? box_count(parts.b[a]) : mx;
         } else {
-            parts.p[a] = parts.p[0];
+            parts.b[a] = parts.b[0];
         }
     }
     const VelArr<T> zx = zero_x ? *zero_x : VelArr<T>{{nullptr, nullptr, nullptr}};
@@ -2117,16 +1960,16 @@ template <typename T>
 void launch_prolong_add(const Grid &gc, const Grid &gf, int ncomp, const int *vmasks, int role,
                         const VelArrC<T> &coarse, const VelArr<T> &fine, hipStream_t s)
 {
-    VelPBox parts;
+    VelBox parts;
     int masks = 0;
     long long mx = 0;
     for (int a = 0; a < 3; ++a) {
         if (a < ncomp) {
-            parts.p[a] = prolong_pbox(gc, unk_box(gf, vmasks[a]), vmasks[a], role);
+            parts.b[a] = unk_box(gf, vmasks[a]);
             masks |= vmasks[a] << (4 * a);
-            mx = pbox_total(parts.p[a]) > mx ? pbox_total(parts.p[a]) : mx;
+            mx = box_count(parts.b[a]) > mx ? box_count(parts.b[a]) : mx;
         } else {
-            parts.p[a] = parts.p[0];
+            parts.b[a] = parts.b[0];
         }
     }
     if (mx <= 0) return;
