@@ -1612,13 +1612,33 @@ __global__ void __launch_bounds__(wg_threads(D, VEL)) k_coarse_vcycle(const LevT
 template <typename T>
 __device__ inline const LevTab<T> &tab_of(const void *p) { return *static_cast<const LevTab<T> *>(p); }
 
+// A copy of the i-th level table at p, read through scalar loads.  The tables
+// are written once when a context is created and every lane of a block reads
+// the same one; through a generic pointer they would come in with vector
+// loads, one more round trip that the row's own loads wait behind.
+template <typename T>
+__device__ inline LevTab<T> tab_copy(const void *p, int i = 0)
+{
+    constexpr int N = sizeof(LevTab<T>) / 4;
+    static_assert(sizeof(LevTab<T>) % 4 == 0, "the table is read in 4-byte words");
+    typedef const __attribute__((address_space(4))) unsigned int ConstWord;
+    const ConstWord *w = (const ConstWord *)p + (long long)i * N;
+    struct Words {
+        unsigned int v[N];
+    } r;
+#pragma unroll
+    for (int k = 0; k < N; ++k) r.v[k] = w[k];
+    return __builtin_bit_cast(LevTab<T>, r);
+}
+
 template <typename T, int D, int VEL, int A>
 __global__ void __launch_bounds__(256) k_bsweep(const BEntry *__restrict__ ent, const int *__restrict__ flags,
                                                 int colour)
 {
     const BEntry E = ent[blockIdx.x];
-    if (!flags[E.ctx]) return;
-    const LevTab<T> lt = tab_of<T>(E.tab);
+    const int on = flags[E.ctx];
+    const LevTab<T> lt = tab_copy<T>(E.tab);
+    if (!on) return;
     const Box box = unk_box(lt.g, VEL ? face_mask(A) : 0);
     sweep_at<T, D, VEL, A>(lt, box, colour, (int)(blockIdx.x - E.base) * blockDim.x + threadIdx.x);
 }
@@ -1630,8 +1650,9 @@ template <typename T, int D, int VEL>
 __global__ void __launch_bounds__(256) k_bresid(const BEntry *__restrict__ ent, const int *__restrict__ flags)
 {
     const BEntry E = ent[blockIdx.x];
-    if (!flags[E.ctx]) return;
-    const LevTab<T> lt = tab_of<T>(E.tab);
+    const int on = flags[E.ctx];
+    const LevTab<T> lt = tab_copy<T>(E.tab);
+    if (!on) return;
     const int a = blockIdx.y;
     const int lb = blockIdx.x - E.base;
     const Box box = unk_box(lt.g, VEL ? face_mask(a) : 0);
@@ -1672,9 +1693,8 @@ __global__ void __launch_bounds__(256) k_brestrict(const BEntry *__restrict__ en
 {
     const BEntry E = ent[blockIdx.x];
     if (!flags[E.ctx]) return;
-    const LevTab<T> *tp = static_cast<const LevTab<T> *>(E.tab);
-    const LevTab<T> lt = tp[0];
-    const LevTab<T> lc = tp[1];
+    const LevTab<T> lt = tab_copy<T>(E.tab, 0);
+    const LevTab<T> lc = tab_copy<T>(E.tab, 1);
     const int a = blockIdx.y;
     const Box box = unk_box(lc.g, VEL ? face_mask(a) : 0);
     const int t = (blockIdx.x - E.base) * blockDim.x + threadIdx.x;
@@ -1689,9 +1709,8 @@ __global__ void __launch_bounds__(256) k_bprolong(const BEntry *__restrict__ ent
 {
     const BEntry E = ent[blockIdx.x];
     if (!flags[E.ctx]) return;
-    const LevTab<T> *tp = static_cast<const LevTab<T> *>(E.tab);
-    const LevTab<T> lt = tp[0];
-    const LevTab<T> lc = tp[1];
+    const LevTab<T> lt = tab_copy<T>(E.tab, 0);
+    const LevTab<T> lc = tab_copy<T>(E.tab, 1);
     const int a = blockIdx.y;
     const Box box = unk_box(lt.g, VEL ? face_mask(a) : 0);
     const int t = (blockIdx.x - E.base) * blockDim.x + threadIdx.x;
