@@ -1221,27 +1221,29 @@ ibb_status rebuild_coefficients(ibb_ctx *c)
                 launch_restrict<double>(F.g, L.g, c->E, em3, ROLE_C, true, fe, ce, gm, c->s);
             }
         }
+        // beta, then the ghost layers of every coefficient, then the FP32
+        // copies: one launch each, over all of the level's arrays
+        launch_beta_faces(L.g, VelArrC<double>{{L.rho[0], L.rho[1], L.rho[2]}},
+                          VelArr<double>{{L.beta[0], L.beta[1], L.beta[2]}}, c->s);
+        CoefSet<double> set;
+        set.n = 0;
+        float *set32[COEF_SET];
+        auto add = [&](int vmask, double *v, float *v32) {
+            set.vmask[set.n] = vmask;
+            set.v[set.n] = v;
+            set32[set.n++] = v32;
+        };
         for (int a = 0; a < D; ++a) {
-            launch_beta_face(L.g, a, L.rho[a], L.beta[a], c->s);
-            launch_coef_ghosts<double>(L.g, face_mask(a), L.rho[a], c->s);
-            launch_coef_ghosts<double>(L.g, face_mask(a), L.beta[a], c->s);
+            add(face_mask(a), L.rho[a], L.rho32[a]);
+            add(face_mask(a), L.beta[a], L.beta32[a]);
         }
         if (visc) {
-            launch_coef_ghosts<double>(L.g, 0, L.muc, c->s);
+            add(0, L.muc, L.muc32);
             for (int e = 0; e < c->E; ++e)
-                launch_coef_ghosts<double>(L.g, edge_mask(D, c->edge_axis[e]), L.mue[c->edge_axis[e]], c->s);
+                add(edge_mask(D, c->edge_axis[e]), L.mue[c->edge_axis[e]], L.mue32[c->edge_axis[e]]);
         }
-        if (d->precision == IBB_FP32_REFINED) {
-            for (int a = 0; a < D; ++a) {
-                launch_to_f32(L.rho[a], L.rho32[a], L.g.nel, c->s);
-                launch_to_f32(L.beta[a], L.beta32[a], L.g.nel, c->s);
-            }
-            if (visc) {
-                launch_to_f32(L.muc, L.muc32, L.g.nel, c->s);
-                for (int e = 0; e < c->E; ++e)
-                    launch_to_f32(L.mue[c->edge_axis[e]], L.mue32[c->edge_axis[e]], L.g.nel, c->s);
-            }
-        }
+        launch_coef_ghosts<double>(L.g, set, c->s);
+        if (d->precision == IBB_FP32_REFINED) launch_to_f32(set, set32, L.g.nel, c->s);
     }
     // coarsest inverses
     Level &LC = c->lv[c->L - 1];

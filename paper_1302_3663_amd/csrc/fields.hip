@@ -288,36 +288,52 @@ void launch_copy(const double *src, double *dst, long long n, hipStream_t s)
     hipLaunchKernelGGL(k_copy, dim3(b ? b : 1), dim3(256), 0, s, src, dst, n);
 }
 
-// beta = 1 / rho on every stored position of the faces normal to axis a
-__global__ void k_beta(Grid g, int vmask, const double *__restrict__ rho, double *__restrict__ beta)
+// beta = 1 / rho on every stored position of the faces normal to axis
+// a = blockIdx.y
+__global__ void k_beta(Grid g, VelArrC<double> rho, VelArr<double> beta)
 {
+    const int a = blockIdx.y;
+    const int vmask = face_mask(a);
     int ext[3];
     for (int d = 0; d < 3; ++d) ext[d] = stored_extent(g, d, (vmask >> d) & 1);
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     int i, j, k;
     if (!box_at(ext, t, i, j, k)) return;
     const long long e = at(g, i, j, k);
-    beta[e] = 1.0 / rho[e];
+    beta.c[a][e] = 1.0 / rho.c[a][e];
 }
 
-void launch_beta_face(const Grid &g, int a, const double *rho, double *beta, hipStream_t s)
+void launch_beta_faces(const Grid &g, const VelArrC<double> &rho, const VelArr<double> &beta, hipStream_t s)
 {
-    long long n = 1;
-    for (int d = 0; d < 3; ++d) n *= stored_extent(g, d, d == a);
-    hipLaunchKernelGGL(k_beta, dim3(nblk(n)), dim3(256), 0, s, g, face_mask(a), rho, beta);
+    long long mx = 0;
+    for (int a = 0; a < g.D; ++a) {
+        long long n = 1;
+        for (int d = 0; d < 3; ++d) n *= stored_extent(g, d, d == a);
+        mx = n > mx ? n : mx;
+    }
+    hipLaunchKernelGGL(k_beta, dim3(nblk(mx), g.D), dim3(256), 0, s, g, rho, beta);
 }
 
-__global__ void k_to_f32(const double *__restrict__ src, float *__restrict__ dst, long long n)
+// array q = blockIdx.y of the set
+struct F32Dst {
+    float *v[COEF_SET];
+};
+__global__ void k_to_f32(CoefSet<double> src, F32Dst dst, long long n)
 {
+    const double *__restrict__ a = src.v[blockIdx.y];
+    float *__restrict__ b = dst.v[blockIdx.y];
     for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x)
-        dst[t] = (float)src[t];
+        b[t] = (float)a[t];
 }
 
-void launch_to_f32(const double *src, float *dst, long long n, hipStream_t s)
+void launch_to_f32(const CoefSet<double> &src, float *const dst[COEF_SET], long long n, hipStream_t s)
 {
+    if (src.n <= 0 || n <= 0) return;
+    F32Dst d;
+    for (int q = 0; q < COEF_SET; ++q) d.v[q] = q < src.n ? dst[q] : nullptr;
     unsigned b = nblk(n);
     if (b > 4096) b = 4096;
-    hipLaunchKernelGGL(k_to_f32, dim3(b ? b : 1), dim3(256), 0, s, src, dst, n);
+    hipLaunchKernelGGL(k_to_f32, dim3(b, src.n), dim3(256), 0, s, src, d, n);
 }
 
 // plain sum of a cell field into partial sums (for the mean of the pressure)

@@ -90,9 +90,19 @@ void launch_dense_apply(const Grid &g, int velocity, int n, const long long *uid
 template <typename T>
 void launch_load_unknowns(const Grid &g, int ncomp, const int *vmasks, const VelArrC<T> &src, const VelArr<T> &dst,
                           hipStream_t s);
-// fill the ghost layer of a coefficient field from its stored positions
+// Arrays of one level that one launch treats together (blockIdx.y picks
+// the array): up to D face densities and inverse densities, the cell and
+// the edge viscosities.
+constexpr int COEF_SET = 10;
 template <typename T>
-void launch_coef_ghosts(const Grid &g, int vmask, T *v, hipStream_t s);
+struct CoefSet {
+    int n;
+    int vmask[COEF_SET];   // lattice of each array
+    T *v[COEF_SET];
+};
+// fill the ghost layers of the set's fields from their stored positions
+template <typename T>
+void launch_coef_ghosts(const Grid &g, const CoefSet<T> &set, hipStream_t s);
 template <typename T>
 void launch_fill(T *p, long long n, T v, hipStream_t s);
 template <typename Ts, typename Td>
@@ -227,9 +237,11 @@ void launch_add_scalar_cells(const Grid &g, double *v, const double *sum, double
 void launch_project(const Grid &g, const Phys &ph, const VelArrC<double> &ut, const double *p,
                     const CoefP<double> &beta, const VelArr<double> &u, hipStream_t s);
 void launch_copy(const double *src, double *dst, long long n, hipStream_t s);
-void launch_beta_face(const Grid &g, int a, const double *rho, double *beta, hipStream_t s);
+// beta_a = 1 / rho_a at the stored positions of every face lattice a < D
+void launch_beta_faces(const Grid &g, const VelArrC<double> &rho, const VelArr<double> &beta, hipStream_t s);
 int launch_sum_cells(const Grid &g, const double *v, double *partial, hipStream_t s);
-void launch_to_f32(const double *src, float *dst, long long n, hipStream_t s);
+// FP32 copies of whole arrays of n entries: dst[q][t] = (float) src.v[q][t]
+void launch_to_f32(const CoefSet<double> &src, float *const dst[COEF_SET], long long n, hipStream_t s);
 
 // ---- immersed boundary (ib.hip) ----
 struct Bins {

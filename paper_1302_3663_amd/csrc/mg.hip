@@ -1115,8 +1115,13 @@ __global__ void __launch_bounds__(256) k_load_unknowns(Grid g, VelBox boxes, int
 
 // coefficient ghost layer: every stored position writes its even images
 template <typename T>
-__global__ void __launch_bounds__(256) k_coef_ghosts(Grid g, Box box, int vmask, T *v)
+__global__ void __launch_bounds__(256) k_coef_ghosts(Grid g, CoefSet<T> set)
 {
+    const int q = blockIdx.y;
+    const int vmask = set.vmask[q];
+    T *v = set.v[q];
+    Box box{{0, 0, 0}, {1, 1, 1}};
+    for (int d = 0; d < 3; ++d) box.ext[d] = stored_extent(g, d, (vmask >> d) & 1);
     int i, j, k;
     if (!box_pos(box, blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
     write_images(g, vmask, ROLE_C, v, i, j, k, v[at(g, i, j, k)]);
@@ -2067,10 +2072,12 @@ void launch_load_unknowns(const Grid &g, int ncomp, const int *vmasks, const Vel
 }
 
 template <typename T>
-void launch_coef_ghosts(const Grid &g, int vmask, T *v, hipStream_t s)
+void launch_coef_ghosts(const Grid &g, const CoefSet<T> &set, hipStream_t s)
 {
-    const Box box = stored_box(g, vmask);
-    hipLaunchKernelGGL(k_coef_ghosts<T>, dim3(blocks_for(box_count(box))), dim3(256), 0, s, g, box, vmask, v);
+    long long mx = 0;
+    for (int q = 0; q < set.n; ++q) mx = std::max(mx, box_count(stored_box(g, set.vmask[q])));
+    if (set.n > 0 && mx > 0)
+        hipLaunchKernelGGL(k_coef_ghosts<T>, dim3(blocks_for(mx), set.n), dim3(256), 0, s, g, set);
 }
 
 int wg_lds_budget()
@@ -2338,7 +2345,7 @@ void launch_gcr_update(const Grid &g, int velocity, const double *num, const dou
                                         const VelArrC<T> &, const VelArr<T> &, hipStream_t);                        \
     template void launch_load_unknowns<T>(const Grid &, int, const int *, const VelArrC<T> &, const VelArr<T> &,    \
                                           hipStream_t);                                                             \
-    template void launch_coef_ghosts<T>(const Grid &, int, T *, hipStream_t);                                       \
+    template void launch_coef_ghosts<T>(const Grid &, const CoefSet<T> &, hipStream_t);                                       \
     template void launch_fill<T>(T *, long long, T, hipStream_t);
 INST(double)
 INST(float)
