@@ -11,6 +11,8 @@ from oracle import step as S
 from paper_1302_3663_amd import _lib as L
 from paper_1302_3663_amd import synth
 
+from parity import rel  # larger of the relative 2-norm and max-norm differences
+
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
@@ -24,10 +26,6 @@ def dev(x):
 def host(t):
     torch.cuda.synchronize()
     return t.detach().cpu().numpy()
-
-
-def rel(a, b):
-    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300)
 
 
 CASES = {

@@ -1,6 +1,10 @@
 """HIP path against the FP64 oracle, through the C interface, on the same
-seeded inputs.  Tolerance: 1e-12 relative (2-norm over the field) for FP64
-results; solves must take the same number of V-cycles as the oracle."""
+seeded inputs.  Tolerance: 1e-12 relative for FP64
+results, in the 2-norm and in the max norm of every field; solves must take
+the same number of V-cycles as the oracle.  Both sides are deterministic
+(fixed summation orders), so the differences measured here are repeatable:
+FP64 full steps differ by at most ~1e-14 in velocity and pressure and
+~1e-12 in the spring forces, whose sums cancel (springs near rest)."""
 import numpy as np
 import pytest
 
@@ -8,17 +12,13 @@ import oracle as O
 from oracle import step as S
 from paper_1302_3663_amd import synth
 
+from parity import rel  # larger of the relative 2-norm and max-norm differences
+
+
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
-
-
-def rel(a, b):
-    a = np.asarray(a, dtype=np.float64)
-    b = np.asarray(b, dtype=np.float64)
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
 def dev(x, dtype=torch.float64):
@@ -172,8 +172,8 @@ def test_full_steps(name, steps, ibmg_mod):
     u, pr = ctx.get_state()
     X, F, alive = ctx.get_nodes()
     assert rel(host(u), st.u) < TOL
-    assert rel(host(pr), st.pres) < 1e-11
+    assert rel(host(pr), st.pres) < TOL
     assert rel(host(X), st.X) < TOL
-    assert rel(host(F), st.F) < 1e-10
+    assert rel(host(F), st.F) < TOL
     assert np.array_equal(host(alive), st.alive)
     ctx.close()

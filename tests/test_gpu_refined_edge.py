@@ -15,17 +15,12 @@ from oracle import step as S
 from paper_1302_3663_amd import _lib as L
 from paper_1302_3663_amd import synth
 
+from parity import rel  # larger of the relative 2-norm and max-norm differences
+
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
-
-
-def rel(a, b):
-    a = np.asarray(a, np.float64)
-    b = np.asarray(b, np.float64)
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
 def dev(x, dtype=torch.float64):
@@ -104,23 +99,28 @@ def test_refined_solve(name, vel, inner, ibmg):
     ctx.close()
 
 
-@pytest.mark.parametrize("name", ["3d_tube", "channel2d_64x32"])
+@pytest.mark.parametrize("name", ["3d_tube", "channel2d_64x32", "2d_inout_walls"])
 def test_refined_full_steps(name, ibmg):
+    """Three refined steps against the FP64 oracle, velocity within 1e-9.
+    A relative residual of 1e-10 bounds the error of a solve only by the
+    condition number times 1e-10 (about 1e-8 here), so for this comparison
+    both sides solve to rtol 1e-12: their difference is then the refined
+    solver's own error, which must stay below 1e-9."""
     case = CASES[name]()
+    case["params"] = dict(case["params"], rtol=1e-12)
     print("case", name, flush=True)
     ctx = ibmg.from_case(case, precision=L.IBB_FP32_REFINED, inner_cycles=2)
     st = oracle_state(case)
     for n in range(3):
         sg = ctx.projection_step()
         S.projection_step(st)
-        assert sg["relres_u"] <= 1e-10 and sg["relres_p"] <= 1e-10
+        assert sg["relres_u"] <= 1e-12 and sg["relres_p"] <= 1e-12
         ctx.lagrangian_update()
         S.lagrangian_update(st)
     u, pr = ctx.get_state()
     X, _, _ = ctx.get_nodes()
-    # both solves stop at 1e-10; the trajectories agree to the error bound of
-    # the stopping test (conditioning times tolerance) rather than to rounding
-    assert rel(host(u), st.u) < 1e-8
+    print("velocity", rel(host(u), st.u), "positions", rel(host(X), st.X), flush=True)
+    assert rel(host(u), st.u) < 1e-9
     assert rel(host(X), st.X) < 1e-10
     ctx.close()
 

@@ -21,12 +21,10 @@ import oracle as O
 from paper_1302_3663_amd import _lib as L
 from paper_1302_3663_amd import synth
 
+from parity import rel  # larger of the relative 2-norm and max-norm differences
+
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
-
-
-def rel(a, b):
-    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b)
 
 
 def host(t):
@@ -196,4 +194,59 @@ def test_film_full_size_sampled():
     u_o = O.project(p, ut, pres, rho)
     c = p["eps"] * p["dt"] / p["sigma"]
     assert np.linalg.norm(O.divergence(p, u_o)) / c / np.linalg.norm(bp) <= 1e-10 * (1 + 1e-6)
+    ctx.close()
+
+
+@pytest.mark.timeout(1200)
+def test_tube_64x64x128_fp64_steps_against_oracle():
+    """Five full FP64 steps of the 64 x 64 x 128 tube (5 000 nodes, 72 532
+    springs), in the launch configuration bench.py times, against the oracle
+    stepped alongside: equal cycle counts in every solve, and velocity,
+    pressure, node positions, spring forces and alive flags within 1e-12 (both
+    norms) after the last step.  The oracle takes about half a minute per
+    step here (its hierarchy is assembled anew after every node move)."""
+    import time
+    from oracle import step as S
+    from paper_1302_3663_amd import ibmg
+    case = workload_case("tube3d_64x64x128")
+    t0 = time.time()
+    ctx = ibmg.from_case(case, precision=L.IBB_FP64)
+    st = S.State(case["params"], case["u0"], case["p0"], case["X"], case["ij"], case["rest"], case["K"])
+    S.setup(st)
+    for n in range(5):
+        sg = ctx.projection_step()
+        so = S.projection_step(st)
+        assert sg["cycles_u"] == so["u"]["cycles"] and sg["cycles_p"] == so["p"]["cycles"], (n, sg, so["u"], so["p"])
+        ctx.lagrangian_update()
+        S.lagrangian_update(st)
+        print(f"step {n}: cycles {sg['cycles_u']} {sg['cycles_p']}, {time.time() - t0:.0f} s", flush=True)
+    u, pr = [host(t) for t in ctx.get_state()]
+    X, F, alive = [host(t) for t in ctx.get_nodes()]
+    errs = dict(u=rel(u, st.u), p=rel(pr, st.pres), X=rel(X, st.X), F=rel(F, st.F))
+    print("differences after 5 steps", errs, flush=True)
+    assert all(e < 1e-12 for e in errs.values()), errs
+    assert np.array_equal(alive, st.alive)
+    ctx.close()
+
+
+@pytest.mark.timeout(900)
+def test_tube_64x64x128_refined_step_velocity():
+    """One refined step (FP32 V-cycles, 4 per FP64 correction) of the
+    64 x 64 x 128 tube against the oracle's FP64 step, both solved to a
+    relative residual of 1e-11 (the residual floor of these systems in FP64
+    lies near 1e-12): velocity within 1e-9 in both norms."""
+    from oracle import step as S
+    from paper_1302_3663_amd import ibmg
+    case = dict(workload_case("tube3d_64x64x128"))
+    case["params"] = dict(case["params"], rtol=1e-11)
+    ctx = ibmg.from_case(case, precision=L.IBB_FP32_REFINED, inner_cycles=4)
+    st = S.State(case["params"], case["u0"], case["p0"], case["X"], case["ij"], case["rest"], case["K"])
+    S.setup(st)
+    sg = ctx.projection_step()
+    so = S.projection_step(st)
+    assert sg["relres_u"] <= 1e-11 and sg["relres_p"] <= 1e-11
+    assert so["u"]["relres"] <= 1e-11 and so["p"]["relres"] <= 1e-11
+    u, _ = [host(t) for t in ctx.get_state()]
+    print("refined velocity against the oracle", rel(u, st.u), flush=True)
+    assert rel(u, st.u) < 1e-9
     ctx.close()
