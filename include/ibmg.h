@@ -254,6 +254,29 @@ ibb_status ibb_interp(ibb_ctx *ctx, double width, int64_t n, const double *X, co
  * `width` (eq:discrForceCouple); out is compact faces. */
 ibb_status ibb_spread(ibb_ctx *ctx, double width, int64_t n, const double *X, const double *F, double *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): the spread of
+ * ibb_spread without a context or workspace.  desc describes the grid (it
+ * must pass the checks of ibb_create); X [dim][n] and F [dim][n] are node
+ * positions and vectors, out receives the compact face field (every face
+ * lattice, written in full).  The work is enqueued on `stream` (a
+ * hipStream_t, NULL for the default stream) and the call does not wait for
+ * it; it allocates nothing.  Its scratch (the bins of the nodes and one padded
+ * face lattice of staging) is one static device array per GPU of
+ * IBB_SPREAD_STATIC_MAX_BYTES, held until the process ends and shared by
+ * every call on that GPU: calls that overlap on one GPU (several streams or
+ * host threads) race and must be serialised by the caller.  The scratch
+ * needs, each part rounded up to 256 bytes: 4 n (bin of each node) +
+ * 4 B (counts) + 4 (B + 1) (starts) + 4 n (sorted ids) + 4 (ceil(max(B, n + 1)
+ * / 1024) + 2) (scan sums) + 8 prod(n_a + 3) (staging), with B the number of
+ * bins, prod over the axes of floor(n_a h / (2 width)) (at least 1 each);
+ * IBB_ENOMEM if that exceeds the maximum (about 8 M padded grid points and a
+ * few million nodes), IBB_EINVAL for bad arguments (as ibb_spread), both
+ * before any work is enqueued; IBB_EDEVICE if the HIP runtime fails. */
+#define IBB_SPREAD_STATIC_MAX_BYTES (64u << 20)
+ibb_status ibb_spread_static(const ibb_desc *desc, double width, int64_t n, const double *X, const double *F,
+                             double *out, void *stream);
+
 /* Detached fragments (the results section observes pieces of biofilm
  * breaking off; the paper gives no algorithm): the connected components of
  * the graph of nodes joined by alive springs.  label (device, int32 [eta],

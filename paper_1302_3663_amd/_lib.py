@@ -128,6 +128,7 @@ ABI_FUNCTIONS = {
     "ibb_project": (ctypes.c_int, [CTX, VP, VP, VP]),
     "ibb_interp": (ctypes.c_int, [CTX, ctypes.c_double, I64, VP, VP, VP]),
     "ibb_spread": (ctypes.c_int, [CTX, ctypes.c_double, I64, VP, VP, VP]),
+    "ibb_spread_static": (ctypes.c_int, [DESC, ctypes.c_double, I64, VP, VP, VP, VP]),
     "ibb_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ibb_last_error": (ctypes.c_char_p, [CTX]),
     "ibb_profile_enable": (ctypes.c_int, [CTX, ctypes.c_int]),

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1830,6 +1831,107 @@ ibb_status ibb_spread(ibb_ctx *c, double width, int64_t n, const double *X, cons
     for (int a = 0; a < c->d.dim; ++a)
         launch_spread_face(L0.g, c->ph, b, X, F, n > 0 ? n : 1, a, width, L0.ru[a], nullptr, c->s);
     faces_out(c, 0, L0.ru, out);
+    HIPCHK(hipGetLastError());
+    return IBB_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Scratch of ibb_spread_static: the bins of the nodes and one face lattice
+// of staging, IBB_SPREAD_STATIC_MAX_BYTES per GPU, held until the process
+// ends.  In host code `spread_scratch` only names the symbol; kernels get the
+// device address that hipGetSymbolAddress returns for the current device.
+__device__ __align__(256) unsigned char spread_scratch[IBB_SPREAD_STATIC_MAX_BYTES];
+
+constexpr int SPREAD_STATIC_MAX_DEVICES = 64;
+std::mutex spread_scratch_mu;
+void *spread_scratch_ptr[SPREAD_STATIC_MAX_DEVICES] = {};
+
+// the current device's copy of the scratch array (looked up once per device)
+hipError_t spread_scratch_of_current(void **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= SPREAD_STATIC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(spread_scratch_mu);
+    if (!spread_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(spread_scratch));
+        if (e != hipSuccess) return e;
+        spread_scratch_ptr[dev] = p;
+    }
+    *out = spread_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
+extern "C" {
+
+ibb_status ibb_spread_static(const ibb_desc *desc, double width, int64_t n, const double *X, const double *F,
+                             double *out, void *stream)
+{
+    ibb_ctx *c = nullptr;   // no context: HIPCHK records no message
+    if (check_desc(desc) || n < 0 || n > INT32_MAX / 2 || (n > 0 && (!X || !F)) || !out || !(width > 0))
+        return IBB_EINVAL;
+    const double wmin = desc->omega < desc->h ? desc->omega : desc->h;
+    if (width < wmin) return IBB_EINVAL;
+    for (int a = 0; a < desc->dim; ++a)
+        if (desc->axis_bc[a] == IBB_AXIS_PERIODIC && 4.0 * width > desc->n[a] * desc->h) return IBB_EINVAL;
+    const Grid g = make_grid(desc, 0);
+    Bins b{};
+    bins_for_width(desc, width, b.nb, b.bs);
+    b.nbins = b.nb[0] * b.nb[1] * b.nb[2];
+    // the scratch layout: bin of each node, bin counts, bin starts, node ids
+    // by bin, scan block sums, one padded face lattice of staging
+    const size_t eta = (size_t)n;
+    const size_t o_bin = 0;
+    const size_t o_cnt = o_bin + align256(eta * sizeof(int));
+    const size_t o_start = o_cnt + align256((size_t)b.nbins * sizeof(int));
+    const size_t o_sorted = o_start + align256(((size_t)b.nbins + 1) * sizeof(int));
+    const size_t o_scan = o_sorted + align256(eta * sizeof(int));
+    const size_t o_stage =
+        o_scan + align256((size_t)scan_scratch_ints(std::max<long long>(b.nbins, (long long)eta + 1)) * sizeof(int));
+    const size_t need = o_stage + align256((size_t)g.nel * sizeof(double));
+    if (need > (size_t)IBB_SPREAD_STATIC_MAX_BYTES) return IBB_ENOMEM;
+    void *base = nullptr;
+    HIPCHK(spread_scratch_of_current(&base));
+    char *sc = static_cast<char *>(base);
+    b.bin_of = reinterpret_cast<int *>(sc + o_bin);
+    b.count = reinterpret_cast<int *>(sc + o_cnt);
+    b.start = reinterpret_cast<int *>(sc + o_start);
+    b.sorted = reinterpret_cast<int *>(sc + o_sorted);
+    int *scan_tmp = reinterpret_cast<int *>(sc + o_scan);
+    double *stage = reinterpret_cast<double *>(sc + o_stage);
+    Phys ph{};
+    ph.sigma = desc->sigma;
+    ph.eps = desc->eps;
+    ph.inv_re = desc->inv_re;
+    ph.force_coef = desc->force_coef;
+    ph.dt = desc->dt;
+    ph.rho0 = desc->rho0;
+    ph.rho_b = desc->rho_b;
+    ph.d0_pow_d = desc->d0_pow_d;
+    ph.mu_out = desc->mu_out;
+    ph.mu_max = desc->mu_max;
+    ph.omega = desc->omega;
+    ph.kernel = desc->kernel;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // the same launches as ibb_spread; the bin counts are cleared by the sort
+    // itself, and every stored face position of the staging is written
+    // before it is read
+    launch_bin_nodes(g, b, X, n > 0 ? n : 1, (int)n, scan_tmp, s);
+    long long off = 0;
+    for (int a = 0; a < desc->dim; ++a) {
+        launch_spread_face(g, ph, b, X, F, n > 0 ? n : 1, a, width, stage, nullptr, s);
+        launch_layout(g, face_mask(a), stage, out + off, false, s);
+        off += lattice_count(g, face_mask(a));
+    }
     HIPCHK(hipGetLastError());
     return IBB_OK;
 }

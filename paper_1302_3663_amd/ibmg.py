@@ -55,6 +55,23 @@ def footprint_bytes(params, max_nodes, max_springs, precision=L.IBB_FP64, inner_
     return n.value
 
 
+def spread_static(params, width, X, F, out=None, stream=None, check=True):
+    """ibb_spread_static: the spread of node vectors F [dim][n] at X to the
+    face lattices (compact) without a context; the library's static scratch
+    holds the bins.  Returns (out, status)."""
+    lib = L.load()
+    d = L.make_desc(params)
+    dev = X.device
+    if out is None:
+        out = torch.zeros(sum(face_counts(params)), dtype=torch.float64, device=dev)
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    st = lib.ibb_spread_static(ctypes.byref(d), float(width), X.shape[1], _ptr(X), _ptr(F), _ptr(out),
+                               ctypes.c_void_p(s.cuda_stream))
+    if check:
+        _chk(lib, st, "ibb_spread_static")
+    return out, st
+
+
 class Context:
     """One biofilm problem resident on a GPU."""
 
