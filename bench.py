@@ -46,24 +46,53 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "MG solve DOF/s at 1e-10 rel residual, FP32-refined vs FP64; p50/p99 latency"
 
-# kernel classes of ibb_profile_read and their algorithmic bytes per unknown
-# (minimum traffic of one full update or evaluation, in units of the word size)
-CLASS_NAMES = {0: "smooth_u_f64", 1: "smooth_p_f64", 2: "smooth_u_f32", 3: "smooth_p_f32", 4: "resid_u_f64",
-               5: "resid_p_f64"}
-KERNEL_SYMBOLS = {0: "k_smooth_u<double>", 1: "k_smooth_p<double>", 2: "k_smooth_u<float>", 3: "k_smooth_p<float>",
-                  4: "k_resid_u<double>", 5: "k_resid_p<double>"}
+# launch sites of ibb_profile_read (class = site + 32 x level): kernel symbol,
+# word size, and algorithmic words moved per unit (per unknown updated or
+# evaluated; a restriction per coarse unknown, the coarse cycle per unknown
+# of its start level) -- the minimum traffic of one pass
+SITES = {
+    0: ("k_smooth_u<double>", 8), 1: ("k_smooth_p<double>", 8), 2: ("k_smooth_u<float>", 4),
+    3: ("k_smooth_p<float>", 4), 4: ("k_resid_u<double>", 8), 5: ("k_resid_p<double>", 8),
+    6: ("k_resid_u<float>", 4), 7: ("k_resid_p<float>", 4), 8: ("k_restrict<double>", 8),
+    9: ("k_restrict<float>", 4), 10: ("k_prolong_add<double>", 8), 11: ("k_prolong_add<float>", 4),
+    12: ("k_coarse_vcycle<double, D, 1>", 8), 13: ("k_coarse_vcycle<double, D, 0>", 8),
+    14: ("k_coarse_vcycle<float, D, 1>", 4), 15: ("k_coarse_vcycle<float, D, 0>", 4),
+    16: ("k_dense_apply", 8), 17: ("outer-loop passes (norms, casts, clears, corrections)", 8),
+    18: ("GCR vector passes", 8), 19: ("k_smooth_u_dec<double>", 8), 20: ("k_smooth_u_dec<float>", 4),
+    21: ("k_smooth_rb<double>", 8), 22: ("k_smooth_rb<float>", 4),
+    23: ("k_spread_face", 8), 24: ("k_spread_visc", 8), 25: ("k_interp", 8), 26: ("k_spring_force", 8),
+}
+VISCOUS_SITES = {0, 2, 4, 6, 12, 14, 21, 22}
+PRESSURE_SITES = {1, 3, 5, 7, 13, 15}
 
 
-def words_per_unknown(cls, D, decoupled=False):
-    if decoupled and cls in (0, 2, 4):   # u_a read+write, b, rho
-        return 4
-    if cls in (0, 2, 4):   # u_a read+write (residual: read + r write), b, rho, mu_c, D-1 mu_e, D-1 u_b
-        return 5 + 2 * (D - 1)
-    return 2 + 1 + D       # p read+write (residual: read + r write), b, D beta
+def words_per_unit(site, D, decoupled=False):
+    """algorithmic words per unit of a launch site (see SITES)"""
+    if site in (19, 20) or (decoupled and site in (0, 2, 4, 6)):
+        return 4                                   # u_a read+write, b, rho
+    if site in (0, 2, 4, 6, 21, 22):               # u_a read+write (residual: read + r), b, rho, mu_c,
+        return 5 + 2 * (D - 1)                     # D-1 mu_e, D-1 other components
+    if site in (1, 3, 5, 7):
+        return 2 + 1 + D                           # p read+write, b, D beta
+    if site in (8, 9):
+        return 2 ** D + 2                          # fine residual, coarse b written, coarse x cleared
+    if site in (10, 11):
+        return 2 + 2.0 ** -D                       # fine x read+write, coarse x
+    if site in (12, 13, 14, 15):
+        return 6                                   # start level x read+write, b, its coefficients
+    if site == 23:
+        return 2                                   # per lattice point: f and rho written (gather)
+    if site == 24:
+        return 1                                   # per lattice point: mu written
+    if site == 25:
+        return 4 ** D + 1                          # per node and component: 4^D face values, U written
+    if site == 26:
+        return 3 * D + 20 * (D + 3)                # per node: X, F; about 20 springs: partner X, rest, K, ids
+    return 3
 
 
-def word_size(cls):
-    return 4 if cls in (2, 3) else 8
+def site_name(site, level, D):
+    return SITES[site][0].replace("D,", f"{D},") + f" (level {level})"
 
 
 def source_digest():
@@ -74,10 +103,10 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def committed_traffic(cls, workload):
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{CLASS_NAMES[cls]}_{workload}.md")
+def committed_traffic(site, level, workload):
+    """HBM bytes per launch from the committed counter summary of this launch
+    site and level, if it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_site{site}_level{level}_{workload}.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -86,6 +115,116 @@ def committed_traffic(cls, workload):
     if not m_sha or not m_val or m_sha.group(1) != source_digest():
         return None
     return float(m_val.group(1))
+
+
+def site_table(prof, D, steps, decoupled=False):
+    """Rows per launch site and level, largest device time first: launches,
+    device ms per step, average launch, algorithmic bytes per launch, the
+    bandwidth those bytes imply, and the share of all timed kernels of a step
+    (the solves and the Lagrangian update)."""
+    total = sum(v["total_ms"] for v in prof.values()) or 1.0
+    rows = []
+    for cls, v in prof.items():
+        site, level = cls % 32, cls // 32
+        bpl = words_per_unit(site, D, decoupled) * SITES[site][1] * v["units"] / v["launches"]
+        avg = v["total_ms"] / v["launches"]
+        rows.append(dict(site=site, level=level, kernel=site_name(site, level, D), launches=v["launches"],
+                         ms_per_step=v["total_ms"] / steps, avg_us=avg * 1e3, bytes_per_launch=bpl,
+                         gbs=bpl / (avg * 1e-3) / 1e9 if avg > 0 else 0.0, share=v["total_ms"] / total))
+    rows.sort(key=lambda r: -r["ms_per_step"])
+    return rows, total
+
+
+def unknown_extents(p, level, vmask):
+    """extent of the unknowns of a lattice along each axis on a level"""
+    ext = []
+    for d in range(p["dim"]):
+        n = p["n"][d] >> level
+        if not (vmask >> d) & 1:
+            ext.append(n)
+        else:
+            ext.append({0: n, 1: n - 1, 2: n}[p["axis_bc"][d]])
+    return ext + [1] * (3 - p["dim"])
+
+
+def site_launches(p, site, level):
+    """(kernel symbol, grid size in work-items or None for any) of the
+    launches of a smoother or coarse-cycle site, as rocprofv3 names them"""
+    D = p["dim"]
+    T = "float" if SITES[site][1] == 4 else "double"
+    if site in (12, 13, 14, 15):
+        return [(f"k_coarse_vcycle<{T}, {D}, {1 if site in (12, 14) else 0}>", None)]
+    out = []
+    if site in (0, 2):
+        comps = [(f"k_smooth_u<{T}, {D}, {a}>", 1 << a) for a in range(D)]
+    elif site in (1, 3):
+        comps = [(f"k_smooth_p<{T}, {D}>", 0)]
+    else:
+        return []
+    for sym, vmask in comps:
+        e = unknown_extents(p, level, vmask)
+        n = ((e[0] + 1) // 2) * e[1] * e[2]
+        out.append((sym, 256 * ((n + 255) // 256)))
+    return out
+
+
+def rocprof_average(p, site, level, workload):
+    """Average launch duration (us) of a launch site from the committed
+    rocprofv3 summary of this workload (rows per kernel symbol and grid
+    size), when that summary was taken on the current kernel sources; else
+    None."""
+    path = os.path.join(ROOT, "profiles", f"launch_sites_{workload}.md")
+    want = site_launches(p, site, level)
+    if not os.path.exists(path) or not want:
+        return None
+    text = open(path).read()
+    m_sha = re.search(r"source_digest:\s*([0-9a-f]+)", text)
+    if not m_sha or m_sha.group(1) != source_digest():
+        return None
+    calls, total = 0, 0.0
+    for line in text.splitlines():
+        cells = [c.strip().strip("`") for c in line.split("|")]
+        if len(cells) < 6:
+            continue
+        for sym, grid in want:
+            if cells[1] == sym and (grid is None or cells[2] == str(grid)):
+                try:
+                    c, avg = int(cells[3]), float(cells[4])
+                except ValueError:
+                    continue
+                calls += c
+                total += c * avg
+    return round(total / calls, 3) if calls else None
+
+
+def summarize_trace(csv_path, out_path, workload, command):
+    """rocprofv3 kernel-trace CSV -> markdown rows per kernel symbol and grid
+    size (calls, average and total device time), with the command that took
+    the trace and the digest of the kernel sources it ran."""
+    import csv
+    rows = {}
+    with open(csv_path) as f:
+        for r in csv.DictReader(f):
+            name = r.get("Kernel_Name", "")
+            m = re.search(r"(k_\w+)(<[^()]*>)?", name)
+            sym = (m.group(1) + (m.group(2) or "")) if m else name.split("(")[0]
+            if "Grid_Size_X" in r:
+                grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+            else:
+                grid = int(r.get("Grid_Size", 0))
+            us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            e = rows.setdefault((sym, grid), [0, 0.0])
+            e[0] += 1
+            e[1] += us
+    total_ms = sum(v[1] for v in rows.values()) / 1e3
+    lines = [f"# Launch sites: {workload}", "", "Command (run from /tmp with TMPDIR=/tmp on one MI355X):", "", "```",
+             command, "```", "", f"Kernels by symbol and grid size (work-items), largest total first; all kernels "
+             f"{total_ms:.1f} ms.", "", "| kernel | grid | calls | avg us | total ms |", "|---|---:|---:|---:|---:|"]
+    for (sym, grid), (n, us) in sorted(rows.items(), key=lambda kv: -kv[1][1])[:60]:
+        lines.append(f"| `{sym}` | {grid} | {n} | {us / n:.3f} | {us / 1e3:.3f} |")
+    lines += ["", f"source_digest: {source_digest()}", ""]
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines))
 
 
 def percentile(v, q):
@@ -132,7 +271,11 @@ def run_mode(case, precision, inner, steps, warmup, log, krylov=0, prof_steps=0)
             ctx.projection_step()
             ctx.lagrangian_update()
         torch.cuda.synchronize()
-        prof = {cls: ctx.profile_read(cls) for cls in CLASS_NAMES}
+        prof = {}
+        for cls in range(512):
+            r = ctx.profile_read(cls)
+            if r["launches"]:
+                prof[cls] = r
         ctx.profile_enable(False)
     ctx.close()
     return dict(dof_per_s=dof / (solve_ms / 1e3), wall_s=wall, ms_per_step=wall * 1e3 / steps, solve_ms=solve_ms,
@@ -163,7 +306,14 @@ def cpu_baseline(case, log):
     dof = H.nunk[0][0] + H.nunk[0][1]
     secs = (t1 - t0) + (t3 - t2)
     log(f"  oracle: viscous {t1 - t0:.1f} s ({su['cycles']} cycles), pressure {t3 - t2:.1f} s ({sp['cycles']} cycles)")
-    return dict(value=dof / secs, unit="DOF/s", cores=1, kind="oracle",
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
+    return dict(value=dof / secs, unit="DOF/s", cores=1, kind="oracle", cpu_model=model,
+                host_cpu_count=os.cpu_count(),
                 sample="one viscous and one pressure solve (FP64, V(2,2) to 1e-10) of the first step of the "
                        f"same workload, {secs:.1f} s single-threaded")
 
@@ -233,6 +383,8 @@ def run_serving(args, log):
         "peak_bytes": s["peak_bytes"],
         "busy_dof_per_s": round(s["busy_dof_per_s"], 1),
         "failed_steps": s["failed_steps"],
+        "group_build_s": round(s["group_build_s"], 3),
+        "wall_outside_ticks_s": round(s["wall_outside_ticks_s"], 3),
         "roofline": None,
         "cpu_baseline": None,
     }
@@ -265,7 +417,19 @@ def main():
                     help="also step the workload at uniform viscosity, coupled and constant-viscosity form")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="also run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--serving-requests", type=int, default=256,
+                    help="also run the serving stream with this many requests and report its latency keys (0: skip)")
+    ap.add_argument("--film", type=int, default=1, choices=[0, 1],
+                    help="also step the 256x256x512 film once per solver and report its sweep fractions")
+    ap.add_argument("--set", action="append", default=[], metavar="KEY=VALUE",
+                    help="override a workload parameter (descriptor field), e.g. smoother_zblock=1")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("CSV", "OUT_MD"),
+                    help="write the per-kernel summary of a rocprofv3 kernel-trace CSV and exit")
+    ap.add_argument("--trace-command", default="", help="with --summarize-trace: the command that took the trace")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace[0], args.summarize_trace[1], args.workload, args.trace_command)
+        return
     if args.inner is None:
         args.inner = 2 if args.workload == "serving" else 4
     if args.gpus != 1:
@@ -289,6 +453,9 @@ def main():
         return
     log(f"workload {args.workload}: generating inputs")
     case = synth.WORKLOADS[args.workload]()
+    for kv in args.set:
+        k, v = kv.split("=", 1)
+        case["params"][k] = type(case["params"].get(k, 0))(float(v)) if k in case["params"] else int(v)
     p = case["params"]
     modes = {"both": ["fp64", "refined"], "fp64": ["fp64"], "refined": ["refined"]}[args.modes]
     res = {}
@@ -311,6 +478,43 @@ def main():
                 f"{args.warmup} warmup + {args.steps} timed steps")
             const[dec] = run_mode(dict(case, params=cp), pkg.IBB_FP32_REFINED if "refined" in modes else pkg.IBB_FP64,
                                   args.inner, args.steps, args.warmup, log, prof_steps=args.steps)
+    serving = None
+    if args.serving_requests > 0:
+        sargs = argparse.Namespace(**vars(args))
+        sargs.requests, sargs.inner, sargs.warmup = args.serving_requests, 2, 4
+        sv = run_serving(sargs, log)
+        serving = {k: sv[k] for k in ("value", "p50_step_ms", "p99_step_ms", "p50_request_s", "p99_request_s",
+                                      "wall_s", "ticks", "peak_resident", "peak_bytes", "busy_dof_per_s",
+                                      "failed_steps")}
+        serving["unit"] = "DOF/s"
+        serving["requests"] = args.serving_requests
+        serving["rate_per_s"] = args.rate
+        for k in ("steps", "ms_per_step", "group_build_s", "wall_outside_ticks_s"):
+            if k in sv:
+                serving[k] = sv[k]
+    film = None
+    if args.film:
+        log("film3d_256x256x512: generating inputs")
+        fcase = synth.WORKLOADS["film3d_256x256x512"]()
+        film = {"grid": fcase["params"]["n"], "nodes": int(fcase["X"].shape[1])}
+        fres = {}
+        for m in ("fp64", "refined"):
+            log(f"film, mode {m}: 1 warmup + 1 timed step + 1 kernel-timed step")
+            fres[m] = run_mode(fcase, pkg.IBB_FP32_REFINED if m == "refined" else pkg.IBB_FP64, args.inner, 1, 1,
+                               log, prof_steps=1)
+            rows, _ = site_table(fres[m]["prof"], 3, 1)
+            sites = {}
+            for r in rows:
+                if r["level"] == 0 and r["site"] in (0, 2, 4, 23, 24, 25, 26):
+                    sites[r["kernel"]] = dict(avg_launch_us=round(r["avg_us"], 2), achieved=round(r["gbs"], 1),
+                                              frac=round(r["gbs"] / HBM_PEAK_GBS, 4),
+                                              algorithmic_bytes_per_launch=int(r["bytes_per_launch"]),
+                                              share_of_step_kernels=round(r["share"], 4))
+            film[m] = dict(dof_per_s=round(fres[m]["dof_per_s"], 1), ms_per_step=round(fres[m]["ms_per_step"], 3),
+                           cycles_u=fres[m]["cycles_u"][0], cycles_p=fres[m]["cycles_p"][0],
+                           largest_site=rows[0]["kernel"], level0=sites)
+        film["refined_over_fp64"] = round(fres["refined"]["dof_per_s"] / fres["fp64"]["dof_per_s"], 3)
+        del fcase
     if args.calibrate_copy > 0:
         n = args.calibrate_copy * (1 << 20) // 4
         a = torch.empty(n, dtype=torch.float32, device="cuda:0").fill_(1.0)
@@ -321,19 +525,36 @@ def main():
         log(f"copy calibration: 5 copies of {args.calibrate_copy} MiB")
     head = res["refined"] if "refined" in res else res["fp64"]
     head_mode = "refined" if "refined" in res else "fp64"
-    # roofline of the dominant finest-level kernel of the headline mode
+    # roofline of the launch site with the largest device time per step in
+    # the headline mode (kernel-by-kernel steps after the timed ones)
     D = p["dim"]
-    dom = max(head["prof"], key=lambda c: head["prof"][c]["total_ms"])
-    pr = head["prof"][dom]
-    bpu = words_per_unknown(dom, D) * word_size(dom)
-    per_launch_bytes = bpu * pr["units"] / max(pr["launches"], 1)
-    avg_ms = pr["total_ms"] / max(pr["launches"], 1)
-    achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
-    traffic = committed_traffic(dom, args.workload)
-    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=KERNEL_SYMBOLS[dom],
-                avg_launch_us=round(avg_ms * 1e3, 2), launches=pr["launches"],
-                algorithmic_bytes_per_launch=int(per_launch_bytes), bytes_per_unknown=bpu)
+    rows, _ = site_table(head["prof"], D, args.steps)
+    dom = rows[0]
+    roof = dict(bound="hbm", achieved=round(dom["gbs"], 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(dom["gbs"] / HBM_PEAK_GBS, 4),
+                traffic=committed_traffic(dom["site"], dom["level"], args.workload),
+                kernel=dom["kernel"], avg_launch_us=round(dom["avg_us"], 2), launches=dom["launches"],
+                algorithmic_bytes_per_launch=int(dom["bytes_per_launch"]),
+                bytes_per_unit=words_per_unit(dom["site"], D) * SITES[dom["site"]][1],
+                device_ms_per_step=round(dom["ms_per_step"], 3), share_of_step_kernels=round(dom["share"], 4))
+    if dom["site"] in (12, 13, 14, 15, 16):
+        roof["limited_by"] = "latency (one workgroup, barriers between passes)"
+    rp = rocprof_average(p, dom["site"], dom["level"], args.workload)
+    if rp:
+        roof["rocprof_avg_launch_us"] = rp
+        roof["rocprof_frac"] = round(dom["bytes_per_launch"] / (rp * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+    # the finest-level viscous sweep of the headline mode (the pass the
+    # bandwidth target is about), whether or not it dominates
+    sw = next((r for r in rows if r["site"] == (2 if head_mode == "refined" else 0) and r["level"] == 0), None)
+    sweep = None
+    if sw:
+        sweep = dict(kernel=sw["kernel"], achieved=round(sw["gbs"], 1), frac=round(sw["gbs"] / HBM_PEAK_GBS, 4),
+                     avg_launch_us=round(sw["avg_us"], 2), algorithmic_bytes_per_launch=int(sw["bytes_per_launch"]),
+                     device_ms_per_step=round(sw["ms_per_step"], 3), share_of_step_kernels=round(sw["share"], 4))
+        rs = rocprof_average(p, sw["site"], sw["level"], args.workload)
+        if rs:
+            sweep["rocprof_avg_launch_us"] = rs
+            sweep["rocprof_frac"] = round(sw["bytes_per_launch"] / (rs * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle")
@@ -353,6 +574,7 @@ def main():
         "dtype": "f32-inner/f64-outer" if head_mode == "refined" else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": p["n"][:p["dim"]], "nodes": int(case["X"].shape[1]),
+                   "overrides": args.set or None,
                    "springs": int(case["ij"].shape[1]), "viscosity_ratio": p["mu_max"] / p["mu_out"],
                    "density_ratio": (p["rho0"] + p["rho_b"]) / p["rho0"], "rtol": p["rtol"],
                    "nu": [p["nu1"], p["nu2"]], "gamma_2h": p["gamma"][1], "precision": head_mode,
@@ -360,7 +582,10 @@ def main():
         "p50_step_ms": round(percentile(all_steps, 50), 3),
         "p99_step_ms": round(percentile(all_steps, 99), 3),
         "roofline": roof,
+        "sweep": sweep,
         "cpu_baseline": cpu,
+        "serving": serving,
+        "film3d_256x256x512": film,
     }
     for m in res:
         r = res[m]
@@ -370,9 +595,10 @@ def main():
                       mean_vcycles=float(np.mean(r["vcycles"])), max_relres=r["max_relres"],
                       p50_step_ms=round(percentile(r["step_ms"], 50), 3),
                       p99_step_ms=round(percentile(r["step_ms"], 99), 3),
-                      kernels={CLASS_NAMES[c]: dict(launches=v["launches"], avg_us=round(
-                          1e3 * v["total_ms"] / max(v["launches"], 1), 2), total_ms=round(v["total_ms"], 3))
-                          for c, v in r["prof"].items() if v["launches"]})
+                      sites=[dict(kernel=t["kernel"], launches=t["launches"], avg_us=round(t["avg_us"], 2),
+                                  ms_per_step=round(t["ms_per_step"], 3), share=round(t["share"], 4),
+                                  frac=round(t["gbs"] / HBM_PEAK_GBS, 4))
+                             for t in site_table(r["prof"], D, args.steps)[0][:10]])
     if "fp64" in res and "refined" in res:
         out["refined_over_fp64"] = round(res["refined"]["dof_per_s"] / res["fp64"]["dof_per_s"], 3)
     if gcr:
@@ -386,20 +612,21 @@ def main():
                                  p99_step_ms=round(percentile(r["step_ms"], 99), 3),
                                  speedup_vs_plain=round(r["dof_per_s"] / res[m]["dof_per_s"], 3))
     if const:
-        sm = 2 if "refined" in modes else 0
+        refined_cv = "refined" in modes
         cv = {"viscosity_ratio": 1.0, "precision": head_mode}
         for dec, key in ((0, "coupled"), (1, "decoupled")):
             r = const[dec]
-            pr = r["prof"][sm]
+            sm = (20 if refined_cv else 19) if dec else (2 if refined_cv else 0)
+            pr = r["prof"].get(sm, dict(launches=0, total_ms=0.0, units=0))
             avg_ms = pr["total_ms"] / max(pr["launches"], 1)
-            bpl = words_per_unknown(sm, D, bool(dec)) * word_size(sm) * pr["units"] / max(pr["launches"], 1)
+            bpl = words_per_unit(sm, D, bool(dec)) * SITES[sm][1] * pr["units"] / max(pr["launches"], 1)
             gbs = bpl / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
             cv[key] = dict(dof_per_s=round(r["dof_per_s"], 1), ms_per_step=round(r["ms_per_step"], 3),
                            solve_ms_per_step=round(r["solve_ms"] / args.steps, 3),
                            mean_cycles_u=float(np.mean(r["cycles_u"])), mean_cycles_p=float(np.mean(r["cycles_p"])),
                            max_relres=r["max_relres"],
-                           smoother=dict(kernel="k_smooth_u_dec" if dec else KERNEL_SYMBOLS[sm],
-                                         launches=pr["launches"], avg_launch_us=round(avg_ms * 1e3, 2),
+                           smoother=dict(kernel=SITES[sm][0], launches=pr["launches"],
+                                         avg_launch_us=round(avg_ms * 1e3, 2),
                                          algorithmic_bytes_per_launch=int(bpl), achieved_gbs=round(gbs, 1),
                                          frac=round(gbs / HBM_PEAK_GBS, 4)))
         cv["decoupled_over_coupled"] = round(const[1]["dof_per_s"] / const[0]["dof_per_s"], 3)

@@ -132,6 +132,18 @@ typedef struct {
      * level); needs mu_max == mu_out, otherwise IBB_EINVAL.  The components'
      * smoothing passes of one colour share a launch. */
     int decoupled;
+    /* 0: the levels below the start of the one-workgroup cycle (see
+     * wg_coarse_max) are applied as their linear map, a matrix rebuilt with
+     * every coefficient update by running those levels' passes on each unit
+     * right-hand side (when the level below the start has at most 512
+     * unknowns and all levels from there fit one workgroup's LDS); it gives
+     * the same result as the recursion up to rounding.  < 0: always recurse. */
+    int coarse_tail;
+    /* 1: colour passes of launched 3D levels walk z in blocks of planes (one
+     * workgroup per band of rows and run of 16 planes) instead of one point
+     * per thread across the whole level; same bits, slower on the grids
+     * measured here.  0 (default) or < 0: one point per thread. */
+    int smoother_zblock;
 } ibb_desc;
 
 typedef struct {
@@ -328,15 +340,35 @@ const char *ibb_group_last_error(const ibb_group *group);
 
 /* --- diagnostics ----------------------------------------------------------- */
 
-/* Device timing of the finest-level multigrid kernels.  While enabled, every
- * launch of a finest-level smoother colour pass or residual carries a pair of
- * HIP events that its dispatch records at the kernel's start and end (on the
- * context's stream); the durations accumulate per kernel class until read.
- * Classes: 0 viscous smoother FP64, 1 pressure smoother FP64, 2 viscous
- * smoother FP32, 3 pressure smoother FP32, 4 viscous residual FP64,
- * 5 pressure residual FP64.  ibb_profile_read (host outputs) returns the
- * launches, their summed device time and the summed number of unknowns they
- * updated or evaluated; enabling resets the totals. */
+/* Device timing of the solver kernels.  While enabled, every launch of a
+ * multigrid solve (and the main kernels of the Lagrangian update) carries a
+ * pair of HIP events that its dispatch records at
+ * the kernel's start and end (on the context's stream; solver iterations are
+ * then launched kernel by kernel instead of as graph replays); the durations
+ * accumulate per kernel class until read.  kernel_class = site + 32 x level,
+ * level the multigrid level the launch works on (for a restriction the
+ * coarse one, for the one-workgroup coarse cycle its start level), site:
+ *    0 viscous smoother colour pass FP64      1 pressure smoother FP64
+ *    2 viscous smoother FP32                  3 pressure smoother FP32
+ *    4 viscous residual FP64                  5 pressure residual FP64
+ *    6 viscous residual FP32                  7 pressure residual FP32
+ *    8 restriction FP64                       9 restriction FP32
+ *   10 prolongation FP64                     11 prolongation FP32
+ *   12 one-workgroup coarse cycle, viscous FP64   13 ... pressure FP64
+ *   14 one-workgroup coarse cycle, viscous FP32   15 ... pressure FP32
+ *   16 coarsest dense solve apply            17 outer-loop passes of level 0
+ *      (norms, reductions, FP32 casts, clears, FP64 corrections)
+ *   18 GCR vector passes                     19/20 constant-viscosity
+ *      smoother FP64/FP32                    21/22 one-launch red-black
+ *      sweep FP64/FP32
+ * and, in the Lagrangian update (level 0): 23 spread of force and density
+ * (per face lattice, units = its points), 24 viscosity gather (per cell or
+ * edge lattice), 25 interpolation (units = nodes x dim), 26 spring forces
+ * (units = nodes)
+ * ibb_profile_read (host outputs) returns the launches, their summed device
+ * time and the summed number of unknowns they updated or evaluated (for the
+ * cycle, the start level's unknowns); enabling resets the totals. */
+#define IBB_PROFILE_CLASSES 512
 ibb_status ibb_profile_enable(ibb_ctx *ctx, int enable);
 ibb_status ibb_profile_read(ibb_ctx *ctx, int kernel_class, long long *launches, double *total_ms,
                             long long *units);

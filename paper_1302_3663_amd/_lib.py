@@ -54,6 +54,8 @@ class Desc(ctypes.Structure):
         ("krylov_restart", ctypes.c_int),
         ("smoother_passes", ctypes.c_int),
         ("decoupled", ctypes.c_int),
+        ("coarse_tail", ctypes.c_int),
+        ("smoother_zblock", ctypes.c_int),
     ]
 
 
@@ -97,6 +99,8 @@ def make_desc(p, precision=IBB_FP64, inner_cycles=1):
     d.krylov_restart = int(p.get("krylov_restart", 0))
     d.smoother_passes = int(p.get("smoother_passes", 0))
     d.decoupled = int(p.get("decoupled", 0))
+    d.coarse_tail = int(p.get("coarse_tail", 0))
+    d.smoother_zblock = int(p.get("smoother_zblock", 0))
     return d
 
 

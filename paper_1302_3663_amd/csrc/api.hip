@@ -43,6 +43,8 @@ struct Level {
     // times mu_out and the product of gamma down to this level
     double cvu = 0;
     int dec = 0;
+    // colour passes of this level z-blocked (3D launched levels)
+    int zb = 0;
 };
 
 struct Carver {
@@ -87,6 +89,12 @@ struct ibb_ctx {
     // 1: FP32) and system (0: pressure, 1: velocity)
     LdsLevel *ldslev[2][2] = {};
     int lds_ls[2][2] = {}, lds_bytes[2][2] = {};
+    // tails of the one-workgroup cycle per system (0 pressure, 1 velocity),
+    // in the precision of the context's V-cycles: matrix, unknown list, and
+    // the plan that stages every level of the tail for the column build
+    Tail tail[2] = {};
+    LdsLevel *tplan[2] = {};
+    int tplan_bytes[2] = {};
     // nodes and springs
     long long eta_max = 0, m_max = 0;
     int eta = 0, m = 0;
@@ -122,9 +130,9 @@ struct ibb_ctx {
     std::vector<int> pcls;                 // class of each recorded pair
     std::vector<long long> punits;         // unknowns of each recorded pair
     int pused = 0;
-    long long plaunch[8] = {};
-    double pms[8] = {};
-    long long punit_tot[8] = {};
+    long long plaunch[IBB_PROFILE_CLASSES] = {};
+    double pms[IBB_PROFILE_CLASSES] = {};
+    long long punit_tot[IBB_PROFILE_CLASSES] = {};
     std::string err;
 };
 
@@ -147,11 +155,39 @@ ibb_status fail(ibb_ctx *c, ibb_status st, const char *msg)
 
 constexpr int PROF_PAIRS = 2048;
 
+// launch sites of the solvers (ibb_profile_read class = site + 32 x level)
+enum ProfSite {
+    PS_SMOOTH_U64 = 0, PS_SMOOTH_P64 = 1, PS_SMOOTH_U32 = 2, PS_SMOOTH_P32 = 3,
+    PS_RESID_U64 = 4, PS_RESID_P64 = 5, PS_RESID_U32 = 6, PS_RESID_P32 = 7,
+    PS_RESTRICT64 = 8, PS_RESTRICT32 = 9, PS_PROLONG64 = 10, PS_PROLONG32 = 11,
+    PS_COARSE_U64 = 12, PS_COARSE_P64 = 13, PS_COARSE_U32 = 14, PS_COARSE_P32 = 15,
+    PS_DENSE = 16, PS_OUTER = 17, PS_GCR = 18, PS_SMOOTH_UDEC64 = 19, PS_SMOOTH_UDEC32 = 20,
+    PS_SMOOTH_RB64 = 21, PS_SMOOTH_RB32 = 22,
+    // the Lagrangian update (level 0)
+    PS_SPREAD_FACE = 23, PS_SPREAD_VISC = 24, PS_INTERP = 25, PS_SPRING_FORCE = 26
+};
+
+inline int prof_class(int site, int level) { return site + 32 * level; }
+
+int prof_begin(ibb_ctx *c, int cls, long long units);
+void prof_end(ibb_ctx *, int k);
+
+// times the next launch within its scope (when kernel timing is on)
+struct Timed {
+    ibb_ctx *c;
+    int k;
+    Timed(ibb_ctx *c_, int site, int level, long long units) : c(c_), k(prof_begin(c_, prof_class(site, level), units)) {}
+    ~Timed() { prof_end(c, k); }
+};
+
+void prof_flush(ibb_ctx *c);
+
 // time the next launch (of class cls): its dispatch records the kernel's
 // start and end into the slot's event pair; returns the slot or -1
 int prof_begin(ibb_ctx *c, int cls, long long units)
 {
-    if (!c->prof || c->pused >= PROF_PAIRS) return -1;
+    if (!c->prof || cls < 0 || cls >= IBB_PROFILE_CLASSES) return -1;
+    if (c->pused >= PROF_PAIRS) prof_flush(c);
     const int k = c->pused++;
     c->pcls[k] = cls;
     c->punits[k] = units;
@@ -336,6 +372,16 @@ size_t carve(ibb_ctx *c, char *base, bool dry)
     c->tab32 = cv.take<LevTab<float>>(MAXLEV);
     for (int pr = 0; pr < 2; ++pr)
         for (int v = 0; v < 2; ++v) c->ldslev[pr][v] = cv.take<LdsLevel>(WG_MAXLEV);
+    for (int v = 0; v < 2; ++v) {
+        Tail &t = c->tail[v];
+        if (t.n <= 0) continue;
+        const size_t w = refined ? sizeof(float) : sizeof(double);
+        const size_t ld = w == 4 ? ((size_t)t.n + 3) & ~(size_t)3 : ((size_t)t.n + 1) & ~(size_t)1;
+        t.Tm = cv.take<char>((size_t)t.n * ld * w);
+        t.idx = cv.take<long long>((size_t)t.n);
+        t.comp = cv.take<int>((size_t)t.n);
+        c->tplan[v] = cv.take<LdsLevel>(WG_MAXLEV);
+    }
     c->partial = cv.take<double>(3 * NORM_BLOCKS);
     c->scalar = cv.take<double>(8);
     const size_t em = (size_t)(c->eta_max > 0 ? c->eta_max : 1);
@@ -379,6 +425,25 @@ size_t carve(ibb_ctx *c, char *base, bool dry)
     return cv.off + 256;
 }
 
+// LDS per workgroup that the tail decision assumes (gfx950: 160 KB, less
+// the kernels' own shared data); fixed, so that footprints do not depend on
+// the device queried
+constexpr int TAIL_LDS_BUDGET = 163840 - (int)(WG_MAXLEV * sizeof(LevTab<double>)) - 1024 -
+                                (int)(TAIL_MAX * sizeof(double));
+
+// bytes of one level's array in the arena, and of every level from lt down
+// staged whole (solver arrays and coefficients of one system)
+int arena_array_bytes(const Grid &g, int wsz) { return (int)(((g.nel * wsz + 15) / 16) * 16); }
+
+long long tail_lds_bytes(const ibb_ctx *c, bool f32, bool vel, int lt)
+{
+    const int D = c->d.dim;
+    const int nsolve = vel ? 3 * D : 3, ncoef = vel ? D + 1 + c->E : D;
+    long long b = 0;
+    for (int l = lt; l < c->L; ++l) b += (long long)arena_array_bytes(c->lv[l].g, f32 ? 4 : 8) * (nsolve + ncoef);
+    return b;
+}
+
 void setup_shapes(ibb_ctx *c, const ibb_desc *d, int64_t max_nodes, int64_t max_springs)
 {
     c->d = *d;
@@ -417,6 +482,25 @@ void setup_shapes(ibb_ctx *c, const ibb_desc *d, int64_t max_nodes, int64_t max_
         for (int l = 0; l < c->L; ++l)
             if ((c->lv[l].np + 1) / 2 <= wgmax) { c->lc_p = l; break; }
     }
+    // tails: the levels below the one-workgroup start level as one matrix,
+    // when the level below the start has at most TAIL_MAX unknowns and all
+    // levels from there fit the LDS arena of one workgroup (gfx950: 160 KB,
+    // less the kernels' own shared data), so that the columns can be built
+    // one workgroup each
+    for (int v = 0; v < 2; ++v) {
+        c->tail[v] = Tail{};
+        const int lc = v ? c->lc_u : c->lc_p;
+        if (d->coarse_tail < 0 || lc >= c->L - 1) continue;
+        const int lt = lc + 1;
+        const long long n = v ? c->lv[lt].nu : c->lv[lt].np;
+        if (n < 1 || n > TAIL_MAX) continue;
+        if (tail_lds_bytes(c, d->precision == IBB_FP32_REFINED, v == 1, lt) > TAIL_LDS_BUDGET) continue;
+        c->tail[v].n = (int)n;
+        c->tail[v].level = lt;
+    }
+    // z-blocked colour passes on every 3D level when asked for (measured
+    // slower than the flat passes, so not the default)
+    for (int l = 0; l < c->L; ++l) c->lv[l].zb = d->dim == 3 && d->smoother_zblock > 0 ? 1 : 0;
     // levels swept with launched passes may use the one-launch red-black
     // sweep: an even number of sweeps per cycle, even periodic extents
     for (int l = 0; l < c->L; ++l) {
@@ -530,11 +614,11 @@ void sweep(ibb_ctx *c, bool vel, int l)
         const T cvp = (T)(1.0 / (L.g.h * L.g.h));
         const T cvu = (T)L.cvu;
         const T mass = (T)(c->d.sigma / c->d.dt);
-        const int cls = (vel ? 0 : 1) + (sizeof(T) == 4 ? 2 : 0);
+        const int cls = prof_class(sizeof(T) == 4 ? PS_SMOOTH_RB32 : PS_SMOOTH_RB64, l);
         for (int a = 0; a < (vel ? c->d.dim : 1); ++a) {
             View<T> v = view<T>(L);
             const VelArrC<T> xin = vel ? cview(v.xu) : VelArrC<T>{{v.xp, nullptr, nullptr}};
-            const int k = l == 0 ? prof_begin(c, cls, unknowns_of(L.g, vel ? face_mask(a) : 0)) : -1;
+            const int k = prof_begin(c, cls, unknowns_of(L.g, vel ? face_mask(a) : 0));
             launch_smooth_rb<T>(L.g, vel ? 1 : 0, a, xin, vel ? v.bu.c[a] : v.bp, v.cu, v.cp, mass, vel ? cvu : cvp,
                                 *alt_x<T>(L, vel, a), c->s);
             prof_end(c, k);
@@ -546,26 +630,26 @@ void sweep(ibb_ctx *c, bool vel, int l)
     const T cvp = (T)(1.0 / (L.g.h * L.g.h));
     const T cvu = (T)L.cvu;
     const T mass = (T)(c->d.sigma / c->d.dt);
-    const int cls = (vel ? 0 : 1) + (sizeof(T) == 4 ? 2 : 0);
+    const int cls = prof_class((vel ? 0 : 1) + (sizeof(T) == 4 ? 2 : 0), l);
     if (vel && L.dec) {
         for (int colour = 0; colour < 2; ++colour) {
             long long units = 0;
             for (int a = 0; a < c->d.dim; ++a) units += unknowns_of(L.g, face_mask(a)) / 2;
-            const int k = l == 0 ? prof_begin(c, cls, units) : -1;
+            const int k = prof_begin(c, prof_class(sizeof(T) == 4 ? PS_SMOOTH_UDEC32 : PS_SMOOTH_UDEC64, l), units);
             launch_smooth_u_dec<T>(L.g, cview(v.bu), v.xu, v.cu, mass, cvu, colour, c->s);
             prof_end(c, k);
         }
     } else if (vel) {
         for (int a = 0; a < c->d.dim; ++a)
             for (int colour = 0; colour < 2; ++colour) {
-                const int k = l == 0 ? prof_begin(c, cls, unknowns_of(L.g, face_mask(a)) / 2) : -1;
-                launch_smooth_u<T>(L.g, a, v.bu.c[a], v.xu, v.cu, mass, cvu, colour, c->s);
+                const int k = prof_begin(c, cls, unknowns_of(L.g, face_mask(a)) / 2);
+                launch_smooth_u<T>(L.g, a, v.bu.c[a], v.xu, v.cu, mass, cvu, colour, c->s, L.zb);
                 prof_end(c, k);
             }
     } else {
         for (int colour = 0; colour < 2; ++colour) {
-            const int k = l == 0 ? prof_begin(c, cls, L.np / 2) : -1;
-            launch_smooth_p<T>(L.g, v.bp, v.xp, v.cp, cvp, colour, c->s);
+            const int k = prof_begin(c, cls, L.np / 2);
+            launch_smooth_p<T>(L.g, v.bp, v.xp, v.cp, cvp, colour, c->s, L.zb);
             prof_end(c, k);
         }
     }
@@ -580,22 +664,103 @@ int residual(ibb_ctx *c, bool vel, int l, double *partial)
     const T cvp = (T)(1.0 / (L.g.h * L.g.h));
     const T cvu = (T)L.cvu;
     const T mass = (T)(c->d.sigma / c->d.dt);
-    if (vel) return launch_resid_u<T>(L.g, cview(v.bu), v.xu, v.cu, mass, cvu, v.ru, partial, c->s);
-    return launch_resid_p<T>(L.g, v.bp, v.xp, v.cp, cvp, v.rp, partial, c->s);
+    const int site = (vel ? PS_RESID_U64 : PS_RESID_P64) + (sizeof(T) == 4 ? 2 : 0);
+    const int k = prof_begin(c, prof_class(site, l), vel ? L.nu : L.np);
+    const int np = vel ? launch_resid_u<T>(L.g, cview(v.bu), v.xu, v.cu, mass, cvu, v.ru, partial, c->s)
+                       : launch_resid_p<T>(L.g, v.bp, v.xp, v.cp, cvp, v.rp, partial, c->s);
+    prof_end(c, k);
+    return np;
 }
 
 // LDS plan of the one-workgroup cycle: the deepest levels whose arrays fit
 // the workgroup's LDS budget, laid out level by level
+// whether the context's V-cycles in precision prec (0 FP64, 1 FP32) use the
+// tail of system vel
+bool has_tail(const ibb_ctx *c, int prec, bool vel)
+{
+    return c->tail[vel ? 1 : 0].n > 0 && prec == (c->d.precision == IBB_FP32_REFINED ? 1 : 0);
+}
+
+void clear_plan(std::vector<LdsLevel> &out)
+{
+    out.assign(WG_MAXLEV, LdsLevel{});
+    for (LdsLevel &o : out) {
+        for (int a = 0; a < 3; ++a) o.xu[a] = o.bu[a] = o.ru[a] = o.rho[a] = o.beta[a] = o.mue[a] = -1;
+        o.xp = o.bp = o.rp = o.muc = -1;
+    }
+}
+
+// place level l's arrays of one system in the arena from offset *off:
+// solver arrays (x only, or x, b and r) and, with coefs, the coefficients
+void place_level(const ibb_ctx *c, bool vel, int l, int wsz, bool x_only, bool coefs, LdsLevel &o, int *off)
+{
+    const int one = arena_array_bytes(c->lv[l].g, wsz);
+    auto take = [&]() { const int r = *off; *off += one; return r; };
+    if (vel) {
+        for (int a = 0; a < c->d.dim; ++a) {
+            o.xu[a] = take();
+            if (!x_only) {
+                o.bu[a] = take();
+                o.ru[a] = take();
+            }
+            if (coefs) o.rho[a] = take();
+        }
+        if (coefs) {
+            o.muc = take();
+            for (int e = 0; e < c->E; ++e) o.mue[c->edge_axis[e]] = take();
+        }
+    } else {
+        o.xp = take();
+        if (!x_only) {
+            o.bp = take();
+            o.rp = take();
+        }
+        if (coefs)
+            for (int a = 0; a < c->d.dim; ++a) o.beta[a] = take();
+    }
+}
+
+// LDS plan of a tail's column build: every level from the tail's level down,
+// whole (the tail exists only when they fit)
+void plan_tail_build(ibb_ctx *c, bool vel, std::vector<LdsLevel> &out)
+{
+    clear_plan(out);
+    const Tail &t = c->tail[vel ? 1 : 0];
+    const int wsz = c->d.precision == IBB_FP32_REFINED ? 4 : 8;
+    int off = 0;
+    for (int l = t.level; l < c->L; ++l) place_level(c, vel, l, wsz, false, true, out[l], &off);
+    c->tplan_bytes[vel ? 1 : 0] = off;
+}
+
 void plan_lds(ibb_ctx *c, int prec, bool vel, std::vector<LdsLevel> &out)
 {
     const int wsz = prec ? 4 : 8;
     const int D = c->d.dim;
     const int lc = std::min(vel ? c->lc_u : c->lc_p, c->L - 1);
     const int budget = wg_lds_budget();
-    out.assign(WG_MAXLEV, LdsLevel{});
-    for (LdsLevel &o : out) {
-        for (int a = 0; a < 3; ++a) o.xu[a] = o.bu[a] = o.ru[a] = o.rho[a] = o.beta[a] = o.mue[a] = -1;
-        o.xp = o.bp = o.rp = o.muc = -1;
+    clear_plan(out);
+    if (has_tail(c, prec, vel)) {
+        // the cycle works on the start level and writes the tail level's
+        // iterate: stage the start level whole, or its solver arrays, and
+        // the tail level's x
+        const int lt = c->tail[vel ? 1 : 0].level;
+        const int nsolve = vel ? 3 * D : 3, ncoef = vel ? D + 1 + c->E : D;
+        const long long one = arena_array_bytes(c->lv[lc].g, wsz);
+        const long long xt = (long long)arena_array_bytes(c->lv[lt].g, wsz) * (vel ? D : 1);
+        int off = 0;
+        int ls = lt;
+        if (one * (nsolve + ncoef) + xt <= budget) {
+            place_level(c, vel, lc, wsz, false, true, out[lc], &off);
+            ls = lc;
+        } else if (one * nsolve + xt <= budget) {
+            place_level(c, vel, lc, wsz, false, false, out[lc], &off);
+            ls = lc;
+        }
+        if (xt <= budget) place_level(c, vel, lt, wsz, true, false, out[lt], &off);
+        else ls = c->L;
+        c->lds_ls[prec][vel ? 1 : 0] = ls;
+        c->lds_bytes[prec][vel ? 1 : 0] = off;
+        return;
     }
     // bytes of one level's arrays in this system: solver arrays (x, b, r)
     // and coefficients
@@ -675,15 +840,19 @@ void vcycle(ibb_ctx *c, bool vel, int l)
         Level &LC = c->lv[c->L - 1];
         const long long nc = vel ? LC.nu : LC.np;
         const int ndense = nc <= DENSE_MAX ? (int)nc : 0;
+        Timed t(c, (vel ? PS_COARSE_U64 : PS_COARSE_P64) + (sizeof(T) == 4 ? 2 : 0), l, vel ? L.nu : L.np);
+        const int prec = sizeof(T) == 4 ? 1 : 0;
         launch_coarse_vcycle<T>(D, level_table<T>(c), l, c->L, vel ? 1 : 0, c->d.nu1, c->d.nu2, ndense,
                                 vel ? c->uidx_u : c->uidx_p, vel ? c->ucomp_u : c->ucomp_p, vel ? c->Mu : c->Mp,
-                                lds_plan(c, sizeof(T) == 4 ? 1 : 0, vel), c->s);
+                                lds_plan(c, prec, vel), has_tail(c, prec, vel) ? c->tail[vel ? 1 : 0] : Tail{},
+                                c->s);
         return;
     }
     View<T> v = view<T>(L);
     if (l == c->L - 1) {
         const long long n = vel ? L.nu : L.np;
         if (n <= DENSE_MAX) {
+            Timed t(c, PS_DENSE, l, n);
             if (vel) launch_dense_apply<T>(L.g, 1, (int)n, c->uidx_u, c->ucomp_u, c->Mu, cview(v.bu), v.xu, c->s);
             else {
                 VelArr<T> x{{v.xp, nullptr, nullptr}};
@@ -699,23 +868,29 @@ void vcycle(ibb_ctx *c, bool vel, int l)
     residual<T>(c, vel, l, nullptr);
     Level &C = c->lv[l + 1];
     View<T> w = view<T>(C);
+    const int rsite = sizeof(T) == 4 ? PS_RESTRICT32 : PS_RESTRICT64;
     if (vel) {
+        Timed t(c, rsite, l + 1, C.nu);
         launch_restrict<T>(L.g, C.g, D, vm, ROLE_V, false, cview(v.ru), w.bu, (T)1, c->s, &w.xu);
     } else {
         VelArrC<T> rf{{v.rp, nullptr, nullptr}};
         VelArr<T> bc{{w.bp, nullptr, nullptr}};
         VelArr<T> xc{{w.xp, nullptr, nullptr}};
+        Timed t(c, rsite, l + 1, C.np);
         launch_restrict<T>(L.g, C.g, 1, pm, ROLE_P, false, rf, bc, (T)1, c->s, &xc);
     }
     vcycle<T>(c, vel, l + 1);
     // the one-launch sweep alternates a level's iterate buffers: look them up again
     v = view<T>(L);
     w = view<T>(C);
+    const int psite = sizeof(T) == 4 ? PS_PROLONG32 : PS_PROLONG64;
     if (vel) {
+        Timed t(c, psite, l, L.nu);
         launch_prolong_add<T>(C.g, L.g, D, vm, ROLE_V, cview(w.xu), v.xu, c->s);
     } else {
         VelArrC<T> xc{{w.xp, nullptr, nullptr}};
         VelArr<T> xf{{v.xp, nullptr, nullptr}};
+        Timed t(c, psite, l, L.np);
         launch_prolong_add<T>(C.g, L.g, 1, pm, ROLE_P, xc, xf, c->s);
     }
     for (int s = 0; s < c->d.nu2; ++s) sweep<T>(c, vel, l);
@@ -731,7 +906,10 @@ ibb_status fetch_scalar(ibb_ctx *c, double *out)
 
 ibb_status read_scalar(ibb_ctx *c, int nparts, double *out)
 {
-    launch_reduce_final(c->partial, nparts, c->scalar, c->s);
+    {
+        Timed t(c, PS_OUTER, 0, nparts);
+        launch_reduce_final(c->partial, nparts, c->scalar, c->s);
+    }
     return fetch_scalar(c, out);
 }
 
@@ -778,8 +956,11 @@ ibb_status norm_b(ibb_ctx *c, bool vel, double *out)
     vel_masks(c->d.dim, vm);
     const int pm[3] = {0, 0, 0};
     int np;
-    if (vel) np = launch_norm2<double>(L.g, c->d.dim, vm, VelArrC<double>{{L.bu[0], L.bu[1], L.bu[2]}}, c->partial, c->s);
-    else np = launch_norm2<double>(L.g, 1, pm, VelArrC<double>{{L.bp, nullptr, nullptr}}, c->partial, c->s);
+    {
+        Timed t(c, PS_OUTER, 0, vel ? L.nu : L.np);
+        if (vel) np = launch_norm2<double>(L.g, c->d.dim, vm, VelArrC<double>{{L.bu[0], L.bu[1], L.bu[2]}}, c->partial, c->s);
+        else np = launch_norm2<double>(L.g, 1, pm, VelArrC<double>{{L.bp, nullptr, nullptr}}, c->partial, c->s);
+    }
     double s2;
     ibb_status st = read_scalar(c, np, &s2);
     *out = sqrt(s2);
@@ -788,9 +969,7 @@ ibb_status norm_b(ibb_ctx *c, bool vel, double *out)
 
 ibb_status resid_norm(ibb_ctx *c, bool vel, double *out)
 {
-    const int k = prof_begin(c, vel ? 4 : 5, vel ? c->lv[0].nu : c->lv[0].np);
     const int np = residual<double>(c, vel, 0, c->partial);
-    prof_end(c, k);
     double s2;
     ibb_status st = read_scalar(c, np, &s2);
     *out = sqrt(s2);
@@ -1092,16 +1271,28 @@ ibb_status solve(ibb_ctx *c, bool vel, int max_cycles, int exact, SolveOut *o)
             return;
         }
         // r64 already holds b - A x (from the last residual evaluation)
+        const long long units = vel ? L0.nu : L0.np;
         if (vel) {
-            launch_cast_unknowns<double, float>(L0.g, D, vm, VelArrC<double>{{L0.ru[0], L0.ru[1], L0.ru[2]}},
-                                                VelArr<float>{{L0.bu32[0], L0.bu32[1], L0.bu32[2]}}, c->s);
-            for (int a = 0; a < D; ++a) launch_fill<float>(L0.xu32[a], L0.g.nel, 0.0f, c->s);
+            {
+                Timed t(c, PS_OUTER, 0, units);
+                launch_cast_unknowns<double, float>(L0.g, D, vm, VelArrC<double>{{L0.ru[0], L0.ru[1], L0.ru[2]}},
+                                                    VelArr<float>{{L0.bu32[0], L0.bu32[1], L0.bu32[2]}}, c->s);
+            }
+            for (int a = 0; a < D; ++a) {
+                Timed t(c, PS_OUTER, 0, units);
+                launch_fill<float>(L0.xu32[a], L0.g.nel, 0.0f, c->s);
+            }
         } else {
-            launch_cast_unknowns<double, float>(L0.g, 1, pm, VelArrC<double>{{L0.rp, nullptr, nullptr}},
-                                                VelArr<float>{{L0.bp32, nullptr, nullptr}}, c->s);
+            {
+                Timed t(c, PS_OUTER, 0, units);
+                launch_cast_unknowns<double, float>(L0.g, 1, pm, VelArrC<double>{{L0.rp, nullptr, nullptr}},
+                                                    VelArr<float>{{L0.bp32, nullptr, nullptr}}, c->s);
+            }
+            Timed t(c, PS_OUTER, 0, units);
             launch_fill<float>(L0.xp32, L0.g.nel, 0.0f, c->s);
         }
         for (int it = 0; it < c->d.inner_cycles; ++it) vcycle<float>(c, vel, 0);
+        Timed t(c, PS_OUTER, 0, units);
         if (vel)
             launch_add_correction(L0.g, D, vm, VelArrC<float>{{L0.xu32[0], L0.xu32[1], L0.xu32[2]}},
                                   VelArr<double>{{L0.xu[0], L0.xu[1], L0.xu[2]}}, c->s);
@@ -1151,6 +1342,26 @@ ibb_status solve(ibb_ctx *c, bool vel, int max_cycles, int exact, SolveOut *o)
     return IBB_OK;
 }
 
+// unknowns of level l of one system in the order comp, z, y, x: padded
+// index and component
+void level_unknowns(ibb_ctx *c, int l, bool vel, std::vector<long long> &idx, std::vector<int> &cmp)
+{
+    Level &L = c->lv[l];
+    idx.clear();
+    cmp.clear();
+    for (int a = 0; a < (vel ? c->d.dim : 1); ++a) {
+        const int vmask = vel ? face_mask(a) : 0;
+        int lo[3], hi[3];
+        for (int d = 0; d < 3; ++d) unk_range(L.g, d, (vmask >> d) & 1, lo[d], hi[d]);
+        for (int k = lo[2]; k <= hi[2]; ++k)
+            for (int j = lo[1]; j <= hi[1]; ++j)
+                for (int i = lo[0]; i <= hi[0]; ++i) {
+                    idx.push_back(at(L.g, i, j, k));
+                    cmp.push_back(a);
+                }
+    }
+}
+
 // host-side table of coarsest unknowns in the order comp, z, y, x
 void coarsest_tables(ibb_ctx *c, std::vector<long long> &ip, std::vector<int> &cp, std::vector<long long> &iu,
                      std::vector<int> &cu)
@@ -1179,24 +1390,33 @@ ibb_status rebuild_coefficients(ibb_ctx *c)
     const long long em = c->eta_max > 0 ? c->eta_max : 1;
     // spring forces at the current positions
     for (int a = 0; a < D; ++a) launch_fill<double>(c->F + a * em, em, 0.0, c->s);
-    if (c->have_springs && c->m > 0)
+    if (c->have_springs && c->m > 0) {
+        Timed t(c, PS_SPRING_FORCE, 0, c->eta);
         launch_spring_force(L0.g, c->X, em, c->eta, c->ij, c->m, c->rest, c->K, c->alive, c->inc_start, c->inc_list,
                             c->F, c->s);
+    }
     // bins at width omega, then the gathers
     Bins b = c->bins;
     bins_for_width(d, d->omega, b.nb, b.bs);
     b.nbins = b.nb[0] * b.nb[1] * b.nb[2];
     launch_bin_nodes(L0.g, b, c->X, em, c->eta, c->scan_tmp, c->s);
-    for (int a = 0; a < D; ++a)
+    for (int a = 0; a < D; ++a) {
+        Timed t(c, PS_SPREAD_FACE, 0, lattice_count(L0.g, face_mask(a)));
         launch_spread_face(L0.g, c->ph, b, c->X, c->F, em, a, d->omega, c->f[a], L0.rho[a], c->s);
+    }
     // with constant viscosity (eq:NSdis1) no row reads the viscosity fields,
     // which keep the fluid value they were created with
     const bool visc = !d->decoupled;
     if (visc) {
-        launch_spread_visc(L0.g, c->ph, b, c->X, em, 0, L0.muc, c->s);
-        for (int e = 0; e < c->E; ++e)
+        {
+            Timed t(c, PS_SPREAD_VISC, 0, lattice_count(L0.g, 0));
+            launch_spread_visc(L0.g, c->ph, b, c->X, em, 0, L0.muc, c->s);
+        }
+        for (int e = 0; e < c->E; ++e) {
+            Timed t(c, PS_SPREAD_VISC, 0, lattice_count(L0.g, edge_mask(D, c->edge_axis[e])));
             launch_spread_visc(L0.g, c->ph, b, c->X, em, edge_mask(D, c->edge_axis[e]), L0.mue[c->edge_axis[e]],
                                c->s);
+        }
     }
     // coarse levels: full weighting of rho, mu (times gamma)
     int fm[3], em3[3];
@@ -1256,6 +1476,21 @@ ibb_status rebuild_coefficients(ibb_ctx *c)
     if (LC.nu <= DENSE_MAX)
         launch_dense_inverse(LC.g, 1, (int)LC.nu, c->uidx_u, c->ucomp_u, v.cp, v.cu, d->sigma / d->dt,
                              LC.cvu, c->Atmp, 0, c->Aw, c->Mu, c->s);
+    // tails on the new coefficients (and the new coarsest inverses)
+    for (int s = 0; s < 2; ++s) {
+        const Tail &t = c->tail[s];
+        if (t.n <= 0) continue;
+        const LdsPlan tp{c->tplan[s], t.level, c->tplan_bytes[s]};
+        const long long nc = s ? LC.nu : LC.np;
+        const int ndense = nc <= DENSE_MAX ? (int)nc : 0;
+        const long long *ui = s ? c->uidx_u : c->uidx_p;
+        const int *uc = s ? c->ucomp_u : c->ucomp_p;
+        const double *M = s ? c->Mu : c->Mp;
+        if (d->precision == IBB_FP32_REFINED)
+            launch_tail_columns<float>(D, c->tab32, c->L, s, d->nu1, d->nu2, ndense, ui, uc, M, tp, t, c->s);
+        else
+            launch_tail_columns<double>(D, c->tab64, c->L, s, d->nu1, d->nu2, ndense, ui, uc, M, tp, t, c->s);
+    }
     c->have_coefs = true;
     return IBB_OK;
 }
@@ -1375,8 +1610,11 @@ ibb_status lag_launch(ibb_ctx *c)
 {
     Level &L0 = c->lv[0];
     const long long em = c->eta_max > 0 ? c->eta_max : 1;
-    launch_interp(L0.g, c->d.kernel, c->d.h, VelArrC<double>{{c->u[0], c->u[1], c->u[2]}}, c->X, em, c->eta, c->U,
-                  em, c->s);
+    {
+        Timed t(c, PS_INTERP, 0, (long long)c->eta * c->d.dim);
+        launch_interp(L0.g, c->d.kernel, c->d.h, VelArrC<double>{{c->u[0], c->u[1], c->u[2]}}, c->X, em, c->eta,
+                      c->U, em, c->s);
+    }
     launch_euler(L0.g, c->d.dt / c->d.sigma, c->U, c->X, em, c->eta, c->s);
     launch_fill<int>(c->counters, 4, 0, c->s);
     if (c->have_springs && c->m > 0)
@@ -1506,6 +1744,30 @@ ibb_status ibb_create(const ibb_desc *desc, int64_t max_nodes, int64_t max_sprin
         a.nu = b.nu = L.nu;
         a.np = b.np = L.np;
         a.dec = b.dec = L.dec;
+    }
+    // tails: the unknowns of the tail level and the plan of the column
+    // build, whose levels must fit this device's arena (otherwise the cycle
+    // recurses as without a tail)
+    std::vector<LdsLevel> tplans[2];
+    std::vector<long long> tidx[2];
+    std::vector<int> tcomp[2];
+    for (int v = 0; v < 2 && e == hipSuccess; ++v) {
+        Tail &t = c->tail[v];
+        if (t.n <= 0) continue;
+        plan_tail_build(c, v == 1, tplans[v]);
+        if (c->tplan_bytes[v] > wg_lds_budget()) {
+            t.n = 0;
+            continue;
+        }
+        level_unknowns(c, t.level, v == 1, tidx[v], tcomp[v]);
+        e = hipMemcpyAsync(const_cast<long long *>(t.idx), tidx[v].data(), tidx[v].size() * sizeof(long long),
+                           hipMemcpyHostToDevice, c->s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(const_cast<int *>(t.comp), tcomp[v].data(), tcomp[v].size() * sizeof(int),
+                               hipMemcpyHostToDevice, c->s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->tplan[v], tplans[v].data(), WG_MAXLEV * sizeof(LdsLevel), hipMemcpyHostToDevice,
+                               c->s);
     }
     std::vector<LdsLevel> plans[2][2];
     for (int pr = 0; pr < 2; ++pr)
@@ -1948,7 +2210,7 @@ ibb_status ibb_profile_enable(ibb_ctx *c, int enable)
     }
     c->prof = enable != 0;
     c->pused = 0;
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < IBB_PROFILE_CLASSES; ++i) {
         c->plaunch[i] = 0;
         c->pms[i] = 0.0;
         c->punit_tot[i] = 0;
@@ -1958,7 +2220,7 @@ ibb_status ibb_profile_enable(ibb_ctx *c, int enable)
 
 ibb_status ibb_profile_read(ibb_ctx *c, int kernel_class, long long *launches, double *total_ms, long long *units)
 {
-    if (!c || kernel_class < 0 || kernel_class >= 8) return IBB_EINVAL;
+    if (!c || kernel_class < 0 || kernel_class >= IBB_PROFILE_CLASSES) return IBB_EINVAL;
     prof_flush(c);
     if (launches) *launches = c->plaunch[kernel_class];
     if (total_ms) *total_ms = c->pms[kernel_class];
@@ -2124,6 +2386,7 @@ void plan_vcycle(Plan &P, std::vector<GOp> &ops, const std::vector<ibb_ctx *> &m
             it.ctx = i;
             it.lds = c->ldslev[prec][vel ? 1 : 0];
             it.lds_from = c->lds_ls[prec][vel ? 1 : 0];
+            it.tail = has_tail(c, prec, vel) ? c->tail[vel ? 1 : 0] : Tail{};
             op.lds = std::max(op.lds, c->lds_bytes[prec][vel ? 1 : 0]);
             P.cent.push_back(it);
             op.n++;

@@ -101,22 +101,46 @@ __global__ void k_scatter_keys(const int *__restrict__ keys, int n, const int *_
     ids[pos] = t;
 }
 
-// insertion sort of each bucket by id modulo `mod` (mod = 0: by id);
-// buckets are short
-__global__ void k_sort_buckets(const int *__restrict__ start, int nb, int *ids, int mod)
+// order each bucket by id modulo `mod` (mod = 0: by id).  A one-wavefront
+// workgroup takes the buckets blockIdx.x, + gridDim.x, ...: it loads the
+// bucket's ids into LDS and writes every entry to its rank, the number of
+// entries with a smaller key (keys within a bucket are distinct).  A bucket
+// longer than the LDS tile is ordered by the first lane, by insertion.
+constexpr int RANK_TILE = 1024;
+constexpr int RANK_GRID = 8192;
+
+__global__ void __launch_bounds__(64) k_sort_buckets(const int *__restrict__ start, int nb, int *ids, int mod)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nb) return;
-    const int lo = start[b], hi = start[b + 1];
-    for (int i = lo + 1; i < hi; ++i) {
-        const int v = ids[i];
-        const int kv = mod ? v % mod : v;
-        int j = i - 1;
-        while (j >= lo && (mod ? ids[j] % mod : ids[j]) > kv) {
-            ids[j + 1] = ids[j];
-            --j;
+    __shared__ int tile[RANK_TILE];
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        const int lo = start[b], hi = start[b + 1], n = hi - lo;
+        if (n < 2) continue;
+        if (n <= RANK_TILE) {
+            for (int q = threadIdx.x; q < n; q += blockDim.x) tile[q] = ids[lo + q];
+            __syncthreads();
+            for (int q = threadIdx.x; q < n; q += blockDim.x) {
+                const int v = tile[q];
+                const int kv = mod ? v % mod : v;
+                int rank = 0;
+                for (int r = 0; r < n; ++r) {
+                    const int w = tile[r];
+                    rank += (mod ? w % mod : w) < kv;
+                }
+                ids[lo + rank] = v;
+            }
+            __syncthreads();
+        } else if (threadIdx.x == 0) {
+            for (int i = lo + 1; i < hi; ++i) {
+                const int v = ids[i];
+                const int kv = mod ? v % mod : v;
+                int j = i - 1;
+                while (j >= lo && (mod ? ids[j] % mod : ids[j]) > kv) {
+                    ids[j + 1] = ids[j];
+                    --j;
+                }
+                ids[j + 1] = v;
+            }
         }
-        ids[j + 1] = v;
     }
 }
 
@@ -131,7 +155,8 @@ void launch_bucket_sort(const int *keys, int n, int nbuckets, int *count, int *s
     hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(SCAN_TILE), 0, s, count, nbuckets, scan_tmp, start);
     launch_fill<int>(count, nbuckets, 0, s);
     if (n > 0) hipLaunchKernelGGL(k_scatter_keys, dim3(nblk(n)), dim3(256), 0, s, keys, n, start, count, ids);
-    hipLaunchKernelGGL(k_sort_buckets, dim3(nblk(nbuckets)), dim3(256), 0, s, start, nbuckets, ids, mod);
+    const unsigned ng = (unsigned)(nbuckets < RANK_GRID ? (nbuckets > 0 ? nbuckets : 1) : RANK_GRID);
+    launch_timed(k_sort_buckets, dim3(ng), dim3(64), s, start, nbuckets, ids, mod);
 }
 
 // ---------------------------------------------------------------------------
@@ -265,7 +290,7 @@ void launch_spread_face(const Grid &g, const Phys &ph, const Bins &bins, const d
 {
     long long n = 1;
     for (int d = 0; d < 3; ++d) n *= stored_extent(g, d, d == a);
-    hipLaunchKernelGGL(k_spread_face, dim3(nblk(n)), dim3(256), 0, s, g, ph, bins, X, F, stride, a, width, f_out,
+    launch_timed(k_spread_face, dim3(nblk(n)), dim3(256), s, g, ph, bins, X, F, stride, a, width, f_out,
                        rho_out);
 }
 
@@ -318,7 +343,7 @@ void launch_spread_visc(const Grid &g, const Phys &ph, const Bins &bins, const d
 {
     long long n = 1;
     for (int d = 0; d < 3; ++d) n *= stored_extent(g, d, (vmask >> d) & 1);
-    hipLaunchKernelGGL(k_spread_visc, dim3(nblk(n)), dim3(256), 0, s, g, ph, bins, X, stride, vmask, mu_out);
+    launch_timed(k_spread_visc, dim3(nblk(n)), dim3(256), s, g, ph, bins, X, stride, vmask, mu_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -388,7 +413,7 @@ void launch_interp(const Grid &g, int kernel, double width, const VelArrC<double
                    long long xstride, int eta, double *U, long long ustride, hipStream_t s)
 {
     if (eta <= 0) return;
-    hipLaunchKernelGGL(k_interp, dim3(eta, g.D), dim3(INTERP_BLOCK), 0, s, g, kernel, width, u, X, xstride, eta, U,
+    launch_timed(k_interp, dim3(eta, g.D), dim3(INTERP_BLOCK), s, g, kernel, width, u, X, xstride, eta, U,
                        ustride);
 }
 
@@ -493,7 +518,7 @@ void launch_spring_force(const Grid &g, const double *X, long long stride, int e
                          const int *inc_list, double *F, hipStream_t s)
 {
     if (eta > 0)
-        hipLaunchKernelGGL(k_spring_force, dim3(nblk(eta)), dim3(256), 0, s, g, X, stride, eta, ij, m, rest, K, alive,
+        launch_timed(k_spring_force, dim3(nblk(eta)), dim3(256), s, g, X, stride, eta, ij, m, rest, K, alive,
                            inc_start, inc_list, F);
 }
 

@@ -1,6 +1,8 @@
 // Argument bundles and host launchers of the library's kernels.
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "common.h"
 
 namespace ibmg {
@@ -49,10 +51,11 @@ inline VelArrC<T> cview(const VelArr<T> &v)
 
 // ---- multigrid (mg.hip) ----
 template <typename T>
-void launch_smooth_p(const Grid &g, const T *b, T *x, const CoefP<T> &cf, T cvisc, int colour, hipStream_t s);
+void launch_smooth_p(const Grid &g, const T *b, T *x, const CoefP<T> &cf, T cvisc, int colour, hipStream_t s,
+                     int zb = 0);
 template <typename T>
 void launch_smooth_u(const Grid &g, int a, const T *b, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc,
-                     int colour, hipStream_t s);
+                     int colour, hipStream_t s, int zb = 0);
 // one colour of every component of the constant-viscosity system, one launch
 template <typename T>
 void launch_smooth_u_dec(const Grid &g, const VelArrC<T> &b, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc,
@@ -149,12 +152,37 @@ struct LdsPlan {
     int bytes;             // arena size
 };
 
+// The part of a V-cycle below the start level of the one-workgroup cycle,
+// as its linear map.  That part (smoothing, residuals and transfers down to
+// the coarsest level and back) starts from a zero iterate, so its result is
+// a fixed matrix times the restricted right-hand side.  Tm holds that matrix
+// row by row ([r * ld + j]: row r, column j, rows padded to ld = n rounded
+// up to 16 bytes, in the precision of the cycle), built by running the same
+// passes on every unit right-hand side;
+// idx and comp list the n unknowns of level `level` (padded index and
+// component, in the order comp, z, y, x).  n == 0: no tail, the cycle
+// recurses to the coarsest level.
+constexpr int TAIL_MAX = 512;
+struct Tail {
+    const void *Tm;
+    const long long *idx;
+    const int *comp;
+    int n, level;
+};
+
 // sets the dynamic-LDS limit of the one-workgroup kernels (once per process)
 void wg_prepare();
 template <typename T>
 void launch_coarse_vcycle(int D, const LevTab<T> *tab, int l0, int L, int vel, int nu1, int nu2, int ndense,
                           const long long *uidx, const int *ucomp, const double *M, const LdsPlan &plan,
-                          hipStream_t s);
+                          const Tail &tail, hipStream_t s);
+// columns of a tail: one workgroup per unknown of level tail.level runs the
+// cycle from there on that unit right-hand side (every level of it staged in
+// LDS by `plan`) and writes the result into column j of tail.Tm
+template <typename T>
+void launch_tail_columns(int D, const LevTab<T> *tab, int L, int vel, int nu1, int nu2, int ndense,
+                         const long long *uidx, const int *ucomp, const double *M, const LdsPlan &plan,
+                         const Tail &tail, hipStream_t s);
 // largest LDS arena the coarse cycle may use on the current device (bytes)
 int wg_lds_budget();
 
@@ -181,6 +209,24 @@ void launch_smooth_rb(const Grid &g, int vel, int a, const VelArrC<T> &xin, cons
 // Arm a start/stop event pair for the next smoother or residual launch of
 // this thread: the dispatch itself records the kernel's start and end.
 void set_launch_events(hipEvent_t start, hipEvent_t stop);
+// the armed pair, handed to the next launch and disarmed (false: none armed)
+bool take_launch_events(hipEvent_t *start, hipEvent_t *stop);
+
+// launch `kernel`; when a pair of events is armed, its dispatch records the
+// kernel's own start and end into them
+template <typename K, typename... Args>
+inline void launch_timed_shm(K kernel, dim3 grid, dim3 block, unsigned shm, hipStream_t s, Args... args)
+{
+    hipEvent_t e0, e1;
+    if (take_launch_events(&e0, &e1)) hipExtLaunchKernelGGL(kernel, grid, block, shm, s, e0, e1, 0, args...);
+    else hipLaunchKernelGGL(kernel, grid, block, shm, s, args...);
+}
+
+template <typename K, typename... Args>
+inline void launch_timed(K kernel, dim3 grid, dim3 block, hipStream_t s, Args... args)
+{
+    launch_timed_shm(kernel, grid, block, 0, s, args...);
+}
 
 // ---- batched passes over several contexts (mg.hip) ----
 // One entry per block of a batched launch: the context's level table(s) at
@@ -205,6 +251,7 @@ struct BCoarse {
     const LdsLevel *lds;   // the member's LDS plan (levels >= lds_from)
     int l0, L, ndense, ctx;
     int lds_from, pad;
+    Tail tail;             // the member's tail (n == 0: none)
 };
 
 // pass kinds

@@ -439,6 +439,65 @@ __global__ void __launch_bounds__(256) k_smooth_u(Grid g, Box box, const T *__re
     write_images(g, face_mask(A), ROLE_V, x.c[A], i, j, k, xn);
 }
 
+// The same colour passes (3D), z-blocked: a workgroup owns a band of `rows`
+// rows of one colour in each plane of a run of ZB_PLANES consecutive planes
+// and walks those planes in order, so that the planes a point reads above
+// and below were read by the same workgroup one step before (hits in its
+// caches) rather than fetched again by other workgroups at other times.  The
+// points of one colour are independent, so this order gives the same bits
+// as the flat launch.
+constexpr int ZB_PLANES = 16;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_smooth_p_zb(Grid g, Box box, const T *__restrict__ b, T *x, CoefP<T> cf,
+                                                     T cvisc, int colour, int rows, int nbands)
+{
+    const int half = (box.ext[0] + 1) >> 1;
+    const int j0 = (blockIdx.x % nbands) * rows, kz0 = (blockIdx.x / nbands) * ZB_PLANES;
+    const int npts = half * min(rows, box.ext[1] - j0);
+    const int kz1 = min(kz0 + ZB_PLANES, box.ext[2]);
+    for (int kz = kz0; kz < kz1; ++kz) {
+        const int k = box.lo[2] + kz;
+        for (int t = threadIdx.x; t < npts; t += blockDim.x) {
+            const int j = box.lo[1] + j0 + t / half;
+            const int i = box.lo[0] + 2 * (t % half) + ((box.lo[0] + j + k + colour) & 1);
+            if (i >= box.lo[0] + box.ext[0]) continue;
+            const long long c = at(g, i, j, k);
+            const T bc = b[c], xc = x[c];
+            T Ax, dg;
+            p_row<T, 3>(g, x, cf, cvisc, i, j, k, Ax, dg);
+            const T xn = xc + (bc - Ax) / dg;
+            x[c] = xn;
+            write_images(g, 0, ROLE_P, x, i, j, k, xn);
+        }
+    }
+}
+
+template <typename T, int A>
+__global__ void __launch_bounds__(256) k_smooth_u_zb(Grid g, Box box, const T *__restrict__ b, VelArr<T> x, CoefU<T> cf,
+                                                     T mass, T cvisc, int colour, int rows, int nbands)
+{
+    const int half = (box.ext[0] + 1) >> 1;
+    const int j0 = (blockIdx.x % nbands) * rows, kz0 = (blockIdx.x / nbands) * ZB_PLANES;
+    const int npts = half * min(rows, box.ext[1] - j0);
+    const int kz1 = min(kz0 + ZB_PLANES, box.ext[2]);
+    for (int kz = kz0; kz < kz1; ++kz) {
+        const int k = box.lo[2] + kz;
+        for (int t = threadIdx.x; t < npts; t += blockDim.x) {
+            const int j = box.lo[1] + j0 + t / half;
+            const int i = box.lo[0] + 2 * (t % half) + ((box.lo[0] + j + k + colour) & 1);
+            if (i >= box.lo[0] + box.ext[0]) continue;
+            const long long f = at(g, i, j, k);
+            const T bf = b[f], xf = x.c[A][f];
+            T Ax, dg;
+            u_row<T, 3, A>(g, x, cf, mass, cvisc, i, j, k, Ax, dg);
+            const T xn = xf + (bf - Ax) / dg;
+            x.c[A][f] = xn;
+            write_images(g, face_mask(A), ROLE_V, x.c[A], i, j, k, xn);
+        }
+    }
+}
+
 // one colour of every component of the constant-viscosity system (eq:NSdis1)
 // in one launch: the components do not couple, so this is the sweep of the
 // components one after another.  blockIdx.y is the component.
@@ -1401,17 +1460,96 @@ __device__ inline void wg_prolong_comp(const LevTab<T> &lcr, const LevTab<T> &lt
     }
 }
 
+// Restriction of the fine residual onto the tail's unknowns, as a compact
+// vector (bv[t]: the t-th unknown of the tail level); the same arithmetic as
+// the restriction into the coarse level's b.
+template <typename T, int D, int VEL>
+__device__ inline void wg_restrict_tail(const LevTab<T> &ltr, const Grid &gc, const Tail &tail, T *bv)
+{
+    const LevTab<T> lt = ltr;
+    const int role = VEL ? ROLE_V : ROLE_P;
+    for (int t = threadIdx.x; t < tail.n; t += blockDim.x) {
+        const int a = tail.comp[t];
+        int I, J, K;
+        decode(gc, tail.idx[t], I, J, K);
+        const T *src = VEL ? (a == 0 ? lt.ru[0] : (a == 1 ? lt.ru[1] : lt.ru[2])) : lt.rp;
+        bv[t] = (T)restrict_any<T, D>(VEL ? face_mask(a) : 0, lt.g, role, src, I, J, K);
+    }
+}
+
+// x = Tm bv at the tail's unknowns, with the ghost images of x; the rest of
+// x is zero already.  Each thread streams its own row of Tm (rows padded to
+// 16 bytes, so that a row reads as 16-byte vectors, several in flight), and
+// sums it in column order.
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+    using type = float4;
+    static constexpr int n = 4;
+};
+template <>
+struct Vec16<double> {
+    using type = double2;
+    static constexpr int n = 2;
+};
+
+__host__ __device__ inline int tail_ld(int n, int wsz) { return wsz == 4 ? (n + 3) & ~3 : (n + 1) & ~1; }
+
+template <typename T>
+__device__ inline T row_dot(const T *__restrict__ row, const T *bv, int n)
+{
+    using V = typename Vec16<T>::type;
+    constexpr int W = Vec16<T>::n;
+    const V *rv = reinterpret_cast<const V *>(row);
+    T sum = T(0);
+    const int nv = n / W;
+#pragma unroll 8
+    for (int q = 0; q < nv; ++q) {
+        const V t = rv[q];
+        const T *tt = reinterpret_cast<const T *>(&t);
+#pragma unroll
+        for (int w = 0; w < W; ++w) sum += tt[w] * bv[q * W + w];
+    }
+    for (int j = nv * W; j < n; ++j) sum += row[j] * bv[j];
+    return sum;
+}
+
+template <typename T, int D, int VEL>
+__device__ inline void wg_apply_tail(const LevTab<T> &lcr, const Tail &tail, const T *bv)
+{
+    const LevTab<T> lc = lcr;
+    const T *__restrict__ Tm = static_cast<const T *>(tail.Tm);
+    const int n = tail.n;
+    const int ld = tail_ld(n, (int)sizeof(T));
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+        const T sum = row_dot<T>(Tm + (long long)r * ld, bv, n);
+        const int a = tail.comp[r];
+        T *x = VEL ? (a == 0 ? lc.xu[0] : (a == 1 ? lc.xu[1] : lc.xu[2])) : lc.xp;
+        const long long e = tail.idx[r];
+        x[e] = sum;
+        int i, j, k;
+        decode(lc.g, e, i, j, k);
+        write_images(lc.g, VEL ? face_mask(a) : 0, VEL ? ROLE_V : ROLE_P, x, i, j, k, sum);
+    }
+}
+
 // The part of a V-cycle from level l0 down to the coarsest level and back,
 // in one workgroup: the same passes, in the same order, as the launched
-// kernels, with a barrier where a launch boundary would be.
+// kernels, with a barrier where a launch boundary would be.  With a tail
+// (tail.n > 0, tail.level = l0 + 1) the levels below l0 are the tail's
+// matrix applied to the restricted residual (bv: shared scratch of
+// TAIL_MAX values).
 template <typename T, int D, int VEL>
 __device__ __attribute__((always_inline)) inline void coarse_cycle(const LevTab<T> *__restrict__ tab, int l0, int L, int nu1,
                                                                   int nu2, int ndense,
                                     const long long *__restrict__ uidx, const int *__restrict__ ucomp,
-                                    const double *__restrict__ M)
+                                    const double *__restrict__ M, const Tail &tail, T *bv)
 {
     constexpr int A2 = D == 3 ? 2 : 1;
-    for (int l = l0; l < L - 1; ++l) {
+    const bool tailed = tail.n > 0;
+    const int lb = tailed ? tail.level : L - 1;   // bottom of the recursion
+    for (int l = l0; l < lb; ++l) {
         const LevTab<T> &lt = tab[l];
         for (int s = 0; s < nu1; ++s) wg_sweep<T, D, VEL>(lt);
         wg_residual_comp<T, D, VEL, 0>(lt);
@@ -1421,27 +1559,34 @@ __device__ __attribute__((always_inline)) inline void coarse_cycle(const LevTab<
         }
         __syncthreads();
         const LevTab<T> &lc = tab[l + 1];
-        wg_restrict_comp<T, D, VEL, 0>(lt, lc);
-        if (VEL) {
-            wg_restrict_comp<T, D, VEL, 1>(lt, lc);
-            if (D == 3) wg_restrict_comp<T, D, VEL, A2>(lt, lc);
+        if (tailed && l + 1 == lb) {
+            wg_restrict_tail<T, D, VEL>(lt, lc.g, tail, bv);
+        } else {
+            wg_restrict_comp<T, D, VEL, 0>(lt, lc);
+            if (VEL) {
+                wg_restrict_comp<T, D, VEL, 1>(lt, lc);
+                if (D == 3) wg_restrict_comp<T, D, VEL, A2>(lt, lc);
+            }
         }
         __syncthreads();
     }
-    {
+    if (tailed) {
+        wg_apply_tail<T, D, VEL>(tab[lb], tail, bv);
+        __syncthreads();
+    } else {
         const LevTab<T> lt = tab[L - 1];
         if (ndense > 0) {
-            __shared__ double bv[64];
+            __shared__ double dv[64];
             const int r = threadIdx.x;
             if (r < ndense) {
                 const int c = ucomp[r];
                 const T *b = VEL ? (c == 0 ? lt.bu[0] : (c == 1 ? lt.bu[1] : lt.bu[2])) : lt.bp;
-                bv[r] = (double)b[uidx[r]];
+                dv[r] = (double)b[uidx[r]];
             }
             __syncthreads();
             if (r < ndense) {
                 double sum = 0.0;
-                for (int j = 0; j < ndense; ++j) sum += M[r * ndense + j] * bv[j];
+                for (int j = 0; j < ndense; ++j) sum += M[r * ndense + j] * dv[j];
                 const int c = ucomp[r];
                 T *x = VEL ? (c == 0 ? lt.xu[0] : (c == 1 ? lt.xu[1] : lt.xu[2])) : lt.xp;
                 x[uidx[r]] = (T)sum;
@@ -1454,7 +1599,7 @@ __device__ __attribute__((always_inline)) inline void coarse_cycle(const LevTab<
             for (int s = 0; s < nu1 + nu2; ++s) wg_sweep<T, D, VEL>(lt);
         }
     }
-    for (int l = L - 2; l >= l0; --l) {
+    for (int l = lb - 1; l >= l0; --l) {
         const LevTab<T> &lt = tab[l];
         const LevTab<T> &lc = tab[l + 1];
         wg_prolong_comp<T, D, VEL, 0>(lc, lt);
@@ -1479,9 +1624,10 @@ __device__ inline T *arena_ptr(unsigned char *arena, int off, T *global)
 // The workgroup's table of levels: the global tables, with the arrays of the
 // levels from ls down that the plan places in the LDS arena rebased there.
 // Staged coefficients are copied in.  Staged solver arrays are cleared,
-// except on the start level l0, whose x and b carry the cycle's input.
+// except on the start level l0, whose x and b carry the cycle's input.  Only
+// levels ls .. lend - 1 are touched, and of them only the staged arrays.
 template <typename T, int D, int VEL>
-__device__ inline void stage_levels(const LevTab<T> *__restrict__ tab, int l0, int L, int ls,
+__device__ inline void stage_levels(const LevTab<T> *__restrict__ tab, int l0, int L, int ls, int lend,
                                     const LdsLevel *__restrict__ lev, unsigned char *arena, LevTab<T> *wt)
 {
     for (int l = threadIdx.x; l < L; l += blockDim.x) {
@@ -1505,7 +1651,7 @@ __device__ inline void stage_levels(const LevTab<T> *__restrict__ tab, int l0, i
         wt[l] = t;
     }
     __syncthreads();
-    for (int l = ls; l < L; ++l) {
+    for (int l = ls; l < lend; ++l) {
         const LevTab<T> src = tab[l];
         const LevTab<T> dst = wt[l];
         const bool start = l == l0;
@@ -1538,9 +1684,9 @@ __device__ inline void stage_levels(const LevTab<T> *__restrict__ tab, int l0, i
 #pragma unroll
                     for (int a = 0; a < D; ++a) {
                         if (dst.rho[a] != src.rho[a]) const_cast<T *>(dst.rho[a])[e] = rh[u][a];
-                        dst.xu[a][e] = xv[u][a];
-                        dst.bu[a][e] = bv[u][a];
-                        dst.ru[a][e] = T(0);
+                        if (dst.xu[a] != src.xu[a]) dst.xu[a][e] = xv[u][a];
+                        if (dst.bu[a] != src.bu[a]) dst.bu[a][e] = bv[u][a];
+                        if (dst.ru[a] != src.ru[a]) dst.ru[a][e] = T(0);
                     }
                     if (dst.muc != src.muc) const_cast<T *>(dst.muc)[e] = mc[u];
 #pragma unroll
@@ -1566,9 +1712,9 @@ __device__ inline void stage_levels(const LevTab<T> *__restrict__ tab, int l0, i
 #pragma unroll
                     for (int a = 0; a < D; ++a)
                         if (dst.beta[a] != src.beta[a]) const_cast<T *>(dst.beta[a])[e] = bt[u][a];
-                    dst.xp[e] = xv[u];
-                    dst.bp[e] = bv[u];
-                    dst.rp[e] = T(0);
+                    if (dst.xp != src.xp) dst.xp[e] = xv[u];
+                    if (dst.bp != src.bp) dst.bp[e] = bv[u];
+                    if (dst.rp != src.rp) dst.rp[e] = T(0);
                 }
             }
         }
@@ -1599,13 +1745,50 @@ template <typename T, int D, int VEL>
 __global__ void __launch_bounds__(wg_threads(D, VEL)) k_coarse_vcycle(const LevTab<T> *__restrict__ tab, int l0, int L, int nu1,
                                                                int nu2, int ndense, const long long *__restrict__ uidx,
                                                                const int *__restrict__ ucomp,
-                                                               const double *__restrict__ M, LdsPlan plan)
+                                                               const double *__restrict__ M, LdsPlan plan, Tail tail)
 {
     extern __shared__ __align__(16) unsigned char wg_arena[];
     __shared__ LevTab<T> wt[WG_MAXLEV];
-    stage_levels<T, D, VEL>(tab, l0, L, plan.ls, plan.lev, wg_arena, wt);
-    coarse_cycle<T, D, VEL>(wt, l0, L, nu1, nu2, ndense, uidx, ucomp, M);
+    __shared__ T bv[TAIL_MAX];
+    stage_levels<T, D, VEL>(tab, l0, L, plan.ls, tail.n > 0 ? tail.level + 1 : L, plan.lev, wg_arena, wt);
+    coarse_cycle<T, D, VEL>(wt, l0, L, nu1, nu2, ndense, uidx, ucomp, M, tail, bv);
     unstage_start<T, D, VEL>(tab, l0, plan.ls, wt);
+}
+
+// Column j of a tail's matrix: the cycle from the tail's level down and back,
+// on the unit right-hand side of its j-th unknown, every level staged in LDS
+// (the plan stages all of them; no level is a start level, so every solver
+// array begins at zero).
+template <typename T, int D, int VEL>
+__global__ void __launch_bounds__(wg_threads(D, VEL)) k_tail_columns(const LevTab<T> *__restrict__ tab, int L, int nu1,
+                                                                    int nu2, int ndense,
+                                                                    const long long *__restrict__ uidx,
+                                                                    const int *__restrict__ ucomp,
+                                                                    const double *__restrict__ M, LdsPlan plan,
+                                                                    Tail tail)
+{
+    extern __shared__ __align__(16) unsigned char wg_arena[];
+    __shared__ LevTab<T> wt[WG_MAXLEV];
+    __shared__ T bv[1];
+    const int lt = tail.level;
+    const int j = blockIdx.x;
+    stage_levels<T, D, VEL>(tab, -1, L, plan.ls, L, plan.lev, wg_arena, wt);
+    if (threadIdx.x == 0) {
+        const int a = tail.comp[j];
+        T *b = VEL ? (a == 0 ? wt[lt].bu[0] : (a == 1 ? wt[lt].bu[1] : wt[lt].bu[2])) : wt[lt].bp;
+        b[tail.idx[j]] = T(1);
+    }
+    __syncthreads();
+    const Tail none{nullptr, nullptr, nullptr, 0, 0};
+    coarse_cycle<T, D, VEL>(wt, lt, L, nu1, nu2, ndense, uidx, ucomp, M, none, bv);
+    __syncthreads();
+    T *Tm = const_cast<T *>(static_cast<const T *>(tail.Tm));
+    const int ld = tail_ld(tail.n, (int)sizeof(T));
+    for (int r = threadIdx.x; r < tail.n; r += blockDim.x) {
+        const int a = tail.comp[r];
+        const T *x = VEL ? (a == 0 ? wt[lt].xu[0] : (a == 1 ? wt[lt].xu[1] : wt[lt].xu[2])) : wt[lt].xp;
+        Tm[(long long)r * ld + j] = x[tail.idx[r]];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1780,9 +1963,10 @@ __global__ void __launch_bounds__(wg_threads(D, VEL)) k_bcoarse(const BCoarse *_
     if (!flags[I.ctx]) return;
     extern __shared__ __align__(16) unsigned char wg_arena[];
     __shared__ LevTab<T> wt[WG_MAXLEV];
+    __shared__ T bv[TAIL_MAX];
     const LevTab<T> *tab = static_cast<const LevTab<T> *>(I.tab);
-    stage_levels<T, D, VEL>(tab, I.l0, I.L, I.lds_from, I.lds, wg_arena, wt);
-    coarse_cycle<T, D, VEL>(wt, I.l0, I.L, nu1, nu2, I.ndense, I.uidx, I.ucomp, I.M);
+    stage_levels<T, D, VEL>(tab, I.l0, I.L, I.lds_from, I.tail.n > 0 ? I.tail.level + 1 : I.L, I.lds, wg_arena, wt);
+    coarse_cycle<T, D, VEL>(wt, I.l0, I.L, nu1, nu2, I.ndense, I.uidx, I.ucomp, I.M, I.tail, bv);
     unstage_start<T, D, VEL>(tab, I.l0, I.lds_from, wt);
 }
 
@@ -1801,24 +1985,34 @@ void set_launch_events(hipEvent_t start, hipEvent_t stop)
     t_ev_stop = stop;
 }
 
-template <typename K, typename... Args>
-static void launch_timed(K kernel, dim3 grid, dim3 block, hipStream_t s, Args... args)
+bool take_launch_events(hipEvent_t *start, hipEvent_t *stop)
 {
-    if (t_ev_start) {
-        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, t_ev_start, t_ev_stop, 0, args...);
-        t_ev_start = t_ev_stop = nullptr;
-    } else {
-        hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
-    }
+    if (!t_ev_start) return false;
+    *start = t_ev_start;
+    *stop = t_ev_stop;
+    t_ev_start = t_ev_stop = nullptr;
+    return true;
 }
+
 static inline long long box_count(const Box &b) { return (long long)b.ext[0] * b.ext[1] * b.ext[2]; }
 
+// rows per band of a z-blocked pass: about one point of the colour per
+// thread in each plane, at least 4 rows
+static inline int zb_rows(const Box &P) { return std::max(4, 256 / std::max(1, (P.ext[0] + 1) / 2)); }
+
 template <typename T>
-void launch_smooth_p(const Grid &g, const T *b, T *x, const CoefP<T> &cf, T cvisc, int colour, hipStream_t s)
+void launch_smooth_p(const Grid &g, const T *b, T *x, const CoefP<T> &cf, T cvisc, int colour, hipStream_t s, int zb)
 {
     const Box P = unk_box(g, 0);
     const long long n = (long long)((P.ext[0] + 1) / 2) * P.ext[1] * P.ext[2];
     if (n <= 0) return;
+    if (zb && g.D == 3) {
+        const int rows = zb_rows(P), nbands = (P.ext[1] + rows - 1) / rows;
+        const int nz = (P.ext[2] + ZB_PLANES - 1) / ZB_PLANES;
+        launch_timed(k_smooth_p_zb<T>, dim3((unsigned)(nbands * nz)), dim3(256), s, g, P, b, x, cf, cvisc, colour, rows,
+                     nbands);
+        return;
+    }
     const int remap = g.nel <= XCD_REMAP_MAX_NEL;
     if (g.D == 3)
         launch_timed(k_smooth_p<T, 3>, dim3(blocks_for(n)), dim3(256), s, g, P, b, x, cf, cvisc, colour, remap);
@@ -1828,11 +2022,20 @@ void launch_smooth_p(const Grid &g, const T *b, T *x, const CoefP<T> &cf, T cvis
 
 template <typename T>
 void launch_smooth_u(const Grid &g, int a, const T *b, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc,
-                     int colour, hipStream_t s)
+                     int colour, hipStream_t s, int zb)
 {
     const Box P = unk_box(g, face_mask(a));
     const long long n = (long long)((P.ext[0] + 1) / 2) * P.ext[1] * P.ext[2];
     if (n <= 0) return;
+    if (zb && g.D == 3) {
+        const int rows = zb_rows(P), nbands = (P.ext[1] + rows - 1) / rows;
+        const int nz = (P.ext[2] + ZB_PLANES - 1) / ZB_PLANES;
+        const dim3 grid((unsigned)(nbands * nz)), blk(256);
+        if (a == 0) launch_timed(k_smooth_u_zb<T, 0>, grid, blk, s, g, P, b, x, cf, mass, cvisc, colour, rows, nbands);
+        else if (a == 1) launch_timed(k_smooth_u_zb<T, 1>, grid, blk, s, g, P, b, x, cf, mass, cvisc, colour, rows, nbands);
+        else launch_timed(k_smooth_u_zb<T, 2>, grid, blk, s, g, P, b, x, cf, mass, cvisc, colour, rows, nbands);
+        return;
+    }
     const dim3 grid(blocks_for(n)), blk(256);
     const int remap = g.nel <= XCD_REMAP_MAX_NEL;
     if (g.D == 3) {
@@ -1934,13 +2137,13 @@ int launch_norm2(const Grid &g, int ncomp, const int *vmasks, const VelArrC<T> &
         if (a < ncomp && box_count(boxes.b[a]) > mx) mx = box_count(boxes.b[a]);
     }
     const unsigned nb = stride_blocks(mx);
-    hipLaunchKernelGGL(k_norm2<T>, dim3(nb, ncomp), dim3(256), 0, s, boxes, g, v, partial);
+    launch_timed(k_norm2<T>, dim3(nb, ncomp), dim3(256), s, boxes, g, v, partial);
     return (int)nb * ncomp;
 }
 
 void launch_reduce_final(const double *partial, long long n, double *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, partial, n, out);
+    launch_timed(k_reduce_final, dim3(1), dim3(256), s, partial, n, out);
 }
 
 static inline Box stored_box(const Grid &g, int vmask)
@@ -1973,11 +2176,11 @@ void launch_restrict(const Grid &gf, const Grid &gc, int ncomp, const int *vmask
     const VelArr<T> zx = zero_x ? *zero_x : VelArr<T>{{nullptr, nullptr, nullptr}};
     if (mx <= 0) return;
     if (gf.D == 3)
-        hipLaunchKernelGGL((k_restrict<T, 3>), dim3(blocks_for(mx), ncomp), dim3(256), 0, s, gf, gc, parts, masks, role,
-                           fine, coarse, scale, zx);
+        launch_timed(k_restrict<T, 3>, dim3(blocks_for(mx), ncomp), dim3(256), s, gf, gc, parts, masks, role, fine,
+                     coarse, scale, zx);
     else
-        hipLaunchKernelGGL((k_restrict<T, 2>), dim3(blocks_for(mx), ncomp), dim3(256), 0, s, gf, gc, parts, masks, role,
-                           fine, coarse, scale, zx);
+        launch_timed(k_restrict<T, 2>, dim3(blocks_for(mx), ncomp), dim3(256), s, gf, gc, parts, masks, role, fine,
+                     coarse, scale, zx);
 }
 
 template <typename T>
@@ -1998,11 +2201,11 @@ void launch_prolong_add(const Grid &gc, const Grid &gf, int ncomp, const int *vm
     }
     if (mx <= 0) return;
     if (gf.D == 3)
-        hipLaunchKernelGGL((k_prolong_add<T, 3>), dim3(blocks_for(mx), ncomp), dim3(256), 0, s, gc, gf, parts, masks,
-                           role, coarse, fine);
+        launch_timed(k_prolong_add<T, 3>, dim3(blocks_for(mx), ncomp), dim3(256), s, gc, gf, parts, masks, role,
+                     coarse, fine);
     else
-        hipLaunchKernelGGL((k_prolong_add<T, 2>), dim3(blocks_for(mx), ncomp), dim3(256), 0, s, gc, gf, parts, masks,
-                           role, coarse, fine);
+        launch_timed(k_prolong_add<T, 2>, dim3(blocks_for(mx), ncomp), dim3(256), s, gc, gf, parts, masks, role,
+                     coarse, fine);
 }
 
 void launch_dense_inverse(const Grid &g, int velocity, int n, const long long *uidx, const int *ucomp,
@@ -2019,7 +2222,7 @@ template <typename T>
 void launch_dense_apply(const Grid &g, int velocity, int n, const long long *uidx, const int *ucomp, const double *M,
                         const VelArrC<T> &b, const VelArr<T> &x, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_dense_apply<T>, dim3(1), dim3(64), 0, s, g, velocity, n, uidx, ucomp, M, b, x);
+    launch_timed(k_dense_apply<T>, dim3(1), dim3(64), s, g, velocity, n, uidx, ucomp, M, b, x);
 }
 
 template <typename T>
@@ -2028,7 +2231,7 @@ void launch_fill(T *p, long long n, T v, hipStream_t s)
     unsigned nb = blocks_for(n);
     if (nb > 2048) nb = 2048;
     if (nb == 0) nb = 1;
-    hipLaunchKernelGGL(k_fill<T>, dim3(nb), dim3(256), 0, s, p, n, v);
+    launch_timed(k_fill<T>, dim3(nb), dim3(256), s, p, n, v);
 }
 
 template <typename Ts, typename Td>
@@ -2041,7 +2244,7 @@ void launch_cast_unknowns(const Grid &g, int ncomp, const int *vmasks, const Vel
         boxes.b[a] = a < ncomp ? unk_box(g, vmasks[a]) : Box{{0, 0, 0}, {0, 0, 0}};
         if (a < ncomp && box_count(boxes.b[a]) > mx) mx = box_count(boxes.b[a]);
     }
-    hipLaunchKernelGGL((k_cast_unknowns<Ts, Td>), dim3(blocks_for(mx), ncomp), dim3(256), 0, s, g, boxes, src, dst);
+    launch_timed(k_cast_unknowns<Ts, Td>, dim3(blocks_for(mx), ncomp), dim3(256), s, g, boxes, src, dst);
 }
 
 void launch_add_correction(const Grid &g, int ncomp, const int *vmasks, const VelArrC<float> &e,
@@ -2054,7 +2257,7 @@ void launch_add_correction(const Grid &g, int ncomp, const int *vmasks, const Ve
         boxes.b[a] = a < ncomp ? unk_box(g, vmasks[a]) : Box{{0, 0, 0}, {0, 0, 0}};
         if (a < ncomp && box_count(boxes.b[a]) > mx) mx = box_count(boxes.b[a]);
     }
-    hipLaunchKernelGGL(k_add_correction, dim3(blocks_for(mx), ncomp), dim3(256), 0, s, g, boxes, velocity, e, x);
+    launch_timed(k_add_correction, dim3(blocks_for(mx), ncomp), dim3(256), s, g, boxes, velocity, e, x);
 }
 
 template <typename T>
@@ -2068,7 +2271,7 @@ void launch_load_unknowns(const Grid &g, int ncomp, const int *vmasks, const Vel
         if (a < ncomp && box_count(boxes.b[a]) > mx) mx = box_count(boxes.b[a]);
     }
     const int velocity = vmasks[0] != 0 ? 1 : 0;
-    hipLaunchKernelGGL(k_load_unknowns<T>, dim3(blocks_for(mx), ncomp), dim3(256), 0, s, g, boxes, velocity, src, dst);
+    launch_timed(k_load_unknowns<T>, dim3(blocks_for(mx), ncomp), dim3(256), s, g, boxes, velocity, src, dst);
 }
 
 template <typename T>
@@ -2087,8 +2290,9 @@ int wg_lds_budget()
         int dev = 0, v = 0;
         (void)hipGetDevice(&dev);
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 65536;
-        // the kernel's own shared data: the level table and the coarsest right-hand side
-        budget = v - (int)(WG_MAXLEV * sizeof(LevTab<double>)) - 1024;
+        // the kernel's own shared data: the level table, the coarsest
+        // right-hand side and the tail's right-hand side
+        budget = v - (int)(WG_MAXLEV * sizeof(LevTab<double>)) - 1024 - (int)(TAIL_MAX * sizeof(double));
         if (budget < 0) budget = 0;
     }
     return budget;
@@ -2116,6 +2320,7 @@ void wg_prepare()
     do {                                             \
         allow_lds(k_coarse_vcycle<T, DD, VV>, b);    \
         allow_lds(k_bcoarse<T, DD, VV>, b);          \
+        allow_lds(k_tail_columns<T, DD, VV>, b);     \
     } while (0)
     PREP(double, 2, 0); PREP(double, 2, 1); PREP(double, 3, 0); PREP(double, 3, 1);
     PREP(float, 2, 0); PREP(float, 2, 1); PREP(float, 3, 0); PREP(float, 3, 1);
@@ -2125,13 +2330,13 @@ void wg_prepare()
 template <typename T>
 void launch_coarse_vcycle(int D, const LevTab<T> *tab, int l0, int L, int vel, int nu1, int nu2, int ndense,
                           const long long *uidx, const int *ucomp, const double *M, const LdsPlan &plan,
-                          hipStream_t s)
+                          const Tail &tail, hipStream_t s)
 {
 #define LAUNCH(DD, VV)                                                                                              \
     do {                                                                                                            \
         allow_lds(k_coarse_vcycle<T, DD, VV>, plan.bytes);                                                          \
-        hipLaunchKernelGGL((k_coarse_vcycle<T, DD, VV>), dim3(1), dim3(wg_threads(DD, VV)), plan.bytes, s, tab, l0, \
-                           L, nu1, nu2, ndense, uidx, ucomp, M, plan);                                              \
+        launch_timed_shm(k_coarse_vcycle<T, DD, VV>, dim3(1), dim3(wg_threads(DD, VV)), plan.bytes, s, tab, l0, L, \
+                         nu1, nu2, ndense, uidx, ucomp, M, plan, tail);                                             \
     } while (0)
     if (D == 3) {
         if (vel) LAUNCH(3, 1);
@@ -2144,10 +2349,36 @@ void launch_coarse_vcycle(int D, const LevTab<T> *tab, int l0, int L, int vel, i
 }
 template void launch_coarse_vcycle<double>(int, const LevTab<double> *, int, int, int, int, int, int,
                                            const long long *, const int *, const double *, const LdsPlan &,
-                                           hipStream_t);
+                                           const Tail &, hipStream_t);
 template void launch_coarse_vcycle<float>(int, const LevTab<float> *, int, int, int, int, int, int,
                                           const long long *, const int *, const double *, const LdsPlan &,
-                                          hipStream_t);
+                                          const Tail &, hipStream_t);
+
+template <typename T>
+void launch_tail_columns(int D, const LevTab<T> *tab, int L, int vel, int nu1, int nu2, int ndense,
+                         const long long *uidx, const int *ucomp, const double *M, const LdsPlan &plan,
+                         const Tail &tail, hipStream_t s)
+{
+    if (tail.n <= 0) return;
+#define LAUNCH(DD, VV)                                                                                              \
+    do {                                                                                                            \
+        allow_lds(k_tail_columns<T, DD, VV>, plan.bytes);                                                           \
+        hipLaunchKernelGGL((k_tail_columns<T, DD, VV>), dim3(tail.n), dim3(wg_threads(DD, VV)), plan.bytes, s, tab, \
+                           L, nu1, nu2, ndense, uidx, ucomp, M, plan, tail);                                         \
+    } while (0)
+    if (D == 3) {
+        if (vel) LAUNCH(3, 1);
+        else LAUNCH(3, 0);
+    } else {
+        if (vel) LAUNCH(2, 1);
+        else LAUNCH(2, 0);
+    }
+#undef LAUNCH
+}
+template void launch_tail_columns<double>(int, const LevTab<double> *, int, int, int, int, int, const long long *,
+                                          const int *, const double *, const LdsPlan &, const Tail &, hipStream_t);
+template void launch_tail_columns<float>(int, const LevTab<float> *, int, int, int, int, int, const long long *,
+                                         const int *, const double *, const LdsPlan &, const Tail &, hipStream_t);
 
 int batch_blocks(int kind, const Grid &g, const Grid &gc, int vel, int A)
 {
@@ -2325,9 +2556,9 @@ void launch_gcr_update(const Grid &g, int velocity, const double *num, const dou
 
 // explicit instantiations
 #define INST(T)                                                                                                     \
-    template void launch_smooth_p<T>(const Grid &, const T *, T *, const CoefP<T> &, T, int, hipStream_t);          \
+    template void launch_smooth_p<T>(const Grid &, const T *, T *, const CoefP<T> &, T, int, hipStream_t, int);          \
     template void launch_smooth_u<T>(const Grid &, int, const T *, const VelArr<T> &, const CoefU<T> &, T, T, int,  \
-                                     hipStream_t);                                                                  \
+                                     hipStream_t, int);                                                                  \
     template void launch_smooth_u_dec<T>(const Grid &, const VelArrC<T> &, const VelArr<T> &, const CoefU<T> &, T,  \
                                          T, int, hipStream_t);                                                      \
     template void launch_smooth_rb<T>(const Grid &, int, int, const VelArrC<T> &, const T *, const CoefU<T> &,      \

@@ -216,6 +216,16 @@ class Context:
         return nl.value, tuple(n)
 
 
+def group_footprint_bytes(contexts):
+    """ibb_group_footprint_bytes: the workspace a group of these contexts needs."""
+    lib = L.load()
+    n = len(contexts)
+    arr = (L.CTX * n)(*[c.ctx.value for c in contexts])
+    nbytes = ctypes.c_size_t()
+    _chk(lib, lib.ibb_group_footprint_bytes(arr, n, ctypes.byref(nbytes)), "ibb_group_footprint_bytes")
+    return nbytes.value
+
+
 class Group:
     """Several contexts stepped together: their multigrid passes share
     launches and each solve tick is a replayed HIP graph.  The members must
@@ -245,10 +255,13 @@ class Group:
             raise L.IbbError(st, where, msg)
 
     def projection_step(self, check=True):
+        """check=True raises on any failure; check=False raises only on
+        failures other than a member's non-convergence or non-finite
+        residual, which its statistics record."""
         n = len(self.members)
         stats = (L.SolveStats * n)()
         st = self.lib.ibb_group_projection_step(self.group, stats)
-        if check:
+        if check or st not in (L.IBB_OK, L.IBB_ENOCONV, L.IBB_ENUMERIC):
             self._err(st, "ibb_group_projection_step")
         out = []
         for s in stats:

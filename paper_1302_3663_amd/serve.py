@@ -2,9 +2,10 @@
 
 Requests arrive over time.  At every tick the loop
   1. admits, in arrival order, the requests that have arrived, while the slot
-     cap and the device-memory budget (each request's workspace, from
-     ibb_footprint_bytes) both allow; a request that does not fit waits, and
-     so do the ones behind it;
+     cap and the device-memory budget allow: the budget covers every resident
+     request's workspace (ibb_footprint_bytes) plus the workspace of the group
+     that steps them together (ibb_group_footprint_bytes); a request that does
+     not fit waits, and so do the ones behind it;
   2. steps every resident request once, together: one group projection step
      and one group Lagrangian update, whose multigrid passes share launches
      across the requests and whose solve ticks are replayed HIP graphs;
@@ -81,24 +82,33 @@ class Server:
             if r.footprint > self.budget:
                 raise ValueError(f"request {r.rid} needs {r.footprint} bytes, above the budget {self.budget}")
         live, finished = [], []
-        used = 0
+        used = 0                        # workspaces of the resident requests
+        group_bytes = 0                 # workspace of the current group
         peak_used, peak_live = 0, 0
         group, members = None, ()
-        ticks, tick_sizes, busy = 0, [], 0.0
+        ticks, tick_sizes, busy, build_s = 0, [], 0.0, 0.0
         t0 = time.perf_counter()
         while pending or live:
             now = time.perf_counter() - t0
+            ts = time.perf_counter()       # a tick runs from its admissions to the end of its step
             while (pending and pending[0].arrival <= now and len(live) < self.max_slots
                    and used + pending[0].footprint <= self.budget):
-                r = pending.pop(0)
-                r.ctx = ibmg.from_case(self.request_case(r.case), precision=self.precision,
-                                       inner_cycles=self.inner, device=self.device)
+                r = pending[0]
+                ctx = ibmg.from_case(self.request_case(r.case), precision=self.precision,
+                                     inner_cycles=self.inner, device=self.device)
+                gb = ibmg.group_footprint_bytes([q.ctx for q in live] + [ctx])
+                if used + r.footprint + gb > self.budget:
+                    ctx.close()
+                    if not live:
+                        raise ValueError(f"request {r.rid} with its group workspace needs {r.footprint + gb} "
+                                         f"bytes, above the budget {self.budget}")
+                    break
+                pending.pop(0)
+                r.ctx = ctx
                 r.admitted = time.perf_counter() - t0
                 r.dof = r.ctx.n_face + r.ctx.n_cell
                 used += r.footprint
                 live.append(r)
-            peak_used = max(peak_used, used)
-            peak_live = max(peak_live, len(live))
             if not live:
                 wait = pending[0].arrival - (time.perf_counter() - t0)
                 if wait > 0:
@@ -106,11 +116,15 @@ class Server:
                 continue
             ids = tuple(r.rid for r in live)
             if ids != members:
+                tb = time.perf_counter()
                 if group is not None:
                     group.close()
                 group = ibmg.Group([r.ctx for r in live])
+                group_bytes = group.nbytes
                 members = ids
-            ts = time.perf_counter()
+                build_s += time.perf_counter() - tb
+            peak_used = max(peak_used, used + group_bytes)
+            peak_live = max(peak_live, len(live))
             ss = group.projection_step(check=False)
             group.lagrangian_update()
             torch.cuda.synchronize(self.device)
@@ -143,7 +157,7 @@ class Server:
             if len(still) != len(live):
                 if group is not None:
                     group.close()
-                    group, members = None, ()
+                    group, members, group_bytes = None, (), 0
                 for r in live:
                     if r.finished is not None:
                         r.ctx.close()
@@ -165,5 +179,5 @@ class Server:
             p50_request_s=float(np.percentile(lat, 50)), p99_request_s=float(np.percentile(lat, 99)),
             p50_wait_s=float(np.percentile(waits, 50)), p99_wait_s=float(np.percentile(waits, 99)),
             solve_dof_per_s=dof / wall, busy_s=busy, busy_dof_per_s=dof / busy if busy > 0 else 0.0,
-            failed_steps=failed,
+            failed_steps=failed, group_build_s=build_s, wall_outside_ticks_s=wall - busy,
         )

@@ -42,11 +42,17 @@ def test_lattice_sizes_match_oracle(ci):
 
 
 def test_footprint_grows_with_precision_and_nodes():
-    p = synth.tiny_3d()["params"]
+    # without the coarse tail (whose matrix is FP64 in FP64 mode and FP32
+    # when refined), the refined solver's FP32 copies add to the footprint
+    p = dict(synth.tiny_3d()["params"], coarse_tail=-1)
     a = ibmg.footprint_bytes(p, 10, 10)
     b = ibmg.footprint_bytes(p, 1000, 10)
     c = ibmg.footprint_bytes(p, 10, 10, precision=L.IBB_FP32_REFINED, inner_cycles=1)
     assert 0 < a < b and a < c
+    # the tail's matrix: 320 velocity and 128 pressure unknowns on level 1
+    t64 = ibmg.footprint_bytes(dict(p, coarse_tail=0), 10, 10)
+    t32 = ibmg.footprint_bytes(dict(p, coarse_tail=0), 10, 10, precision=L.IBB_FP32_REFINED, inner_cycles=1)
+    assert t64 - a >= 8 * (320 ** 2 + 128 ** 2) and t32 - c >= 4 * (320 ** 2 + 128 ** 2)
 
 
 @pytest.mark.parametrize("field,value", [("dim", 4), ("h", 0.0), ("omega", -1.0), ("nu1", -1), ("kernel", 7),

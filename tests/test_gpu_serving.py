@@ -62,3 +62,39 @@ def test_budget_binds():
     reqs = [serve.Request(i, 0.0, c, 2) for i, c in enumerate(cases)]
     summary = srv.run(reqs)
     assert summary["peak_resident"] == 1 and summary["requests"] == 3 and one > 0
+    # the budget covers the group's workspace as well as the requests'
+    assert summary["peak_bytes"] <= srv.budget
+
+
+def test_large_members_equal_alone():
+    """Members of the largest serving sizes (64^3 and 64 x 64 x 128, the
+    ones whose coarse levels run as batched launched passes) mixed with small
+    2D and 3D members: two group steps, each member bitwise equal to the same
+    request stepped alone."""
+    from paper_1302_3663_amd import ibmg
+    want = {(64, 64, 64): None, (64, 64, 128): None}
+    j = 0
+    while any(v is None for v in want.values()):
+        r = synth.serving_request(j, steps=2)
+        # a few thousand nodes; viscosity ratio below 100 (plain V-cycles)
+        if (tuple(r["size"]) in want and want[tuple(r["size"])] is None and r["X"].shape[1] >= 1000
+                and r["params"]["mu_max"] < 100 * r["params"]["mu_out"]):
+            want[tuple(r["size"])] = r
+        j += 1
+    cases = list(want.values()) + small_serving_requests(2) + [synth.tiny_2d(inout=True)]
+    for c in cases:
+        print("member", c["size"] if "size" in c else c["params"]["n"], "nodes", c["X"].shape[1], flush=True)
+    ctxs = [ibmg.from_case(c, precision=L.IBB_FP32_REFINED, inner_cycles=2) for c in cases]
+    g = ibmg.Group(ctxs)
+    for _ in range(2):
+        g.projection_step()
+        g.lagrangian_update()
+    g.close()
+    for c, ctx in zip(cases, ctxs):
+        u, p = ctx.get_state()
+        X, F, alive = ctx.get_nodes()
+        torch.cuda.synchronize()
+        got = [t.cpu().numpy() for t in (u, p, X, F, alive)]
+        ctx.close()
+        ref = alone(c, 2, L.IBB_FP32_REFINED)
+        assert all(np.array_equal(a, b) for a, b in zip(got, ref)), c.get("size")
