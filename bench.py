@@ -227,6 +227,91 @@ def summarize_trace(csv_path, out_path, workload, command):
         f.write("\n".join(lines))
 
 
+def summarize_counters(pmc_dir, workload, site, level, copy_mib, commands, out_path):
+    """Four rocprofv3 --pmc runs of the same command (subdirectories fetch:
+    FETCH_SIZE; write: WRITE_SIZE; rdreq: TCC_EA0_RDREQ_128B/64B/32B_sum;
+    wrreq: TCC_EA0_WRREQ_sum, TCC_EA0_WRREQ_64B_sum) -> the L2-to-fabric
+    bytes per launch of one launch site, from the request counts by size,
+    with FETCH_SIZE and WRITE_SIZE scaled by what they read for the
+    command's plain device copy of copy_mib MiB beside them."""
+    import csv
+    import collections
+    from paper_1302_3663_amd import synth
+    p = synth.WORKLOADS[workload]()["params"]
+    want = site_launches(p, site, level)
+
+    def load(sub):
+        per = collections.defaultdict(lambda: collections.defaultdict(float))
+        info = {}
+        with open(os.path.join(pmc_dir, sub, "run_counter_collection.csv")) as f:
+            for r in csv.DictReader(f):
+                d = int(r["Dispatch_Id"])
+                per[d][r["Counter_Name"]] += float(r["Counter_Value"])
+                m = re.search(r"(k_\w+)(<[^()]*>)?", r["Kernel_Name"])
+                sym = (m.group(1) + (m.group(2) or "")) if m else r["Kernel_Name"].split("(")[0]
+                info[d] = (sym, int(r["Grid_Size"]), "copyBuffer" in r["Kernel_Name"])
+        return per, info
+
+    def select(per, info, copy):
+        rows = []
+        # the calibration copy: the copies of the largest grid (torch's
+        # uploads are copies too, of other sizes)
+        big = max((g for _, g, c in info.values() if c), default=-1)
+        for d, cs in per.items():
+            sym, grid, is_copy = info[d]
+            if copy and is_copy and grid == big:
+                rows.append(cs)
+            elif not copy and any(sym == w and (g is None or grid == g) for w, g in want):
+                rows.append(cs)
+        return rows
+
+    def mean(rows, expr):
+        return sum(expr(r) for r in rows) / len(rows) if rows else float("nan")
+    runs = {k: load(k) for k in ("fetch", "write", "rdreq", "wrreq")}
+    rd = lambda r: 128 * r.get("TCC_EA0_RDREQ_128B_sum", 0) + 64 * r.get("TCC_EA0_RDREQ_64B_sum", 0) + \
+        32 * r.get("TCC_EA0_RDREQ_32B_sum", 0)
+    wr = lambda r: 64 * r.get("TCC_EA0_WRREQ_64B_sum", 0) + \
+        32 * (r.get("TCC_EA0_WRREQ_sum", 0) - r.get("TCC_EA0_WRREQ_64B_sum", 0))
+    copy_bytes = copy_mib * (1 << 20)
+    k_rd = select(*runs["rdreq"], copy=False)
+    k_wr = select(*runs["wrreq"], copy=False)
+    c_rd = select(*runs["rdreq"], copy=True)
+    c_wr = select(*runs["wrreq"], copy=True)
+    k_f = select(*runs["fetch"], copy=False)
+    k_w = select(*runs["write"], copy=False)
+    c_f = select(*runs["fetch"], copy=True)
+    c_w = select(*runs["write"], copy=True)
+    read_b, write_b = mean(k_rd, rd), mean(k_wr, wr)
+    f_scale = copy_bytes / (1024 * mean(c_f, lambda r: r["FETCH_SIZE"]))
+    w_scale = copy_bytes / (1024 * mean(c_w, lambda r: r["WRITE_SIZE"]))
+    fetch_b = 1024 * mean(k_f, lambda r: r["FETCH_SIZE"]) * f_scale
+    wsize_b = 1024 * mean(k_w, lambda r: r["WRITE_SIZE"]) * w_scale
+    D = p["dim"]
+    units = {0: None}
+    kernel = site_name(site, level, D)
+    lines = [f"# L2-to-fabric traffic: {kernel}, {workload}", "",
+             "Four counter runs of the same command, one counter group each (run from /tmp with TMPDIR=/tmp on "
+             "one MI355X, each under `timeout -s KILL 150`):", "", "```"] + commands + ["```", "",
+             f"The command copies a {copy_mib} MiB device buffer 5 times beside the solver "
+             "(`__amd_rocclr_copyBuffer`, known bytes read and written).", "",
+             "| counters | the copy reads | per launch of the site |", "|---|---:|---:|",
+             f"| read requests by size (128 B x RDREQ_128B + 64 B x RDREQ_64B + 32 B x RDREQ_32B) | "
+             f"{mean(c_rd, rd) / 2**20:.1f} MiB | {read_b / 1e6:.3f} MB |",
+             f"| write requests by size (64 B x WRREQ_64B + 32 B x the rest) | {mean(c_wr, wr) / 2**20:.1f} MiB | "
+             f"{write_b / 1e6:.3f} MB |",
+             f"| FETCH_SIZE x {f_scale:.4f} (the copy's factor) | {copy_mib} MiB | {fetch_b / 1e6:.3f} MB |",
+             f"| WRITE_SIZE x {w_scale:.4f} | {copy_mib} MiB | {wsize_b / 1e6:.3f} MB |", "",
+             f"Launches matched: {len(k_rd)} (symbols and grid sizes: "
+             + ", ".join(f"`{w}` {g if g is not None else 'any'}" for w, g in want) + ").", "",
+             "The request counts by size need no calibration: the copy reads and writes its own size.  The derived "
+             "FETCH_SIZE counts 128-byte reads through TCC_BUBBLE, which reads 0 on this chip, so it counts every "
+             "read as 64 bytes; its copy factor restores the size.  Both count the L2's traffic to the fabric, "
+             "which the 256 MB last-level cache serves in part.", "",
+             f"source_digest: {source_digest()}", f"hbm_bytes_per_launch: {read_b + write_b:.0f}", ""]
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines))
+
+
 def percentile(v, q):
     import numpy as np
     return float(np.percentile(np.asarray(v), q)) if v else None
@@ -426,9 +511,18 @@ def main():
     ap.add_argument("--summarize-trace", nargs=2, metavar=("CSV", "OUT_MD"),
                     help="write the per-kernel summary of a rocprofv3 kernel-trace CSV and exit")
     ap.add_argument("--trace-command", default="", help="with --summarize-trace: the command that took the trace")
+    ap.add_argument("--summarize-counters", nargs=4, metavar=("PMC_DIR", "SITE", "LEVEL", "OUT_MD"),
+                    help="write the traffic summary of a launch site from four rocprofv3 --pmc runs and exit")
+    ap.add_argument("--counter-commands", action="append", default=[],
+                    help="with --summarize-counters: the commands that took the counters (repeat)")
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(args.summarize_trace[0], args.summarize_trace[1], args.workload, args.trace_command)
+        return
+    if args.summarize_counters:
+        d, site, level, out = args.summarize_counters
+        summarize_counters(d, args.workload, int(site), int(level), args.calibrate_copy or 256, args.counter_commands,
+                           out)
         return
     if args.inner is None:
         args.inner = 2 if args.workload == "serving" else 4

@@ -382,7 +382,7 @@ size_t carve(ibb_ctx *c, char *base, bool dry)
         t.comp = cv.take<int>((size_t)t.n);
         c->tplan[v] = cv.take<LdsLevel>(WG_MAXLEV);
     }
-    c->partial = cv.take<double>(3 * NORM_BLOCKS);
+    c->partial = cv.take<double>(3 * NORM_BLOCKS_MAX);
     c->scalar = cv.take<double>(8);
     const size_t em = (size_t)(c->eta_max > 0 ? c->eta_max : 1);
     const size_t mm = (size_t)(c->m_max > 0 ? c->m_max : 1);

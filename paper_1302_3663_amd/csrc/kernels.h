@@ -7,8 +7,11 @@
 
 namespace ibmg {
 
-// grid-stride reductions use at most this many blocks per component
+// grid-stride reductions use at most NORM_BLOCKS blocks per component, or
+// on large lattices as many as keep about 16 points per thread, up to
+// NORM_BLOCKS_MAX (per-thread loops are latency-bound once they grow long)
 constexpr unsigned NORM_BLOCKS = 1024;
+constexpr unsigned NORM_BLOCKS_MAX = 8192;
 
 // a box of lattice positions: lo[d] .. lo[d] + ext[d] - 1
 struct Box {

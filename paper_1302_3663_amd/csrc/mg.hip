@@ -2094,8 +2094,10 @@ void launch_smooth_rb(const Grid &g, int vel, int a, const VelArrC<T> &xin, cons
 
 static inline unsigned stride_blocks(long long n)
 {
-    unsigned b = blocks_for(n);
-    return b < NORM_BLOCKS ? (b ? b : 1) : NORM_BLOCKS;
+    const unsigned b = blocks_for(n);
+    const long long want = std::max<long long>(NORM_BLOCKS, (n + 256 * 16 - 1) / (256 * 16));
+    const unsigned cap = (unsigned)std::min<long long>(want, NORM_BLOCKS_MAX);
+    return b < cap ? (b ? b : 1) : cap;
 }
 
 template <typename T>
