@@ -159,8 +159,8 @@ struct LdsPlan {
 // as its linear map.  That part (smoothing, residuals and transfers down to
 // the coarsest level and back) starts from a zero iterate, so its result is
 // a fixed matrix times the restricted right-hand side.  Tm holds that matrix
-// row by row ([r * ld + j]: row r, column j, rows padded to ld = n rounded
-// up to 16 bytes, in the precision of the cycle), built by running the same
+// (n rows, n columns, in the precision of the cycle) in blocks of 16 bytes'
+// worth of columns, each block row after row, built by running the same
 // passes on every unit right-hand side;
 // idx and comp list the n unknowns of level `level` (padded index and
 // component, in the order comp, z, y, x).  n == 0: no tail, the cycle

@@ -1478,9 +1478,10 @@ __device__ inline void wg_restrict_tail(const LevTab<T> &ltr, const Grid &gc, co
 }
 
 // x = Tm bv at the tail's unknowns, with the ghost images of x; the rest of
-// x is zero already.  Each thread streams its own row of Tm (rows padded to
-// 16 bytes, so that a row reads as 16-byte vectors, several in flight), and
-// sums it in column order.
+// x is zero already.  Tm is stored in blocks of W columns (W = 16 bytes over
+// the element size): block q holds, row after row, the W entries of columns
+// qW .. qW+W-1, so that the 64 rows of a wave read one contiguous kilobyte
+// per 16-byte load.  Each thread sums its own row in column order.
 template <typename T>
 struct Vec16;
 template <>
@@ -1496,34 +1497,34 @@ struct Vec16<double> {
 
 __host__ __device__ inline int tail_ld(int n, int wsz) { return wsz == 4 ? (n + 3) & ~3 : (n + 1) & ~1; }
 
+// position of entry (row r, column j) of an n-row tail matrix
 template <typename T>
-__device__ inline T row_dot(const T *__restrict__ row, const T *bv, int n)
+__device__ inline long long tail_at(int n, int r, int j)
 {
-    using V = typename Vec16<T>::type;
     constexpr int W = Vec16<T>::n;
-    const V *rv = reinterpret_cast<const V *>(row);
-    T sum = T(0);
-    const int nv = n / W;
-#pragma unroll 8
-    for (int q = 0; q < nv; ++q) {
-        const V t = rv[q];
-        const T *tt = reinterpret_cast<const T *>(&t);
-#pragma unroll
-        for (int w = 0; w < W; ++w) sum += tt[w] * bv[q * W + w];
-    }
-    for (int j = nv * W; j < n; ++j) sum += row[j] * bv[j];
-    return sum;
+    return (long long)(j / W) * ((long long)n * W) + (long long)r * W + (j % W);
 }
 
 template <typename T, int D, int VEL>
 __device__ inline void wg_apply_tail(const LevTab<T> &lcr, const Tail &tail, const T *bv)
 {
+    using V = typename Vec16<T>::type;
+    constexpr int W = Vec16<T>::n;
     const LevTab<T> lc = lcr;
     const T *__restrict__ Tm = static_cast<const T *>(tail.Tm);
     const int n = tail.n;
-    const int ld = tail_ld(n, (int)sizeof(T));
+    const int nq = n / W;
     for (int r = threadIdx.x; r < n; r += blockDim.x) {
-        const T sum = row_dot<T>(Tm + (long long)r * ld, bv, n);
+        const V *__restrict__ rv = reinterpret_cast<const V *>(Tm) + r;
+        T sum = T(0);
+#pragma unroll 8
+        for (int q = 0; q < nq; ++q) {
+            const V t = rv[(long long)q * n];
+            const T *tt = reinterpret_cast<const T *>(&t);
+#pragma unroll
+            for (int w = 0; w < W; ++w) sum += tt[w] * bv[q * W + w];
+        }
+        for (int j = nq * W; j < n; ++j) sum += Tm[tail_at<T>(n, r, j)] * bv[j];
         const int a = tail.comp[r];
         T *x = VEL ? (a == 0 ? lc.xu[0] : (a == 1 ? lc.xu[1] : lc.xu[2])) : lc.xp;
         const long long e = tail.idx[r];
@@ -1783,11 +1784,10 @@ __global__ void __launch_bounds__(wg_threads(D, VEL)) k_tail_columns(const LevTa
     coarse_cycle<T, D, VEL>(wt, lt, L, nu1, nu2, ndense, uidx, ucomp, M, none, bv);
     __syncthreads();
     T *Tm = const_cast<T *>(static_cast<const T *>(tail.Tm));
-    const int ld = tail_ld(tail.n, (int)sizeof(T));
     for (int r = threadIdx.x; r < tail.n; r += blockDim.x) {
         const int a = tail.comp[r];
         const T *x = VEL ? (a == 0 ? wt[lt].xu[0] : (a == 1 ? wt[lt].xu[1] : wt[lt].xu[2])) : wt[lt].xp;
-        Tm[(long long)r * ld + j] = x[tail.idx[r]];
+        Tm[tail_at<T>(tail.n, r, j)] = x[tail.idx[r]];
     }
 }
 
