@@ -55,6 +55,7 @@ class Desc(ctypes.Structure):
         ("rtol", ctypes.c_double),
         ("gamma", ctypes.c_double * 16),
         ("decoupled", ctypes.c_int),
+        ("galerkin", ctypes.c_int),
     ]
 
 
@@ -75,6 +76,7 @@ def make_desc(p):
     for l in range(16):
         d.gamma[l] = g[l] if l < len(g) else 1.0
     d.decoupled = int(p.get("decoupled", 0))
+    d.galerkin = int(p.get("galerkin", 0))
     return d
 
 
@@ -116,6 +118,7 @@ def lib():
         L.orc_vcycles.argtypes = [vp, ctypes.c_int, dp, dp, ctypes.c_int]
         L.orc_solve_gcr.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, ip, dp]
         L.orc_smooth.argtypes = [vp, ctypes.c_int, dp, dp, ctypes.c_int]
+        L.orc_smooth_level.argtypes = [vp, ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int]
         L.orc_relres.restype = ctypes.c_double
         L.orc_relres.argtypes = [vp, ctypes.c_int, dp, dp]
         L.orc_csr_nnz.restype = ctypes.c_long
@@ -369,6 +372,12 @@ class Hierarchy:
     def smooth(self, velocity, b, x0, k):
         x = _f64(x0).copy()
         _check(lib().orc_smooth(self.h, int(velocity), _d(_f64(b)), _d(x), k), "smooth")
+        return x
+
+    def smooth_level(self, velocity, level, b, x0, k):
+        """k sweeps of the smoother of `level` on vectors of its unknowns."""
+        x = _f64(x0).copy()
+        _check(lib().orc_smooth_level(self.h, int(velocity), level, _d(_f64(b)), _d(x), k), "smooth_level")
         return x
 
     def relres(self, velocity, b, x):

@@ -23,7 +23,9 @@
  *   - geometric multigrid with red-black Gauss-Seidel, full-weighting
  *     restriction, linear prolongation and V-cycles to a relative residual
  *     (Sec. "Multigrid"), with the coarse-viscosity scaling of
- *     eq:ViscCoarseGrid.
+ *     eq:ViscCoarseGrid, or with Galerkin coarse operators R A P for the
+ *     viscous system (the second remedy named in Sec. "Numerical
+ *     Concerns"; see galerkin_level).
  *
  * Style: every field lives in a ghost-padded array.  Boundary conditions
  * are imposed by filling the ghost layer from a rule table, and the
@@ -60,6 +62,7 @@ typedef struct {
     double rtol;
     double gamma[16];
     int decoupled;      /* 1: constant-viscosity momentum operator, eq:NSdis1 */
+    int galerkin;       /* 1: viscous coarse operators R A P (Sec. "Numerical Concerns") */
 } orc_desc;
 
 enum { ORC_OK = 0, ORC_EINVAL = 1, ORC_ENOMEM = 2, ORC_ENOCONV = 3, ORC_ENUMERIC = 4 };
@@ -747,6 +750,8 @@ static int count_levels(const orc_desc *d)
     return L;
 }
 
+static int galerkin_level(hier_t *H, int l);
+
 static int desc_check(const orc_desc *d)
 {
     if (d->dim != 2 && d->dim != 3) return ORC_EINVAL;
@@ -758,6 +763,9 @@ static int desc_check(const orc_desc *d)
     if (d->decoupled != 0 && d->decoupled != 1) return ORC_EINVAL;
     /* the decoupled form holds only where the viscosity is one constant */
     if (d->decoupled && d->mu_max != d->mu_out) return ORC_EINVAL;
+    if (d->galerkin != 0 && d->galerkin != 1) return ORC_EINVAL;
+    /* the Galerkin levels replace the coupled operator's coarse levels */
+    if (d->galerkin && d->decoupled) return ORC_EINVAL;
     return ORC_OK;
 }
 
@@ -823,7 +831,9 @@ void *orc_hier_create(const orc_desc *d, const double *rho_faces, const double *
     }
     for (int l = 0; l < H->L; ++l) {
         if ((*status = assemble(&H->lv[l], d, 0, &H->lv[l].Ap))) { orc_hier_destroy(H); return NULL; }
-        if ((*status = assemble(&H->lv[l], d, 1, &H->lv[l].Au))) { orc_hier_destroy(H); return NULL; }
+        if (d->galerkin && l > 0) *status = galerkin_level(H, l);
+        else *status = assemble(&H->lv[l], d, 1, &H->lv[l].Au);
+        if (*status) { orc_hier_destroy(H); return NULL; }
     }
     return H;
 }
@@ -960,12 +970,221 @@ static void prolong_add(hier_t *H, int l, int velocity, const double *xc, double
     for (int c = 0; c < uc->ncomp; ++c) free(pad[c]);
 }
 
+/* ------------------------------------------------------------------ */
+/* Galerkin coarse operators                                            */
+/* ------------------------------------------------------------------ */
+/* Sec. "Numerical Concerns" names, as the second way to restore fast
+ * convergence at large mu_max, coarse operators that satisfy the Galerkin
+ * condition: A_{l+1} = R_l A_l P_l, with R_l and P_l the restriction and
+ * prolongation of the V-cycle between levels l and l+1.  Here R_l and P_l
+ * are the matrices of restrict_residual and prolong_add (boundary rules
+ * included), assembled by probing, and the product is formed as
+ * R_l (A_l P_l) with sparse matrix products. */
+
+/* C = A B (A: n x k, B: k x ncol), row by row with a dense accumulator;
+ * the columns of each row of C are sorted */
+static int lcmp(const void *x, const void *y)
+{
+    long a = *(const long *)x, b = *(const long *)y;
+    return a < b ? -1 : (a > b);
+}
+
+static int csr_mul(const csr_t *A, const csr_t *B, long ncol, csr_t *C)
+{
+    long n = A->nrow;
+    long *mark = (long *)malloc(sizeof(long) * (ncol ? ncol : 1));
+    double *acc = (double *)calloc(ncol ? ncol : 1, sizeof(double));
+    long *cols = (long *)malloc(sizeof(long) * (ncol ? ncol : 1));
+    C->nrow = n;
+    C->rowptr = (long *)calloc(n + 1, sizeof(long));
+    if (!mark || !acc || !cols || !C->rowptr) { free(mark); free(acc); free(cols); return ORC_ENOMEM; }
+    for (long j = 0; j < ncol; ++j) mark[j] = -1;
+    /* row lengths */
+    for (long i = 0; i < n; ++i) {
+        long len = 0;
+        for (long t = A->rowptr[i]; t < A->rowptr[i + 1]; ++t) {
+            long k = A->col[t];
+            for (long u = B->rowptr[k]; u < B->rowptr[k + 1]; ++u)
+                if (mark[B->col[u]] != i) { mark[B->col[u]] = i; ++len; }
+        }
+        C->rowptr[i + 1] = C->rowptr[i] + len;
+    }
+    C->nnz = C->rowptr[n];
+    C->col = (long *)malloc(sizeof(long) * (C->nnz ? C->nnz : 1));
+    C->val = (double *)malloc(sizeof(double) * (C->nnz ? C->nnz : 1));
+    if (!C->col || !C->val) { free(mark); free(acc); free(cols); return ORC_ENOMEM; }
+    for (long j = 0; j < ncol; ++j) mark[j] = -1;
+    for (long i = 0; i < n; ++i) {
+        long len = 0;
+        for (long t = A->rowptr[i]; t < A->rowptr[i + 1]; ++t) {
+            long k = A->col[t];
+            double a = A->val[t];
+            for (long u = B->rowptr[k]; u < B->rowptr[k + 1]; ++u) {
+                long j = B->col[u];
+                if (mark[j] != i) { mark[j] = i; acc[j] = 0.0; cols[len++] = j; }
+                acc[j] += a * B->val[u];
+            }
+        }
+        qsort(cols, len, sizeof(long), lcmp);
+        for (long q = 0; q < len; ++q) {
+            C->col[C->rowptr[i] + q] = cols[q];
+            C->val[C->rowptr[i] + q] = acc[cols[q]];
+        }
+    }
+    free(mark);
+    free(acc);
+    free(cols);
+    return ORC_OK;
+}
+
+/* The matrix of the restriction (restrict_ = 1: coarse rows, fine columns)
+ * or of the prolongation (fine rows, coarse columns) between levels l and
+ * l+1.  Probing: the input unknowns of one component whose positions are
+ * congruent to o modulo m (per axis) are set to one together; an output
+ * row reads inputs only within a few points of its own position (in fine
+ * units: |2t - q| <= 3 for the prolongation, |t - 2q| <= 3 for the
+ * restriction), and there the congruence leaves exactly one candidate
+ * (checked), which is the column of the value the row receives. */
+static int probe_transfer(hier_t *H, int l, int restrict_, csr_t *M)
+{
+    level_t *F = &H->lv[l], *C = &H->lv[l + 1];
+    const umap_t *uin = restrict_ ? &F->uu : &C->uu, *uout = restrict_ ? &C->uu : &F->uu;
+    const grid_t *gin = restrict_ ? &F->g : &C->g;
+    long nin = umap_total(uin), nout = umap_total(uout);
+    int m[3];
+    for (int d = 0; d < 3; ++d) {
+        m[d] = d >= gin->D ? 1 : (restrict_ ? 8 : 4);
+        if (d < gin->D && gin->bc[d] == AX_PERIODIC && gin->n[d] % m[d] != 0) m[d] = gin->n[d];
+    }
+    double *in = (double *)malloc(sizeof(double) * (nin ? nin : 1));
+    double *out = (double *)malloc(sizeof(double) * (nout ? nout : 1));
+    long cap = 16 * nout + 16, nt = 0;
+    trip_t *T = (trip_t *)malloc(sizeof(trip_t) * cap);
+    int st = ORC_OK;
+    if (!in || !out || !T) st = ORC_ENOMEM;
+    for (int ca = 0; ca < uin->ncomp && !st; ++ca)
+        for (int o2 = 0; o2 < m[2] && !st; ++o2)
+            for (int o1 = 0; o1 < m[1] && !st; ++o1)
+                for (int o0 = 0; o0 < m[0] && !st; ++o0) {
+                    int o[3] = {o0, o1, o2}, any = 0;
+                    memset(in, 0, sizeof(double) * nin);
+                    for (long r = uin->off[ca]; r < uin->off[ca + 1]; ++r) {
+                        int c, q[3];
+                        umap_pos(uin, r, &c, q);
+                        if (q[0] % m[0] == o0 && q[1] % m[1] == o1 && q[2] % m[2] == o2) { in[r] = 1.0; any = 1; }
+                    }
+                    if (!any) continue;
+                    if (restrict_) restrict_residual(H, l, 1, in, out);
+                    else {
+                        memset(out, 0, sizeof(double) * nout);
+                        prolong_add(H, l, 1, in, out);
+                    }
+                    for (long r = 0; r < nout; ++r) {
+                        if (out[r] == 0.0) continue;
+                        int cb, q[3], t[3];
+                        umap_pos(uout, r, &cb, q);
+                        for (int d = 0; d < 3; ++d) {
+                            t[d] = INT32_MIN;
+                            if (d >= gin->D) { t[d] = 0; continue; }
+                            int lo = restrict_ ? 2 * q[d] - 3 : (q[d] - 3 + 1) / 2 - 1;
+                            int hi = restrict_ ? 2 * q[d] + 3 : (q[d] + 3) / 2 + 1;
+                            for (int v = lo; v <= hi; ++v) {
+                                if (!restrict_ && abs(2 * v - q[d]) > 3) continue;
+                                int w = v;
+                                if (gin->bc[d] == AX_PERIODIC) w = ((w % gin->n[d]) + gin->n[d]) % gin->n[d];
+                                if (w < uin->lo[ca][d] || w > uin->hi[ca][d] || w % m[d] != o[d]) continue;
+                                if (t[d] != INT32_MIN && t[d] != w) { st = ORC_EINVAL; break; }
+                                t[d] = w;
+                            }
+                        }
+                        if (st) break;
+                        if (t[0] == INT32_MIN || t[1] == INT32_MIN || t[2] == INT32_MIN) { st = ORC_EINVAL; break; }
+                        if (nt == cap) {
+                            cap *= 2;
+                            trip_t *T2 = (trip_t *)realloc(T, sizeof(trip_t) * cap);
+                            if (!T2) { st = ORC_ENOMEM; break; }
+                            T = T2;
+                        }
+                        T[nt].r = r;
+                        T[nt].c = umap_index(uin, ca, t);
+                        T[nt].v = out[r];
+                        ++nt;
+                    }
+                }
+    free(in);
+    free(out);
+    if (st) { free(T); return st; }
+    qsort(T, nt, sizeof(trip_t), trip_cmp);
+    M->nrow = nout;
+    M->nnz = nt;
+    M->rowptr = (long *)calloc(nout + 1, sizeof(long));
+    M->col = (long *)malloc(sizeof(long) * (nt ? nt : 1));
+    M->val = (double *)malloc(sizeof(double) * (nt ? nt : 1));
+    if (!M->rowptr || !M->col || !M->val) { free(T); return ORC_ENOMEM; }
+    for (long t = 0; t < nt; ++t) {
+        M->rowptr[T[t].r + 1]++;
+        M->col[t] = T[t].c;
+        M->val[t] = T[t].v;
+    }
+    for (long r = 0; r < nout; ++r) M->rowptr[r + 1] += M->rowptr[r];
+    free(T);
+    return ORC_OK;
+}
+
+/* viscous operator of level l >= 1 as R_{l-1} (A_{l-1} P_{l-1}) */
+static int galerkin_level(hier_t *H, int l)
+{
+    csr_t R = {0}, P = {0}, AP = {0};
+    long nc = umap_total(&H->lv[l].uu);
+    int st = probe_transfer(H, l - 1, 1, &R);
+    if (!st) st = probe_transfer(H, l - 1, 0, &P);
+    if (!st) st = csr_mul(&H->lv[l - 1].Au, &P, nc, &AP);
+    if (!st) st = csr_mul(&R, &AP, nc, &H->lv[l].Au);
+    csr_free(&R);
+    csr_free(&P);
+    csr_free(&AP);
+    return st;
+}
+
+/* A red-black sweep on a Galerkin level.  R A P couples points of one
+ * colour, so the rows of each (component, colour) set are all updated from
+ * the values the set had before its pass: Jacobi within a set, Gauss-Seidel
+ * from set to set, in the order of gs_sweep.  Where no two rows of a set
+ * couple (every rediscretised level) this is gs_sweep itself. */
+static void gs_sweep_sets(const csr_t *A, const umap_t *u, const double *b, double *x)
+{
+    long n = A->nrow;
+    double *xn = (double *)malloc(sizeof(double) * (n ? n : 1));
+    for (int c = 0; c < u->ncomp; ++c)
+        for (int colour = 0; colour < 2; ++colour) {
+            for (long r = u->off[c]; r < u->off[c + 1]; ++r) {
+                if (row_colour(u, r) != colour) continue;
+                double s = b[r], diag = 0.0;
+                for (long t = A->rowptr[r]; t < A->rowptr[r + 1]; ++t) {
+                    if (A->col[t] == r) diag = A->val[t];
+                    else s -= A->val[t] * x[A->col[t]];
+                }
+                xn[r] = s / diag;
+            }
+            for (long r = u->off[c]; r < u->off[c + 1]; ++r)
+                if (row_colour(u, r) == colour) x[r] = xn[r];
+        }
+    free(xn);
+}
+
+/* one smoothing sweep of level l */
+static void smooth_level(hier_t *H, int velocity, int l, const double *b, double *x)
+{
+    level_t *L = &H->lv[l];
+    if (velocity && H->d.galerkin && l > 0) gs_sweep_sets(&L->Au, &L->uu, b, x);
+    else gs_sweep(velocity ? &L->Au : &L->Ap, velocity ? &L->uu : &L->up, b, x);
+}
+
 /* V(nu1, nu2) cycle on level l (Sec. "Multigrid") */
 static void vcycle(hier_t *H, int velocity, int l, const double *b, double *x, double *wu)
 {
     level_t *L = &H->lv[l];
     const csr_t *A = velocity ? &L->Au : &L->Ap;
-    const umap_t *u = velocity ? &L->uu : &L->up;
     long n = A->nrow;
     double frac = (double)n / (double)(velocity ? H->lv[0].Au.nrow : H->lv[0].Ap.nrow);
     int singular = !velocity && H->singular_p;
@@ -973,12 +1192,12 @@ static void vcycle(hier_t *H, int velocity, int l, const double *b, double *x, d
         if (n <= DENSE_MAX) {
             dense_solve(A, singular, b, x);
         } else {
-            for (int s = 0; s < H->d.nu1 + H->d.nu2; ++s) gs_sweep(A, u, b, x);
+            for (int s = 0; s < H->d.nu1 + H->d.nu2; ++s) smooth_level(H, velocity, l, b, x);
             *wu += (H->d.nu1 + H->d.nu2) * frac;
         }
         return;
     }
-    for (int s = 0; s < H->d.nu1; ++s) gs_sweep(A, u, b, x);
+    for (int s = 0; s < H->d.nu1; ++s) smooth_level(H, velocity, l, b, x);
     double *r = (double *)malloc(sizeof(double) * n);
     residual(A, b, x, r);
     level_t *C = &H->lv[l + 1];
@@ -988,7 +1207,7 @@ static void vcycle(hier_t *H, int velocity, int l, const double *b, double *x, d
     restrict_residual(H, l, velocity, r, bc);
     vcycle(H, velocity, l + 1, bc, xc, wu);
     prolong_add(H, l, velocity, xc, x);
-    for (int s = 0; s < H->d.nu2; ++s) gs_sweep(A, u, b, x);
+    for (int s = 0; s < H->d.nu2; ++s) smooth_level(H, velocity, l, b, x);
     *wu += (H->d.nu1 + H->d.nu2) * frac;
     free(r);
     free(bc);
@@ -1185,6 +1404,16 @@ int orc_smooth(void *hp, int velocity, const double *bc, double *xc, int k)
     vec_to_compact(H, velocity, x, xc);
     free(b);
     free(x);
+    return ORC_OK;
+}
+
+/* exactly k smoothing sweeps of level l on vectors of that level's
+ * unknowns (the smoother the V-cycle uses there) */
+int orc_smooth_level(void *hp, int velocity, int level, const double *b, double *x, int k)
+{
+    hier_t *H = (hier_t *)hp;
+    if (level < 0 || level >= H->L) return ORC_EINVAL;
+    for (int i = 0; i < k; ++i) smooth_level(H, velocity, level, b, x);
     return ORC_OK;
 }
 
