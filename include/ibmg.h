@@ -144,6 +144,17 @@ typedef struct {
      * per thread across the whole level; same bits, slower on the grids
      * measured here.  0 (default) or < 0: one point per thread. */
     int smoother_zblock;
+    /* 1: the viscous system's coarse operators satisfy the Galerkin
+     * condition, A_{l+1} = R_l A_l P_l with the V-cycle's own restriction and
+     * prolongation (Sec. "Numerical Concerns", second remedy for slow
+     * convergence at large mu_max), rebuilt with the coefficients; such a
+     * level is smoothed red-black with every (component, colour) set updated
+     * from its values before the pass, since R A P couples points of one
+     * colour.  The velocity V-cycles then run launched passes to the
+     * coarsest level (no one-workgroup cycle or tail); the pressure system
+     * is unchanged.  Not with decoupled = 1, nor in an ibb_group.  0: the
+     * coarse operators are rediscretised on restricted coefficients. */
+    int galerkin;
 } ibb_desc;
 
 typedef struct {
@@ -314,8 +325,9 @@ ibb_status ibb_fragments(ibb_ctx *ctx, int32_t *label, int *n_fragments, int *n_
  * ibb_projection_step / ibb_lagrangian_update, so its results are the same
  * as when it is stepped alone.
  *
- * Members must agree on precision, nu1, nu2 and (refined) inner_cycles
- * (IBB_EINVAL otherwise) and may not repeat.  Members with krylov_restart > 0
+ * Members must agree on precision, nu1, nu2 and (refined) inner_cycles,
+ * may not use Galerkin coarse operators (IBB_EINVAL otherwise) and may not
+ * repeat.  Members with krylov_restart > 0
  * are solved one by one (their GCR solves do not share launches); the other
  * members share them.  They must outlive the group and
  * keep their workspaces; a member can still be used on its own between group
@@ -364,7 +376,9 @@ const char *ibb_group_last_error(const ibb_group *group);
  * and, in the Lagrangian update (level 0): 23 spread of force and density
  * (per face lattice, units = its points), 24 viscosity gather (per cell or
  * edge lattice), 25 interpolation (units = nodes x dim), 26 spring forces
- * (units = nodes)
+ * (units = nodes); with Galerkin coarse operators (level >= 1): 27 operator
+ * build (units = the level's viscous unknowns), 28/29 smoother colour pass
+ * FP64/FP32, 30/31 residual FP64/FP32
  * ibb_profile_read (host outputs) returns the launches, their summed device
  * time and the summed number of unknowns they updated or evaluated (for the
  * cycle, the start level's unknowns); enabling resets the totals. */

@@ -56,6 +56,7 @@ class Desc(ctypes.Structure):
         ("decoupled", ctypes.c_int),
         ("coarse_tail", ctypes.c_int),
         ("smoother_zblock", ctypes.c_int),
+        ("galerkin", ctypes.c_int),
     ]
 
 
@@ -101,6 +102,7 @@ def make_desc(p, precision=IBB_FP64, inner_cycles=1):
     d.decoupled = int(p.get("decoupled", 0))
     d.coarse_tail = int(p.get("coarse_tail", 0))
     d.smoother_zblock = int(p.get("smoother_zblock", 0))
+    d.galerkin = int(p.get("galerkin", 0))
     return d
 
 

@@ -45,6 +45,12 @@ struct Level {
     int dec = 0;
     // colour passes of this level z-blocked (3D launched levels)
     int zb = 0;
+    // Galerkin operator of the viscous system on this level (levels >= 1
+    // when the descriptor asks for it), FP64 and, refined, FP32, and the
+    // second buffer of its colour passes (swapped with x after each pass)
+    bool gal = false;
+    double *gv[3] = {}, *gy[3] = {};
+    float *gv32[3] = {}, *gy32[3] = {};
 };
 
 struct Carver {
@@ -106,6 +112,7 @@ struct ibb_ctx {
     unsigned char *alive = nullptr;
     int *inc_keys = nullptr, *inc_count = nullptr, *inc_start = nullptr, *inc_list = nullptr;
     int *counters = nullptr;   // [0] broken this update, [1] alive, [2] fragments, [3] detached
+    int *gal_err = nullptr;    // set when a Galerkin product leaves its stencil box
     // GCR on the finest level: right-hand side, iterate, residual, and the
     // stored directions z_j, q_j (component arrays of the finest level)
     double *gb[3] = {}, *gx[3] = {}, *gr[3] = {};
@@ -164,7 +171,8 @@ enum ProfSite {
     PS_DENSE = 16, PS_OUTER = 17, PS_GCR = 18, PS_SMOOTH_UDEC64 = 19, PS_SMOOTH_UDEC32 = 20,
     PS_SMOOTH_RB64 = 21, PS_SMOOTH_RB32 = 22,
     // the Lagrangian update (level 0)
-    PS_SPREAD_FACE = 23, PS_SPREAD_VISC = 24, PS_INTERP = 25, PS_SPRING_FORCE = 26
+    PS_SPREAD_FACE = 23, PS_SPREAD_VISC = 24, PS_INTERP = 25, PS_SPRING_FORCE = 26,
+    PS_GAL_BUILD = 27, PS_GAL_SMOOTH64 = 28, PS_GAL_SMOOTH32 = 29, PS_GAL_RESID64 = 30, PS_GAL_RESID32 = 31
 };
 
 inline int prof_class(int site, int level) { return site + 32 * level; }
@@ -237,6 +245,8 @@ ibb_status check_desc(const ibb_desc *d)
     // the decoupled form holds only where the viscosity is one constant
     if (d->decoupled != 0 && d->decoupled != 1) return IBB_EINVAL;
     if (d->decoupled && d->mu_max != d->mu_out) return IBB_EINVAL;
+    if (d->galerkin != 0 && d->galerkin != 1) return IBB_EINVAL;
+    if (d->galerkin && d->decoupled) return IBB_EINVAL;
     for (int a = 0; a < d->dim; ++a)
         if (d->axis_bc[a] == IBB_AXIS_PERIODIC && 4.0 * d->omega > d->n[a] * d->h) return IBB_EINVAL;
     // array indices are formed in 32-bit arithmetic: every padded array
@@ -339,6 +349,17 @@ size_t carve(ibb_ctx *c, char *base, bool dry)
                 for (int a = 0; a < D; ++a) L.xu32_alt[a] = cv.take<float>(n);
             }
         }
+        if (L.gal) {
+            for (int a = 0; a < D; ++a) {
+                const size_t ns = (size_t)gal_row_slots(D, a) * n;
+                L.gv[a] = cv.take<double>(ns);
+                L.gy[a] = cv.take<double>(n);
+                if (refined) {
+                    L.gv32[a] = cv.take<float>(ns);
+                    L.gy32[a] = cv.take<float>(n);
+                }
+            }
+        }
         if (refined) {
             L.xp32 = cv.take<float>(n);
             L.bp32 = cv.take<float>(n);
@@ -402,6 +423,7 @@ size_t carve(ibb_ctx *c, char *base, bool dry)
     c->inc_count = cv.take<int>(em);
     c->inc_start = cv.take<int>(em + 1);
     c->counters = cv.take<int>(8);
+    c->gal_err = cv.take<int>(1);
     if (d->krylov_restart > 0) {
         const int m = d->krylov_restart;
         c->gz.assign(3 * (size_t)m, nullptr);
@@ -482,6 +504,10 @@ void setup_shapes(ibb_ctx *c, const ibb_desc *d, int64_t max_nodes, int64_t max_
         for (int l = 0; l < c->L; ++l)
             if ((c->lv[l].np + 1) / 2 <= wgmax) { c->lc_p = l; break; }
     }
+    // Galerkin coarse operators: the velocity V-cycles run launched passes
+    // down to the coarsest level
+    for (int l = 0; l < c->L; ++l) c->lv[l].gal = d->galerkin && l > 0;
+    if (d->galerkin) c->lc_u = MAXLEV;
     // tails: the levels below the one-workgroup start level as one matrix,
     // when the level below the start has at most TAIL_MAX unknowns and all
     // levels from there fit the LDS arena of one workgroup (gfx950: 160 KB,
@@ -607,9 +633,37 @@ template <>
 float **alt_x<float>(Level &L, bool vel, int a) { return vel ? &L.xu32_alt[a] : &L.xp32_alt; }
 
 template <typename T>
+GalOpC<T> gal_op(const Level &L);
+template <>
+GalOpC<double> gal_op<double>(const Level &L) { return GalOpC<double>{{L.gv[0], L.gv[1], L.gv[2]}}; }
+template <>
+GalOpC<float> gal_op<float>(const Level &L) { return GalOpC<float>{{L.gv32[0], L.gv32[1], L.gv32[2]}}; }
+template <typename T>
+T **gal_y(Level &L, int a);
+template <>
+double **gal_y<double>(Level &L, int a) { return &L.gy[a]; }
+template <>
+float **gal_y<float>(Level &L, int a) { return &L.gy32[a]; }
+
+template <typename T>
 void sweep(ibb_ctx *c, bool vel, int l)
 {
     Level &L = c->lv[l];
+    if (vel && L.gal) {
+        // each colour pass writes the second buffer, which then becomes x:
+        // two exchanges per component bring every buffer back
+        const int cls = prof_class(sizeof(T) == 4 ? PS_GAL_SMOOTH32 : PS_GAL_SMOOTH64, l);
+        for (int a = 0; a < c->d.dim; ++a)
+            for (int colour = 0; colour < 2; ++colour) {
+                View<T> v = view<T>(L);
+                const int k = prof_begin(c, cls, unknowns_of(L.g, face_mask(a)) / 2);
+                launch_gal_smooth<T>(c->d.dim, L.g, a, colour, gal_op<T>(L), v.bu.c[a], cview(v.xu), *gal_y<T>(L, a),
+                                     c->s);
+                prof_end(c, k);
+                std::swap(*cur_x<T>(L, true, a), *gal_y<T>(L, a));
+            }
+        return;
+    }
     if (L.fused && l < (vel ? c->lc_u : c->lc_p)) {
         const T cvp = (T)(1.0 / (L.g.h * L.g.h));
         const T cvu = (T)L.cvu;
@@ -664,6 +718,13 @@ int residual(ibb_ctx *c, bool vel, int l, double *partial)
     const T cvp = (T)(1.0 / (L.g.h * L.g.h));
     const T cvu = (T)L.cvu;
     const T mass = (T)(c->d.sigma / c->d.dt);
+    if (vel && L.gal) {
+        // coarse levels only: no norm partials
+        const int k = prof_begin(c, prof_class(sizeof(T) == 4 ? PS_GAL_RESID32 : PS_GAL_RESID64, l), L.nu);
+        launch_gal_resid<T>(c->d.dim, L.g, gal_op<T>(L), cview(v.bu), cview(v.xu), v.ru, c->s);
+        prof_end(c, k);
+        return 0;
+    }
     const int site = (vel ? PS_RESID_U64 : PS_RESID_P64) + (sizeof(T) == 4 ? 2 : 0);
     const int k = prof_begin(c, prof_class(site, l), vel ? L.nu : L.np);
     const int np = vel ? launch_resid_u<T>(L.g, cview(v.bu), v.xu, v.cu, mass, cvu, v.ru, partial, c->s)
@@ -1466,6 +1527,24 @@ ibb_status rebuild_coefficients(ibb_ctx *c)
         launch_coef_ghosts<double>(L.g, set, c->s);
         if (d->precision == IBB_FP32_REFINED) launch_to_f32(set, set32, L.g.nel, c->s);
     }
+    // Galerkin operators of the viscous system, level by level from the
+    // finest (Sec. "Numerical Concerns"), with their FP32 copies
+    if (d->galerkin) {
+        launch_fill<int>(c->gal_err, 1, 0, c->s);
+        for (int l = 1; l < c->L; ++l) {
+            Level &F = c->lv[l - 1], &L = c->lv[l];
+            const GalOpC<double> fine = gal_op<double>(F);
+            Timed t(c, PS_GAL_BUILD, l, L.nu);
+            launch_gal_build(D, F.g, L.g, view64(F).cu, d->sigma / d->dt, F.cvu, l > 1 ? &fine : nullptr,
+                             GalOp<double>{{L.gv[0], L.gv[1], L.gv[2]}}, c->gal_err, c->s);
+            if (d->precision == IBB_FP32_REFINED)
+                launch_gal_to_f32(D, L.g, gal_op<double>(L), GalOp<float>{{L.gv32[0], L.gv32[1], L.gv32[2]}}, c->s);
+        }
+        int bad = 0;
+        HIPCHK(hipMemcpyAsync(&bad, c->gal_err, sizeof(int), hipMemcpyDeviceToHost, c->s));
+        HIPCHK(hipStreamSynchronize(c->s));
+        if (bad) return fail(c, IBB_EINVAL, "a Galerkin coarse-operator entry falls outside its stencil box");
+    }
     // coarsest inverses
     Level &LC = c->lv[c->L - 1];
     const double hc2 = LC.g.h * LC.g.h;
@@ -1473,9 +1552,14 @@ ibb_status rebuild_coefficients(ibb_ctx *c)
     if (LC.np <= DENSE_MAX)
         launch_dense_inverse(LC.g, 0, (int)LC.np, c->uidx_p, c->ucomp_p, v.cp, v.cu, d->sigma / d->dt, 1.0 / hc2,
                              c->Atmp, c->singular_p ? 1 : 0, c->Aw, c->Mp, c->s);
-    if (LC.nu <= DENSE_MAX)
-        launch_dense_inverse(LC.g, 1, (int)LC.nu, c->uidx_u, c->ucomp_u, v.cp, v.cu, d->sigma / d->dt,
-                             LC.cvu, c->Atmp, 0, c->Aw, c->Mu, c->s);
+    if (LC.nu <= DENSE_MAX) {
+        if (LC.gal)
+            launch_gal_dense_inverse(D, LC.g, (int)LC.nu, c->uidx_u, c->ucomp_u, gal_op<double>(LC), c->Aw, c->Mu,
+                                     c->s);
+        else
+            launch_dense_inverse(LC.g, 1, (int)LC.nu, c->uidx_u, c->ucomp_u, v.cp, v.cu, d->sigma / d->dt,
+                                 LC.cvu, c->Atmp, 0, c->Aw, c->Mu, c->s);
+    }
     // tails on the new coefficients (and the new coarsest inverses)
     for (int s = 0; s < 2; ++s) {
         const Tail &t = c->tail[s];
@@ -2463,6 +2547,8 @@ ibb_status check_members(ibb_ctx *const *ctxs, int n)
         const ibb_desc &a = ctxs[0]->d, &b = ctxs[i]->d;
         if (a.precision != b.precision || a.nu1 != b.nu1 || a.nu2 != b.nu2) return IBB_EINVAL;
         if (a.precision == IBB_FP32_REFINED && a.inner_cycles != b.inner_cycles) return IBB_EINVAL;
+        // the batched passes know the rediscretised operators only
+        if (b.galerkin) return IBB_EINVAL;
     }
     return IBB_OK;
 }

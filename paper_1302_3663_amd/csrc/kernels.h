@@ -22,6 +22,75 @@ struct VelBox {
     Box b[3];
 };
 
+// unknown boxes and their colour classes
+__host__ __device__ inline Box unk_box(const Grid &g, int vmask)
+{
+    Box b;
+    for (int d = 0; d < 3; ++d) {
+        int lo, hi;
+        unk_range(g, d, (vmask >> d) & 1, lo, hi);
+        b.lo[d] = lo;
+        b.ext[d] = hi - lo + 1;
+    }
+    return b;
+}
+
+__host__ __device__ inline bool box_pos(const Box &b, int t, int &i, int &j, int &k)
+{
+    const int n = b.ext[0] * b.ext[1] * b.ext[2];
+    if (t >= n) return false;
+    i = b.lo[0] + t % b.ext[0];
+    t /= b.ext[0];
+    j = b.lo[1] + t % b.ext[1];
+    k = b.lo[2] + t / b.ext[1];
+    return true;
+}
+
+// t-th point of colour `colour` ((i + j + k) mod 2) in the box
+__host__ __device__ inline bool box_colour_pos(const Box &b, int colour, int t, int &i, int &j, int &k)
+{
+    const int half = (b.ext[0] + 1) >> 1;
+    if (t >= half * b.ext[1] * b.ext[2]) return false;
+    const int ih = t % half;
+    t /= half;
+    j = b.lo[1] + t % b.ext[1];
+    k = b.lo[2] + t / b.ext[1];
+    i = b.lo[0] + 2 * ih + ((b.lo[0] + j + k + colour) & 1);
+    return i < b.lo[0] + b.ext[0];
+}
+
+// Taps of the transfers along one axis (vert: the lattice is vertex-centred
+// along it): full weighting of the fine points around coarse index I, and
+// linear interpolation of fine index f from its coarse neighbours.
+__host__ __device__ inline int rst_weights(int vert, int I, int *fq, double *w)
+{
+    if (vert) {
+        fq[0] = 2 * I - 1; w[0] = 0.25;
+        fq[1] = 2 * I;     w[1] = 0.5;
+        fq[2] = 2 * I + 1; w[2] = 0.25;
+        return 3;
+    }
+    fq[0] = 2 * I - 1; w[0] = 0.125;
+    fq[1] = 2 * I;     w[1] = 0.375;
+    fq[2] = 2 * I + 1; w[2] = 0.375;
+    fq[3] = 2 * I + 2; w[3] = 0.125;
+    return 4;
+}
+
+__host__ __device__ inline int prl_weights(int vert, int f, int *cq, double *w)
+{
+    if (vert) {
+        if ((f & 1) == 0) { cq[0] = f >> 1; w[0] = 1.0; return 1; }
+        cq[0] = (f - 1) >> 1; w[0] = 0.5;
+        cq[1] = (f + 1) >> 1; w[1] = 0.5;
+        return 2;
+    }
+    const int I = f >> 1;
+    cq[0] = I; w[0] = 0.75;
+    cq[1] = (f & 1) ? I + 1 : I - 1; w[1] = 0.25;
+    return 2;
+}
+
 template <typename T>
 struct VelArr {
     T *c[3];
@@ -230,6 +299,83 @@ inline void launch_timed(K kernel, dim3 grid, dim3 block, hipStream_t s, Args...
 {
     launch_timed_shm(kernel, grid, block, 0, s, args...);
 }
+
+// ---- Galerkin coarse operators of the viscous system (galerkin.hip) ----
+// Row (a, I) of R A P couples unknown (b, I + delta) only for delta in a box
+// per axis: same component: [-1, 1] along a and [-2, 2] across it; another
+// component b: [-2, 1] along a, [-1, 2] along b, [-2, 2] along the third
+// axis (the reach of full weighting, the 7 + 8 point rows and linear
+// prolongation, which R A P keeps from level to level once the third axis
+// has grown from [-1, 1] on the first coarse level; a product landing
+// outside is reported, never dropped).
+// The entries of the rows of component a are stored slot-major: slot s of
+// the row at position e is v[a][s * nel + e]; a row's slots list column
+// component b = 0 .. D-1 in turn, each box x fastest.  On a periodic axis a
+// column that several offsets of the box reach sits in the offset of least
+// magnitude (the more negative one on a tie), so every column is in exactly
+// one slot and the diagonal is offset 0 of the row's own component.
+struct GalBox {
+    int lo[3], n[3];
+};
+__host__ __device__ inline GalBox gal_box(int D, int a, int b)
+{
+    GalBox x;
+    for (int d = 0; d < 3; ++d) {
+        if (d >= D) { x.lo[d] = 0; x.n[d] = 1; continue; }
+        if (a == b) { x.lo[d] = d == a ? -1 : -2; x.n[d] = d == a ? 3 : 5; }
+        else if (d == a) { x.lo[d] = -2; x.n[d] = 4; }
+        else if (d == b) { x.lo[d] = -1; x.n[d] = 4; }
+        else { x.lo[d] = -2; x.n[d] = 5; }
+    }
+    return x;
+}
+__host__ __device__ inline int gal_box_slots(int D, int a, int b)
+{
+    const GalBox x = gal_box(D, a, b);
+    return x.n[0] * x.n[1] * x.n[2];
+}
+__host__ __device__ inline int gal_first_slot(int D, int a, int b)
+{
+    int s = 0;
+    for (int c = 0; c < b; ++c) s += gal_box_slots(D, a, c);
+    return s;
+}
+__host__ __device__ inline int gal_row_slots(int D, int a) { return gal_first_slot(D, a, D); }
+constexpr int GAL_MAX_BOX = 80;
+
+template <typename T>
+struct GalOp {
+    T *v[3];
+};
+template <typename T>
+struct GalOpC {
+    const T *v[3];
+};
+
+// The operator of level l+1 (grid gc) from level l (grid gf), in FP64.
+// fine == nullptr: level l is the finest, whose rows are the viscous stencil
+// on the coefficients cu (mass = sigma / dt, cvisc = Re^-1 / h^2); otherwise
+// level l's own Galerkin operator.  *err is set to 1 when a product falls
+// outside its box.
+void launch_gal_build(int D, const Grid &gf, const Grid &gc, const CoefU<double> &cu, double mass, double cvisc,
+                      const GalOpC<double> *fine, const GalOp<double> &out, int *err, hipStream_t s);
+// FP32 copy of a level's operator
+void launch_gal_to_f32(int D, const Grid &g, const GalOpC<double> &src, const GalOp<float> &dst, hipStream_t s);
+// One colour pass over component a: every row of that colour from the
+// values x held before the pass, written to y together with the other
+// colour's unchanged values (y then replaces x[a]).
+template <typename T>
+void launch_gal_smooth(int D, const Grid &g, int a, int colour, const GalOpC<T> &op, const T *b, const VelArrC<T> &x,
+                       T *y, hipStream_t s);
+// r = b - A x at every unknown
+template <typename T>
+void launch_gal_resid(int D, const Grid &g, const GalOpC<T> &op, const VelArrC<T> &b, const VelArrC<T> &x,
+                      const VelArr<T> &r, hipStream_t s);
+// inverse of a coarsest Galerkin operator of n <= DENSE_LDS unknowns
+void launch_gal_dense_inverse(int D, const Grid &g, int n, const long long *uidx, const int *ucomp,
+                              const GalOpC<double> &op, double *Aw, double *M, hipStream_t s);
+// Gauss-Jordan inverse of the n x n matrix Aw (mg.hip)
+void launch_dense_gj(int n, int singular, const double *Aw, double *M, hipStream_t s);
 
 // ---- batched passes over several contexts (mg.hip) ----
 // One entry per block of a batched launch: the context's level table(s) at

@@ -344,45 +344,6 @@ __device__ inline void u_row_slow_any(const Grid &g, const VelArr<T> &x, const C
 }
 
 // ---------------------------------------------------------------------------
-// index helpers: unknown boxes and their colour classes
-// ---------------------------------------------------------------------------
-__host__ __device__ inline Box unk_box(const Grid &g, int vmask)
-{
-    Box b;
-    for (int d = 0; d < 3; ++d) {
-        int lo, hi;
-        unk_range(g, d, (vmask >> d) & 1, lo, hi);
-        b.lo[d] = lo;
-        b.ext[d] = hi - lo + 1;
-    }
-    return b;
-}
-
-__host__ __device__ inline bool box_pos(const Box &b, int t, int &i, int &j, int &k)
-{
-    const int n = b.ext[0] * b.ext[1] * b.ext[2];
-    if (t >= n) return false;
-    i = b.lo[0] + t % b.ext[0];
-    t /= b.ext[0];
-    j = b.lo[1] + t % b.ext[1];
-    k = b.lo[2] + t / b.ext[1];
-    return true;
-}
-
-// t-th point of colour `colour` ((i + j + k) mod 2) in the box
-__host__ __device__ inline bool box_colour_pos(const Box &b, int colour, int t, int &i, int &j, int &k)
-{
-    const int half = (b.ext[0] + 1) >> 1;
-    if (t >= half * b.ext[1] * b.ext[2]) return false;
-    const int ih = t % half;
-    t /= half;
-    j = b.lo[1] + t % b.ext[1];
-    k = b.lo[2] + t / b.ext[1];
-    i = b.lo[0] + 2 * ih + ((b.lo[0] + j + k + colour) & 1);
-    return i < b.lo[0] + b.ext[0];
-}
-
-// ---------------------------------------------------------------------------
 // Workgroups go to the chip's 8 XCDs in turn (workgroup b to XCD b mod 8),
 // and each XCD has its own L2.  Renumbered so that each XCD works through one
 // contiguous range of the index space, the rows and planes that neighbouring
@@ -821,35 +782,6 @@ __global__ void __launch_bounds__(256) k_reduce_final(const double *__restrict__
 // ---------------------------------------------------------------------------
 // transfers
 // ---------------------------------------------------------------------------
-__host__ __device__ inline int rst_weights(int vert, int I, int *fq, double *w)
-{
-    if (vert) {
-        fq[0] = 2 * I - 1; w[0] = 0.25;
-        fq[1] = 2 * I;     w[1] = 0.5;
-        fq[2] = 2 * I + 1; w[2] = 0.25;
-        return 3;
-    }
-    fq[0] = 2 * I - 1; w[0] = 0.125;
-    fq[1] = 2 * I;     w[1] = 0.375;
-    fq[2] = 2 * I + 1; w[2] = 0.375;
-    fq[3] = 2 * I + 2; w[3] = 0.125;
-    return 4;
-}
-
-__host__ __device__ inline int prl_weights(int vert, int f, int *cq, double *w)
-{
-    if (vert) {
-        if ((f & 1) == 0) { cq[0] = f >> 1; w[0] = 1.0; return 1; }
-        cq[0] = (f - 1) >> 1; w[0] = 0.5;
-        cq[1] = (f + 1) >> 1; w[1] = 0.5;
-        return 2;
-    }
-    const int I = f >> 1;
-    cq[0] = I; w[0] = 0.75;
-    cq[1] = (f & 1) ? I + 1 : I - 1; w[1] = 0.25;
-    return 2;
-}
-
 // Per-axis taps of a transfer, resolved through the boundary rules once per
 // axis: index along the axis, sign, and weight (zero for a fixed face).
 struct AxisTaps {
@@ -2217,6 +2149,12 @@ void launch_dense_inverse(const Grid &g, int velocity, int n, const long long *u
     if (n <= 0 || n > DENSE_LDS) return;
     hipLaunchKernelGGL(k_dense_assemble, dim3(n), dim3(256), 0, s, g, velocity, n, uidx, ucomp, cp, cu, mass, cvisc,
                        tmp, Aw);
+    hipLaunchKernelGGL(k_dense_gj, dim3(1), dim3(1024), 0, s, n, singular, Aw, M);
+}
+
+void launch_dense_gj(int n, int singular, const double *Aw, double *M, hipStream_t s)
+{
+    if (n <= 0 || n > DENSE_LDS) return;
     hipLaunchKernelGGL(k_dense_gj, dim3(1), dim3(1024), 0, s, n, singular, Aw, M);
 }
 
