@@ -61,8 +61,10 @@ SITES = {
     18: ("GCR vector passes", 8), 19: ("k_smooth_u_dec<double>", 8), 20: ("k_smooth_u_dec<float>", 4),
     21: ("k_smooth_rb<double>", 8), 22: ("k_smooth_rb<float>", 4),
     23: ("k_spread_face", 8), 24: ("k_spread_visc", 8), 25: ("k_interp", 8), 26: ("k_spring_force", 8),
+    27: ("k_gal_build", 8), 28: ("k_gal_smooth<double>", 8), 29: ("k_gal_smooth<float>", 4),
+    30: ("k_gal_resid<double>", 8), 31: ("k_gal_resid<float>", 4),
 }
-VISCOUS_SITES = {0, 2, 4, 6, 12, 14, 21, 22}
+VISCOUS_SITES = {0, 2, 4, 6, 12, 14, 21, 22, 27, 28, 29, 30, 31}
 PRESSURE_SITES = {1, 3, 5, 7, 13, 15}
 
 
@@ -88,6 +90,13 @@ def words_per_unit(site, D, decoupled=False):
         return 4 ** D + 1                          # per node and component: 4^D face values, U written
     if site == 26:
         return 3 * D + 20 * (D + 3)                # per node: X, F; about 20 springs: partner X, rest, K, ids
+    gal = 235 if D == 3 else 31                    # Galerkin row: stencil-box entries
+    if site == 27:
+        return gal                                 # per coarse unknown: its row written
+    if site in (28, 29):
+        return gal + 4                             # row, b, x written; the other colour copied (read + write)
+    if site in (30, 31):
+        return gal + 2                             # row, b, r written (x reads hit the caches)
     return 3
 
 
@@ -504,6 +513,9 @@ def main():
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--serving-requests", type=int, default=256,
                     help="also run the serving stream with this many requests and report its latency keys (0: skip)")
+    ap.add_argument("--high-contrast", type=int, default=1, choices=[0, 1],
+                    help="cycles at viscosity ratio 1e3 on the 128x128x256 tube: rediscretised (gamma 1 and 0.7), "
+                         "Galerkin, GCR(8) and both")
     ap.add_argument("--film", type=int, default=1, choices=[0, 1],
                     help="also step the 256x256x512 film once per solver and report its sweep fractions")
     ap.add_argument("--set", action="append", default=[], metavar="KEY=VALUE",
@@ -609,6 +621,38 @@ def main():
                            largest_site=rows[0]["kernel"], level0=sites)
         film["refined_over_fp64"] = round(fres["refined"]["dof_per_s"] / fres["fp64"]["dof_per_s"], 3)
         del fcase
+    high = None
+    if args.high_contrast:
+        # cycles to the tolerance at viscosity ratio 1e3 (FP64 V-cycles): the
+        # coarse-operator remedies of Sec. "Numerical Concerns" side by side
+        log("tube3d_128x128x256 (viscosity ratio 1e3): generating inputs")
+        hcase = synth.WORKLOADS["tube3d_128x128x256"]()
+        hp = hcase["params"]
+        high = {"workload": "tube3d_128x128x256", "viscosity_ratio": hp["mu_max"] / hp["mu_out"],
+                "precision": "fp64", "rtol": hp["rtol"], "steps": 2, "warmup": 1}
+        variants = [("rediscretised_gamma_1", dict(gamma=[1.0] * 16), 0),
+                    ("rediscretised_gamma_0.7", {}, 0),
+                    ("galerkin", dict(galerkin=1), 0),
+                    ("gcr8_gamma_0.7", {}, 8),
+                    ("galerkin_gcr8", dict(galerkin=1), 8)]
+        for name, over, kr in variants:
+            log(f"high contrast, {name}: 1 warmup + 2 timed steps")
+            r = run_mode(dict(hcase, params=dict(hp, **over)), pkg.IBB_FP64, 1, 2, 1, log, krylov=kr, prof_steps=1)
+            build = r["prof"].get(27, None)
+            build_ms = 0.0
+            for cls, pr in r["prof"].items():
+                if cls % 32 == 27:
+                    build_ms += pr["total_ms"]
+            high[name] = dict(mean_cycles_u=float(np.mean(r["cycles_u"])), mean_cycles_p=float(np.mean(r["cycles_p"])),
+                              solve_ms_per_step=round(r["solve_ms"] / 2, 3), ms_per_step=round(r["ms_per_step"], 3),
+                              dof_per_s=round(r["dof_per_s"], 1), max_relres=r["max_relres"])
+            if build is not None or build_ms > 0:
+                high[name]["galerkin_build_ms_per_step"] = round(build_ms, 3)
+            high[name]["sites"] = [dict(kernel=t["kernel"], launches=t["launches"], avg_us=round(t["avg_us"], 2),
+                                        ms_per_step=round(t["ms_per_step"], 3), share=round(t["share"], 4),
+                                        frac=round(t["gbs"] / HBM_PEAK_GBS, 4))
+                                   for t in site_table(r["prof"], 3, 1)[0][:8]]
+        del hcase
     if args.calibrate_copy > 0:
         n = args.calibrate_copy * (1 << 20) // 4
         a = torch.empty(n, dtype=torch.float32, device="cuda:0").fill_(1.0)
@@ -680,6 +724,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
         "film3d_256x256x512": film,
+        "high_contrast": high,
     }
     for m in res:
         r = res[m]

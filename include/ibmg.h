@@ -23,7 +23,8 @@
  * Errors.  Every call returns an ibb_status; nothing is thrown across the
  *   interface.  Arguments are validated before any work is enqueued.
  *   IBB_ENOCONV is not fatal: the iterate is kept and statistics are filled.
- *   ibb_last_error() gives a message for the last failure on a context.
+ *   ibb_last_error() gives a message for the last failure on a context;
+ *   with a null context, that of the last failed ibb_create on the thread.
  * Units.  Nondimensional, as in the paper's scaling (sigma = Strouhal number,
  *   eps = Euler number, Re = Reynolds number).
  *

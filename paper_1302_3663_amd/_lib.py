@@ -166,6 +166,10 @@ def load():
     path = library_path()
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with paper_1302_3663_amd/build.py (no fallback exists)")
+    # torch provides the device memory and streams, so the library must bind
+    # to the HIP runtime torch loads; loaded before torch, the library would
+    # bring in a second runtime, which then finds no device
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     for name, (res, args) in ABI_FUNCTIONS.items():
         fn = getattr(L, name)

@@ -225,6 +225,9 @@ void prof_flush(ibb_ctx *c)
     c->pused = 0;
 }
 
+// message of the last failed ibb_create on this thread
+thread_local std::string create_err;
+
 ibb_status check_desc(const ibb_desc *d)
 {
     if (!d) return IBB_EINVAL;
@@ -1734,7 +1737,7 @@ const char *ibb_status_string(ibb_status s)
     return "unknown status";
 }
 
-const char *ibb_last_error(const ibb_ctx *c) { return c ? c->err.c_str() : ""; }
+const char *ibb_last_error(const ibb_ctx *c) { return c ? c->err.c_str() : create_err.c_str(); }
 
 ibb_status ibb_lattice_count(const ibb_desc *desc, int kind, int axis, int64_t *count, int dims[3])
 {
@@ -1866,12 +1869,15 @@ ibb_status ibb_create(const ibb_desc *desc, int64_t max_nodes, int64_t max_sprin
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->tab32, t32.data(), MAXLEV * sizeof(LevTab<float>), hipMemcpyHostToDevice, c->s);
     for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&c->ev[i]);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->s);
-    if (e == hipSuccess) e = hipGetLastError();
+    const char *what = e == hipSuccess ? "" : "copying the level tables";
+    if (e == hipSuccess && (e = hipStreamSynchronize(c->s)) != hipSuccess) what = "running the initial fills";
+    if (e == hipSuccess && (e = hipGetLastError()) != hipSuccess) what = "an earlier launch";
     if (e != hipSuccess) {
+        create_err = std::string("ibb_create: ") + what + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
         delete c;
         return IBB_EDEVICE;
     }
+    create_err.clear();
     *out = c;
     return IBB_OK;
 }

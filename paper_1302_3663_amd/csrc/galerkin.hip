@@ -266,63 +266,126 @@ __global__ void __launch_bounds__(256) k_gal_cast(const double *__restrict__ src
         dst[t] = (float)src[t];
 }
 
-// sum over the row's slots of w * x[column], the diagonal left out when
-// skip_diag (the smoother) and returned in dg
-template <typename T, int D>
-__device__ inline T gal_row(const Grid &g, int a, const int q[3], long long e, const T *__restrict__ v,
-                            const VelArrC<T> &x, bool skip_diag, T &dg)
+// Where the offsets -2 .. 2 from a row's position lead along each axis,
+// for a cell-centred (c = 0) and a vertex-centred (c = 1) column lattice:
+// the (wrapped) coordinate of the unknown there, or, where no unknown sits,
+// a coordinate of the array's ghost or fixed-face layer (never an unknown).
+// The build leaves every slot whose column is no unknown at zero, so such a
+// slot adds 0 times a finite value and the row needs no test per entry.
+struct AxisReach {
+    int p[3][2][5];
+};
+
+__device__ inline AxisReach axis_reach(const Grid &g, const int q[3])
 {
-    T acc = T(0);
-    int s = 0;
-    for (int c = 0; c < D; ++c) {
-        const GalBox bx = gal_box(D, a, c);
-        const T *__restrict__ xc = x.c[c];
-        for (int dz = 0; dz < bx.n[2]; ++dz)
-            for (int dy = 0; dy < bx.n[1]; ++dy)
-                for (int dx = 0; dx < bx.n[0]; ++dx, ++s) {
-                    const int dl[3] = {bx.lo[0] + dx, bx.lo[1] + dy, bx.lo[2] + dz};
-                    const T w = v[(long long)s * g.nel + e];
-                    if (c == a && dl[0] == 0 && dl[1] == 0 && dl[2] == 0) {
-                        dg = w;
-                        if (skip_diag) continue;
-                    }
-                    long long col;
-                    if (!gal_col(g, c, q, dl, col)) continue;
-                    acc += w * xc[col];
+    AxisReach r;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int o = 0; o < 5; ++o) {
+                if (d >= g.D) {
+                    r.p[d][c][o] = 0;   // only offset 0 is used
+                    continue;
                 }
-    }
+                int t = q[d] + o - 2;
+                if (g.bc[d] == AX_PERIODIC) {
+                    t = t < 0 ? t + g.n[d] : (t >= g.n[d] ? t - g.n[d] : t);
+                    t = t < 0 ? t + g.n[d] : (t >= g.n[d] ? t - g.n[d] : t);   // periods of 1 or 2
+                } else {
+                    int lo, hi;
+                    unk_range(g, d, c, lo, hi);
+                    if (t < lo) t = t < -1 ? -1 : t;
+                    else if (t > hi) t = t > g.n[d] + 1 ? g.n[d] + 1 : t;
+                }
+                r.p[d][c][o] = t;
+            }
+    return r;
+}
+
+// acc += sum over the box of column component C of w * x[column] (the
+// diagonal, offset 0 of the row's own component, goes to dg and is left out
+// of acc when SKIP); the box has compile-time extents, so the loop unrolls
+// and every load of the row issues independently
+template <typename T, int D, int A, int C, bool SKIP>
+__device__ inline void gal_row_box(const Grid &g, long long e, const AxisReach &rch, const T *__restrict__ v,
+                                   const T *__restrict__ xc, T &acc, T &dg)
+{
+    constexpr GalBox bx = gal_box(D, A, C);
+    constexpr int first = gal_first_slot(D, A, C);
+#pragma unroll
+    for (int dz = 0; dz < bx.n[2]; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < bx.n[1]; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < bx.n[0]; ++dx) {
+                const int s = first + dx + bx.n[0] * (dy + bx.n[1] * dz);
+                const int ox = bx.lo[0] + dx, oy = bx.lo[1] + dy, oz = bx.lo[2] + dz;
+                const T w = v[(long long)s * g.nel + e];
+                if (C == A && ox == 0 && oy == 0 && oz == 0) {
+                    dg = w;
+                    if (SKIP) continue;
+                }
+                const int px = rch.p[0][C == 0][ox + 2];
+                const int py = rch.p[1][C == 1][oy + 2];
+                const int pz = rch.p[2][C == 2][oz + 2];
+                acc += w * xc[at(g, px, py, pz)];
+            }
+}
+
+// sum over the row's slots of w * x[column], the diagonal left out when
+// SKIP (the smoother) and returned in dg
+template <typename T, int D, int A, bool SKIP>
+__device__ inline T gal_row(const Grid &g, const int q[3], long long e, const T *__restrict__ v, const VelArrC<T> &x,
+                            T &dg)
+{
+    const AxisReach rch = axis_reach(g, q);
+    T acc = T(0);
+    gal_row_box<T, D, A, 0, SKIP>(g, e, rch, v, x.c[0], acc, dg);
+    gal_row_box<T, D, A, 1, SKIP>(g, e, rch, v, x.c[1], acc, dg);
+    if (D == 3) gal_row_box<T, D, A, D == 3 ? 2 : 1, SKIP>(g, e, rch, v, x.c[D == 3 ? 2 : 1], acc, dg);
     return acc;
 }
 
-template <typename T, int D>
-__global__ void __launch_bounds__(256) k_gal_smooth(Grid g, Box box, int a, int colour, GalOpC<T> op,
+template <typename T, int D, int A>
+__global__ void __launch_bounds__(256) k_gal_smooth(Grid g, Box box, int colour, GalOpC<T> op,
                                                     const T *__restrict__ b, VelArrC<T> x, T *y)
 {
     int i, j, k;
     if (!box_pos(box, blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
     const long long e = at(g, i, j, k);
     if (((i + j + k) & 1) != colour) {
-        y[e] = x.c[a][e];
+        y[e] = x.c[A][e];
         return;
     }
     const int q[3] = {i, j, k};
     T dg = T(1);
-    const T off = gal_row<T, D>(g, a, q, e, op.v[a], x, true, dg);
+    const T off = gal_row<T, D, A, true>(g, q, e, op.v[A], x, dg);
     y[e] = (b[e] - off) / dg;
+}
+
+template <typename T, int D, int A>
+__device__ inline void gal_resid_point(const Grid &g, const Box &box, int t, const GalOpC<T> &op, const VelArrC<T> &b,
+                                       const VelArrC<T> &x, const VelArr<T> &r)
+{
+    int i, j, k;
+    if (!box_pos(box, t, i, j, k)) return;
+    const long long e = at(g, i, j, k);
+    const int q[3] = {i, j, k};
+    T dg;
+    const T ax = gal_row<T, D, A, false>(g, q, e, op.v[A], x, dg);
+    r.c[A][e] = b.c[A][e] - ax;
 }
 
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_gal_resid(Grid g, VelBox boxes, GalOpC<T> op, VelArrC<T> b, VelArrC<T> x,
                                                    VelArr<T> r)
 {
-    const int a = blockIdx.y;
-    int i, j, k;
-    if (!box_pos(boxes.b[a], blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
-    const long long e = at(g, i, j, k);
-    const int q[3] = {i, j, k};
-    T dg;
-    const T ax = gal_row<T, D>(g, a, q, e, op.v[a], x, false, dg);
-    r.c[a][e] = b.c[a][e] - ax;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.y == 0) gal_resid_point<T, D, 0>(g, boxes.b[0], t, op, b, x, r);
+    else if (blockIdx.y == 1) gal_resid_point<T, D, 1>(g, boxes.b[1], t, op, b, x, r);
+    else gal_resid_point<T, D, D == 3 ? 2 : 1>(g, boxes.b[D == 3 ? 2 : 1], t, op, b, x, r);
 }
 
 // row r of the coarsest operator as a dense row over the listed unknowns
@@ -406,8 +469,15 @@ void launch_gal_smooth(int D, const Grid &g, int a, int colour, const GalOpC<T> 
     const Box box = unk_box(g, face_mask(a));
     const long long n = (long long)box.ext[0] * box.ext[1] * box.ext[2];
     if (n <= 0) return;
-    if (D == 3) launch_timed(k_gal_smooth<T, 3>, dim3(blocks_of(n, 256)), dim3(256), s, g, box, a, colour, op, b, x, y);
-    else launch_timed(k_gal_smooth<T, 2>, dim3(blocks_of(n, 256)), dim3(256), s, g, box, a, colour, op, b, x, y);
+    const dim3 grid(blocks_of(n, 256));
+    if (D == 3) {
+        if (a == 0) launch_timed(k_gal_smooth<T, 3, 0>, grid, dim3(256), s, g, box, colour, op, b, x, y);
+        else if (a == 1) launch_timed(k_gal_smooth<T, 3, 1>, grid, dim3(256), s, g, box, colour, op, b, x, y);
+        else launch_timed(k_gal_smooth<T, 3, 2>, grid, dim3(256), s, g, box, colour, op, b, x, y);
+    } else {
+        if (a == 0) launch_timed(k_gal_smooth<T, 2, 0>, grid, dim3(256), s, g, box, colour, op, b, x, y);
+        else launch_timed(k_gal_smooth<T, 2, 1>, grid, dim3(256), s, g, box, colour, op, b, x, y);
+    }
 }
 
 template <typename T>

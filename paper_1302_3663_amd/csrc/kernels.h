@@ -317,9 +317,9 @@ inline void launch_timed(K kernel, dim3 grid, dim3 block, hipStream_t s, Args...
 struct GalBox {
     int lo[3], n[3];
 };
-__host__ __device__ inline GalBox gal_box(int D, int a, int b)
+__host__ __device__ constexpr GalBox gal_box(int D, int a, int b)
 {
-    GalBox x;
+    GalBox x{};
     for (int d = 0; d < 3; ++d) {
         if (d >= D) { x.lo[d] = 0; x.n[d] = 1; continue; }
         if (a == b) { x.lo[d] = d == a ? -1 : -2; x.n[d] = d == a ? 3 : 5; }
@@ -329,18 +329,17 @@ __host__ __device__ inline GalBox gal_box(int D, int a, int b)
     }
     return x;
 }
-__host__ __device__ inline int gal_box_slots(int D, int a, int b)
+__host__ __device__ constexpr int gal_box_slots(int D, int a, int b)
 {
-    const GalBox x = gal_box(D, a, b);
-    return x.n[0] * x.n[1] * x.n[2];
+    return gal_box(D, a, b).n[0] * gal_box(D, a, b).n[1] * gal_box(D, a, b).n[2];
 }
-__host__ __device__ inline int gal_first_slot(int D, int a, int b)
+__host__ __device__ constexpr int gal_first_slot(int D, int a, int b)
 {
     int s = 0;
     for (int c = 0; c < b; ++c) s += gal_box_slots(D, a, c);
     return s;
 }
-__host__ __device__ inline int gal_row_slots(int D, int a) { return gal_first_slot(D, a, D); }
+__host__ __device__ constexpr int gal_row_slots(int D, int a) { return gal_first_slot(D, a, D); }
 constexpr int GAL_MAX_BOX = 80;
 
 template <typename T>

@@ -12,10 +12,9 @@ from . import _lib as L
 def _chk(lib, st, where, ctx=None):
     if st != L.IBB_OK:
         msg = lib.ibb_status_string(st).decode()
-        if ctx is not None:
-            extra = lib.ibb_last_error(ctx)
-            if extra:
-                msg += ": " + extra.decode()
+        extra = lib.ibb_last_error(ctx)
+        if extra:
+            msg += ": " + extra.decode()
         raise L.IbbError(st, where, msg)
 
 

@@ -55,6 +55,35 @@ def test_footprint_grows_with_precision_and_nodes():
     assert t64 - a >= 8 * (320 ** 2 + 128 ** 2) and t32 - c >= 4 * (320 ** 2 + 128 ** 2)
 
 
+def test_galerkin_footprint_and_flags():
+    """Galerkin levels hold 235 (3D) / 31 (2D) entries per row and lattice
+    point of every coarse level (FP64, plus FP32 when refined) and a second
+    iterate buffer; the flag takes 0 or 1 and excludes the constant-viscosity
+    form."""
+    lib = L.load()
+    for case, slots in ((synth.tiny_3d(), (235, 235, 235)), (synth.tiny_2d(), (31, 31))):
+        p = dict(case["params"], coarse_tail=-1)
+        D = p["dim"]
+        nel = 0
+        n = list(p["n"][:D])
+        levels = 1
+        while all(v % 2 == 0 and v // 2 >= 2 for v in n):
+            n = [v // 2 for v in n]
+            levels += 1
+            pad = 1
+            for v in n:
+                pad *= v + 3
+            nel += pad
+        for prec, w in ((L.IBB_FP64, 8), (L.IBB_FP32_REFINED, 12)):
+            base = ibmg.footprint_bytes(p, 10, 10, precision=prec, inner_cycles=1)
+            gal = ibmg.footprint_bytes(dict(p, galerkin=1), 10, 10, precision=prec, inner_cycles=1)
+            assert gal - base >= w * sum(slots) * nel
+        for over in (dict(galerkin=2), dict(galerkin=1, decoupled=1, mu_max=p["mu_out"])):
+            d = L.make_desc(dict(p, **over))
+            nb = ctypes.c_size_t()
+            assert lib.ibb_footprint_bytes(ctypes.byref(d), 10, 10, ctypes.byref(nb)) == L.IBB_EINVAL
+
+
 @pytest.mark.parametrize("field,value", [("dim", 4), ("h", 0.0), ("omega", -1.0), ("nu1", -1), ("kernel", 7),
                                          ("precision", 5)])
 def test_invalid_descriptor_rejected(field, value):
