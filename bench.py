@@ -426,11 +426,14 @@ def run_serving(args, log):
     log(f"serving: generating {args.requests} requests")
     cases = [synth.serving_request(j) for j in range(args.requests)]
     arrivals = serve.poisson_arrivals(args.requests, args.rate, seed=4)
-    srv = serve.Server(budget_bytes=int(args.budget_gb * (1 << 30)), max_slots=args.slots,
+    srv = serve.Server(budget_bytes=int(args.budget_gb * (1 << 30)), max_slots=args.slots or None,
                        precision=L.IBB_FP32_REFINED, inner_cycles=args.inner, krylov=args.krylov,
-                       krylov_ratio=args.krylov_ratio)
-    # warmup: a few requests through the same loop (loads the code objects)
-    warm = [serve.Request(-1 - j, 0.0, cases[j], 1) for j in range(min(args.warmup, len(cases)))]
+                       krylov_ratio=args.krylov_ratio, max_active=args.active or None)
+    # warmup: the stream's first requests, one step each, arriving at once,
+    # through the same server: loads the code objects and leaves a pool of
+    # slots (at most the concurrency cap) that the timed stream reuses
+    nwarm = min(max(args.warmup, args.active or 0), len(cases))
+    warm = [serve.Request(-1 - j, 0.0, cases[j], 1) for j in range(nwarm)]
     if warm:
         srv.run(warm)
     reqs = [serve.Request(j, a, c, c["steps"]) for j, (a, c) in enumerate(zip(arrivals, cases))]
@@ -442,6 +445,7 @@ def run_serving(args, log):
             log(m)
     torch.cuda.synchronize()
     s = srv.run(reqs, log=tick_log)
+    srv.close()
     sizes = {}
     for c in cases:
         key = "x".join(str(v) for v in c["size"])
@@ -461,7 +465,8 @@ def run_serving(args, log):
         "dtype": "f32-inner/f64-outer",
         "data": "synthetic",
         "config": {"workload": "serving", "requests": args.requests, "rate_per_s": args.rate,
-                   "steps_per_request": cases[0]["steps"], "slots": args.slots, "budget_gb": args.budget_gb,
+                   "steps_per_request": cases[0]["steps"], "slot_cap": args.slots or None,
+                   "active_cap": args.active or None, "budget_gb": args.budget_gb, "warm_requests": nwarm,
                    "sizes": sizes, "inner_cycles": args.inner,
                    "gcr": {"restart": args.krylov, "from_viscosity_ratio": args.krylov_ratio} if args.krylov else None},
         "p50_step_ms": round(s["p50_step_ms"], 3),
@@ -479,6 +484,9 @@ def run_serving(args, log):
         "failed_steps": s["failed_steps"],
         "group_build_s": round(s["group_build_s"], 3),
         "wall_outside_ticks_s": round(s["wall_outside_ticks_s"], 3),
+        "slots": s["slots"],
+        "group_builds": s["group_builds"],
+        "slots_given_back": s["slots_given_back"],
         "roofline": None,
         "cpu_baseline": None,
     }
@@ -497,7 +505,9 @@ def main():
                     help="a synth.WORKLOADS entry, or 'serving' for the mixed request stream")
     ap.add_argument("--requests", type=int, default=256, help="serving: number of requests")
     ap.add_argument("--rate", type=float, default=40.0, help="serving: arrivals per second")
-    ap.add_argument("--slots", type=int, default=32, help="serving: resident request cap")
+    ap.add_argument("--slots", type=int, default=0, help="serving: cap on the pool of slots (0: the budget binds)")
+    ap.add_argument("--active", type=int, default=32,
+                    help="serving: cap on the requests stepped together (0: none)")
     ap.add_argument("--budget-gb", type=float, default=32.0, help="serving: device-memory budget")
     ap.add_argument("--krylov-ratio", type=float, default=100.0,
                     help="serving: GCR for requests with at least this viscosity ratio (with --krylov > 0)")
@@ -595,7 +605,8 @@ def main():
         serving["unit"] = "DOF/s"
         serving["requests"] = args.serving_requests
         serving["rate_per_s"] = args.rate
-        for k in ("steps", "ms_per_step", "group_build_s", "wall_outside_ticks_s"):
+        for k in ("steps", "ms_per_step", "group_build_s", "wall_outside_ticks_s", "slots", "group_builds",
+                  "slots_given_back", "mean_resident", "p50_wait_s", "p99_wait_s"):
             if k in sv:
                 serving[k] = sv[k]
     film = None

@@ -206,6 +206,19 @@ ibb_status ibb_destroy(ibb_ctx *ctx);
 ibb_status ibb_set_state(ibb_ctx *ctx, const double *u, const double *p);
 ibb_status ibb_get_state(ibb_ctx *ctx, double *u, double *p);
 
+/* Reload a context with another problem of the same shape (a serving slot):
+ * desc (host) replaces the descriptor the context was created with, and
+ * must agree with it in every field except rho_b, d0_pow_d, mu_max (the
+ * biofilm's density and viscosity, eq:discrDensCouple, eq:ViscExp),
+ * break_ratio, track_fragments, attach_axis, attach_dist, rtol and
+ * max_cycles (IBB_EINVAL otherwise, the context unchanged).  None of these
+ * is an argument of a captured solver iteration, so the context's graphs
+ * (and those of a group it belongs to) stay valid; nothing is allocated.
+ * The coefficients must then be rebuilt (ibb_update_coefficients, after
+ * ibb_set_nodes, which reads the attachment fields): ibb_projection_step
+ * returns IBB_ESTATE until then.  Host only: no device work. */
+ibb_status ibb_set_params(ibb_ctx *ctx, const ibb_desc *desc);
+
 /* Node positions X [dim][n], n <= max_nodes. */
 ibb_status ibb_set_nodes(ibb_ctx *ctx, int64_t n, const double *X);
 
@@ -342,6 +355,15 @@ typedef struct ibb_group ibb_group;
 ibb_status ibb_group_footprint_bytes(ibb_ctx *const *ctxs, int n, size_t *bytes);
 ibb_status ibb_group_create(ibb_ctx *const *ctxs, int n, void *workspace, size_t bytes, ibb_group **out);
 ibb_status ibb_group_destroy(ibb_group *group);
+/* Take member `member` (its index in ctxs at creation) out of the group's
+ * later calls (active = 0) or back in (1); members start active.  A member
+ * that is out gets no work from ibb_group_projection_step or
+ * ibb_group_lagrangian_update (its statistics entries are zeroed), and may
+ * meanwhile be reloaded on its own (ibb_set_params, ibb_set_state,
+ * ibb_set_nodes, ibb_set_springs, ibb_update_coefficients).  The group's
+ * graphs are not captured again: this is how a serving loop admits and
+ * retires requests in slots of a fixed group.  Host only. */
+ibb_status ibb_group_set_active(ibb_group *group, int member, int active);
 /* One projection step of every member (as ibb_projection_step); per_ctx
  * (host, n entries, may be null) receives each member's statistics, with the
  * group's solve times.  A member that did not converge is reported in its

@@ -119,6 +119,7 @@ ABI_FUNCTIONS = {
     "ibb_create": (ctypes.c_int, [DESC, I64, I64, VP, ctypes.c_size_t, VP, ctypes.POINTER(CTX)]),
     "ibb_destroy": (ctypes.c_int, [CTX]),
     "ibb_set_state": (ctypes.c_int, [CTX, VP, VP]),
+    "ibb_set_params": (ctypes.c_int, [CTX, ctypes.POINTER(Desc)]),
     "ibb_get_state": (ctypes.c_int, [CTX, VP, VP]),
     "ibb_set_nodes": (ctypes.c_int, [CTX, I64, VP]),
     "ibb_get_nodes": (ctypes.c_int, [CTX, VP, VP, VP]),
@@ -146,6 +147,7 @@ ABI_FUNCTIONS = {
     "ibb_group_create": (ctypes.c_int, [ctypes.POINTER(CTX), ctypes.c_int, VP, ctypes.c_size_t,
                                         ctypes.POINTER(VP)]),
     "ibb_group_destroy": (ctypes.c_int, [VP]),
+    "ibb_group_set_active": (ctypes.c_int, [VP, ctypes.c_int, ctypes.c_int]),
     "ibb_group_projection_step": (ctypes.c_int, [VP, ctypes.POINTER(SolveStats)]),
     "ibb_group_lagrangian_update": (ctypes.c_int, [VP, ctypes.POINTER(LagStats)]),
     "ibb_group_last_error": (ctypes.c_char_p, [VP]),

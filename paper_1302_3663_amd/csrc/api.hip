@@ -1900,6 +1900,33 @@ ibb_status ibb_destroy(ibb_ctx *c)
     return IBB_OK;
 }
 
+ibb_status ibb_set_params(ibb_ctx *c, const ibb_desc *desc)
+{
+    if (!c) return IBB_EINVAL;
+    if (check_desc(desc)) return fail(c, IBB_EINVAL, "ibb_set_params: invalid descriptor");
+    const ibb_desc &a = *desc, &b = c->d;
+    bool same = a.dim == b.dim && a.h == b.h && a.sigma == b.sigma && a.eps == b.eps && a.inv_re == b.inv_re &&
+                a.force_coef == b.force_coef && a.dt == b.dt && a.rho0 == b.rho0 && a.mu_out == b.mu_out &&
+                a.omega == b.omega && a.kernel == b.kernel && a.nu1 == b.nu1 && a.nu2 == b.nu2 &&
+                a.max_levels == b.max_levels && a.precision == b.precision && a.inner_cycles == b.inner_cycles &&
+                a.wg_coarse_max == b.wg_coarse_max && a.krylov_restart == b.krylov_restart &&
+                a.smoother_passes == b.smoother_passes && a.decoupled == b.decoupled &&
+                a.coarse_tail == b.coarse_tail && a.smoother_zblock == b.smoother_zblock && a.galerkin == b.galerkin;
+    for (int k = 0; k < 3; ++k)
+        same = same && a.n[k] == b.n[k] && a.axis_bc[k] == b.axis_bc[k] && a.body_force[k] == b.body_force[k];
+    for (int k = 0; k < 16; ++k) same = same && a.gamma[k] == b.gamma[k];
+    if (!same)
+        return fail(c, IBB_EINVAL,
+                    "ibb_set_params: only rho_b, d0_pow_d, mu_max, break_ratio, the fragment fields, rtol and "
+                    "max_cycles may change");
+    c->d = a;
+    c->ph.rho_b = a.rho_b;
+    c->ph.d0_pow_d = a.d0_pow_d;
+    c->ph.mu_max = a.mu_max;
+    c->have_coefs = false;
+    return IBB_OK;
+}
+
 ibb_status ibb_set_state(ibb_ctx *c, const double *u, const double *p)
 {
     if (!c || !u) return fail(c, IBB_EINVAL, "ibb_set_state: null pointer");
@@ -2373,6 +2400,7 @@ struct ibb_group {
     Plan plan;
     hipGraphExec_t exec[2] = {};
     std::vector<int> hflags, dflags;   // wanted flags, flags on the device
+    std::vector<char> active;          // members taking part in the group's calls
     hipEvent_t ev[5] = {};
     // side streams (default priority) for members solved by GCR, which
     // advance in lock step with the shared ticks, and one event each
@@ -2639,8 +2667,10 @@ ibb_status group_solve(ibb_group *g, bool vel, GroupSolve &R)
     std::vector<GcrRun> gr(n);
     std::vector<int> side(n, -1);
     int ngcr = 0;
-    for (int i = 0; i < n; ++i)
-        if (g->m[i]->d.krylov_restart > 0) side[i] = ngcr++ % GROUP_SIDE_STREAMS;
+    for (int i = 0; i < n; ++i) {
+        if (!g->active[i]) R.done[i] = 1;
+        else if (g->m[i]->d.krylov_restart > 0) side[i] = ngcr++ % GROUP_SIDE_STREAMS;
+    }
     const int nside = ngcr < GROUP_SIDE_STREAMS ? ngcr : GROUP_SIDE_STREAMS;
     while ((int)g->side.size() < nside) {
         hipStream_t sd;
@@ -2826,6 +2856,7 @@ ibb_status ibb_group_create(ibb_ctx *const *ctxs, int n, void *workspace, size_t
     g->counts = cv.take<int>(4 * (size_t)n);
     g->hflags.assign(n, 0);
     g->dflags.assign(n, 0);
+    g->active.assign(n, 1);
     auto bail = [&](const char *what, hipError_t e) {
         fprintf(stderr, "ibb_group_create: %s: %s\n", what, hipGetErrorString(e));
         for (int v = 0; v < 2; ++v)
@@ -2871,6 +2902,13 @@ ibb_status ibb_group_create(ibb_ctx *const *ctxs, int n, void *workspace, size_t
     return IBB_OK;
 }
 
+ibb_status ibb_group_set_active(ibb_group *g, int member, int active)
+{
+    if (!g || member < 0 || member >= (int)g->m.size() || (active != 0 && active != 1)) return IBB_EINVAL;
+    g->active[member] = (char)active;
+    return IBB_OK;
+}
+
 ibb_status ibb_group_destroy(ibb_group *g)
 {
     if (!g) return IBB_EINVAL;
@@ -2895,8 +2933,9 @@ const char *ibb_group_last_error(const ibb_group *g) { return g ? g->err.c_str()
 ibb_status ibb_group_projection_step(ibb_group *g, ibb_solve_stats *per_ctx)
 {
     if (!g) return IBB_EINVAL;
-    for (ibb_ctx *c : g->m)
-        if (!c->have_coefs) {
+    const int n = (int)g->m.size();
+    for (int i = 0; i < n; ++i)
+        if (g->active[i] && !g->m[i]->have_coefs) {
             g->err = "ibb_group_projection_step: coefficients not built";
             return IBB_ESTATE;
         }
@@ -2907,15 +2946,18 @@ ibb_status ibb_group_projection_step(ibb_group *g, ibb_solve_stats *per_ctx)
     for (ibb_ctx *c : g->m) streams.push_back(c->s);
     {
         Borrow b(g);
-        for (ibb_ctx *c : g->m) proj_viscous_rhs(c);
+        for (int i = 0; i < n; ++i)
+            if (g->active[i]) proj_viscous_rhs(g->m[i]);
         GCHK(hipEventRecord(g->ev[0], g->s));
         if ((st = group_solve(g, true, su))) return st;
         GCHK(hipEventRecord(g->ev[1], g->s));
-        for (ibb_ctx *c : g->m) proj_pressure_rhs(c);
+        for (int i = 0; i < n; ++i)
+            if (g->active[i]) proj_pressure_rhs(g->m[i]);
         GCHK(hipEventRecord(g->ev[2], g->s));
         if ((st = group_solve(g, false, sp))) return st;
         GCHK(hipEventRecord(g->ev[3], g->s));
-        for (ibb_ctx *c : g->m) proj_finish(c);
+        for (int i = 0; i < n; ++i)
+            if (g->active[i]) proj_finish(g->m[i]);
         GCHK(hipGetLastError());
         GCHK(hipStreamSynchronize(g->s));
     }
@@ -2924,7 +2966,11 @@ ibb_status ibb_group_projection_step(ibb_group *g, ibb_solve_stats *per_ctx)
     (void)hipEventElapsedTime(&tu, g->ev[0], g->ev[1]);
     (void)hipEventElapsedTime(&tp, g->ev[2], g->ev[3]);
     ibb_status worst = IBB_OK;
-    for (size_t i = 0; i < g->m.size(); ++i) {
+    for (int i = 0; i < n; ++i) {
+        if (!g->active[i]) {
+            if (per_ctx) memset(per_ctx + i, 0, sizeof(ibb_solve_stats));
+            continue;
+        }
         fill_stats(g->m[i], su.out[i], sp.out[i], tu, tp, per_ctx ? per_ctx + i : nullptr);
         if (!worst && su.out[i].status) worst = (ibb_status)su.out[i].status;
         if (!worst && sp.out[i].status) worst = (ibb_status)sp.out[i].status;
@@ -2936,14 +2982,14 @@ ibb_status ibb_group_projection_step(ibb_group *g, ibb_solve_stats *per_ctx)
 ibb_status ibb_group_lagrangian_update(ibb_group *g, ibb_lag_stats *per_ctx)
 {
     if (!g) return IBB_EINVAL;
-    for (ibb_ctx *c : g->m)
-        if (!c->have_coefs) {
+    const int n = (int)g->m.size();
+    for (int i = 0; i < n; ++i)
+        if (g->active[i] && !g->m[i]->have_coefs) {
             g->err = "ibb_group_lagrangian_update: coefficients not built";
             return IBB_ESTATE;
         }
     ibb_status st = join_in(g);
     if (st) return st;
-    const int n = (int)g->m.size();
     std::vector<hipStream_t> streams;
     for (ibb_ctx *c : g->m) streams.push_back(c->s);
     std::vector<int> cnt(4 * (size_t)n, 0);
@@ -2952,6 +2998,7 @@ ibb_status ibb_group_lagrangian_update(ibb_group *g, ibb_lag_stats *per_ctx)
         GCHK(hipEventRecord(g->ev[0], g->s));
         for (int i = 0; i < n; ++i) {
             ibb_ctx *c = g->m[i];
+            if (!g->active[i]) continue;
             if ((st = lag_launch(c))) {
                 g->err = c->err;
                 return st;

@@ -80,6 +80,8 @@ class Context:
         self.params = dict(params)
         self.device = torch.device(device)
         self.desc = L.make_desc(params, precision, inner_cycles)
+        self.precision, self.inner_cycles = precision, inner_cycles
+        self.capacity = (int(max_nodes), int(max_springs))
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         nbytes = footprint_bytes(params, max_nodes, max_springs, precision, inner_cycles)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
@@ -113,6 +115,26 @@ class Context:
         _chk(self.lib, st, where, self.ctx)
 
     # ---- state ----
+    def set_params(self, params):
+        """Another problem of the same shape (see ibb_set_params)."""
+        desc = L.make_desc(params, self.precision, self.inner_cycles)
+        self._c(self.lib.ibb_set_params(self.ctx, ctypes.byref(desc)), "ibb_set_params")
+        self.desc, self.params = desc, dict(params)
+
+    def load(self, case):
+        """Load a synthetic case (dict from synth) into this context and build
+        its coefficients; the case must fit the context's shape and
+        capacities."""
+        dev = self.device
+        self.set_params(case["params"])
+        self.set_state(torch.as_tensor(case["u0"], dtype=torch.float64, device=dev).contiguous(),
+                       torch.as_tensor(case["p0"], dtype=torch.float64, device=dev).contiguous())
+        self.set_nodes(torch.as_tensor(case["X"], dtype=torch.float64, device=dev).contiguous())
+        self.set_springs(torch.as_tensor(case["ij"], dtype=torch.int32, device=dev).contiguous(),
+                         torch.as_tensor(case["rest"], dtype=torch.float64, device=dev).contiguous(),
+                         torch.as_tensor(case["K"], dtype=torch.float64, device=dev).contiguous())
+        self.update_coefficients()
+
     def set_state(self, u, p=None):
         self._c(self.lib.ibb_set_state(self.ctx, _ptr(u), _ptr(p)), "ibb_set_state")
 
@@ -267,6 +289,10 @@ class Group:
             d = {k: getattr(s, k) for k, _ in L.SolveStats._fields_}
             out.append(d)
         return out
+
+    def set_active(self, member, active):
+        """Take member `member` out of the group's calls (False) or back in."""
+        self._err(self.lib.ibb_group_set_active(self.group, int(member), 1 if active else 0), "ibb_group_set_active")
 
     def lagrangian_update(self):
         n = len(self.members)

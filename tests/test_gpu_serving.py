@@ -1,6 +1,10 @@
 """The serving loop: requests of different grids, dimensions and contrasts
-arrive over time, are admitted as slots free up (continuous batching) and
-stepped together; each one's result must equal the request run alone."""
+arrive over time, are loaded into free slots of a fixed group (continuous
+batching; the group is built again only when the pool of slots grows) and
+stepped together; each one's result must equal the request run alone in a
+context of its own.  Also: a context reloaded with another problem of its
+shape equals a fresh one, a switched-off member gets no work, and only the
+per-problem fields of the descriptor may change."""
 import numpy as np
 import pytest
 
@@ -45,6 +49,7 @@ def test_serving_results_equal_alone(max_slots):
     reqs = [serve.Request(i, a, c, k) for i, (a, c, k) in enumerate(zip(arrivals, cases, steps))]
     srv = serve.Server(budget_bytes=8 << 30, max_slots=max_slots, precision=L.IBB_FP32_REFINED)
     summary = srv.run(reqs, keep_state=True, log=lambda m: print(m, flush=True))
+    srv.close()
     assert summary["requests"] == len(reqs) and summary["failed_steps"] == 0
     assert summary["peak_resident"] <= max_slots
     for r in reqs:
@@ -61,6 +66,7 @@ def test_budget_binds():
     srv.budget = int(1.5 * max(srv.footprint(c) for c in cases))
     reqs = [serve.Request(i, 0.0, c, 2) for i, c in enumerate(cases)]
     summary = srv.run(reqs)
+    srv.close()
     assert summary["peak_resident"] == 1 and summary["requests"] == 3 and one > 0
     # the budget covers the group's workspace as well as the requests'
     assert summary["peak_bytes"] <= srv.budget
@@ -98,3 +104,121 @@ def test_large_members_equal_alone():
         ctx.close()
         ref = alone(c, 2, L.IBB_FP32_REFINED)
         assert all(np.array_equal(a, b) for a, b in zip(got, ref)), c.get("size")
+
+
+def same_shape_cases():
+    """Three problems of one shape (the 3D test tube) with different nodes,
+    springs, viscosity and density ratios."""
+    out = []
+    for seed, mu, rb in ((21, 10.0, 0.1), (22, 300.0, 0.25), (23, 1.0, 0.0)):
+        c = synth.tiny_3d(seed=seed)
+        c["params"] = dict(c["params"], mu_max=mu, rho_b=rb)
+        out.append(c)
+    return out
+
+
+@pytest.mark.parametrize("precision", [L.IBB_FP64, L.IBB_FP32_REFINED])
+def test_reloaded_context_equals_fresh(precision):
+    from paper_1302_3663_amd import ibmg
+    a, b, _ = same_shape_cases()
+    ctx = ibmg.Context(a["params"], 5000, 50000, precision, 2)
+    ctx.load(a)
+    for _ in range(2):
+        ctx.projection_step()
+        ctx.lagrangian_update()
+    ctx.load(b)
+    for _ in range(2):
+        ctx.projection_step()
+        ctx.lagrangian_update()
+    u, p = ctx.get_state()
+    X, F, alive = ctx.get_nodes()
+    torch.cuda.synchronize()
+    got = [t.cpu().numpy() for t in (u, p, X, F, alive)]
+    ctx.close()
+    ref = alone(b, 2, precision) if precision == L.IBB_FP32_REFINED else None
+    if ref is None:
+        fresh = ibmg.from_case(b)
+        for _ in range(2):
+            fresh.projection_step()
+            fresh.lagrangian_update()
+        u, p = fresh.get_state()
+        X, F, alive = fresh.get_nodes()
+        torch.cuda.synchronize()
+        ref = [t.cpu().numpy() for t in (u, p, X, F, alive)]
+        fresh.close()
+    assert all(np.array_equal(x, y) for x, y in zip(got, ref))
+
+
+def test_switched_off_member_gets_no_work():
+    """A member switched off keeps its state through group steps, while the
+    others step exactly as alone; reloaded and switched back on, it steps as
+    its new problem alone."""
+    from paper_1302_3663_amd import ibmg
+    a, b, c = same_shape_cases()
+    ctxs = [ibmg.Context(a["params"], 5000, 50000, L.IBB_FP32_REFINED, 2) for _ in range(2)]
+    ctxs[0].load(a)
+    ctxs[1].load(b)
+    g = ibmg.Group(ctxs)
+    g.set_active(1, False)
+    u_before, _ = ctxs[1].get_state()
+    u_before = u_before.cpu().numpy()
+    for _ in range(2):
+        ss = g.projection_step()
+        g.lagrangian_update()
+        assert ss[1]["cycles_u"] == 0 and ss[1]["dof_u"] == 0
+    u_after, _ = ctxs[1].get_state()
+    assert np.array_equal(u_after.cpu().numpy(), u_before)
+    ctxs[1].load(c)
+    g.set_active(1, True)
+    for _ in range(2):
+        g.projection_step()
+        g.lagrangian_update()
+    g.close()
+    for ctx, case, steps in ((ctxs[0], a, 4), (ctxs[1], c, 2)):
+        u, p = ctx.get_state()
+        X, F, alive = ctx.get_nodes()
+        torch.cuda.synchronize()
+        got = [t.cpu().numpy() for t in (u, p, X, F, alive)]
+        ctx.close()
+        ref = alone(case, steps, L.IBB_FP32_REFINED)
+        assert all(np.array_equal(x, y) for x, y in zip(got, ref))
+
+
+def test_set_params_refuses_shape_changes():
+    from paper_1302_3663_amd import ibmg
+    a = synth.tiny_2d()
+    ctx = ibmg.from_case(a)
+    for k, v in (("nu1", 3), ("dt", a["params"]["dt"] * 2), ("omega", a["params"]["omega"] * 1.5),
+                 ("gamma", [1.0, 0.5] + [1.0] * 14)):
+        with pytest.raises(L.IbbError) as e:
+            ctx.set_params(dict(a["params"], **{k: v}))
+        assert e.value.status == L.IBB_EINVAL, k
+    ctx.set_params(dict(a["params"], mu_max=2 * a["params"]["mu_max"]))
+    with pytest.raises(L.IbbError) as e:
+        ctx.projection_step()
+    assert e.value.status == L.IBB_ESTATE
+    ctx.close()
+
+
+def test_pool_reuses_slots():
+    """Six requests of one shape, all arrived at once, through a pool capped
+    at two slots: the group is built once and the later requests reuse the
+    slots; every request equals its run alone."""
+    from paper_1302_3663_amd import serve
+    cases = same_shape_cases() * 2
+    reqs = [serve.Request(i, 0.0, c, 2) for i, c in enumerate(cases)]
+    srv = serve.Server(budget_bytes=8 << 30, max_slots=2, precision=L.IBB_FP32_REFINED)
+    summary = srv.run(reqs, keep_state=True)
+    assert summary["slots"] == 2 and summary["group_builds"] == 1 and summary["requests"] == 6
+    assert summary["slots_given_back"] == 0
+    for r in reqs:
+        ref = alone(r.case, r.steps, L.IBB_FP32_REFINED)
+        assert all(np.array_equal(a, b) for a, b in zip(r.final, ref)), r.rid
+    # a second stream through the same pool builds nothing new
+    again = [serve.Request(10 + i, 0.0, c, 1) for i, c in enumerate(cases[:3])]
+    s2 = srv.run(again, keep_state=True)
+    srv.close()
+    assert s2["group_builds"] == 0 and s2["requests"] == 3
+    for r in again:
+        ref = alone(r.case, 1, L.IBB_FP32_REFINED)
+        assert all(np.array_equal(a, b) for a, b in zip(r.final, ref)), r.rid
