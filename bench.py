@@ -290,7 +290,9 @@ def summarize_counters(pmc_dir, workload, site, level, copy_mib, commands, out_p
     k_w = select(*runs["write"], copy=False)
     c_f = select(*runs["fetch"], copy=True)
     c_w = select(*runs["write"], copy=True)
-    read_b, write_b = mean(k_rd, rd), mean(k_wr, wr)
+    rd_scale = copy_bytes / mean(c_rd, rd)
+    wr_scale = copy_bytes / mean(c_wr, wr)
+    read_b, write_b = mean(k_rd, rd) * rd_scale, mean(k_wr, wr) * wr_scale
     f_scale = copy_bytes / (1024 * mean(c_f, lambda r: r["FETCH_SIZE"]))
     w_scale = copy_bytes / (1024 * mean(c_w, lambda r: r["WRITE_SIZE"]))
     fetch_b = 1024 * mean(k_f, lambda r: r["FETCH_SIZE"]) * f_scale
@@ -303,20 +305,25 @@ def summarize_counters(pmc_dir, workload, site, level, copy_mib, commands, out_p
              "one MI355X, each under `timeout -s KILL 150`):", "", "```"] + commands + ["```", "",
              f"The command copies a {copy_mib} MiB device buffer 5 times beside the solver "
              "(`__amd_rocclr_copyBuffer`, known bytes read and written).", "",
-             "| counters | the copy reads | per launch of the site |", "|---|---:|---:|",
+             "Every figure is the counter's value times the factor that makes it read the copy's size.", "",
+             "| counters | the copy reads (unscaled) | factor | per launch of the site |", "|---|---:|---:|---:|",
+             f"| FETCH_SIZE | {mean(c_f, lambda r: r['FETCH_SIZE']) / 1024:.1f} MiB | {f_scale:.4f} | "
+             f"{fetch_b / 1e6:.3f} MB |",
+             f"| WRITE_SIZE | {mean(c_w, lambda r: r['WRITE_SIZE']) / 1024:.1f} MiB | {w_scale:.4f} | "
+             f"{wsize_b / 1e6:.3f} MB |",
              f"| read requests by size (128 B x RDREQ_128B + 64 B x RDREQ_64B + 32 B x RDREQ_32B) | "
-             f"{mean(c_rd, rd) / 2**20:.1f} MiB | {read_b / 1e6:.3f} MB |",
+             f"{mean(c_rd, rd) / 2**20:.1f} MiB | {rd_scale:.4f} | {read_b / 1e6:.3f} MB |",
              f"| write requests by size (64 B x WRREQ_64B + 32 B x the rest) | {mean(c_wr, wr) / 2**20:.1f} MiB | "
-             f"{write_b / 1e6:.3f} MB |",
-             f"| FETCH_SIZE x {f_scale:.4f} (the copy's factor) | {copy_mib} MiB | {fetch_b / 1e6:.3f} MB |",
-             f"| WRITE_SIZE x {w_scale:.4f} | {copy_mib} MiB | {wsize_b / 1e6:.3f} MB |", "",
+             f"{wr_scale:.4f} | {write_b / 1e6:.3f} MB |", "",
              f"Launches matched: {len(k_rd)} (symbols and grid sizes: "
              + ", ".join(f"`{w}` {g if g is not None else 'any'}" for w, g in want) + ").", "",
-             "The request counts by size need no calibration: the copy reads and writes its own size.  The derived "
-             "FETCH_SIZE counts 128-byte reads through TCC_BUBBLE, which reads 0 on this chip, so it counts every "
-             "read as 64 bytes; its copy factor restores the size.  Both count the L2's traffic to the fabric, "
-             "which the 256 MB last-level cache serves in part.", "",
-             f"source_digest: {source_digest()}", f"hbm_bytes_per_launch: {read_b + write_b:.0f}", ""]
+             "The derived FETCH_SIZE counts 128-byte reads through TCC_BUBBLE, which reads 0 on this chip, so it "
+             "counts a 128-byte read as 64 bytes; its factor (near 2 when the reads are whole lines) restores the "
+             "size.  The request counts by size read the copy's own size in some runs and less in others, so they "
+             "are scaled the same way; the two readings agree after scaling.  Both count the L2's traffic to the "
+             "fabric, which the 256 MB last-level cache serves in part.  The traffic figure is scaled FETCH_SIZE "
+             "plus scaled WRITE_SIZE.", "",
+             f"source_digest: {source_digest()}", f"hbm_bytes_per_launch: {fetch_b + wsize_b:.0f}", ""]
     with open(out_path, "w") as f:
         f.write("\n".join(lines))
 
