@@ -177,25 +177,40 @@ class Server:
                 if slot is None:
                     c = self.request_case(r.case)
                     cap = self.capacity_for(r.case)
-                    ctx = ibmg.Context(c["params"], cap[0], cap[1], self.precision, self.inner, self.device)
-                    while True:
-                        gb = ibmg.group_footprint_bytes([s.ctx for s in slots] + [ctx])
-                        fits = used + r.footprint + gb <= self.budget and (
-                            self.max_slots is None or len(slots) < self.max_slots)
-                        free = [s for s in slots if s.req is None]
-                        if fits or not free:
-                            break
-                        # give back the free slot used longest ago (the group,
-                        # whose graphs use its arrays, goes first)
+
+                    def give_back():
+                        # the free slot used longest ago goes (the group, whose
+                        # graphs use its arrays, goes first)
+                        nonlocal group, group_bytes, used, evicted, grew
                         if group is not None:
                             group.close()
                             group, group_bytes = None, 0
-                        old = min(free, key=lambda s: s.last_used)
+                        old = min((s for s in slots if s.req is None), key=lambda s: s.last_used)
                         slots.remove(old)
                         old.ctx.close()
                         used -= old.footprint
                         evicted += 1
                         grew = True
+
+                    # room by the slot cap and the slots' budget first, so that a
+                    # request that must wait creates nothing
+                    while ((self.max_slots is not None and len(slots) >= self.max_slots)
+                           or used + r.footprint > self.budget) and any(s.req is None for s in slots):
+                        give_back()
+                    if (self.max_slots is not None and len(slots) >= self.max_slots) or \
+                            used + r.footprint > self.budget:
+                        if not any(s.req is not None for s in slots):
+                            raise ValueError(f"request {r.rid} needs {r.footprint} bytes, above the budget "
+                                             f"{self.budget}")
+                        break
+                    ctx = ibmg.Context(c["params"], cap[0], cap[1], self.precision, self.inner, self.device)
+                    # then the group's workspace, which needs the context
+                    while True:
+                        gb = ibmg.group_footprint_bytes([s.ctx for s in slots] + [ctx])
+                        fits = used + r.footprint + gb <= self.budget
+                        if fits or not any(s.req is None for s in slots):
+                            break
+                        give_back()
                     if not fits:
                         ctx.close()
                         if not any(s.req is not None for s in slots):
