@@ -285,13 +285,76 @@ __global__ void __launch_bounds__(256) k_spread_face(Grid g, Phys ph, Bins bins,
     if (rho_out) rho_out[u] = ph.rho0 + ph.rho_b * ph.d0_pow_d * accw;
 }
 
+// The same gather with one wave per lattice point, for lattices too small
+// to fill the chip with one point per thread while a point may see
+// thousands of nodes (small grids, dense biofilms).  The 64 lanes evaluate
+// the weights of 64 consecutive candidates at once; the sums then take them
+// in candidate order, through the same expressions as k_spread_face, so
+// the result is the same bits.
+constexpr long long SPREAD_WAVE_MAX_POINTS = 65536;
+
+__global__ void __launch_bounds__(256) k_spread_face_w(Grid g, Phys ph, Bins bins, const double *__restrict__ X,
+                                                       const double *__restrict__ F, long long stride, int a,
+                                                       double width, double *f_out, double *rho_out)
+{
+    const int vmask = face_mask(a);
+    const int lane = threadIdx.x & 63;
+    int ext[3];
+    for (int d = 0; d < 3; ++d) ext[d] = stored_extent(g, d, (vmask >> d) & 1);
+    long long t = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= (long long)ext[0] * ext[1] * ext[2]) return;   // the whole wave
+    const int i = (int)(t % ext[0]);
+    t /= ext[0];
+    const int j = (int)(t % ext[1]);
+    const int k = (int)(t / ext[1]);
+    double x[3];
+    lattice_coord(g, vmask, i, j, k, x);
+    const double inv_w = 1.0 / width;
+    double scale = 1.0;
+    for (int d = 0; d < g.D; ++d) scale /= width;
+    const BinNbr nbr = bin_neighbours(g, bins, x);
+    double accf = 0.0, accw = 0.0;
+    for (int c = 0; c < nbr.cnt[2]; ++c)
+        for (int b = 0; b < nbr.cnt[1]; ++b)
+            for (int e = 0; e < nbr.cnt[0]; ++e) {
+                const int bin = (nbr.lst[2][c] * bins.nb[1] + nbr.lst[1][b]) * bins.nb[0] + nbr.lst[0][e];
+                const int p1 = bins.start[bin + 1];
+                for (int base = bins.start[bin]; base < p1; base += 64) {
+                    const int p = base + lane;
+                    double w = 0.0, fv = 0.0;
+                    if (p < p1) {
+                        const int s = bins.sorted[p];
+                        w = delta_w(g, ph.kernel, inv_w, scale, x, X, stride, s);
+                        if (F) fv = F[a * stride + s];
+                    }
+                    const int cnt = p1 - base < 64 ? p1 - base : 64;
+                    for (int q = 0; q < cnt; ++q) {
+                        const double wq = __shfl(w, q);
+                        const double fq = __shfl(fv, q);
+                        if (wq == 0.0) continue;
+                        if (F) accf += fq * wq;
+                        accw += wq;
+                    }
+                }
+            }
+    if (lane == 0) {
+        const long long u = at(g, i, j, k);
+        if (f_out) f_out[u] = accf;
+        if (rho_out) rho_out[u] = ph.rho0 + ph.rho_b * ph.d0_pow_d * accw;
+    }
+}
+
 void launch_spread_face(const Grid &g, const Phys &ph, const Bins &bins, const double *X, const double *F,
                         long long stride, int a, double width, double *f_out, double *rho_out, hipStream_t s)
 {
     long long n = 1;
     for (int d = 0; d < 3; ++d) n *= stored_extent(g, d, d == a);
-    launch_timed(k_spread_face, dim3(nblk(n)), dim3(256), s, g, ph, bins, X, F, stride, a, width, f_out,
-                       rho_out);
+    if (n <= SPREAD_WAVE_MAX_POINTS)
+        launch_timed(k_spread_face_w, dim3((unsigned)((n + 3) / 4)), dim3(256), s, g, ph, bins, X, F, stride, a,
+                     width, f_out, rho_out);
+    else
+        launch_timed(k_spread_face, dim3(nblk(n)), dim3(256), s, g, ph, bins, X, F, stride, a, width, f_out,
+                     rho_out);
 }
 
 // mu(x) = max over nodes of (2 omega)^D (mu_max - mu_out) delta~ + mu_out,
@@ -338,12 +401,66 @@ __global__ void __launch_bounds__(256) k_spread_visc(Grid g, Phys ph, Bins bins,
     mu_out[at(g, i, j, k)] = best;
 }
 
+// k_spread_visc with one wave per lattice point (see k_spread_face_w); the
+// largest weight does not depend on the order the candidates are taken in
+__global__ void __launch_bounds__(256) k_spread_visc_w(Grid g, Phys ph, Bins bins, const double *__restrict__ X,
+                                                       long long stride, int vmask, double *mu_out)
+{
+    const int lane = threadIdx.x & 63;
+    int ext[3];
+    for (int d = 0; d < 3; ++d) ext[d] = stored_extent(g, d, (vmask >> d) & 1);
+    long long t = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= (long long)ext[0] * ext[1] * ext[2]) return;   // the whole wave
+    const int i = (int)(t % ext[0]);
+    t /= ext[0];
+    const int j = (int)(t % ext[1]);
+    const int k = (int)(t / ext[1]);
+    double x[3];
+    lattice_coord(g, vmask, i, j, k, x);
+    const double width = ph.omega;
+    const double inv_w = 1.0 / width;
+    double scale = 1.0, vol = 1.0;
+    for (int d = 0; d < g.D; ++d) {
+        scale /= width;
+        vol *= 2.0 * width;
+    }
+    const double dmu = ph.mu_max - ph.mu_out;
+    double best = ph.mu_out;
+    if (dmu > 0.0) {
+        const BinNbr nbr = bin_neighbours(g, bins, x);
+        double wmax = 0.0;
+        for (int c = 0; c < nbr.cnt[2]; ++c)
+            for (int b = 0; b < nbr.cnt[1]; ++b)
+                for (int e = 0; e < nbr.cnt[0]; ++e) {
+                    const int bin = (nbr.lst[2][c] * bins.nb[1] + nbr.lst[1][b]) * bins.nb[0] + nbr.lst[0][e];
+                    const int p1 = bins.start[bin + 1];
+                    for (int p = bins.start[bin] + lane; p < p1; p += 64) {
+                        const double w = delta_w(g, ph.kernel, inv_w, scale, x, X, stride, bins.sorted[p]);
+                        wmax = w > wmax ? w : wmax;
+                    }
+                }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double v = __shfl_xor(wmax, o);
+            wmax = v > wmax ? v : wmax;
+        }
+        if (wmax > 0.0) {
+            const double cand = vol * dmu * wmax + ph.mu_out;
+            best = cand > best ? cand : best;
+        }
+    }
+    if (lane == 0) mu_out[at(g, i, j, k)] = best;
+}
+
 void launch_spread_visc(const Grid &g, const Phys &ph, const Bins &bins, const double *X, long long stride, int vmask,
                         double *mu_out, hipStream_t s)
 {
     long long n = 1;
     for (int d = 0; d < 3; ++d) n *= stored_extent(g, d, (vmask >> d) & 1);
-    launch_timed(k_spread_visc, dim3(nblk(n)), dim3(256), s, g, ph, bins, X, stride, vmask, mu_out);
+    if (n <= SPREAD_WAVE_MAX_POINTS)
+        launch_timed(k_spread_visc_w, dim3((unsigned)((n + 3) / 4)), dim3(256), s, g, ph, bins, X, stride, vmask,
+                     mu_out);
+    else
+        launch_timed(k_spread_visc, dim3(nblk(n)), dim3(256), s, g, ph, bins, X, stride, vmask, mu_out);
 }
 
 // ---------------------------------------------------------------------------
