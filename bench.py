@@ -59,7 +59,8 @@ SITES = {
     14: ("k_coarse_vcycle<float, D, 1>", 4), 15: ("k_coarse_vcycle<float, D, 0>", 4),
     16: ("k_dense_apply", 8), 17: ("outer-loop passes (norms, casts, clears, corrections)", 8),
     18: ("GCR vector passes", 8), 19: ("k_smooth_u_dec<double>", 8), 20: ("k_smooth_u_dec<float>", 4),
-    21: ("k_smooth_rb<double>", 8), 22: ("k_smooth_rb<float>", 4),
+    21: ("one-launch sweep (k_smooth_rb, k_smooth_zm)<double>", 8),
+    22: ("one-launch sweep (k_smooth_rb, k_smooth_zm)<float>", 4),
     23: ("k_spread_face", 8), 24: ("k_spread_visc", 8), 25: ("k_interp", 8), 26: ("k_spring_force", 8),
     27: ("k_gal_build", 8), 28: ("k_gal_smooth<double>", 8), 29: ("k_gal_smooth<float>", 4),
     30: ("k_gal_resid<double>", 8), 31: ("k_gal_resid<float>", 4),
@@ -164,6 +165,22 @@ def site_launches(p, site, level):
     if site in (12, 13, 14, 15):
         return [(f"k_coarse_vcycle<{T}, {D}, {1 if site in (12, 14) else 0}>", None)]
     out = []
+    if site in (21, 22):
+        # one launch per sweep: the z-marching velocity sweep (3D; tiles of
+        # 64 x 8 points, runs of planes as the library picks them) or the
+        # tiled one (8 x 8 x (8 in FP32, 4 in FP64) tiles; 16 x 16 in 2D),
+        # whichever the run used
+        for a in range(D):
+            e = unknown_extents(p, level, 1 << a)
+            if D == 3:
+                tiles = -(-e[0] // 64) * -(-e[1] // 8)
+                runs = max(1, min(-(-2048 // tiles), e[2] // 4))
+                cz = -(-e[2] // runs)
+                out.append((f"k_smooth_zm<{T}, {a}>", 256 * tiles * -(-e[2] // cz)))
+            t = (8, 8, 8 if T == "float" else 4) if D == 3 else (16, 16, 1)
+            nt = -(-e[0] // t[0]) * -(-e[1] // t[1]) * (-(-e[2] // t[2]) if D == 3 else 1)
+            out.append((f"k_smooth_rb<{T}, {D}, 1, {a}>", 256 * nt))
+        return out
     if site in (0, 2):
         comps = [(f"k_smooth_u<{T}, {D}, {a}>", 1 << a) for a in range(D)]
     elif site in (1, 3):

@@ -124,8 +124,12 @@ typedef struct {
     /* launches per red-black sweep of a component on levels swept with
      * launched passes: 0 or 2, one per colour; 1, one launch for both
      * colours (LDS tiles with a redundant red ring, a second iterate
-     * buffer; needs nu1 + nu2 even, otherwise two).  Both give the same
-     * bits; two is faster on the workloads measured here. */
+     * buffer; needs nu1 + nu2 even, otherwise two); 3, one launch for both
+     * colours of a velocity component on 3D levels, each workgroup marching
+     * along z through a run of planes with a window of the component in
+     * LDS (a second iterate buffer; needs nu1 + nu2 even and periodic axes
+     * long enough for the window, otherwise two; the pressure keeps two).
+     * All give the same bits. */
     int smoother_passes;
     /* 0: the coupled viscous system of eq:NSdis1-1.  1: constant viscosity,
      * eq:NSdis1: (sigma rho / dt) u_a - Re^-1 mu L_h u_a for each component

@@ -35,10 +35,11 @@ struct Level {
     float *rho32[3] = {}, *beta32[3] = {}, *muc32 = nullptr, *mue32[3] = {};
     // second iterate buffers of the one-launch red-black sweep (swapped with
     // x after every sweep; an even number of sweeps per V-cycle brings them
-    // back), and whether this level uses that sweep
+    // back), and whether this level uses that sweep: the tiled one for both
+    // systems (fused), or the z-marching one for the velocity (zm)
     double *xu_alt[3] = {}, *xp_alt = nullptr;
     float *xu32_alt[3] = {}, *xp32_alt = nullptr;
-    bool fused = false;
+    bool fused = false, zm = false;
     // Re^-1 / h^2 of the viscous rows; with constant viscosity (eq:NSdis1)
     // times mu_out and the product of gamma down to this level
     double cvu = 0;
@@ -244,7 +245,7 @@ ibb_status check_desc(const ibb_desc *d)
     if (d->precision == IBB_FP32_REFINED && d->inner_cycles < 1) return IBB_EINVAL;
     if (d->attach_axis < 0 || d->attach_axis >= d->dim || !(d->attach_dist >= 0)) return IBB_EINVAL;
     if (d->krylov_restart < 0 || d->krylov_restart > 64) return IBB_EINVAL;
-    if (d->smoother_passes < 0 || d->smoother_passes > 2) return IBB_EINVAL;
+    if (d->smoother_passes < 0 || d->smoother_passes > 3) return IBB_EINVAL;
     // the decoupled form holds only where the viscosity is one constant
     if (d->decoupled != 0 && d->decoupled != 1) return IBB_EINVAL;
     if (d->decoupled && d->mu_max != d->mu_out) return IBB_EINVAL;
@@ -344,7 +345,7 @@ size_t carve(ibb_ctx *c, char *base, bool dry)
         }
         L.muc = cv.take<double>(n);
         for (int e = 0; e < c->E; ++e) L.mue[c->edge_axis[e]] = cv.take<double>(n);
-        if (L.fused) {
+        if (L.fused || L.zm) {
             L.xp_alt = cv.take<double>(n);
             for (int a = 0; a < D; ++a) L.xu_alt[a] = cv.take<double>(n);
             if (refined) {
@@ -539,6 +540,9 @@ void setup_shapes(ibb_ctx *c, const ibb_desc *d, int64_t max_nodes, int64_t max_
         for (int a = 0; a < d->dim; ++a)
             if (d->axis_bc[a] == IBB_AXIS_PERIODIC && L.g.n[a] % 2) ok = false;
         L.fused = ok;
+        // the z-marching sweep: velocity levels swept with launched passes
+        L.zm = d->smoother_passes == 3 && !d->decoupled && (d->nu1 + d->nu2) % 2 == 0 && l < c->L - 1 &&
+               l < c->lc_u && zm_fits(L.g);
     }
     c->eta_max = max_nodes;
     c->m_max = max_springs;
@@ -665,6 +669,19 @@ void sweep(ibb_ctx *c, bool vel, int l)
                 prof_end(c, k);
                 std::swap(*cur_x<T>(L, true, a), *gal_y<T>(L, a));
             }
+        return;
+    }
+    if (vel && L.zm) {
+        const T cvu = (T)L.cvu;
+        const T mass = (T)(c->d.sigma / c->d.dt);
+        const int cls = prof_class(sizeof(T) == 4 ? PS_SMOOTH_RB32 : PS_SMOOTH_RB64, l);
+        for (int a = 0; a < c->d.dim; ++a) {
+            View<T> v = view<T>(L);
+            const int k = prof_begin(c, cls, unknowns_of(L.g, face_mask(a)));
+            launch_smooth_zm<T>(L.g, a, cview(v.xu), v.bu.c[a], v.cu, mass, cvu, *alt_x<T>(L, true, a), c->s);
+            prof_end(c, k);
+            std::swap(*cur_x<T>(L, true, a), *alt_x<T>(L, true, a));
+        }
         return;
     }
     if (L.fused && l < (vel ? c->lc_u : c->lc_p)) {

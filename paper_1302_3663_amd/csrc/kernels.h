@@ -278,6 +278,15 @@ template <typename T>
 void launch_smooth_rb(const Grid &g, int vel, int a, const VelArrC<T> &xin, const T *b, const CoefU<T> &cu,
                       const CoefP<T> &cp, T mass, T cvisc, T *xout, hipStream_t s);
 
+// The same sweep for velocity component a of a 3D level (coupled viscous
+// system), with every workgroup marching along z through a run of planes
+// and holding a window of u_a in LDS; same contract as launch_smooth_rb.
+// zm_fits: the level's periodic axes are long enough for the window and even.
+template <typename T>
+void launch_smooth_zm(const Grid &g, int a, const VelArrC<T> &xin, const T *b, const CoefU<T> &cu, T mass, T cvisc,
+                      T *xout, hipStream_t s);
+bool zm_fits(const Grid &g);
+
 // Arm a start/stop event pair for the next smoother or residual launch of
 // this thread: the dispatch itself records the kernel's start and end.
 void set_launch_events(hipEvent_t start, hipEvent_t stop);

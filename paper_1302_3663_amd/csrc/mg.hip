@@ -269,23 +269,30 @@ __device__ inline void u_row_dec(const Grid &g, const T *__restrict__ ua, const 
     u_row_dec_r<T, D, A>(g, ua, rho[at(g, i, j, k)], mass, cvisc, i, j, k, Ax, dg);
 }
 
-template <typename T, int D, int A>
-__device__ inline void u_row(const Grid &g, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc, int i, int j,
-                             int k, T &Ax, T &dg)
+// u_a at the row's point and its axis neighbours, read from the uniform
+// array at fixed offsets
+template <typename T>
+struct UaFlat {
+    const T *__restrict__ p;
+    int f;
+    int st[3];
+    __device__ T here() const { return p[f]; }
+    __device__ T nb(int ax, int s) const { return p[f + s * st[ax]]; }
+};
+
+// The coupled viscous row (eq:NSdis1-1 with eq:divergencePartial) at uniform
+// entry f, lattice position (i, j, k), with u_a read through `ua` (the
+// uniform array, or a window of it) and every other field through f.  One
+// body for every reader, so that all of them compute the same bits.
+template <typename T, int D, int A, typename UA, typename XV>
+__device__ inline void u_row_core(const Grid &g, const UA &ua, const XV &x, const CoefU<T> &cf, T rho, T mass, T cvisc,
+                                  int f, int i, int j, int k, T &Ax, T &dg)
 {
-    const int f = (int)at(g, i, j, k);
-    // read before the branch, which both forms take it in
-    const T rho = cf.rho[A][f];
-    if (cf.dec) {
-        u_row_dec_r<T, D, A>(g, x.c[A], rho, mass, cvisc, i, j, k, Ax, dg);
-        return;
-    }
     const int st[3] = {1, g.NX, (int)g.NXY};
     const int sa = st[A];
-    const T *__restrict__ ua = x.c[A];
-    const T xf = ua[f];
+    const T xf = ua.here();
     const T cp = T(2) * cf.muc[f], cm = T(2) * cf.muc[f - sa];
-    const T vp = ua[f + sa], vm = ua[f - sa];
+    const T vp = ua.nb(A, 1), vm = ua.nb(A, -1);
     T mp[D - 1], mm[D - 1], ap[D - 1], am[D - 1], b0[D - 1], b1[D - 1], b2[D - 1], b3[D - 1];
 #pragma unroll
     for (int bi = 0; bi < D - 1; ++bi) {
@@ -295,8 +302,8 @@ __device__ inline void u_row(const Grid &g, const VelArr<T> &x, const CoefU<T> &
         const T *__restrict__ me = cf.mue[3 - A - B];
         mp[bi] = me[f + sb];
         mm[bi] = me[f];
-        ap[bi] = ua[f + sb];
-        am[bi] = ua[f - sb];
+        ap[bi] = ua.nb(B, 1);
+        am[bi] = ua.nb(B, -1);
         b0[bi] = ub[f + sb];
         b1[bi] = ub[f + sb - sa];
         b2[bi] = ub[f];
@@ -318,6 +325,21 @@ __device__ inline void u_row(const Grid &g, const VelArr<T> &x, const CoefU<T> &
     const T m = mass * rho;
     Ax = m * xf - cvisc * acc;
     dg = m + cvisc * d;
+}
+
+template <typename T, int D, int A>
+__device__ inline void u_row(const Grid &g, const VelArr<T> &x, const CoefU<T> &cf, T mass, T cvisc, int i, int j,
+                             int k, T &Ax, T &dg)
+{
+    const int f = (int)at(g, i, j, k);
+    // read before the branch, which both forms take it in
+    const T rho = cf.rho[A][f];
+    if (cf.dec) {
+        u_row_dec_r<T, D, A>(g, x.c[A], rho, mass, cvisc, i, j, k, Ax, dg);
+        return;
+    }
+    const UaFlat<T> ua{x.c[A], f, {1, g.NX, (int)g.NXY}};
+    u_row_core<T, D, A>(g, ua, x, cf, rho, mass, cvisc, f, i, j, k, Ax, dg);
 }
 
 // runtime-dimension entry points (coarsest dense assembly)
@@ -685,6 +707,184 @@ __global__ void __launch_bounds__(256) k_smooth_rb(Grid g, Box box, VelArrC<T> x
         write_images(g, vmask, role, xout, q0, q1, q2, val);
     }
 }
+
+// ---------------------------------------------------------------------------
+// One launch per red-black sweep of a velocity component (3D), marching
+// along z.  A workgroup owns a tile of ZM_TX x ZM_TY points in each plane of
+// a run [z0, z1) of planes and holds u_a of ZM_NS consecutive planes, the
+// tile widened by ZM_H points on every side, in LDS.  Stepping p = z0 ..
+// z1 - 1, it loads plane p + 3, updates the red points of plane p + 1 (the
+// tile and a ring of one point around it), then the black points of plane p
+// (the tile).  Ring points, and the red planes z0 - 1 and z1, belong to other
+// workgroups: they are updated again here, from the same values with the
+// same arithmetic, so that the black points at the tile's edge see the red
+// values of after the pass.  Every red point thus reads the black values of
+// before the sweep and every black point the red values of after it: the
+// bits of the two colour passes.  The other fields are read from global
+// memory, each point's once per sweep, so the sweep streams every array
+// about once instead of once per colour.  Results go to a second buffer,
+// since the window's halo must see values from before the sweep.
+//
+// Window planes: red at p + 1 reads p .. p + 2 and writes ghost images up to
+// two planes away (the one past the outflow face); black at p reads
+// p - 1 .. p + 1.  Six slots let the load of plane p + 4 overwrite p - 2
+// while black p may still be reading p - 1, so a step needs two barriers.
+// (Running red p + 1 and black p - 1 in one phase, one barrier a step, was
+// slower.)
+// ---------------------------------------------------------------------------
+constexpr int ZM_TX = 64, ZM_TY = 8, ZM_H = 2, ZM_WX = ZM_TX + 2 * ZM_H, ZM_WY = ZM_TY + 2 * ZM_H;
+constexpr int ZM_PS = ZM_WX * ZM_WY, ZM_NS = 6, ZM_BS = 256;
+
+// u_a at a point of the window and along its axes: in-plane neighbours in the
+// point's plane, z neighbours in the planes below and above
+template <typename T>
+struct UaWin {
+    const T *w;
+    int c;       // position in the plane
+    int pl[3];   // offsets of the planes z - 1, z, z + 1
+    __device__ T here() const { return w[pl[1] + c]; }
+    __device__ T nb(int ax, int s) const
+    {
+        return ax == 2 ? w[pl[1 + s] + c] : w[pl[1] + c + (ax == 0 ? s : s * ZM_WX)];
+    }
+};
+
+__device__ inline int zm_slot(int z) { return (((z % ZM_NS) + ZM_NS) % ZM_NS) * ZM_PS; }
+
+template <typename T, int A>
+__global__ void __launch_bounds__(ZM_BS) k_smooth_zm(Grid g, Box box, VelArrC<T> xin, const T *__restrict__ b,
+                                                      CoefU<T> cf, T mass, T cvisc, T *xout, int cz, int remap)
+{
+    __shared__ T w[ZM_NS * ZM_PS];
+    constexpr int vmask = 1 << A;
+    const int ntx = (box.ext[0] + ZM_TX - 1) / ZM_TX, nty = (box.ext[1] + ZM_TY - 1) / ZM_TY;
+    const int tid = (int)xcd_block(remap);
+    const int t0 = tid % ntx, t1 = (tid / ntx) % nty, ch = tid / (ntx * nty);
+    const int lo0 = box.lo[0] + t0 * ZM_TX, lo1 = box.lo[1] + t1 * ZM_TY;
+    const int hx = min(lo0 + ZM_TX, box.lo[0] + box.ext[0]), hy = min(lo1 + ZM_TY, box.lo[1] + box.ext[1]);
+    const int z0 = box.lo[2] + ch * cz, z1 = min(z0 + cz, box.lo[2] + box.ext[2]);
+    const int o0 = lo0 - ZM_H, o1 = lo1 - ZM_H;
+    int ulo[3], uhi[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) unk_range(g, d, (vmask >> d) & 1, ulo[d], uhi[d]);
+    const bool per[3] = {g.bc[0] == AX_PERIODIC, g.bc[1] == AX_PERIODIC, g.bc[2] == AX_PERIODIC};
+    // a lattice coordinate along a periodic axis, brought into [0, n)
+    auto wrap = [&](int d, int q) { return !per[d] ? q : (q < 0 ? q + g.n[d] : (q >= g.n[d] ? q - g.n[d] : q)); };
+    // positions stored along a non-periodic axis: -1 .. n + 1
+    auto stored = [&](int d, int q) { return per[d] || (q >= -1 && q <= g.n[d] + 1); };
+    const T *__restrict__ xa = xin.c[A];
+
+    auto load_plane = [&](int z) {
+        T *dst = w + zm_slot(z);
+        const int rz = wrap(2, z);
+        const bool zok = stored(2, z);
+        constexpr int PER = (ZM_PS + ZM_BS - 1) / ZM_BS;
+        T v[PER];
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            const int sidx = threadIdx.x + it * ZM_BS;
+            const int qx = o0 + sidx % ZM_WX, qy = o1 + sidx / ZM_WX;
+            const bool ok = sidx < ZM_PS && zok && stored(0, qx) && stored(1, qy);
+            v[it] = ok ? xa[at(g, wrap(0, qx), wrap(1, qy), rz)] : T(0);
+        }
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            const int sidx = threadIdx.x + it * ZM_BS;
+            if (sidx < ZM_PS) dst[sidx] = v[it];
+        }
+    };
+
+    // the ghost images (non-periodic axes) of window point (x, y, z) that
+    // fall inside the window's planes zl .. zh
+    auto win_images = [&](int x, int y, int z, T v, int zl, int zh) {
+        const int q[3] = {x, y, z};
+        AxisImages im[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            im[d] = per[d] ? AxisImages{{0, 0}, {0, 0}} : images_of(g, d, (vmask >> d) & 1, ROLE_V, q[d]);
+        if ((im[0].s[0] | im[0].s[1] | im[1].s[0] | im[1].s[1] | im[2].s[0] | im[2].s[1]) == 0) return;
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+            for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+                for (int aa = 0; aa < 3; ++aa) {
+                    if (aa == 0 && bb == 0 && cc == 0) continue;
+                    const int sa = aa ? im[0].s[aa - 1] : 1;
+                    const int sb = bb ? im[1].s[bb - 1] : 1;
+                    const int sc = cc ? im[2].s[cc - 1] : 1;
+                    if (sa == 0 || sb == 0 || sc == 0) continue;
+                    const int qa = aa ? im[0].q[aa - 1] : x;
+                    const int qb = bb ? im[1].q[bb - 1] : y;
+                    const int qc = cc ? im[2].q[cc - 1] : z;
+                    if (qa < o0 || qa >= o0 + ZM_WX || qb < o1 || qb >= o1 + ZM_WY || qc < zl || qc > zh) continue;
+                    w[zm_slot(qc) + (qb - o1) * ZM_WX + (qa - o0)] = sa * sb * sc > 0 ? v : -v;
+                }
+    };
+
+    constexpr int RH = (ZM_TX + 2) / 2, RY = ZM_TY + 2, NRED = RH * RY;
+    constexpr int BH = ZM_TX / 2, NBLACK = BH * ZM_TY;
+
+    // the t-th red point of plane z in the tile and its ring; zl .. zh:
+    // planes held
+    auto red_point = [&](int z, int t, int zl, int zh) {
+        const int ih = t % RH, r = t / RH;
+        const int y = lo1 - 1 + r;
+        const int x = lo0 - 1 + 2 * ih + ((lo0 - 1 + y + z) & 1);
+        if (x > hx || y > hy) return;
+        if (!per[0] && (x < ulo[0] || x > uhi[0])) return;
+        if (!per[1] && (y < ulo[1] || y > uhi[1])) return;
+        const int rx = wrap(0, x), ry = wrap(1, y), rz = wrap(2, z);
+        const int f = (int)at(g, rx, ry, rz);
+        const UaWin<T> ua{w, (y - o1) * ZM_WX + (x - o0), {zm_slot(z - 1), zm_slot(z), zm_slot(z + 1)}};
+        const T rho = cf.rho[A][f];
+        const T bf = b[f], xe = ua.here();
+        T Ax, dg;
+        u_row_core<T, 3, A>(g, ua, xin, cf, rho, mass, cvisc, f, rx, ry, rz, Ax, dg);
+        const T xn = xe + (bf - Ax) / dg;
+        w[ua.pl[1] + ua.c] = xn;
+        win_images(x, y, z, xn, zl, zh);
+        if (z >= z0 && z < z1 && x >= lo0 && x < hx && y >= lo1 && y < hy) {
+            xout[f] = xn;
+            write_images(g, vmask, ROLE_V, xout, x, y, z, xn);
+        }
+    };
+    auto red_unknown_plane = [&](int z) { return per[2] || (z >= ulo[2] && z <= uhi[2]); };
+
+    // the t-th black point of plane z (in [z0, z1)) in the tile
+    auto black_point = [&](int z, int t) {
+        const int ih = t % BH, r = t / BH;
+        const int y = lo1 + r;
+        const int x = lo0 + 2 * ih + ((lo0 + y + z + 1) & 1);
+        if (x >= hx || y >= hy) return;
+        const int f = (int)at(g, x, y, z);
+        const UaWin<T> ua{w, (y - o1) * ZM_WX + (x - o0), {zm_slot(z - 1), zm_slot(z), zm_slot(z + 1)}};
+        const T rho = cf.rho[A][f];
+        const T bf = b[f], xe = ua.here();
+        T Ax, dg;
+        u_row_core<T, 3, A>(g, ua, xin, cf, rho, mass, cvisc, f, x, y, z, Ax, dg);
+        const T xn = xe + (bf - Ax) / dg;
+        xout[f] = xn;
+        write_images(g, vmask, ROLE_V, xout, x, y, z, xn);
+    };
+
+    for (int z = z0 - 2; z <= z0 + 2; ++z) load_plane(z);
+    __syncthreads();
+    for (int t = threadIdx.x; t < 2 * NRED; t += ZM_BS) {
+        const int z = t < NRED ? z0 - 1 : z0;
+        if (red_unknown_plane(z)) red_point(z, t < NRED ? t : t - NRED, z0 - 2, z0 + 2);
+    }
+    __syncthreads();
+    for (int p = z0; p < z1; ++p) {
+        load_plane(p + 3);
+        __syncthreads();
+        if (red_unknown_plane(p + 1))
+            for (int t = threadIdx.x; t < NRED; t += ZM_BS) red_point(p + 1, t, p, p + 3);
+        __syncthreads();
+        for (int t = threadIdx.x; t < NBLACK; t += ZM_BS) black_point(p, t);
+    }
+}
+
 
 // ---------------------------------------------------------------------------
 // block reduction of one double per thread into partial[slot] (fixed order)
@@ -2024,6 +2224,46 @@ void launch_smooth_rb(const Grid &g, int vel, int a, const VelArrC<T> &xin, cons
 #undef RB
 }
 
+// Runs of planes per workgroup for the z-marching sweep: about
+// ZM_TARGET_BLOCKS workgroups, at least ZM_MIN_RUN planes each (each run also
+// updates the red points of the two planes around it).
+constexpr int ZM_TARGET_BLOCKS = 2048, ZM_MIN_RUN = 4;
+
+int zm_run(const Box &P)
+{
+    const long long tiles = (long long)((P.ext[0] + ZM_TX - 1) / ZM_TX) * ((P.ext[1] + ZM_TY - 1) / ZM_TY);
+    const long long want = std::max<long long>(1, (ZM_TARGET_BLOCKS + tiles - 1) / tiles);
+    const int runs = (int)std::max<long long>(1, std::min<long long>(want, P.ext[2] / ZM_MIN_RUN));
+    return (P.ext[2] + runs - 1) / runs;
+}
+
+bool zm_fits(const Grid &g)
+{
+    if (g.D != 3) return false;
+    const int need[3] = {ZM_WX, ZM_WY, ZM_NS + 2};
+    for (int d = 0; d < 3; ++d)
+        if (g.bc[d] == AX_PERIODIC && (g.n[d] < need[d] || g.n[d] % 2)) return false;
+    return true;
+}
+
+template <typename T>
+void launch_smooth_zm(const Grid &g, int a, const VelArrC<T> &xin, const T *b, const CoefU<T> &cu, T mass, T cvisc,
+                      T *xout, hipStream_t s)
+{
+    const Box P = unk_box(g, face_mask(a));
+    if (box_count(P) <= 0) return;
+    const int cz = zm_run(P);
+    const long long nb = (long long)((P.ext[0] + ZM_TX - 1) / ZM_TX) * ((P.ext[1] + ZM_TY - 1) / ZM_TY) *
+                         ((P.ext[2] + cz - 1) / cz);
+    const dim3 grid((unsigned)nb), blk(ZM_BS);
+    const int remap = 1;
+#define ZM(AA) launch_timed(k_smooth_zm<T, AA>, grid, blk, s, g, P, xin, b, cu, mass, cvisc, xout, cz, remap)
+    if (a == 0) ZM(0);
+    else if (a == 1) ZM(1);
+    else ZM(2);
+#undef ZM
+}
+
 static inline unsigned stride_blocks(long long n)
 {
     const unsigned b = blocks_for(n);
@@ -2503,6 +2743,8 @@ void launch_gcr_update(const Grid &g, int velocity, const double *num, const dou
                                          T, int, hipStream_t);                                                      \
     template void launch_smooth_rb<T>(const Grid &, int, int, const VelArrC<T> &, const T *, const CoefU<T> &,      \
                                       const CoefP<T> &, T, T, T *, hipStream_t);                                    \
+    template void launch_smooth_zm<T>(const Grid &, int, const VelArrC<T> &, const T *, const CoefU<T> &, T, T, T *, \
+                                      hipStream_t);                                                                 \
     template int launch_resid_p<T>(const Grid &, const T *, const T *, const CoefP<T> &, T, T *, double *,          \
                                    hipStream_t);                                                                    \
     template int launch_resid_u<T>(const Grid &, const VelArrC<T> &, const VelArr<T> &, const CoefU<T> &, T, T,     \

@@ -329,11 +329,12 @@ def tiny_2d(seed=11, nx=16, ny=8, eta=12, inout=False):
     return out
 
 
-def tiny_3d(seed=12, n=(8, 8, 16), eta=20, periodic_z=False):
-    """Small 3D tube for the oracle tests."""
+def tiny_3d(seed=12, n=(8, 8, 16), eta=20, periodic_z=False, periodic_x=False):
+    """Small 3D tube for the oracle tests (walls in x and y, inflow and
+    outflow in z; x and z periodic on request)."""
     rng = np.random.default_rng(seed)
     h = 1.0 / n[0]
-    bc = [AX_WALLS, AX_WALLS, AX_PERIODIC if periodic_z else AX_INOUT]
+    bc = [AX_PERIODIC if periodic_x else AX_WALLS, AX_WALLS, AX_PERIODIC if periodic_z else AX_INOUT]
     p = base_params(3, list(n), bc, h)
     if periodic_z:
         p["body_force"] = [0.0, 0.0, 1.0]
