@@ -174,7 +174,7 @@ def site_launches(p, site, level):
             e = unknown_extents(p, level, 1 << a)
             if D == 3:
                 tiles = -(-e[0] // 64) * -(-e[1] // 8)
-                runs = max(1, min(-(-2048 // tiles), e[2] // 4))
+                runs = max(1, min(-(-8192 // tiles), e[2] // 4))
                 cz = -(-e[2] // runs)
                 out.append((f"k_smooth_zm<{T}, {a}>", 256 * tiles * -(-e[2] // cz)))
             t = (8, 8, 8 if T == "float" else 4) if D == 3 else (16, 16, 1)

@@ -2227,7 +2227,7 @@ void launch_smooth_rb(const Grid &g, int vel, int a, const VelArrC<T> &xin, cons
 // Runs of planes per workgroup for the z-marching sweep: about
 // ZM_TARGET_BLOCKS workgroups, at least ZM_MIN_RUN planes each (each run also
 // updates the red points of the two planes around it).
-constexpr int ZM_TARGET_BLOCKS = 2048, ZM_MIN_RUN = 4;
+constexpr int ZM_TARGET_BLOCKS = 8192, ZM_MIN_RUN = 4;
 
 int zm_run(const Box &P)
 {
