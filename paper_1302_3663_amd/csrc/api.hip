@@ -311,12 +311,14 @@ long long lattice_count(const Grid &g, int vmask)
     return n;
 }
 
+// bins at least w wide: a point's support (|x - X| < 2 w) lies within two
+// bins on each side of its own
 void bins_for_width(const ibb_desc *d, double w, int nb[3], double bs[3])
 {
     for (int a = 0; a < 3; ++a) {
         if (a >= d->dim) { nb[a] = 1; bs[a] = 1.0; continue; }
         const double L = d->n[a] * d->h;
-        int k = (int)floor(L / (2.0 * w));
+        int k = (int)floor(L / w);
         if (k < 1) k = 1;
         nb[a] = k;
         bs[a] = L / k;
@@ -418,6 +420,7 @@ size_t carve(ibb_ctx *c, char *base, bool dry)
     c->bins.sorted = cv.take<int>(em);
     c->bins.count = cv.take<int>((size_t)c->nbins_cap);
     c->bins.start = cv.take<int>((size_t)c->nbins_cap + 1);
+    c->bins.near = cv.take<unsigned char>((size_t)c->nbins_cap);
     c->ij = cv.take<int>(2 * mm);
     c->rest = cv.take<double>(mm);
     c->K = cv.take<double>(mm);

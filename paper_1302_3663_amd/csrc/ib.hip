@@ -185,46 +185,118 @@ __global__ void k_bin_of(Grid g, Bins bins, const double *__restrict__ X, long l
     bins.bin_of[s] = (b[2] * bins.nb[1] + b[1]) * bins.nb[0] + b[0];
 }
 
+// Bins are at least the delta width w wide (bins_for_width), so the nodes
+// within a point's support lie in its own bin or the BIN_REACH bins on
+// either side.
+constexpr int BIN_REACH = 2, BIN_SPAN = 2 * BIN_REACH + 1;
+
+// distinct bins along axis d where the points of bin b look for nodes, in
+// increasing offset from b - BIN_REACH (wrapped on a periodic axis; every
+// bin, in order, when a periodic axis has no more than 2 BIN_REACH)
+__device__ inline int bin_candidates(const Grid &g, const Bins &bins, int d, int b, int lst[BIN_SPAN])
+{
+    if (d >= g.D) {
+        lst[0] = 0;
+        return 1;
+    }
+    const int nb = bins.nb[d];
+    if (g.bc[d] == AX_PERIODIC && nb <= 2 * BIN_REACH) {
+        for (int t = 0; t < nb; ++t) lst[t] = t;
+        return nb;
+    }
+    int c = 0;
+    for (int o = -BIN_REACH; o <= BIN_REACH; ++o) {
+        int t = b + o;
+        if (g.bc[d] == AX_PERIODIC) t = (t + nb) % nb;
+        else if (t < 0 || t >= nb) continue;
+        lst[c++] = t;
+    }
+    return c;
+}
+
+// The candidate bins along x as at most two runs of consecutive bins (a
+// wrap splits them): each run's nodes are one range of the sorted ids, in
+// bin order and ascending within a bin, as bin by bin.
+struct XRuns {
+    int lo[2], hi[2];
+    int n;
+};
+
+__device__ inline XRuns x_runs(const int lst[BIN_SPAN], int cnt)
+{
+    XRuns r;
+    r.n = 1;
+    r.lo[0] = r.hi[0] = lst[0];
+    r.lo[1] = r.hi[1] = 0;
+    for (int e = 1; e < cnt; ++e) {
+        if (lst[e] == r.hi[r.n - 1] + 1) {
+            r.hi[r.n - 1] = lst[e];
+        } else {
+            r.lo[r.n] = r.hi[r.n] = lst[e];
+            ++r.n;
+        }
+    }
+    return r;
+}
+
+// near[bin]: does any bin where the bin's points look hold a node?
+__global__ void __launch_bounds__(256) k_bin_near(Grid g, Bins bins)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= bins.nbins) return;
+    const int b[3] = {t % bins.nb[0], (t / bins.nb[0]) % bins.nb[1], t / (bins.nb[0] * bins.nb[1])};
+    int lst[3][BIN_SPAN], cnt[3];
+    for (int d = 0; d < 3; ++d) cnt[d] = bin_candidates(g, bins, d, b[d], lst[d]);
+    const XRuns xr = x_runs(lst[0], cnt[0]);
+    unsigned char any = 0;
+    for (int c = 0; c < cnt[2]; ++c)
+        for (int bb = 0; bb < cnt[1]; ++bb) {
+            const int row = (lst[2][c] * bins.nb[1] + lst[1][bb]) * bins.nb[0];
+            for (int q = 0; q < xr.n; ++q)
+                if (bins.start[row + xr.hi[q] + 1] > bins.start[row + xr.lo[q]]) any = 1;
+        }
+    bins.near[t] = any;
+}
+
 void launch_bin_nodes(const Grid &g, const Bins &bins, const double *X, long long stride, int eta, int *scan_tmp,
                       hipStream_t s)
 {
     if (eta > 0) hipLaunchKernelGGL(k_bin_of, dim3(nblk(eta)), dim3(256), 0, s, g, bins, X, stride, eta);
     launch_bucket_sort(bins.bin_of, eta, bins.nbins, bins.count, bins.start, bins.sorted, 0, scan_tmp, s);
+    if (bins.near) hipLaunchKernelGGL(k_bin_near, dim3(nblk(bins.nbins)), dim3(256), 0, s, g, bins);
 }
 
-// distinct neighbouring bins of a point along each axis
+// the bins where a point looks for nodes, along each axis, and its own bin
 struct BinNbr {
     int cnt[3];
-    int lst[3][3];
+    int lst[3][BIN_SPAN];
+    int own;
 };
 
 __device__ inline BinNbr bin_neighbours(const Grid &g, const Bins &bins, const double x[3])
 {
     BinNbr r;
+    int b[3];
     for (int d = 0; d < 3; ++d) {
-        if (d >= g.D) { r.cnt[d] = 1; r.lst[d][0] = 0; continue; }
-        const int nb = bins.nb[d];
-        if (g.bc[d] == AX_PERIODIC && nb <= 2) {
-            r.cnt[d] = nb;
-            for (int t = 0; t < nb; ++t) r.lst[d][t] = t;
-            continue;
+        b[d] = 0;
+        if (d < g.D) {
+            double xx = x[d];
+            if (g.bc[d] == AX_PERIODIC) {
+                const double L = domain_len(g, d);
+                xx -= L * floor(xx / L);
+            }
+            b[d] = bin_coord(bins, d, xx);
         }
-        double xx = x[d];
-        if (g.bc[d] == AX_PERIODIC) {
-            const double L = domain_len(g, d);
-            xx -= L * floor(xx / L);
-        }
-        const int b = bin_coord(bins, d, xx);
-        int c = 0;
-        for (int o = -1; o <= 1; ++o) {
-            int t = b + o;
-            if (g.bc[d] == AX_PERIODIC) t = (t + nb) % nb;
-            else if (t < 0 || t >= nb) continue;
-            r.lst[d][c++] = t;
-        }
-        r.cnt[d] = c;
+        r.cnt[d] = bin_candidates(g, bins, d, b[d], r.lst[d]);
     }
+    r.own = (b[2] * bins.nb[1] + b[1]) * bins.nb[0] + b[0];
     return r;
+}
+
+// no node where the point looks: every sum over candidates is empty
+__device__ inline bool nothing_near(const Bins &bins, const BinNbr &nbr)
+{
+    return bins.near && !bins.near[nbr.own];
 }
 
 // delta~(x - X_s, w) = w^-D prod_d phi((x_d - X_d) / w), zero outside the support
@@ -268,11 +340,14 @@ __global__ void __launch_bounds__(256) k_spread_face(Grid g, Phys ph, Bins bins,
     for (int d = 0; d < g.D; ++d) scale /= width;
     const BinNbr nbr = bin_neighbours(g, bins, x);
     double accf = 0.0, accw = 0.0;
-    for (int c = 0; c < nbr.cnt[2]; ++c)
+    const int nz = nothing_near(bins, nbr) ? 0 : nbr.cnt[2];
+    const XRuns xr = x_runs(nbr.lst[0], nbr.cnt[0]);
+    for (int c = 0; c < nz; ++c)
         for (int b = 0; b < nbr.cnt[1]; ++b)
-            for (int e = 0; e < nbr.cnt[0]; ++e) {
-                const int bin = (nbr.lst[2][c] * bins.nb[1] + nbr.lst[1][b]) * bins.nb[0] + nbr.lst[0][e];
-                for (int p = bins.start[bin]; p < bins.start[bin + 1]; ++p) {
+            for (int rq = 0; rq < xr.n; ++rq) {
+                const int row = (nbr.lst[2][c] * bins.nb[1] + nbr.lst[1][b]) * bins.nb[0];
+                const int p1 = bins.start[row + xr.hi[rq] + 1];
+                for (int p = bins.start[row + xr.lo[rq]]; p < p1; ++p) {
                     const int s = bins.sorted[p];
                     const double w = delta_w(g, ph.kernel, inv_w, scale, x, X, stride, s);
                     if (w == 0.0) continue;
@@ -314,12 +389,14 @@ __global__ void __launch_bounds__(256) k_spread_face_w(Grid g, Phys ph, Bins bin
     for (int d = 0; d < g.D; ++d) scale /= width;
     const BinNbr nbr = bin_neighbours(g, bins, x);
     double accf = 0.0, accw = 0.0;
-    for (int c = 0; c < nbr.cnt[2]; ++c)
+    const int nz = nothing_near(bins, nbr) ? 0 : nbr.cnt[2];
+    const XRuns xr = x_runs(nbr.lst[0], nbr.cnt[0]);
+    for (int c = 0; c < nz; ++c)
         for (int b = 0; b < nbr.cnt[1]; ++b)
-            for (int e = 0; e < nbr.cnt[0]; ++e) {
-                const int bin = (nbr.lst[2][c] * bins.nb[1] + nbr.lst[1][b]) * bins.nb[0] + nbr.lst[0][e];
-                const int p1 = bins.start[bin + 1];
-                for (int base = bins.start[bin]; base < p1; base += 64) {
+            for (int rq = 0; rq < xr.n; ++rq) {
+                const int row = (nbr.lst[2][c] * bins.nb[1] + nbr.lst[1][b]) * bins.nb[0];
+                const int p1 = bins.start[row + xr.hi[rq] + 1];
+                for (int base = bins.start[row + xr.lo[rq]]; base < p1; base += 64) {
                     const int p = base + lane;
                     double w = 0.0, fv = 0.0;
                     if (p < p1) {
@@ -384,11 +461,14 @@ __global__ void __launch_bounds__(256) k_spread_visc(Grid g, Phys ph, Bins bins,
     if (dmu > 0.0) {
         const BinNbr nbr = bin_neighbours(g, bins, x);
         double wmax = 0.0;
-        for (int c = 0; c < nbr.cnt[2]; ++c)
+        const int nz = nothing_near(bins, nbr) ? 0 : nbr.cnt[2];
+        const XRuns xr = x_runs(nbr.lst[0], nbr.cnt[0]);
+        for (int c = 0; c < nz; ++c)
             for (int b = 0; b < nbr.cnt[1]; ++b)
-                for (int e = 0; e < nbr.cnt[0]; ++e) {
-                    const int bin = (nbr.lst[2][c] * bins.nb[1] + nbr.lst[1][b]) * bins.nb[0] + nbr.lst[0][e];
-                    for (int p = bins.start[bin]; p < bins.start[bin + 1]; ++p) {
+                for (int rq = 0; rq < xr.n; ++rq) {
+                    const int row = (nbr.lst[2][c] * bins.nb[1] + nbr.lst[1][b]) * bins.nb[0];
+                    const int p1 = bins.start[row + xr.hi[rq] + 1];
+                    for (int p = bins.start[row + xr.lo[rq]]; p < p1; ++p) {
                         const double w = delta_w(g, ph.kernel, inv_w, scale, x, X, stride, bins.sorted[p]);
                         wmax = w > wmax ? w : wmax;
                     }
@@ -429,12 +509,14 @@ __global__ void __launch_bounds__(256) k_spread_visc_w(Grid g, Phys ph, Bins bin
     if (dmu > 0.0) {
         const BinNbr nbr = bin_neighbours(g, bins, x);
         double wmax = 0.0;
-        for (int c = 0; c < nbr.cnt[2]; ++c)
+        const int nz = nothing_near(bins, nbr) ? 0 : nbr.cnt[2];
+        const XRuns xr = x_runs(nbr.lst[0], nbr.cnt[0]);
+        for (int c = 0; c < nz; ++c)
             for (int b = 0; b < nbr.cnt[1]; ++b)
-                for (int e = 0; e < nbr.cnt[0]; ++e) {
-                    const int bin = (nbr.lst[2][c] * bins.nb[1] + nbr.lst[1][b]) * bins.nb[0] + nbr.lst[0][e];
-                    const int p1 = bins.start[bin + 1];
-                    for (int p = bins.start[bin] + lane; p < p1; p += 64) {
+                for (int rq = 0; rq < xr.n; ++rq) {
+                    const int row = (nbr.lst[2][c] * bins.nb[1] + nbr.lst[1][b]) * bins.nb[0];
+                    const int p1 = bins.start[row + xr.hi[rq] + 1];
+                    for (int p = bins.start[row + xr.lo[rq]] + lane; p < p1; p += 64) {
                         const double w = delta_w(g, ph.kernel, inv_w, scale, x, X, stride, bins.sorted[p]);
                         wmax = w > wmax ? w : wmax;
                     }

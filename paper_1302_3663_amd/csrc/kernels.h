@@ -456,6 +456,8 @@ struct Bins {
     int *count;         // [nbins] nodes per bin, then a cursor
     int *start;         // [nbins + 1] exclusive prefix
     int *sorted;        // [eta] node ids grouped by bin, ascending within a bin
+    unsigned char *near;  // [nbins] 1 when a node lies in the bin or a neighbouring bin
+                          // (where its points look); null: not kept, every point looks
 };
 void launch_bin_nodes(const Grid &g, const Bins &bins, const double *X, long long stride, int eta, int *scan_tmp,
                       hipStream_t s);
