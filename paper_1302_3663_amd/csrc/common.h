@@ -190,14 +190,8 @@ __host__ __device__ inline AxisImages images_of(const Grid &g, int d, int vert, 
 // write v (times the reflection sign) to every ghost image of (i, j, k):
 // each axis contributes the position itself or one of its images
 template <typename T>
-__device__ inline void write_images(const Grid &g, int vmask, int role, T *x, int i, int j, int k, T v)
+__host__ __device__ inline void write_images_any(const Grid &g, const AxisImages im[3], T *x, int i, int j, int k, T v)
 {
-    const int q[3] = {i, j, k};
-    AxisImages im[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-        im[d] = d < g.D ? images_of(g, d, (vmask >> d) & 1, role, q[d]) : AxisImages{{0, 0}, {0, 0}};
-    if ((im[0].s[0] | im[0].s[1] | im[1].s[0] | im[1].s[1] | im[2].s[0] | im[2].s[1]) == 0) return;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -214,6 +208,37 @@ __device__ inline void write_images(const Grid &g, int vmask, int role, T *x, in
                 const int qc = c ? im[2].q[c - 1] : k;
                 x[at(g, qa, qb, qc)] = sa * sb * sc > 0 ? v : -v;
             }
+}
+
+template <typename T>
+__host__ __device__ inline void write_images(const Grid &g, int vmask, int role, T *x, int i, int j, int k, T v)
+{
+    const int q[3] = {i, j, k};
+    AxisImages im[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        im[d] = d < g.D ? images_of(g, d, (vmask >> d) & 1, role, q[d]) : AxisImages{{0, 0}, {0, 0}};
+    if ((im[0].s[0] | im[0].s[1] | im[1].s[0] | im[1].s[1] | im[2].s[0] | im[2].s[1]) == 0) return;
+    // An axis with images at both ends only on the shortest lattices: there,
+    // every combination of the two.
+    if ((im[0].s[0] && im[0].s[1]) || (im[1].s[0] && im[1].s[1]) || (im[2].s[0] && im[2].s[1])) {
+        write_images_any(g, im, x, i, j, k, v);
+        return;
+    }
+    // Otherwise at most one image per axis: one write for each non-empty
+    // set of the axes that have one (the same positions and values).
+    int p[3], s[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        s[d] = im[d].s[0] ? im[d].s[0] : im[d].s[1];
+        p[d] = im[d].s[0] ? im[d].q[0] : im[d].q[1];
+    }
+#pragma unroll
+    for (int m = 1; m < 8; ++m) {
+        if (((m & 1) && !s[0]) || ((m & 2) && !s[1]) || ((m & 4) && !s[2])) continue;
+        const int sg = ((m & 1) ? s[0] : 1) * ((m & 2) ? s[1] : 1) * ((m & 4) ? s[2] : 1);
+        x[at(g, (m & 1) ? p[0] : i, (m & 2) ? p[1] : j, (m & 4) ? p[2] : k)] = sg > 0 ? v : -v;
+    }
 }
 
 // lattice masks
