@@ -91,6 +91,7 @@ struct ibb_ctx {
     // level tables for the one-workgroup coarse cycle, and where it starts
     LevTab<double> *tab64 = nullptr;
     LevTab<float> *tab32 = nullptr;
+    BoxDiv *boxdiv = nullptr;   // [MAXLEV][4], pointed to by the level tables
     int lc_u = MAXLEV, lc_p = MAXLEV;
     // levels of the one-workgroup cycle kept in LDS, per precision (0: FP64,
     // 1: FP32) and system (0: pressure, 1: velocity)
@@ -397,6 +398,7 @@ size_t carve(ibb_ctx *c, char *base, bool dry)
     c->Atmp = cv.take<double>((size_t)DENSE_MAX * 3 * (size_t)c->lv[c->L - 1].g.nel);
     c->tab64 = cv.take<LevTab<double>>(MAXLEV);
     c->tab32 = cv.take<LevTab<float>>(MAXLEV);
+    c->boxdiv = cv.take<BoxDiv>((size_t)MAXLEV * 4);
     for (int pr = 0; pr < 2; ++pr)
         for (int v = 0; v < 2; ++v) c->ldslev[pr][v] = cv.take<LdsLevel>(WG_MAXLEV);
     for (int v = 0; v < 2; ++v) {
@@ -1828,11 +1830,15 @@ ibb_status ibb_create(const ibb_desc *desc, int64_t max_nodes, int64_t max_sprin
     // level tables for the one-workgroup coarse cycle
     std::vector<LevTab<double>> t64(MAXLEV);
     std::vector<LevTab<float>> t32(MAXLEV);
+    std::vector<BoxDiv> bdv((size_t)MAXLEV * 4);
     for (int l = 0; l < c->L; ++l) {
         Level &L = c->lv[l];
         LevTab<double> &a = t64[l];
         LevTab<float> &b = t32[l];
         a.g = b.g = L.g;
+        for (int k = 0; k < 4; ++k)
+            bdv[(size_t)l * 4 + k] = box_div(unk_box(L.g, k < 3 && k < desc->dim ? face_mask(k) : 0));
+        a.bd = b.bd = c->boxdiv + (size_t)l * 4;
         for (int k = 0; k < 3; ++k) {
             a.xu[k] = L.xu[k]; a.bu[k] = L.bu[k]; a.ru[k] = L.ru[k];
             a.rho[k] = L.rho[k]; a.beta[k] = L.beta[k]; a.mue[k] = L.mue[k];
@@ -1884,6 +1890,8 @@ ibb_status ibb_create(const ibb_desc *desc, int64_t max_nodes, int64_t max_sprin
                 e = hipMemcpyAsync(c->ldslev[pr][v], plans[pr][v].data(), WG_MAXLEV * sizeof(LdsLevel),
                                    hipMemcpyHostToDevice, c->s);
         }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->boxdiv, bdv.data(), bdv.size() * sizeof(BoxDiv), hipMemcpyHostToDevice, c->s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->tab64, t64.data(), MAXLEV * sizeof(LevTab<double>), hipMemcpyHostToDevice, c->s);
     if (e == hipSuccess)

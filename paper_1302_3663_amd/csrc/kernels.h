@@ -59,6 +59,70 @@ __host__ __device__ inline bool box_colour_pos(const Box &b, int colour, int t, 
     return i < b.lo[0] + b.ext[0];
 }
 
+// Division of 0 <= t < 2^31 by a fixed d >= 1 through one 64-bit multiply:
+// with 2^(l-1) < d <= 2^l and m = ceil(2^(31+l) / d), floor(t / d) equals
+// (t m) >> (31 + l) exactly (Granlund and Montgomery, "Division by invariant
+// integers using multiplication", 1994).  m <= 2^32, so t m < 2^63.
+struct Div {
+    unsigned long long m;
+    int sh;
+};
+
+__host__ __device__ inline Div make_div(int d)
+{
+    int l = 0;
+    while ((1ll << l) < (long long)d) ++l;
+    Div r;
+    r.sh = 31 + l;
+    r.m = ((1ull << r.sh) + (unsigned long long)d - 1) / (unsigned long long)d;
+    return r;
+}
+
+__host__ __device__ inline int div_by(const Div &v, int t)
+{
+    return (int)(((unsigned long long)(unsigned)t * v.m) >> v.sh);
+}
+
+// the divisors of a box's point and colour decodes, made once per box (the
+// one-workgroup cycle reads them from its level tables; a launched pass,
+// with one point per thread, is faster dividing than waiting for them)
+struct BoxDiv {
+    Div x, half, y;   // ext[0], (ext[0] + 1) / 2, ext[1]
+};
+
+__host__ __device__ inline BoxDiv box_div(const Box &b)
+{
+    return BoxDiv{make_div(b.ext[0] > 0 ? b.ext[0] : 1), make_div(b.ext[0] > 0 ? (b.ext[0] + 1) >> 1 : 1),
+                  make_div(b.ext[1] > 0 ? b.ext[1] : 1)};
+}
+
+// box_pos and box_colour_pos with the divisions made through bd
+__host__ __device__ inline bool box_pos(const Box &b, const BoxDiv &bd, int t, int &i, int &j, int &k)
+{
+    const int n = b.ext[0] * b.ext[1] * b.ext[2];
+    if (t >= n) return false;
+    const int r = div_by(bd.x, t);
+    i = b.lo[0] + (t - r * b.ext[0]);
+    const int kk = div_by(bd.y, r);
+    j = b.lo[1] + (r - kk * b.ext[1]);
+    k = b.lo[2] + kk;
+    return true;
+}
+
+__host__ __device__ inline bool box_colour_pos(const Box &b, const BoxDiv &bd, int colour, int t, int &i, int &j,
+                                               int &k)
+{
+    const int half = (b.ext[0] + 1) >> 1;
+    if (t >= half * b.ext[1] * b.ext[2]) return false;
+    const int r = div_by(bd.half, t);
+    const int ih = t - r * half;
+    const int kk = div_by(bd.y, r);
+    j = b.lo[1] + (r - kk * b.ext[1]);
+    k = b.lo[2] + kk;
+    i = b.lo[0] + 2 * ih + ((b.lo[0] + j + k + colour) & 1);
+    return i < b.lo[0] + b.ext[0];
+}
+
 // Taps of the transfers along one axis (vert: the lattice is vertex-centred
 // along it): full weighting of the fine points around coarse index I, and
 // linear interpolation of fine index f from its coarse neighbours.
@@ -197,6 +261,7 @@ struct LevTab {
     T mass, cvu, cvp;
     long long nu, np;
     int dec;  // constant viscosity, as CoefU::dec
+    const BoxDiv *bd;  // device array [4]: divisors of the unknown boxes (components 0..2, pressure)
 };
 
 // the V-cycle from level l0 down to the coarsest level and back inside one

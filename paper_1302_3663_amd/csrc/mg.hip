@@ -1500,13 +1500,14 @@ __device__ inline void wg_sweep_comp(const LevTab<T> &ltr)
     const Grid &g = lt.g;
     const int vmask = VEL ? face_mask(A) : 0;
     const Box box = unk_box(g, vmask);
+    const BoxDiv bd = lt.bd[VEL ? A : 3];
     const int n = ((box.ext[0] + 1) >> 1) * box.ext[1] * box.ext[2];
     T *x = VEL ? lt.xu[A] : lt.xp;
     const T *b = VEL ? lt.bu[A] : lt.bp;
     for (int colour = 0; colour < 2; ++colour) {
         for (int t = threadIdx.x; t < n; t += blockDim.x) {
             int i, j, k;
-            if (!box_colour_pos(box, colour, t, i, j, k)) continue;
+            if (!box_colour_pos(box, bd, colour, t, i, j, k)) continue;
             const long long e = at(g, i, j, k);
             const T be = b[e], xe = x[e];
             T Ax, dg;
@@ -1534,12 +1535,13 @@ __device__ inline void wg_residual_comp(const LevTab<T> &ltr)
 {
     const LevTab<T> lt = ltr;
     const Box box = unk_box(lt.g, VEL ? face_mask(A) : 0);
+    const BoxDiv bd = lt.bd[VEL ? A : 3];
     const int n = box.ext[0] * box.ext[1] * box.ext[2];
     T *r = VEL ? lt.ru[A] : lt.rp;
     const T *b = VEL ? lt.bu[A] : lt.bp;
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
         int i, j, k;
-        box_pos(box, t, i, j, k);
+        box_pos(box, bd, t, i, j, k);
         const long long e = at(lt.g, i, j, k);
         const T be = b[e];
         T Ax, dg;
@@ -1557,13 +1559,14 @@ __device__ inline void wg_restrict_comp(const LevTab<T> &ltr, const LevTab<T> &l
     const int vmask = VEL ? face_mask(A) : 0;
     const int role = VEL ? ROLE_V : ROLE_P;
     const Box box = unk_box(lc.g, vmask);
+    const BoxDiv bd = lc.bd[VEL ? A : 3];
     const int n = box.ext[0] * box.ext[1] * box.ext[2];
     const T *src = VEL ? lt.ru[A] : lt.rp;
     T *bc = VEL ? lc.bu[A] : lc.bp;
     T *xc = VEL ? lc.xu[A] : lc.xp;
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
         int I, J, K;
-        box_pos(box, t, I, J, K);
+        box_pos(box, bd, t, I, J, K);
         const long long e = at(lc.g, I, J, K);
         bc[e] = (T)restrict_any<T, D>(vmask, lt.g, role, src, I, J, K);
         xc[e] = T(0);
@@ -1578,12 +1581,13 @@ __device__ inline void wg_prolong_comp(const LevTab<T> &lcr, const LevTab<T> &lt
     const int vmask = VEL ? face_mask(A) : 0;
     const int role = VEL ? ROLE_V : ROLE_P;
     const Box box = unk_box(lt.g, vmask);
+    const BoxDiv bd = lt.bd[VEL ? A : 3];
     const int n = box.ext[0] * box.ext[1] * box.ext[2];
     const T *src = VEL ? lc.xu[A] : lc.xp;
     T *x = VEL ? lt.xu[A] : lt.xp;
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
         int i, j, k;
-        box_pos(box, t, i, j, k);
+        box_pos(box, bd, t, i, j, k);
         const long long e = at(lt.g, i, j, k);
         const T xe = x[e];
         const T v = xe + (T)prolong_any<T, D>(vmask, lc.g, role, src, i, j, k);

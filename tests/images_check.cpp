@@ -1,4 +1,4 @@
-// Host check (built by tests/test_images_cpu.py): the compact ghost-image
+// Host check (built by tests/test_host_checks_cpu.py): the compact ghost-image
 // writer stores exactly what the general one does, for every lattice,
 // role, boundary kind and position on lattices of one to five points a side.
 #include "common.h"
