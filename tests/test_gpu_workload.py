@@ -14,6 +14,8 @@ the oracle can evaluate without its own multigrid:
 - the projection itself, every point;
 - the fused step (ibb_projection_step) equals the step taken piece by piece.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -197,14 +199,12 @@ def test_film_full_size_sampled():
     ctx.close()
 
 
-@pytest.mark.timeout(1200)
-def test_tube_64x64x128_fp64_steps_against_oracle():
-    """Five full FP64 steps of the 64 x 64 x 128 tube (5 000 nodes, 72 532
-    springs), in the launch configuration bench.py times, against the oracle
-    stepped alongside: equal cycle counts in every solve, and velocity,
-    pressure, node positions, spring forces and alive flags within 1e-12 (both
-    norms) after the last step.  The oracle takes about half a minute per
-    step here (its hierarchy is assembled anew after every node move)."""
+def fp64_trajectory_against_oracle(nsteps):
+    """nsteps full FP64 steps of the 64 x 64 x 128 tube, in the launch
+    configuration bench.py times, against the oracle stepped alongside:
+    equal cycle counts in every solve, and velocity, pressure, node
+    positions, spring forces and alive flags within 1e-12 (both norms) after
+    the last step."""
     import time
     from oracle import step as S
     from paper_1302_3663_amd import ibmg
@@ -213,7 +213,7 @@ def test_tube_64x64x128_fp64_steps_against_oracle():
     ctx = ibmg.from_case(case, precision=L.IBB_FP64)
     st = S.State(case["params"], case["u0"], case["p0"], case["X"], case["ij"], case["rest"], case["K"])
     S.setup(st)
-    for n in range(5):
+    for n in range(nsteps):
         sg = ctx.projection_step()
         so = S.projection_step(st)
         assert sg["cycles_u"] == so["u"]["cycles"] and sg["cycles_p"] == so["p"]["cycles"], (n, sg, so["u"], so["p"])
@@ -223,10 +223,27 @@ def test_tube_64x64x128_fp64_steps_against_oracle():
     u, pr = [host(t) for t in ctx.get_state()]
     X, F, alive = [host(t) for t in ctx.get_nodes()]
     errs = dict(u=rel(u, st.u), p=rel(pr, st.pres), X=rel(X, st.X), F=rel(F, st.F))
-    print("differences after 5 steps", errs, flush=True)
+    print(f"differences after {nsteps} steps", errs, flush=True)
     assert all(e < 1e-12 for e in errs.values()), errs
     assert np.array_equal(alive, st.alive)
     ctx.close()
+
+
+@pytest.mark.timeout(1200)
+def test_tube_64x64x128_fp64_steps_against_oracle():
+    """Five full FP64 steps of the 64 x 64 x 128 tube (5 000 nodes, 72 532
+    springs) against the oracle (see fp64_trajectory_against_oracle).  The
+    oracle takes about half a minute per step here (its hierarchy is
+    assembled anew after every node move)."""
+    fp64_trajectory_against_oracle(5)
+
+
+@pytest.mark.timeout(1500)
+@pytest.mark.skipif(os.environ.get("IBMG_LONG_TESTS") != "1",
+                    reason="about ten minutes of oracle time; run with IBMG_LONG_TESTS=1")
+def test_tube_64x64x128_fp64_twenty_steps_against_oracle():
+    """The same over twenty steps."""
+    fp64_trajectory_against_oracle(20)
 
 
 @pytest.mark.timeout(900)
