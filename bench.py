@@ -229,6 +229,7 @@ def summarize_trace(csv_path, out_path, workload, command):
     the trace and the digest of the kernel sources it ran."""
     import csv
     rows = {}
+    spans = []
     with open(csv_path) as f:
         for r in csv.DictReader(f):
             name = r.get("Kernel_Name", "")
@@ -238,7 +239,9 @@ def summarize_trace(csv_path, out_path, workload, command):
                 grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
             else:
                 grid = int(r.get("Grid_Size", 0))
-            us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            t0, t1 = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+            us = (t1 - t0) / 1e3
+            spans.append((t0, t1, sym))
             e = rows.setdefault((sym, grid), [0, 0.0])
             e[0] += 1
             e[1] += us
@@ -248,6 +251,33 @@ def summarize_trace(csv_path, out_path, workload, command):
              f"{total_ms:.1f} ms.", "", "| kernel | grid | calls | avg us | total ms |", "|---|---:|---:|---:|---:|"]
     for (sym, grid), (n, us) in sorted(rows.items(), key=lambda kv: -kv[1][1])[:60]:
         lines.append(f"| `{sym}` | {grid} | {n} | {us / n:.3f} | {us / 1e3:.3f} |")
+    # idle device time: from the end of the kernels so far to the next start;
+    # and, after each k_reduce_final (a solver iteration's last kernel), the
+    # time to the next kernel that is not the runtime's copy bringing the
+    # norm to the host: the host's round trip between two iterations
+    spans.sort()
+    gaps, turn, copies = [], [], 0
+    end = spans[0][1] if spans else 0
+    for i, (t0, t1, sym) in enumerate(spans[:-1]):
+        end = max(end, t1)
+        gaps.append(max(0, spans[i + 1][0] - end) / 1e3)
+        if sym == "k_reduce_final":
+            j = i + 1
+            while j < len(spans) and "copyBuffer" in spans[j][2]:
+                j += 1
+            if j < len(spans):
+                copies += j > i + 1
+                turn.append(max(0, spans[j][0] - t1) / 1e3)
+    if spans:
+        span_ms = (max(t1 for _, t1, _ in spans) - spans[0][0]) / 1e6
+        idle = sum(gaps) / 1e3
+        med = lambda v: sorted(v)[len(v) // 2] if v else float("nan")
+        lines += ["", "Idle device time between kernels over the whole run (from the end of the kernels so far to the "
+                  f"next start): {idle:.1f} ms of a {span_ms:.1f} ms span ({100 * idle / span_ms:.1f}%), median gap "
+                  f"{med(gaps):.2f} us.  From the end of a `k_reduce_final` (the last kernel of a solver iteration) "
+                  "to the next kernel that is not the runtime's copy of the norm to the host (the host reads the "
+                  f"norm, then replays the next iteration or ends the solve): {len(turn)} times ({copies} with the "
+                  f"copy between), median {med(turn):.2f} us, {sum(turn) / 1e3:.1f} ms in all."]
     lines += ["", f"source_digest: {source_digest()}", ""]
     with open(out_path, "w") as f:
         f.write("\n".join(lines))
