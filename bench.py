@@ -603,7 +603,7 @@ def main():
     if args.inner is None:
         args.inner = 2 if args.workload == "serving" else 4
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported: the path runs on one GPU", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
 
     def log(msg):
