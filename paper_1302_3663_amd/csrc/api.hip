@@ -1358,24 +1358,16 @@ ibb_status solve(ibb_ctx *c, bool vel, int max_cycles, int exact, SolveOut *o)
         }
         // r64 already holds b - A x (from the last residual evaluation)
         const long long units = vel ? L0.nu : L0.np;
-        if (vel) {
-            {
-                Timed t(c, PS_OUTER, 0, units);
-                launch_cast_unknowns<double, float>(L0.g, D, vm, VelArrC<double>{{L0.ru[0], L0.ru[1], L0.ru[2]}},
-                                                    VelArr<float>{{L0.bu32[0], L0.bu32[1], L0.bu32[2]}}, c->s);
-            }
-            for (int a = 0; a < D; ++a) {
-                Timed t(c, PS_OUTER, 0, units);
-                launch_fill<float>(L0.xu32[a], L0.g.nel, 0.0f, c->s);
-            }
-        } else {
-            {
-                Timed t(c, PS_OUTER, 0, units);
-                launch_cast_unknowns<double, float>(L0.g, 1, pm, VelArrC<double>{{L0.rp, nullptr, nullptr}},
-                                                    VelArr<float>{{L0.bp32, nullptr, nullptr}}, c->s);
-            }
+        {
             Timed t(c, PS_OUTER, 0, units);
-            launch_fill<float>(L0.xp32, L0.g.nel, 0.0f, c->s);
+            if (vel)
+                launch_inner_start(L0.g, D, vm, VelArrC<double>{{L0.ru[0], L0.ru[1], L0.ru[2]}},
+                                   VelArr<float>{{L0.bu32[0], L0.bu32[1], L0.bu32[2]}},
+                                   VelArr<float>{{L0.xu32[0], L0.xu32[1], L0.xu32[2]}}, c->s);
+            else
+                launch_inner_start(L0.g, 1, pm, VelArrC<double>{{L0.rp, nullptr, nullptr}},
+                                   VelArr<float>{{L0.bp32, nullptr, nullptr}},
+                                   VelArr<float>{{L0.xp32, nullptr, nullptr}}, c->s);
         }
         for (int it = 0; it < c->d.inner_cycles; ++it) vcycle<float>(c, vel, 0);
         Timed t(c, PS_OUTER, 0, units);

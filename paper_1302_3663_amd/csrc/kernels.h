@@ -247,6 +247,10 @@ void launch_fill(T *p, long long n, T v, hipStream_t s);
 template <typename Ts, typename Td>
 void launch_cast_unknowns(const Grid &g, int ncomp, const int *vmasks, const VelArrC<Ts> &src, const VelArr<Td> &dst,
                           hipStream_t s);
+// b32 = (float) r at the unknowns and x32 = 0 everywhere, for ncomp
+// lattices (the start of a refined iteration's FP32 cycles)
+void launch_inner_start(const Grid &g, int ncomp, const int *vmasks, const VelArrC<double> &r, const VelArr<float> &b32,
+                        const VelArr<float> &x32, hipStream_t s);
 void launch_add_correction(const Grid &g, int ncomp, const int *vmasks, const VelArrC<float> &e,
                            const VelArr<double> &x, hipStream_t s);
 

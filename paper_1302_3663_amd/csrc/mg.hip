@@ -1276,6 +1276,25 @@ __global__ void __launch_bounds__(256) k_cast_unknowns(Grid g, VelBox boxes, Vel
     dst.c[a][e] = (Td)src.c[a][e];
 }
 
+// Start of the FP32 inner cycles of a refined iteration, one launch for
+// what a cast and a clear per component would do: b32 = (float) r64 at the
+// unknowns of each component and x32 = 0 over the whole array (ghosts and
+// fixed faces included).  One thread per array entry.
+__global__ void __launch_bounds__(256) k_inner_start(Grid g, VelBox boxes, VelArrC<double> r, VelArr<float> b32,
+                                                     VelArr<float> x32)
+{
+    const int a = blockIdx.y;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= g.nel) return;
+    x32.c[a][e] = 0.0f;
+    int i, j, k;
+    decode(g, e, i, j, k);
+    const Box &b = boxes.b[a];
+    if (i >= b.lo[0] && i < b.lo[0] + b.ext[0] && j >= b.lo[1] && j < b.lo[1] + b.ext[1] && k >= b.lo[2] &&
+        k < b.lo[2] + b.ext[2])
+        b32.c[a][e] = (float)r.c[a][e];
+}
+
 // x(unknowns) += (double) e(unknowns), ghost images of x updated (role:
 // velocity components or pressure)
 __global__ void __launch_bounds__(256) k_add_correction(Grid g, VelBox boxes, int velocity, VelArrC<float> e,
@@ -2429,6 +2448,14 @@ void launch_cast_unknowns(const Grid &g, int ncomp, const int *vmasks, const Vel
         if (a < ncomp && box_count(boxes.b[a]) > mx) mx = box_count(boxes.b[a]);
     }
     launch_timed(k_cast_unknowns<Ts, Td>, dim3(blocks_for(mx), ncomp), dim3(256), s, g, boxes, src, dst);
+}
+
+void launch_inner_start(const Grid &g, int ncomp, const int *vmasks, const VelArrC<double> &r, const VelArr<float> &b32,
+                        const VelArr<float> &x32, hipStream_t s)
+{
+    VelBox boxes;
+    for (int a = 0; a < 3; ++a) boxes.b[a] = a < ncomp ? unk_box(g, vmasks[a]) : Box{{0, 0, 0}, {0, 0, 0}};
+    launch_timed(k_inner_start, dim3(blocks_for(g.nel), ncomp), dim3(256), s, g, boxes, r, b32, x32);
 }
 
 void launch_add_correction(const Grid &g, int ncomp, const int *vmasks, const VelArrC<float> &e,
